@@ -1,0 +1,153 @@
+/*
+ * lbmfno.h -- C ABI of the MI355X (gfx950) hybrid FNO-LBM hot path.
+ *
+ * The library liblbmfno.so implements, in HIP kernels for gfx950:
+ *   - the D2Q9 single-relaxation-time lattice Boltzmann step of the paper's
+ *     Sec. 2.1 (equilibrium Eq. 1, BGK collision Eq. 2 read as
+ *     f* = f - (f - f_eq)/tau, streaming Eq. 3, moments Eqs. 4-5) with halfway
+ *     bounce-back on obstacle masks, periodic sides, Zou-He velocity inlet /
+ *     pressure outlet (the porous-media setup of Sec. 3.1.1) and Guo body forcing;
+ *   - the equilibrium re-initialisation f <- f_eq(rho, u) that hands macroscopic
+ *     fields (e.g. an FNO prediction) back to the lattice (Sec. 2.3);
+ *   - the Fourier Neural Operator forward pass of Sec. 2.2 (Eq. 6);
+ *   - the adjoint (vector-Jacobian product) of one lattice step.
+ *
+ * Conventions (all entry points):
+ *   - Return LBM_OK (0) on success or a negative LBM_E* code; no exception or
+ *     signal crosses the ABI.  lbm_last_error() returns a message for the calling
+ *     thread's most recent failure.
+ *   - Pointers prefixed d_ are device pointers (HIP device memory of the current
+ *     device), h_ host pointers.  All device buffers are owned by the caller and
+ *     must outlive every call (and every context) that uses them.  A context owns
+ *     only small internal buffers (link mask, reduction scratch, graphs).
+ *   - `stream` is a hipStream_t passed as void*; NULL means the default stream.
+ *     Work is enqueued asynchronously on it unless a call says it synchronises.
+ *   - Arguments are validated on the host before any HIP call; invalid ones return
+ *     LBM_EINVAL without touching the device.
+ *   - Lattice planes are [ny][nx] with x fastest.  Populations are structure-of-
+ *     arrays [9][ny][nx] float32 in the order
+ *       q : 0     1     2     3      4      5      6       7       8
+ *       c : (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1)  (-1,1)  (-1,-1) (1,-1)
+ *     with weights w = 4/9, 1/9 (q=1..4), 1/36 (q=5..8) and c_s^2 = 1/3.
+ *   - Obstacle masks are uint8 [ny][nx], 1 = solid, 0 = fluid.
+ *   - One context must not be used from two threads at once.
+ */
+#ifndef LBMFNO_H
+#define LBMFNO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status codes */
+#define LBM_OK 0
+#define LBM_EINVAL (-1)         /* invalid argument (checked before any HIP call) */
+#define LBM_ENOMEM (-2)         /* device or host allocation failed */
+#define LBM_EHIP (-3)           /* a HIP runtime call failed */
+#define LBM_EUNSUPPORTED (-4)   /* valid but not implemented combination */
+#define LBM_ENOTCONVERGED (-5)  /* step budget exhausted before the residual target */
+#define LBM_EDIVERGED (-6)      /* non-finite mass or residual */
+
+/* Boundary handling per axis. */
+#define LBM_BC_PERIODIC 0  /* periodic wrap */
+#define LBM_BC_WALL 1      /* no-slip wall half a cell beyond the first/last node
+                              (halfway bounce-back, link-wise) */
+#define LBM_BC_ZOUHE 2     /* x axis only: Zou-He velocity inlet (u_in, 0) at x = 0
+                              and pressure outlet rho_out at x = nx-1 */
+
+/* Register arithmetic of the collision.  Populations are stored and moved as
+ * float32 in both modes. */
+#define LBM_ARITH_MIXED 0  /* moments, equilibrium and relaxation in FP64 registers,
+                              rounded once to FP32 at the store (default) */
+#define LBM_ARITH_FP32 1   /* everything in FP32 registers */
+
+/* Lattice description.  tau > 1/2 is the BGK relaxation time (nu = (tau-1/2)/3 in
+ * lattice units), (gx, gy) a uniform body force per unit mass (Guo forcing; use 0
+ * with LBM_BC_ZOUHE), arith one of LBM_ARITH_*. */
+typedef struct lbm_config {
+    int32_t nx, ny;
+    int32_t bc_x, bc_y;
+    double tau;
+    double gx, gy;
+    double u_in, rho_out;
+    int32_t arith;
+    int32_t reserved;
+} lbm_config;
+
+/* Diagnostics of the state at time n (FP64 accumulation over fluid nodes). */
+typedef struct lbm_report {
+    double residual;     /* sum |rho(n) - rho(n-1)| / sum rho(n) */
+    double mass;         /* sum rho(n) */
+    double mom_x, mom_y; /* sum rho(n) u(n) */
+    int64_t steps_done;  /* n: steps since the last (re)initialisation */
+    int64_t fluid_nodes;
+} lbm_report;
+
+typedef struct lbm_ctx lbm_ctx;
+
+const char* lbm_status_str(int code);
+/* Message of the calling thread's last failed call ("" if none). */
+const char* lbm_last_error(void);
+
+/* Obstacle raster (paper Sec. 3.1.1: random circular obstacles as a binary mask;
+ * porosity Eq. 8 is 1 - solid fraction).  h_shapes holds nshapes descriptors of
+ * 7 int64 each, (cx, cy, A, B, C, F, R): cell (i, j) is solid iff for some shape
+ * A dx^2 + B dx dy + C dy^2 <= F with |dx|, |dy| <= R, dx = i - cx and dy = j - cy
+ * taken as the periodic image in (-n/2, n/2] when wrap_x / wrap_y is set.  Exact
+ * int64 arithmetic: 0 <= R < 2^15, |cx|, |cy| <= 2^30, (|A|+|B|+|C|) R^2 < 2^62
+ * and |F| < 2^62 are required (else LBM_EINVAL).  Writes d_mask (uint8 [ny][nx]).  Copies the shapes to the device and synchronises
+ * `stream` before returning. */
+int lbm_mask_raster(int32_t nx, int32_t ny, int32_t wrap_x, int32_t wrap_y,
+                    const int64_t* h_shapes, int32_t nshapes, uint8_t* d_mask, void* stream);
+
+/* Create a lattice context on the current device.  d_mask: uint8 [ny][nx]
+ * (copied into per-node link bits; the caller may free it afterwards).  d_fA and
+ * d_fB: caller-owned float32 buffers of 9*nx*ny elements each, used as ping-pong
+ * population stores.  The state is set to rest (rho = 1, u = 0; the paper's
+ * default initialisation, Sec. 2.1, Fig. 1's caption).  nx*ny must be below 2^31
+ * / 9.  Storage detail: a store holds, for every node, the populations its
+ * neighbours pull in the next step, minus the lattice weight w_q (deviation
+ * storage keeps FP32 rounding relative to the small non-equilibrium part). */
+int lbm_init(lbm_ctx** out, const lbm_config* cfg, const uint8_t* d_mask, float* d_fA,
+             float* d_fB, void* stream);
+
+void lbm_destroy(lbm_ctx* ctx);
+
+/* Equilibrium re-initialisation (Sec. 2.1 initialisation block; Sec. 2.3 hand-off
+ * of FNO fields to the lattice): f_q(x, 0) = f_eq_q(rho(x), u(x)) (Eq. 1) on every
+ * fluid node, then the boundary closures; the step counter restarts at 0.
+ * d_rho, d_ux, d_uy: float32 [ny][nx]; values on solid nodes are ignored. */
+int lbm_reinit_from_macro(lbm_ctx* ctx, const float* d_rho, const float* d_ux, const float* d_uy);
+
+/* Advance n >= 0 steps: each gathers f(t) (streaming Eq. 3 with bounce-back and
+ * Zou-He), takes moments (Eqs. 4-5, u = (sum c f + rho g/2)/rho), collides (Eq. 2
+ * with the Guo term) and stores the result for the next pull.  With rep == NULL
+ * the call is fully asynchronous.  With rep != NULL (then n >= 1) the residual,
+ * mass and momentum of the final state are reduced in FP64 on the device, copied
+ * back, and the stream is synchronised. */
+int lbm_step(lbm_ctx* ctx, int32_t n, lbm_report* rep);
+
+/* Macroscopic fields of the current state f(n) (Eqs. 4-5 with the half-force
+ * velocity); solid nodes get (1, 0, 0).  If rho_minus_one != 0, d_rho receives
+ * rho - 1 instead of rho (full FP32 resolution of small density deviations). */
+int lbm_get_macro(lbm_ctx* ctx, float* d_rho, float* d_ux, float* d_uy, int32_t rho_minus_one);
+
+/* Current pre-collision populations f(n) (after streaming and boundary closures),
+ * float32 [9][ny][nx]; solid nodes get the rest weights w_q. */
+int lbm_get_populations(lbm_ctx* ctx, float* d_f);
+
+/* Replace the state by the given pre-collision populations f(n) (float32
+ * [9][ny][nx], solid entries ignored); the step counter is kept. */
+int lbm_set_populations(lbm_ctx* ctx, const float* d_f);
+
+/* Number of fluid nodes and the current step counter (host values). */
+int lbm_info(const lbm_ctx* ctx, int64_t* fluid_nodes, int64_t* steps_done);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBMFNO_H */

@@ -1,0 +1,765 @@
+// lbm.hip -- D2Q9 BGK lattice Boltzmann hot path for gfx950 behind the C ABI of
+// include/lbmfno.h: obstacle raster, link bits, equilibrium (re)initialisation,
+// the fused pull-scheme collide+stream step, macroscopic fields and FP64 sums.
+//
+// Storage.  Populations live in two caller-owned float32 stores of 9 planes
+// [ny][nx] (structure of arrays).  The store for time t holds, for every node y
+// and direction p, the value that will be pulled into f_p(y + c_p, t) -- or, when
+// y + c_p is solid or beyond a wall / open boundary, the value that bounces back
+// into f_{opp p}(y, t) -- minus the weight w_p.  A step therefore reads one store
+// with a pure gather (periodic wrap, halfway bounce-back from per-node link bits,
+// Zou-He on the two open columns), computes the moments and the BGK + Guo
+// collision in registers, and writes the other store in place order: 9 loads, 9
+// stores and one link byte per fluid node, fully coalesced along x.
+//
+// Deviation storage (f - w) keeps FP32 rounding relative to the small
+// non-equilibrium part of f, which the 1e-5 field tolerance against FP64 needs.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+namespace lbmfno {
+
+static thread_local std::string g_err;
+
+void set_error(const char* fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+}
+
+int fail(int code, const char* fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+// --------------------------------------------------------------- kernels
+
+constexpr int TX = 64;  // one wavefront along x
+constexpr int TY = 4;   // four rows per workgroup
+
+__global__ __launch_bounds__(256) void k_mask_raster(int nx, int ny, int wrap_x, int wrap_y,
+                                                     const int64_t* __restrict__ shapes, int ns,
+                                                     uint8_t* __restrict__ mask) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= nx) return;
+    uint8_t solid = 0;
+    for (int s = 0; s < ns && !solid; ++s) {
+        const int64_t* p = shapes + 7 * s;
+        int dx = i - (int)p[0], dy = j - (int)p[1];
+        if (wrap_x) {
+            dx %= nx;
+            if (dx < 0) dx += nx;
+            if (dx > nx / 2) dx -= nx;
+        }
+        if (wrap_y) {
+            dy %= ny;
+            if (dy < 0) dy += ny;
+            if (dy > ny / 2) dy -= ny;
+        }
+        const int R = (int)p[6];
+        if (dx > R || -dx > R || dy > R || -dy > R) continue;
+        const int64_t X = dx, Y = dy;
+        if (p[2] * X * X + p[3] * X * Y + p[4] * Y * Y <= p[5]) solid = 1;
+    }
+    mask[(size_t)j * nx + i] = solid;
+}
+
+// Link bits: bit q-1 (q = 1..8) is set when the pull source x - c_q is solid or
+// lies beyond a non-periodic boundary (halfway bounce-back, or the unknown
+// populations of a Zou-He column, which the closure overwrites).  Solid nodes
+// store 0xFF; a fluid node can also have all eight links bounced (an isolated
+// pocket), so 0xFF is disambiguated by the mask byte, which is read only then.
+__global__ __launch_bounds__(256) void k_links(int nx, int ny, int bc_x, int bc_y,
+                                               const uint8_t* __restrict__ mask,
+                                               uint8_t* __restrict__ link) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= nx) return;
+    const int n = j * nx + i;
+    unsigned bits = 0;
+#pragma unroll
+    for (int q = 1; q < 9; ++q) {
+        int si = i - cx_of(q), sj = j - cy_of(q);
+        bool out = false;
+        if (si < 0 || si >= nx) {
+            if (bc_x == LBM_BC_PERIODIC) si = (si + nx) % nx; else out = true;
+        }
+        if (sj < 0 || sj >= ny) {
+            if (bc_y == LBM_BC_PERIODIC) sj = (sj + ny) % ny; else out = true;
+        }
+        if (out || mask[sj * nx + si]) bits |= 1u << (q - 1);
+    }
+    link[n] = mask[n] ? (uint8_t)0xFF : (uint8_t)bits;
+}
+
+__device__ __forceinline__ bool is_solid(unsigned lk, const uint8_t* __restrict__ mask, int n) {
+    return lk == 0xFFu && mask[n] != 0;
+}
+
+struct LatticeGeom {
+    int nx, ny, N, gridx, bc_x, bc_y;
+};
+
+// Node y + c_p if it is a fluid node inside the domain, else -1.
+__device__ __forceinline__ int push_target(const LatticeGeom& g, const uint8_t* __restrict__ mask,
+                                           int i, int j, int p) {
+    int ti = i + cx_of(p), tj = j + cy_of(p);
+    if (ti < 0 || ti >= g.nx) {
+        if (g.bc_x != LBM_BC_PERIODIC) return -1;
+        ti = (ti + g.nx) % g.nx;
+    }
+    if (tj < 0 || tj >= g.ny) {
+        if (g.bc_y != LBM_BC_PERIODIC) return -1;
+        tj = (tj + g.ny) % g.ny;
+    }
+    const int t = tj * g.nx + ti;
+    return mask[t] ? -1 : t;
+}
+
+// Deviation equilibrium f_eq_p - w_p = w_p [(rho - 1) + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u.u)].
+template <int P, typename R>
+__device__ __forceinline__ R feq_dev(R drho, R rho, R ux, R uy) {
+    const R cu = (R)cx_of(P) * ux + (R)cy_of(P) * uy;
+    const R usq = R(1.5) * (ux * ux + uy * uy);
+    return (R)w_of_d(P) * (drho + rho * (R(3) * cu + R(4.5) * cu * cu - usq));
+}
+
+__device__ __forceinline__ float feq_dev_rt(int p, double drho, double rho, double ux, double uy) {
+    switch (p) {
+        case 0: return (float)feq_dev<0>(drho, rho, ux, uy);
+        case 1: return (float)feq_dev<1>(drho, rho, ux, uy);
+        case 2: return (float)feq_dev<2>(drho, rho, ux, uy);
+        case 3: return (float)feq_dev<3>(drho, rho, ux, uy);
+        case 4: return (float)feq_dev<4>(drho, rho, ux, uy);
+        case 5: return (float)feq_dev<5>(drho, rho, ux, uy);
+        case 6: return (float)feq_dev<6>(drho, rho, ux, uy);
+        case 7: return (float)feq_dev<7>(drho, rho, ux, uy);
+        default: return (float)feq_dev<8>(drho, rho, ux, uy);
+    }
+}
+
+// Scatter f(0) into a store: slot (p, y) receives what y + c_p pulls, or, when that
+// node is solid/outside, what bounces back into y as opp(p).
+//   FROM_FIELDS: f_q(x) = f_eq_q(rho(x), u(x))        (re-initialisation)
+//   else:        f_q(x) = given populations (absolute) (state restore)
+template <bool FROM_FIELDS>
+__global__ __launch_bounds__(256) void k_scatter(LatticeGeom g, const uint8_t* __restrict__ mask,
+                                                 const float* __restrict__ rho,
+                                                 const float* __restrict__ ux,
+                                                 const float* __restrict__ uy,
+                                                 const float* __restrict__ fin,
+                                                 float* __restrict__ dst) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= g.nx) return;
+    const int n = j * g.nx + i;
+    const size_t N = (size_t)g.N;
+    if (mask[n]) {
+#pragma unroll
+        for (int p = 0; p < 9; ++p) dst[p * N + n] = 0.0f;
+        return;
+    }
+#pragma unroll
+    for (int p = 0; p < 9; ++p) {
+        const int t = p == 0 ? n : push_target(g, mask, i, j, p);
+        const int src = t >= 0 ? t : n;
+        const int dir = t >= 0 ? p : opp_of(p);
+        float v;
+        if (FROM_FIELDS) {
+            const double r = rho[src];
+            v = feq_dev_rt(dir, r - 1.0, r, ux[src], uy[src]);
+        } else {
+            v = (float)((double)fin[dir * N + src] - w_of_d(dir));
+        }
+        dst[p * N + n] = v;
+    }
+}
+
+struct StepArgs {
+    const float* __restrict__ src;
+    float* __restrict__ dst;
+    const uint8_t* __restrict__ link;
+    const uint8_t* __restrict__ mask;
+    float* __restrict__ drho_out;
+    LatticeGeom g;
+    double omega, guo, gx, gy, u_in, rho_out;
+};
+
+// Pull gather of f(t) at node (i, j) from the deviation store.
+template <typename R>
+__device__ __forceinline__ void gather(const float* __restrict__ src, const LatticeGeom& g,
+                                       unsigned lk, int i, int j, int n, R f[9]) {
+    const int im = i == 0 ? g.nx - 1 : i - 1, ip = i == g.nx - 1 ? 0 : i + 1;
+    const int jm = j == 0 ? g.ny - 1 : j - 1, jp = j == g.ny - 1 ? 0 : j + 1;
+    const int r0 = j * g.nx, rm = jm * g.nx, rp = jp * g.nx;
+    const int N = g.N;
+    // pull source x - c_q for q = 0..8
+    const int s[9] = {n, r0 + im, rm + i, r0 + ip, rp + i, rm + im, rm + ip, rp + ip, rp + im};
+    f[0] = (R)src[n];
+#pragma unroll
+    for (int q = 1; q < 9; ++q) {
+        const bool bb = (lk >> (q - 1)) & 1u;
+        const int off = bb ? opp_of(q) * N + n : q * N + s[q];
+        f[q] = (R)src[off];
+    }
+}
+
+// Zou-He closures in deviation variables (w_1 = w_3, w_5 = w_7, w_6 = w_8 and
+// sum of the known weights = 1 make the shifted formulas identical in form).
+template <typename R>
+__device__ __forceinline__ void zouhe(R f[9], int i, int nx, R u_in, R rho_out) {
+    if (i == 0) {
+        const R s = f[0] + f[2] + f[4] + R(2) * (f[3] + f[6] + f[7]);
+        const R rho = R(1) + (s + u_in) / (R(1) - u_in);
+        const R ru = rho * u_in;
+        const R h = R(0.5) * (f[2] - f[4]);
+        f[1] = f[3] + (R(2) / R(3)) * ru;
+        f[5] = f[7] - h + (R(1) / R(6)) * ru;
+        f[8] = f[6] + h + (R(1) / R(6)) * ru;
+    } else if (i == nx - 1) {
+        const R s = f[0] + f[2] + f[4] + R(2) * (f[1] + f[5] + f[8]);
+        const R ux = ((R(1) - rho_out) + s) / rho_out;
+        const R ru = rho_out * ux;
+        const R h = R(0.5) * (f[2] - f[4]);
+        f[3] = f[1] - (R(2) / R(3)) * ru;
+        f[6] = f[8] - h - (R(1) / R(6)) * ru;
+        f[7] = f[5] + h - (R(1) / R(6)) * ru;
+    }
+}
+
+template <typename R>
+struct Moments {
+    R drho, rho, ux, uy;
+};
+
+template <bool FORCE, typename R>
+__device__ __forceinline__ Moments<R> moments(const R f[9], R gx, R gy) {
+    Moments<R> m;
+    m.drho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+    m.rho = R(1) + m.drho;
+    const R jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+    const R jy = (f[2] - f[4]) + (f[5] - f[8]) + (f[6] - f[7]);
+    const R inv = R(1) / m.rho;
+    m.ux = jx * inv;
+    m.uy = jy * inv;
+    if (FORCE) {
+        m.ux += R(0.5) * gx;
+        m.uy += R(0.5) * gy;
+    }
+    return m;
+}
+
+template <int Q, bool FORCE, typename R>
+__device__ __forceinline__ float collide_q(R fq, const Moments<R>& m, R omega, R guo, R gx, R gy) {
+    const R fe = feq_dev<Q>(m.drho, m.rho, m.ux, m.uy);
+    R out = fq - omega * (fq - fe);
+    if (FORCE) {
+        constexpr R cxq = (R)cx_of(Q), cyq = (R)cy_of(Q);
+        const R cu = cxq * m.ux + cyq * m.uy;
+        const R cg = cxq * gx + cyq * gy;
+        const R t = R(3) * ((cxq - m.ux) * gx + (cyq - m.uy) * gy) + R(9) * cu * cg;
+        out += guo * (R)w_of_d(Q) * m.rho * t;
+    }
+    return (float)out;
+}
+
+// One fused step t -> t+1 for one node per thread.  R is the register type of
+// the collision arithmetic (double by default; float for the all-FP32 variant);
+// the stores are float either way.
+template <bool ZH, bool FORCE, bool WDRHO, typename R>
+__global__ __launch_bounds__(256) void k_bgk_step(StepArgs a) {
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int by = b / a.g.gridx, bx = b - by * a.g.gridx;
+    const int i = bx * TX + threadIdx.x, j = by * TY + threadIdx.y;
+    if (i >= a.g.nx || j >= a.g.ny) return;
+    const int n = j * a.g.nx + i;
+    const unsigned lk = a.link[n];
+    if (is_solid(lk, a.mask, n)) return;
+    R f[9];
+    gather<R>(a.src, a.g, lk, i, j, n, f);
+    if (ZH) zouhe<R>(f, i, a.g.nx, (R)a.u_in, (R)a.rho_out);
+    const R gx = (R)a.gx, gy = (R)a.gy, om = (R)a.omega, guo = (R)a.guo;
+    const Moments<R> m = moments<FORCE, R>(f, gx, gy);
+    if (WDRHO) a.drho_out[n] = (float)m.drho;
+    float* __restrict__ d = a.dst + n;
+    const size_t N = (size_t)a.g.N;
+    d[0 * N] = collide_q<0, FORCE, R>(f[0], m, om, guo, gx, gy);
+    d[1 * N] = collide_q<1, FORCE, R>(f[1], m, om, guo, gx, gy);
+    d[2 * N] = collide_q<2, FORCE, R>(f[2], m, om, guo, gx, gy);
+    d[3 * N] = collide_q<3, FORCE, R>(f[3], m, om, guo, gx, gy);
+    d[4 * N] = collide_q<4, FORCE, R>(f[4], m, om, guo, gx, gy);
+    d[5 * N] = collide_q<5, FORCE, R>(f[5], m, om, guo, gx, gy);
+    d[6 * N] = collide_q<6, FORCE, R>(f[6], m, om, guo, gx, gy);
+    d[7 * N] = collide_q<7, FORCE, R>(f[7], m, om, guo, gx, gy);
+    d[8 * N] = collide_q<8, FORCE, R>(f[8], m, om, guo, gx, gy);
+}
+
+struct MacroArgs {
+    const float* __restrict__ src;
+    const uint8_t* __restrict__ link;
+    const uint8_t* __restrict__ mask;
+    LatticeGeom g;
+    double gx, gy, u_in, rho_out;
+    float* __restrict__ rho;  // optional outputs
+    float* __restrict__ ux;
+    float* __restrict__ uy;
+    int rho_minus_one;
+    float* __restrict__ fpop;                 // optional absolute populations out
+    const float* __restrict__ drho_prev;      // residual reference (SUMS)
+    double* __restrict__ partials;            // [gridDim.x][4] (SUMS)
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+
+// Gather-only pass over the current store: macroscopic fields, populations and,
+// with SUMS, per-workgroup FP64 partial sums (|drho - drho_prev|, rho, rho ux, rho uy).
+template <bool ZH, bool FORCE, bool SUMS>
+__global__ __launch_bounds__(256) void k_macro(MacroArgs a) {
+    const int b = blockIdx.x;
+    const int by = b / a.g.gridx, bx = b - by * a.g.gridx;
+    const int i = bx * TX + threadIdx.x, j = by * TY + threadIdx.y;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    if (i < a.g.nx && j < a.g.ny) {
+        const int n = j * a.g.nx + i;
+        const unsigned lk = a.link[n];
+        const size_t N = (size_t)a.g.N;
+        if (is_solid(lk, a.mask, n)) {
+            if (a.rho) a.rho[n] = a.rho_minus_one ? 0.0f : 1.0f;
+            if (a.ux) a.ux[n] = 0.0f;
+            if (a.uy) a.uy[n] = 0.0f;
+            if (a.fpop) {
+#pragma unroll
+                for (int q = 0; q < 9; ++q) a.fpop[q * N + n] = w_of(q);
+            }
+        } else {
+            double f[9];
+            gather<double>(a.src, a.g, lk, i, j, n, f);
+            if (ZH) zouhe<double>(f, i, a.g.nx, a.u_in, a.rho_out);
+            const Moments<double> m = moments<FORCE, double>(f, a.gx, a.gy);
+            if (a.rho) a.rho[n] = (float)(a.rho_minus_one ? m.drho : m.rho);
+            if (a.ux) a.ux[n] = (float)m.ux;
+            if (a.uy) a.uy[n] = (float)m.uy;
+            if (a.fpop) {
+#pragma unroll
+                for (int q = 0; q < 9; ++q) a.fpop[q * N + n] = (float)(f[q] + w_of_d(q));
+            }
+            if (SUMS) {
+                // the residual compares FP32-stored density deviations of
+                // consecutive steps (both sides rounded the same way)
+                s0 = fabs((double)(float)m.drho - (double)a.drho_prev[n]);
+                s1 = m.rho;
+                s2 = m.rho * m.ux;
+                s3 = m.rho * m.uy;
+            }
+        }
+    }
+    if (SUMS) {
+        __shared__ double red[4][4];
+        const int lane = threadIdx.x;  // blockDim.x == 64: one wavefront per row
+        const int wave = threadIdx.y;
+        s0 = wave_sum(s0); s1 = wave_sum(s1); s2 = wave_sum(s2); s3 = wave_sum(s3);
+        if (lane == 0) { red[wave][0] = s0; red[wave][1] = s1; red[wave][2] = s2; red[wave][3] = s3; }
+        __syncthreads();
+        if (wave == 0 && lane < 4) {
+            const double t = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+            a.partials[(size_t)b * 4 + lane] = t;
+        }
+    }
+}
+
+// Second, fixed-order pass over the per-workgroup partials (deterministic).
+__global__ __launch_bounds__(256) void k_reduce_final(const double* __restrict__ partials, int nb,
+                                                      double* __restrict__ out) {
+    __shared__ double red[4][4];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = t; b < nb; b += 256)
+        for (int k = 0; k < 4; ++k) s[k] += partials[(size_t)b * 4 + k];
+    for (int k = 0; k < 4; ++k) {
+        const double v = wave_sum(s[k]);
+        if (lane == 0) red[wave][k] = v;
+    }
+    __syncthreads();
+    if (t < 4) out[t] = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
+}
+
+}  // namespace lbmfno
+
+// ------------------------------------------------------------ host side
+
+using namespace lbmfno;
+
+struct lbm_ctx {
+    lbm_config cfg;
+    LatticeGeom g;
+    float* f[2];
+    int cur;
+    hipStream_t stream;
+    uint8_t* d_link;
+    uint8_t* d_mask;
+    float* d_drho;
+    double* d_partials;
+    double* d_out;
+    double* h_out;
+    int nblocks;
+    int64_t fluid;
+    int64_t steps;
+    hipGraphExec_t graph[2];
+    int graph_chunk;
+    int device;
+};
+
+static bool finite_d(double x) { return std::isfinite(x); }
+
+static int validate_config(const lbm_config* c) {
+    if (!c) return fail(LBM_EINVAL, "config is NULL");
+    if (c->nx < 1 || c->ny < 1) return fail(LBM_EINVAL, "lattice size %d x %d", c->nx, c->ny);
+    if ((int64_t)c->nx * c->ny * 9 >= (int64_t)1 << 31)
+        return fail(LBM_EINVAL, "lattice %d x %d too large for 32-bit plane offsets", c->nx, c->ny);
+    if (!(c->tau > 0.5) || !finite_d(c->tau))
+        return fail(LBM_EINVAL, "tau = %g must be finite and > 1/2", c->tau);
+    if (!finite_d(c->gx) || !finite_d(c->gy)) return fail(LBM_EINVAL, "non-finite body force");
+    if (c->arith != LBM_ARITH_MIXED && c->arith != LBM_ARITH_FP32)
+        return fail(LBM_EINVAL, "arith = %d", c->arith);
+    if (c->bc_x < 0 || c->bc_x > 2 || c->bc_y < 0 || c->bc_y > 1)
+        return fail(LBM_EINVAL, "boundary codes bc_x=%d bc_y=%d", c->bc_x, c->bc_y);
+    if (c->bc_x == LBM_BC_ZOUHE) {
+        if (c->nx < 3) return fail(LBM_EINVAL, "Zou-He needs nx >= 3");
+        if (!(c->u_in > -1.0 && c->u_in < 1.0) || !finite_d(c->u_in))
+            return fail(LBM_EINVAL, "u_in = %g out of (-1, 1)", c->u_in);
+        if (!(c->rho_out > 0.0) || !finite_d(c->rho_out))
+            return fail(LBM_EINVAL, "rho_out = %g must be > 0", c->rho_out);
+        if (c->gx != 0.0 || c->gy != 0.0)
+            return fail(LBM_EUNSUPPORTED, "body force with Zou-He boundaries");
+        if (c->bc_y == LBM_BC_WALL)
+            return fail(LBM_EUNSUPPORTED, "Zou-He columns meeting wall rows (corners)");
+    }
+    return LBM_OK;
+}
+
+extern "C" const char* lbm_status_str(int code) {
+    switch (code) {
+        case LBM_OK: return "ok";
+        case LBM_EINVAL: return "invalid argument";
+        case LBM_ENOMEM: return "out of memory";
+        case LBM_EHIP: return "HIP runtime error";
+        case LBM_EUNSUPPORTED: return "unsupported";
+        case LBM_ENOTCONVERGED: return "not converged";
+        case LBM_EDIVERGED: return "diverged";
+        default: return "unknown status";
+    }
+}
+
+extern "C" const char* lbm_last_error(void) { return g_err.c_str(); }
+
+extern "C" int lbm_mask_raster(int32_t nx, int32_t ny, int32_t wrap_x, int32_t wrap_y,
+                               const int64_t* h_shapes, int32_t nshapes, uint8_t* d_mask,
+                               void* stream) {
+    if (nx < 1 || ny < 1 || (int64_t)nx * ny >= ((int64_t)1 << 31))
+        return fail(LBM_EINVAL, "raster size %d x %d", nx, ny);
+    if (nshapes < 0 || (nshapes > 0 && !h_shapes)) return fail(LBM_EINVAL, "shape list");
+    if (!d_mask) return fail(LBM_EINVAL, "d_mask is NULL");
+    for (int s = 0; s < nshapes; ++s) {
+        const int64_t* p = h_shapes + 7 * (size_t)s;
+        const __int128 R = p[6];
+        if (p[6] < 0 || p[6] >= (1 << 15)) return fail(LBM_EINVAL, "shape %d: R = %lld", s, (long long)p[6]);
+        if (p[0] < -(1 << 30) || p[0] > (1 << 30) || p[1] < -(1 << 30) || p[1] > (1 << 30))
+            return fail(LBM_EINVAL, "shape %d: centre out of range", s);
+        const __int128 mag = ((__int128)llabs(p[2]) + llabs(p[3]) + llabs(p[4])) * R * R;
+        if (mag >= ((__int128)1 << 62) || llabs(p[5]) >= ((int64_t)1 << 62))
+            return fail(LBM_EINVAL, "shape %d: coefficients overflow int64 on |dx|,|dy| <= R", s);
+    }
+    hipStream_t st = (hipStream_t)stream;
+    int64_t* d_shapes = nullptr;
+    if (nshapes > 0) {
+        LBM_HIP(hipMalloc(&d_shapes, sizeof(int64_t) * 7 * (size_t)nshapes));
+        hipError_t e = hipMemcpyAsync(d_shapes, h_shapes, sizeof(int64_t) * 7 * (size_t)nshapes,
+                                      hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) {
+            (void)hipFree(d_shapes);
+            return fail(LBM_EHIP, "shape upload: %s", hipGetErrorString(e));
+        }
+    }
+    dim3 blk(256), grd((nx + 255) / 256, ny);
+    k_mask_raster<<<grd, blk, 0, st>>>(nx, ny, wrap_x, wrap_y, d_shapes, nshapes, d_mask);
+    hipError_t e = hipGetLastError();
+    hipError_t e2 = hipStreamSynchronize(st);
+    if (d_shapes) (void)hipFree(d_shapes);
+    if (e != hipSuccess) return fail(LBM_EHIP, "raster launch: %s", hipGetErrorString(e));
+    if (e2 != hipSuccess) return fail(LBM_EHIP, "raster sync: %s", hipGetErrorString(e2));
+    return LBM_OK;
+}
+
+static void release(lbm_ctx* c) {
+    if (!c) return;
+    for (int k = 0; k < 2; ++k)
+        if (c->graph[k]) (void)hipGraphExecDestroy(c->graph[k]);
+    if (c->d_link) (void)hipFree(c->d_link);
+    if (c->d_mask) (void)hipFree(c->d_mask);
+    if (c->d_drho) (void)hipFree(c->d_drho);
+    if (c->d_partials) (void)hipFree(c->d_partials);
+    if (c->d_out) (void)hipFree(c->d_out);
+    if (c->h_out) (void)hipHostFree(c->h_out);
+    delete c;
+}
+
+extern "C" void lbm_destroy(lbm_ctx* ctx) { release(ctx); }
+
+static int launch_step(lbm_ctx* c, bool write_drho) {
+    StepArgs a;
+    a.src = c->f[c->cur];
+    a.dst = c->f[c->cur ^ 1];
+    a.link = c->d_link;
+    a.mask = c->d_mask;
+    a.drho_out = c->d_drho;
+    a.g = c->g;
+    a.omega = 1.0 / c->cfg.tau;
+    a.guo = 1.0 - 0.5 / c->cfg.tau;
+    a.gx = c->cfg.gx;
+    a.gy = c->cfg.gy;
+    a.u_in = c->cfg.u_in;
+    a.rho_out = c->cfg.rho_out;
+    const bool zh = c->cfg.bc_x == LBM_BC_ZOUHE;
+    const bool force = c->cfg.gx != 0.0 || c->cfg.gy != 0.0;
+    const bool f32 = c->cfg.arith == LBM_ARITH_FP32;
+    dim3 blk(TX, TY), grd(c->nblocks);
+    hipStream_t s = c->stream;
+#define LBM_STEP_CASE(Z, F, W)                                                         \
+    if (zh == Z && force == F && write_drho == W) {                                   \
+        if (f32) k_bgk_step<Z, F, W, float><<<grd, blk, 0, s>>>(a);                   \
+        else k_bgk_step<Z, F, W, double><<<grd, blk, 0, s>>>(a);                      \
+    }
+    LBM_STEP_CASE(false, false, false)
+    LBM_STEP_CASE(false, false, true)
+    LBM_STEP_CASE(false, true, false)
+    LBM_STEP_CASE(false, true, true)
+    LBM_STEP_CASE(true, false, false)
+    LBM_STEP_CASE(true, false, true)
+    LBM_STEP_CASE(true, true, false)
+    LBM_STEP_CASE(true, true, true)
+#undef LBM_STEP_CASE
+    c->cur ^= 1;
+    ++c->steps;
+    return LBM_OK;
+}
+
+static int launch_macro(lbm_ctx* c, float* rho, float* ux, float* uy, int rm1, float* fpop,
+                        bool sums) {
+    MacroArgs a;
+    a.src = c->f[c->cur];
+    a.link = c->d_link;
+    a.mask = c->d_mask;
+    a.g = c->g;
+    a.gx = c->cfg.gx;
+    a.gy = c->cfg.gy;
+    a.u_in = c->cfg.u_in;
+    a.rho_out = c->cfg.rho_out;
+    a.rho = rho;
+    a.ux = ux;
+    a.uy = uy;
+    a.rho_minus_one = rm1;
+    a.fpop = fpop;
+    a.drho_prev = c->d_drho;
+    a.partials = c->d_partials;
+    const bool zh = c->cfg.bc_x == LBM_BC_ZOUHE;
+    const bool force = c->cfg.gx != 0.0 || c->cfg.gy != 0.0;
+    dim3 blk(TX, TY), grd(c->nblocks);
+    hipStream_t s = c->stream;
+#define LBM_MACRO_CASE(Z, F, S) \
+    if (zh == Z && force == F && sums == S) k_macro<Z, F, S><<<grd, blk, 0, s>>>(a);
+    LBM_MACRO_CASE(false, false, false)
+    LBM_MACRO_CASE(false, false, true)
+    LBM_MACRO_CASE(false, true, false)
+    LBM_MACRO_CASE(false, true, true)
+    LBM_MACRO_CASE(true, false, false)
+    LBM_MACRO_CASE(true, false, true)
+    LBM_MACRO_CASE(true, true, false)
+    LBM_MACRO_CASE(true, true, true)
+#undef LBM_MACRO_CASE
+    LBM_HIP(hipGetLastError());
+    return LBM_OK;
+}
+
+extern "C" int lbm_init(lbm_ctx** out, const lbm_config* cfg, const uint8_t* d_mask, float* d_fA,
+                        float* d_fB, void* stream) {
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate_config(cfg);
+    if (rc) return rc;
+    if (!d_mask || !d_fA || !d_fB) return fail(LBM_EINVAL, "NULL device buffer");
+    if (d_fA == d_fB) return fail(LBM_EINVAL, "the two population stores must differ");
+    lbm_ctx* c = new (std::nothrow) lbm_ctx();
+    if (!c) return fail(LBM_ENOMEM, "context allocation");
+    c->cfg = *cfg;
+    c->g.nx = cfg->nx;
+    c->g.ny = cfg->ny;
+    c->g.N = cfg->nx * cfg->ny;
+    c->g.gridx = (cfg->nx + TX - 1) / TX;
+    c->g.bc_x = cfg->bc_x;
+    c->g.bc_y = cfg->bc_y;
+    c->nblocks = c->g.gridx * ((cfg->ny + TY - 1) / TY);
+    c->f[0] = d_fA;
+    c->f[1] = d_fB;
+    c->cur = 0;
+    c->stream = (hipStream_t)stream;
+    c->graph_chunk = 32;
+    const size_t N = (size_t)c->g.N;
+#define LBM_TRY(call)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess) {                                                         \
+            int r_ = fail(e_ == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EHIP, "%s: %s",   \
+                          #call, hipGetErrorString(e_));                                \
+            release(c);                                                                 \
+            return r_;                                                                  \
+        }                                                                               \
+    } while (0)
+    LBM_TRY(hipGetDevice(&c->device));
+    LBM_TRY(hipMalloc(&c->d_link, N));
+    LBM_TRY(hipMalloc(&c->d_mask, N));
+    LBM_TRY(hipMemcpyAsync(c->d_mask, d_mask, N, hipMemcpyDeviceToDevice, c->stream));
+    LBM_TRY(hipMalloc(&c->d_drho, N * sizeof(float)));
+    LBM_TRY(hipMalloc(&c->d_partials, (size_t)c->nblocks * 4 * sizeof(double)));
+    LBM_TRY(hipMalloc(&c->d_out, 4 * sizeof(double)));
+    LBM_TRY(hipHostMalloc(&c->h_out, 4 * sizeof(double), hipHostMallocDefault));
+    dim3 blk(256), grd((cfg->nx + 255) / 256, cfg->ny);
+    k_links<<<grd, blk, 0, c->stream>>>(cfg->nx, cfg->ny, cfg->bc_x, cfg->bc_y, c->d_mask, c->d_link);
+    LBM_TRY(hipGetLastError());
+    // rest state: f = w everywhere, i.e. zero deviations
+    LBM_TRY(hipMemsetAsync(d_fA, 0, 9 * N * sizeof(float), c->stream));
+    LBM_TRY(hipMemsetAsync(c->d_drho, 0, N * sizeof(float), c->stream));
+    std::vector<uint8_t> h(N);
+    LBM_TRY(hipMemcpyAsync(h.data(), d_mask, N, hipMemcpyDeviceToHost, c->stream));
+    LBM_TRY(hipStreamSynchronize(c->stream));
+#undef LBM_TRY
+    int64_t fl = 0;
+    for (size_t k = 0; k < N; ++k) fl += h[k] == 0;
+    c->fluid = fl;
+    c->steps = 0;
+    *out = c;
+    return LBM_OK;
+}
+
+extern "C" int lbm_reinit_from_macro(lbm_ctx* c, const float* d_rho, const float* d_ux,
+                                     const float* d_uy) {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (!d_rho || !d_ux || !d_uy) return fail(LBM_EINVAL, "NULL field");
+    dim3 blk(256), grd((c->g.nx + 255) / 256, c->g.ny);
+    k_scatter<true><<<grd, blk, 0, c->stream>>>(c->g, c->d_mask, d_rho, d_ux, d_uy, nullptr,
+                                                c->f[c->cur]);
+    LBM_HIP(hipGetLastError());
+    c->steps = 0;
+    return LBM_OK;
+}
+
+extern "C" int lbm_set_populations(lbm_ctx* c, const float* d_f) {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (!d_f) return fail(LBM_EINVAL, "d_f is NULL");
+    dim3 blk(256), grd((c->g.nx + 255) / 256, c->g.ny);
+    k_scatter<false><<<grd, blk, 0, c->stream>>>(c->g, c->d_mask, nullptr, nullptr, nullptr, d_f,
+                                                 c->f[c->cur]);
+    LBM_HIP(hipGetLastError());
+    return LBM_OK;
+}
+
+static int build_graph(lbm_ctx* c) {
+    const int start = c->cur;
+    const int64_t steps0 = c->steps;
+    hipGraph_t graph = nullptr;
+    LBM_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < c->graph_chunk; ++k) launch_step(c, false);
+    hipError_t e = hipStreamEndCapture(c->stream, &graph);
+    c->cur = start;
+    c->steps = steps0;
+    if (e != hipSuccess) return fail(LBM_EHIP, "graph capture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&c->graph[start], graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        c->graph[start] = nullptr;
+        return fail(LBM_EHIP, "graph instantiate: %s", hipGetErrorString(e));
+    }
+    return LBM_OK;
+}
+
+extern "C" int lbm_step(lbm_ctx* c, int32_t n, lbm_report* rep) {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (n < 0) return fail(LBM_EINVAL, "n = %d < 0", n);
+    if (rep && n < 1) return fail(LBM_EINVAL, "a report needs n >= 1");
+    int plain = rep ? n - 1 : n;
+    // Replay graph-captured chunks of plain steps on a non-default stream; the
+    // chunk length is even, so the store parity is unchanged by a replay.
+    if (c->stream != nullptr) {
+        while (plain >= c->graph_chunk) {
+            if (!c->graph[c->cur]) {
+                int rc = build_graph(c);
+                if (rc) return rc;
+            }
+            LBM_HIP(hipGraphLaunch(c->graph[c->cur], c->stream));
+            c->steps += c->graph_chunk;
+            plain -= c->graph_chunk;
+        }
+    }
+    for (int k = 0; k < plain; ++k) launch_step(c, false);
+    LBM_HIP(hipGetLastError());
+    if (!rep) return LBM_OK;
+    launch_step(c, true);  // writes drho(n-1)
+    LBM_HIP(hipGetLastError());
+    int rc = launch_macro(c, nullptr, nullptr, nullptr, 0, nullptr, true);
+    if (rc) return rc;
+    k_reduce_final<<<1, 256, 0, c->stream>>>(c->d_partials, c->nblocks, c->d_out);
+    LBM_HIP(hipGetLastError());
+    LBM_HIP(hipMemcpyAsync(c->h_out, c->d_out, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    LBM_HIP(hipStreamSynchronize(c->stream));
+    rep->mass = c->h_out[1];
+    rep->residual = c->h_out[0] / c->h_out[1];
+    rep->mom_x = c->h_out[2];
+    rep->mom_y = c->h_out[3];
+    rep->steps_done = c->steps;
+    rep->fluid_nodes = c->fluid;
+    if (!std::isfinite(rep->mass) || !std::isfinite(rep->residual))
+        return fail(LBM_EDIVERGED, "non-finite mass %g or residual %g after %lld steps", rep->mass,
+                    rep->residual, (long long)c->steps);
+    return LBM_OK;
+}
+
+extern "C" int lbm_get_macro(lbm_ctx* c, float* d_rho, float* d_ux, float* d_uy,
+                             int32_t rho_minus_one) {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (!d_rho && !d_ux && !d_uy) return fail(LBM_EINVAL, "no output field");
+    return launch_macro(c, d_rho, d_ux, d_uy, rho_minus_one, nullptr, false);
+}
+
+extern "C" int lbm_get_populations(lbm_ctx* c, float* d_f) {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (!d_f) return fail(LBM_EINVAL, "d_f is NULL");
+    return launch_macro(c, nullptr, nullptr, nullptr, 0, d_f, false);
+}
+
+extern "C" int lbm_info(const lbm_ctx* c, int64_t* fluid_nodes, int64_t* steps_done) {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (fluid_nodes) *fluid_nodes = c->fluid;
+    if (steps_done) *steps_done = c->steps;
+    return LBM_OK;
+}

@@ -1,0 +1,224 @@
+"""ctypes binding of liblbmfno.so (include/lbmfno.h): argument marshalling only.
+
+Every step of the hot path runs in the library's HIP kernels; torch supplies
+device memory and the stream.  There is no fallback: if the library or a GPU is
+missing, load() raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbmfno.so")
+_LIB = None
+
+LBM_OK = 0
+BC_PERIODIC, BC_WALL, BC_ZOUHE = 0, 1, 2
+
+_p = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+
+
+class LbmConfig(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32),
+                ("tau", ctypes.c_double), ("gx", ctypes.c_double), ("gy", ctypes.c_double),
+                ("u_in", ctypes.c_double), ("rho_out", ctypes.c_double),
+                ("arith", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+ARITH_MIXED, ARITH_FP32 = 0, 1
+
+
+class LbmReport(ctypes.Structure):
+    _fields_ = [("residual", ctypes.c_double), ("mass", ctypes.c_double),
+                ("mom_x", ctypes.c_double), ("mom_y", ctypes.c_double),
+                ("steps_done", ctypes.c_int64), ("fluid_nodes", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code, where):
+        lib = _LIB
+        msg = lib.lbm_last_error().decode() if lib else ""
+        name = lib.lbm_status_str(code).decode() if lib else str(code)
+        super().__init__(f"{where}: {name} ({code}): {msg}")
+        self.code = code
+
+
+# (name, restype, argtypes) of every exported entry point declared in include/*.h
+SIGNATURES = [
+    ("lbm_status_str", ctypes.c_char_p, [ctypes.c_int]),
+    ("lbm_last_error", ctypes.c_char_p, []),
+    ("lbm_mask_raster", ctypes.c_int, [_i32, _i32, _i32, _i32, _p, _i32, _p, _p]),
+    ("lbm_init", ctypes.c_int, [ctypes.POINTER(_p), ctypes.POINTER(LbmConfig), _p, _p, _p, _p]),
+    ("lbm_destroy", None, [_p]),
+    ("lbm_reinit_from_macro", ctypes.c_int, [_p, _p, _p, _p]),
+    ("lbm_step", ctypes.c_int, [_p, _i32, ctypes.POINTER(LbmReport)]),
+    ("lbm_get_macro", ctypes.c_int, [_p, _p, _p, _p, _i32]),
+    ("lbm_get_populations", ctypes.c_int, [_p, _p]),
+    ("lbm_set_populations", ctypes.c_int, [_p, _p]),
+    ("lbm_info", ctypes.c_int, [_p, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
+]
+
+
+def load_library(path: str = LIB_PATH):
+    """Load liblbmfno.so (no GPU needed to load) and bind every entry point."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build() "
+                           "(or python paper_2604_27158_amd/build.py)")
+    lib = ctypes.CDLL(path)
+    for name, res, args in SIGNATURES:
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _LIB = lib
+    return lib
+
+
+def load():
+    """Load the library and require a visible GPU (no CPU fallback exists)."""
+    import torch
+    lib = load_library()
+    if not torch.cuda.is_available():
+        raise RuntimeError("liblbmfno needs a ROCm GPU; none is visible")
+    return lib
+
+
+def check(rc: int, where: str):
+    if rc != LBM_OK:
+        raise LbmError(rc, where)
+
+
+def _ptr(t) -> int:
+    return t.data_ptr() if t is not None else None
+
+
+def stream_handle(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def mask_raster(nx: int, ny: int, shapes: np.ndarray, wrap_x: bool, wrap_y: bool, stream=None):
+    """Obstacle mask (uint8 [ny][nx] torch tensor on the GPU) from int64 descriptors."""
+    import torch
+    lib = load()
+    shapes = np.ascontiguousarray(np.asarray(shapes, dtype=np.int64).reshape(-1, 7))
+    mask = torch.empty((ny, nx), dtype=torch.uint8, device="cuda")
+    check(lib.lbm_mask_raster(nx, ny, int(wrap_x), int(wrap_y),
+                              shapes.ctypes.data_as(_p) if shapes.size else None,
+                              shapes.shape[0], mask.data_ptr(), stream_handle(stream)),
+          "lbm_mask_raster")
+    return mask
+
+
+class Lattice:
+    """A device lattice: two population stores (torch float32 [9][ny][nx]) and the
+    library context, all on one dedicated non-default stream (graph replay needs a
+    capturable stream)."""
+
+    def __init__(self, nx, ny, tau, gx=0.0, gy=0.0, bc_x=BC_PERIODIC, bc_y=BC_PERIODIC,
+                 u_in=0.0, rho_out=1.0, mask=None, stream=None, arith=ARITH_MIXED):
+        import torch
+        self.lib = load()
+        self.nx, self.ny = int(nx), int(ny)
+        self.cfg = LbmConfig(self.nx, self.ny, bc_x, bc_y, float(tau), float(gx), float(gy),
+                             float(u_in), float(rho_out), int(arith), 0)
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        with torch.cuda.stream(self.stream):
+            self.fA = torch.empty((9, ny, nx), dtype=torch.float32, device="cuda")
+            self.fB = torch.empty((9, ny, nx), dtype=torch.float32, device="cuda")
+            if mask is None:
+                mask = torch.zeros((ny, nx), dtype=torch.uint8, device="cuda")
+            self.mask = mask
+        self.ctx = _p()
+        check(self.lib.lbm_init(ctypes.byref(self.ctx), ctypes.byref(self.cfg), mask.data_ptr(),
+                                self.fA.data_ptr(), self.fB.data_ptr(), self.stream.cuda_stream),
+              "lbm_init")
+
+    @classmethod
+    def from_workload(cls, lat, stream=None, arith=ARITH_MIXED):
+        """Build from a workloads.Lattice (its mask rasterised on the GPU)."""
+        import torch
+        stream = stream if stream is not None else torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            mask = mask_raster(lat.nx, lat.ny, lat.shapes_array(), lat.wrap_x, lat.wrap_y, stream)
+        return cls(lat.nx, lat.ny, lat.tau, lat.gx, lat.gy, lat.bc_x, lat.bc_y, lat.u_in,
+                   lat.rho_out, mask=mask, stream=stream, arith=arith)
+
+    def close(self):
+        if self.ctx:
+            self.lib.lbm_destroy(self.ctx)
+            self.ctx = _p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n: int, report: bool = False):
+        rep = LbmReport() if report else None
+        check(self.lib.lbm_step(self.ctx, int(n), ctypes.byref(rep) if rep is not None else None),
+              "lbm_step")
+        return rep.as_dict() if rep is not None else None
+
+    def _after_caller(self):
+        import torch
+        self.stream.wait_stream(torch.cuda.current_stream())
+
+    def _before_caller(self):
+        import torch
+        torch.cuda.current_stream().wait_stream(self.stream)
+
+    def reinit(self, rho, ux, uy):
+        import torch
+        self._after_caller()
+        with torch.cuda.stream(self.stream):
+            rho, ux, uy = (t.to(device="cuda", dtype=torch.float32).contiguous() for t in (rho, ux, uy))
+        self._keep = (rho, ux, uy)
+        check(self.lib.lbm_reinit_from_macro(self.ctx, rho.data_ptr(), ux.data_ptr(), uy.data_ptr()),
+              "lbm_reinit_from_macro")
+
+    def macros(self, rho_minus_one: bool = False):
+        import torch
+        with torch.cuda.stream(self.stream):
+            out = torch.empty((3, self.ny, self.nx), dtype=torch.float32, device="cuda")
+        check(self.lib.lbm_get_macro(self.ctx, out[0].data_ptr(), out[1].data_ptr(),
+                                     out[2].data_ptr(), int(rho_minus_one)), "lbm_get_macro")
+        self._before_caller()
+        return out
+
+    def populations(self):
+        import torch
+        with torch.cuda.stream(self.stream):
+            out = torch.empty((9, self.ny, self.nx), dtype=torch.float32, device="cuda")
+        check(self.lib.lbm_get_populations(self.ctx, out.data_ptr()), "lbm_get_populations")
+        self._before_caller()
+        return out
+
+    def set_populations(self, f):
+        import torch
+        self._after_caller()
+        with torch.cuda.stream(self.stream):
+            f = f.to(device="cuda", dtype=torch.float32).contiguous()
+        self._keep_f = f
+        check(self.lib.lbm_set_populations(self.ctx, f.data_ptr()), "lbm_set_populations")
+
+    def info(self):
+        fl, st = _i64(), _i64()
+        check(self.lib.lbm_info(self.ctx, ctypes.byref(fl), ctypes.byref(st)), "lbm_info")
+        return fl.value, st.value
+
+    def synchronize(self):
+        self.stream.synchronize()

@@ -170,12 +170,16 @@ BATCH_SIZES = ((256, 128), (384, 192), (512, 256))
 
 
 def ellipse_flow(seed: int, size=None, re_lo: float = 100.0, re_hi: float = 200.0,
-                 u_in: float = 0.05, nmin: int = 1, nmax: int = 5) -> Lattice:
+                 u_in: float = 0.1, nmin: int = 1, nmax: int = 5, gap: int = 8,
+                 max_attempts: int = 200) -> Lattice:
     """Flow past 1-5 random ellipses: lattice size drawn from BATCH_SIZES unless given,
     semi-axes a ~ U(ny/16, ny/8), b = a*U(0.3, 1), angle U(0, pi); Reynolds number
     Re ~ U(re_lo, re_hi) on D = ny/4 sets nu = u_in*D/Re and tau = 3*nu + 1/2.
     Zou-He inlet/outlet in x, periodic in y; ellipses stay clear of the first and
-    last ny/8 + 2 columns."""
+    last ny/8 + 2 columns, their bounding circles keep `gap` cells apart (periodic
+    in y), and ellipses whose x-extents overlap block at most half the channel
+    height, which keeps the jets between them well below the lattice sound speed.
+    The flows start from the plug flow (rho = 1, u = (u_in, 0)); see plug_flow()."""
     rng = SplitMix64(seed)
     if size is None:
         nx, ny = BATCH_SIZES[rng.randint(0, len(BATCH_SIZES) - 1)]
@@ -186,18 +190,39 @@ def ellipse_flow(seed: int, size=None, re_lo: float = 100.0, re_hi: float = 200.
     tau = 3.0 * nu + 0.5
     n = rng.randint(nmin, nmax)
     keep = ny // 8 + 2
-    shapes = []
-    for _ in range(n):
+    shapes, placed = [], []
+    attempts = 0
+    while len(shapes) < n and attempts < max_attempts:
+        attempts += 1
         a = rng.uniform(ny / 16.0, ny / 8.0)
         b = a * rng.uniform(0.3, 1.0)
         th = rng.uniform(0.0, math.pi)
         R = int(math.ceil(a)) + 1
         cx = rng.randint(keep + R, nx - 1 - keep - R)
         cy = rng.randint(0, ny - 1)
+        ok = True
+        blocked = 2 * R
+        for (px, py, pr) in placed:
+            dy = abs(cy - py)
+            dy = min(dy, ny - dy)
+            if (cx - px) ** 2 + dy * dy < (R + pr + gap) ** 2:
+                ok = False
+                break
+            if abs(cx - px) <= R + pr:
+                blocked += 2 * pr
+        if not ok or blocked > ny // 2:
+            continue
+        placed.append((cx, cy, R))
         shapes.append(ellipse(cx, cy, a, b, th))
     return Lattice(nx=nx, ny=ny, tau=tau, bc_x=BC_ZOUHE, bc_y=BC_PERIODIC, u_in=u_in,
                    rho_out=1.0, shapes=shapes, wrap_x=False, wrap_y=True, seed=seed,
-                   name=f"ellipses{nx}x{ny}-n{n}-Re{re:.0f}-s{seed}")
+                   name=f"ellipses{nx}x{ny}-n{len(shapes)}-Re{re:.0f}-s{seed}")
+
+
+def plug_flow(lat: "Lattice"):
+    """Initial fields (rho, ux, uy) = (1, u_in, 0), float64 [ny][nx]."""
+    shp = (lat.ny, lat.nx)
+    return np.ones(shp), np.full(shp, float(lat.u_in)), np.zeros(shp)
 
 
 def periodic_box(nx: int, ny: int, tau: float, gx: float = 0.0, gy: float = 0.0,

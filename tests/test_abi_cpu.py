@@ -1,0 +1,88 @@
+"""The C ABI library loads without a GPU, exports every entry point include/*.h
+declares, and rejects invalid arguments on the host before any HIP call."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+from paper_2604_27158_amd import lbmfno
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        txt = open(h).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*\**\s*([a-z_][a-z0-9_]*)\s*\(",
+                             txt, flags=re.M):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return lbmfno.load_library()
+
+
+def test_header_declares_the_core_calls():
+    names = declared_functions()
+    for n in ("lbm_init", "lbm_step", "lbm_reinit_from_macro", "lbm_get_macro", "lbm_mask_raster"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported_and_bound(lib):
+    bound = {n for n, _, _ in lbmfno.SIGNATURES}
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+        assert name in bound, f"{name} has no binding"
+
+
+def _cfg(**kw):
+    c = dict(nx=16, ny=8, bc_x=0, bc_y=0, tau=0.8, gx=0.0, gy=0.0, u_in=0.0, rho_out=1.0, arith=0)
+    c.update(kw)
+    return lbmfno.LbmConfig(**c)
+
+
+@pytest.mark.parametrize("kw", [dict(tau=0.5), dict(tau=float("nan")), dict(nx=0), dict(ny=-3),
+                                dict(bc_x=7), dict(bc_y=2), dict(nx=30000, ny=30000),
+                                dict(bc_x=2, u_in=1.5), dict(bc_x=2, rho_out=0.0),
+                                dict(gx=float("inf")), dict(arith=5)])
+def test_lbm_init_rejects_invalid_config(lib, kw):
+    ctx = ctypes.c_void_p()
+    rc = lib.lbm_init(ctypes.byref(ctx), ctypes.byref(_cfg(**kw)), 1, 2, 3, None)
+    assert rc == -1 and not ctx.value
+    assert lib.lbm_last_error()
+
+
+def test_unsupported_combinations(lib):
+    ctx = ctypes.c_void_p()
+    assert lib.lbm_init(ctypes.byref(ctx), ctypes.byref(_cfg(bc_x=2, gx=1e-6)), 1, 2, 3, None) == -4
+    assert lib.lbm_init(ctypes.byref(ctx), ctypes.byref(_cfg(bc_x=2, bc_y=1)), 1, 2, 3, None) == -4
+
+
+def test_null_arguments(lib):
+    ctx = ctypes.c_void_p()
+    assert lib.lbm_init(None, ctypes.byref(_cfg()), 1, 2, 3, None) == -1
+    assert lib.lbm_init(ctypes.byref(ctx), None, 1, 2, 3, None) == -1
+    assert lib.lbm_init(ctypes.byref(ctx), ctypes.byref(_cfg()), None, 2, 3, None) == -1
+    assert lib.lbm_init(ctypes.byref(ctx), ctypes.byref(_cfg()), 1, 2, 2, None) == -1
+    assert lib.lbm_step(None, 1, None) == -1
+    assert lib.lbm_get_macro(None, 1, 2, 3, 0) == -1
+    assert lib.lbm_reinit_from_macro(None, 1, 2, 3) == -1
+
+
+def test_raster_validation(lib):
+    import numpy as np
+    bad = np.array([[0, 0, 1 << 40, 0, 1 << 40, 5, 1 << 14]], dtype=np.int64)
+    assert lib.lbm_mask_raster(8, 8, 0, 0, bad.ctypes.data_as(ctypes.c_void_p), 1, 1, None) == -1
+    assert lib.lbm_mask_raster(0, 8, 0, 0, None, 0, 1, None) == -1
+    assert lib.lbm_mask_raster(8, 8, 0, 0, None, 0, None, None) == -1
+
+
+def test_status_strings(lib):
+    for code in range(0, -7, -1):
+        assert lib.lbm_status_str(code) not in (None, b"unknown status")

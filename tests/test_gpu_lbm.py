@@ -1,0 +1,217 @@
+"""GPU parity of the lattice hot path (masks, init/reinit, fused BGK step with
+bounce-back, Zou-He and Guo forcing, macros, FP64 sums) against the FP64 oracle.
+
+Bars: masks and permutations bit-exact; macroscopic fields within 1e-5 relative L2
+over fluid nodes after 1000 and 2000 FP32 steps; FP64 sums within the FP32 state's
+own rounding of the oracle.  Every case prints its error against FP64."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import lbm as olbm
+from paper_2604_27158_amd import workloads as W
+from tests.helpers import field_errors, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def gpu_lattice(gpu, lat):
+    return gpu.Lattice.from_workload(lat)
+
+
+def np_(t):
+    return t.detach().cpu().numpy()
+
+
+def run_pair(gpu, lat, checkpoints, rho0=None, ux0=None, uy0=None):
+    """Run GPU and oracle side by side; yield (step, gpu macros, oracle macros, mask)."""
+    import torch
+    G = gpu_lattice(gpu, lat)
+    mask = olbm.raster(lat.nx, lat.ny, lat.shapes_array(), lat.wrap_x, lat.wrap_y)
+    O = olbm.Sim(lat, mask)
+    if rho0 is not None:
+        O.init(rho0, ux0, uy0)
+        G.reinit(torch.from_numpy(rho0), torch.from_numpy(ux0), torch.from_numpy(uy0))
+    else:
+        O.init()
+    done = 0
+    for c in checkpoints:
+        G.step(c - done)
+        O.run(c - done)
+        done = c
+        yield c, np_(G.macros()), O.macros(), mask, G, O
+
+
+@pytest.mark.parametrize("maker,args", [
+    (W.channel_walls_circles, dict()),
+    (W.porous_circles, dict()),
+    (W.ellipse_flow, dict()),
+    (W.ellipse_flow, dict(size=(512, 256))),
+])
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_mask_bit_exact(gpu, maker, args, seed):
+    lat = maker(seed, **args)
+    m_gpu = np_(gpu.mask_raster(lat.nx, lat.ny, lat.shapes_array(), lat.wrap_x, lat.wrap_y))
+    m_ref = olbm.raster(lat.nx, lat.ny, lat.shapes_array(), lat.wrap_x, lat.wrap_y)
+    assert m_gpu.dtype == np.uint8 and np.array_equal(m_gpu, m_ref)
+    print(f"{lat.name}: {int(m_ref.sum())} solid cells, porosity {1 - m_ref.mean():.4f}")
+
+
+@pytest.mark.parametrize("seed", list(range(10)))
+def test_channel_parity_1000_2000(gpu, seed):
+    """128x64, periodic x, bounce-back walls and 10 circles, g = 1e-6, tau = 0.8."""
+    lat = W.channel_walls_circles(seed)
+    for step, g, r, mask, _, _ in run_pair(gpu, lat, [1000, 2000]):
+        e = field_errors(g, r, mask)
+        print(f"seed {seed} step {step}: " + " ".join(f"{k}={v:.2e}" for k, v in e.items()))
+        assert e["rho"] < TOL and e["ux"] < TOL and e["uy"] < TOL, e
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_porous_zouhe_parity_full_size(gpu, seed):
+    """1024x512 porous medium, Zou-He inlet u = 0.05 / outlet rho = 1, tau = 0.6."""
+    lat = W.porous_circles(seed)
+    for step, g, r, mask, _, _ in run_pair(gpu, lat, [1000]):
+        e = field_errors(g, r, mask)
+        print(f"{lat.name} step {step}: " + " ".join(f"{k}={v:.2e}" for k, v in e.items()))
+        assert e["rho"] < TOL and e["ux"] < TOL and e["uy"] < TOL, e
+
+
+@pytest.mark.parametrize("seed,size", [(7, (256, 128)), (8, (384, 192)), (9, (512, 256)), (0, None)])
+def test_ellipse_zouhe_parity(gpu, seed, size):
+    """Flow past random ellipses from the plug flow, Zou-He in x, periodic y."""
+    lat = W.ellipse_flow(seed, size=size)
+    for step, g, r, mask, _, _ in run_pair(gpu, lat, [1000], *W.plug_flow(lat)):
+        e = field_errors(g, r, mask)
+        print(f"{lat.name} step {step}: " + " ".join(f"{k}={v:.2e}" for k, v in e.items()))
+        assert e["rho"] < TOL and e["ux"] < TOL and e["uy"] < TOL, e
+
+
+def test_ellipse_high_mach_jet_case(gpu):
+    """Seed 3 drives jets to |u| ~ 0.4 between its ellipses; FP32 and FP64 runs then
+    separate physically after a few hundred steps.  Parity holds before that, and
+    the run stays finite."""
+    lat = W.ellipse_flow(3)
+    for step, g, r, mask, G, _ in run_pair(gpu, lat, [300], *W.plug_flow(lat)):
+        e = field_errors(g, r, mask)
+        print(f"{lat.name} step {step}: " + " ".join(f"{k}={v:.2e}" for k, v in e.items()))
+        assert e["rho"] < TOL and e["ux"] < TOL and e["uy"] < TOL, e
+    G.step(700)
+    assert np.isfinite(np_(G.macros())).all()
+
+
+@pytest.mark.parametrize("nx,ny,bcx,bcy", [
+    (1, 5, 0, 0), (3, 7, 0, 1), (37, 11, 0, 0), (70, 9, 1, 0), (65, 13, 2, 0), (131, 6, 1, 1)])
+def test_ragged_and_tiny_lattices(gpu, nx, ny, bcx, bcy):
+    """Sizes that are not multiples of the 64x4 tile, single columns, all boundary kinds."""
+    shapes = [W.circle(nx // 2, ny // 2, 1)] if nx > 4 and ny > 4 else []
+    lat = W.Lattice(nx=nx, ny=ny, tau=0.7, gx=2e-6 if bcx != 2 else 0.0, bc_x=bcx, bc_y=bcy,
+                    u_in=0.03 if bcx == 2 else 0.0, shapes=shapes, wrap_x=bcx == 0, wrap_y=bcy == 0)
+    rho0, ux0, uy0 = W.random_macro_fields(nx * 100 + ny, nx, ny, amp_u=0.01)
+    for step, g, r, mask, _, _ in run_pair(gpu, lat, [3, 200], rho0, ux0, uy0):
+        e = field_errors(g, r, mask)
+        fl = mask == 0
+        # velocity as a vector field: a component that decays to ~1e-7 next to a
+        # growing one has no meaningful per-component relative error
+        du = np.sqrt((g[1] - r[1]) ** 2 + (g[2] - r[2]) ** 2)[fl]
+        uu = np.sqrt(r[1] ** 2 + r[2] ** 2)[fl]
+        e["u"] = float(np.linalg.norm(du) / np.linalg.norm(uu))
+        print(f"{nx}x{ny} bc=({bcx},{bcy}) step {step}: " + " ".join(f"{k}={v:.2e}" for k, v in e.items()))
+        assert e["rho"] < TOL and e["u"] < TOL, e
+
+
+def test_reinit_gives_equilibrium_populations(gpu):
+    """After lbm_reinit_from_macro the pre-collision populations are f_eq(rho, u)
+    on fluid nodes (oracle init, FP32 rounding only)."""
+    import torch
+    lat = W.channel_walls_circles(3)
+    rho0, ux0, uy0 = W.random_macro_fields(9, lat.nx, lat.ny)
+    G = gpu_lattice(gpu, lat)
+    G.reinit(torch.from_numpy(rho0), torch.from_numpy(ux0), torch.from_numpy(uy0))
+    f = np_(G.populations())
+    O = olbm.Sim(lat).init(rho0, ux0, uy0)
+    fl = O.mask == 0
+    assert np.max(np.abs(f[:, fl] - O.f[:, fl])) < 3e-7
+    assert G.info()[1] == 0
+
+
+def test_set_get_populations_roundtrip_and_step(gpu):
+    """set_populations(f) then get_populations() returns f; one step from it matches
+    the oracle's step from the same f."""
+    import torch
+    lat = W.Lattice(nx=96, ny=40, tau=0.66, gx=1e-5, gy=-3e-6, bc_x=0, bc_y=1,
+                    shapes=[W.circle(30, 20, 6), W.circle(70, 5, 4)], wrap_x=True, wrap_y=False)
+    O = olbm.Sim(lat).init(*W.random_macro_fields(21, lat.nx, lat.ny))
+    O.run(5)
+    G = gpu_lattice(gpu, lat)
+    G.set_populations(torch.from_numpy(O.f.astype(np.float32)))
+    f = np_(G.populations())
+    fl = O.mask == 0
+    assert np.max(np.abs(f[:, fl] - O.f[:, fl])) < 1e-7
+    G.step(1)
+    O.run(1)
+    f1 = np_(G.populations())
+    assert np.max(np.abs(f1[:, fl] - O.f[:, fl])) < 1e-6
+
+
+def test_report_sums_and_residual(gpu):
+    """FP64 device sums equal math.fsum of the GPU's own fields, and mass / residual
+    track the oracle; repeated runs give bit-identical reports."""
+    lat = W.porous_circles(4, nx=256, ny=128, rmin=4, rmax=10, keepout=12)
+    reps = []
+    for _ in range(2):
+        G = gpu_lattice(gpu, lat)
+        rep = G.step(500, report=True)
+        reps.append(rep)
+    assert reps[0] == reps[1]
+    rep = reps[0]
+    m = np_(G.macros(rho_minus_one=True)).astype(np.float64)
+    G2 = gpu_lattice(gpu, lat)
+    G2.step(499)
+    prev = np_(G2.macros(rho_minus_one=True)).astype(np.float64)
+    mask = olbm.raster(lat.nx, lat.ny, lat.shapes_array(), lat.wrap_x, lat.wrap_y)
+    fl = mask == 0
+    mass = math.fsum(1.0 + m[0][fl])
+    res = math.fsum(np.abs(m[0] - prev[0])[fl]) / mass
+    # the device sums rho in FP64 from the unrounded moments; the host only has
+    # rho - 1 rounded to FP32: bound = sum of those roundings
+    assert abs(rep["mass"] - mass) <= 2.0 ** -24 * math.fsum(np.abs(m[0][fl])) + 1e-13 * mass
+    assert abs(rep["residual"] - res) <= 1e-9 * res
+    assert rep["steps_done"] == 500 and rep["fluid_nodes"] == int(fl.sum())
+    O = olbm.Sim(lat, mask).init().run(499)
+    rp = O.macros()[0]
+    O.run(1)
+    r, u, v = O.macros()
+    oref = olbm.sums(mask, r, rp, u, v)
+    print(f"residual gpu {rep['residual']:.4e} oracle {oref[0]:.4e}; mass gpu {rep['mass']:.12e} oracle {oref[1]:.12e}")
+    assert abs(rep["mass"] - oref[1]) <= 1e-6 * oref[1]
+    assert abs(rep["residual"] - oref[0]) <= 1e-3 * oref[0]
+
+
+def test_graph_replay_equals_direct_launches(gpu):
+    """lbm_step(n) replays 32-step graphs; the result is bit-identical to n single steps."""
+    lat = W.channel_walls_circles(5)
+    A = gpu_lattice(gpu, lat)
+    B = gpu_lattice(gpu, lat)
+    A.step(100)
+    for _ in range(100):
+        B.step(1)
+    assert np.array_equal(np_(A.populations()), np_(B.populations()))
+
+
+def test_all_fp32_arithmetic_variant_reports_its_error(gpu):
+    """LBM_ARITH_FP32 (collision in FP32 registers): same bits moved, larger error;
+    printed against FP64 and bounded by 1e-4 (the default mixed mode meets 1e-5)."""
+    lat = W.channel_walls_circles(0)
+    mask = olbm.raster(lat.nx, lat.ny, lat.shapes_array(), lat.wrap_x, lat.wrap_y)
+    G = gpu.Lattice.from_workload(lat, arith=gpu.ARITH_FP32)
+    O = olbm.Sim(lat, mask).init()
+    for n in (1000, 1000):
+        G.step(n)
+        O.run(n)
+        e = field_errors(np_(G.macros()), O.macros(), mask)
+        print(f"all-FP32 step {O.steps}: " + " ".join(f"{k}={v:.2e}" for k, v in e.items()))
+        assert max(e["rho"], e["ux"], e["uy"]) < 1e-4
