@@ -143,6 +143,12 @@ int lbm_get_populations(lbm_ctx* ctx, float* d_f);
  * [9][ny][nx], solid entries ignored); the step counter is kept. */
 int lbm_set_populations(lbm_ctx* ctx, const float* d_f);
 
+/* Plain device-to-device copy of n float32 values (n a multiple of 4, 16-byte
+ * aligned buffers) with 16-byte loads and stores: the achievable-bandwidth
+ * reference against which the lattice kernels' traffic and counters are read.
+ * Asynchronous on `stream`. */
+int lbm_stream_copy(const float* d_src, float* d_dst, size_t n, void* stream);
+
 /* Number of fluid nodes and the current step counter (host values). */
 int lbm_info(const lbm_ctx* ctx, int64_t* fluid_nodes, int64_t* steps_done);
 

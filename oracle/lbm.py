@@ -42,6 +42,7 @@ def lib():
         L.oracle_adjoint_step.restype = _i
         L.oracle_feq_vjp.argtypes = [_i, _i, _p, _p, _p, _p, _p, _p, _p, _p]
         L.oracle_lattice.argtypes = [_p, _p, _p, _p]
+        L.oracle_threads.restype = _i
         _LIB = L
     return _LIB
 
@@ -52,6 +53,11 @@ def _ptr(a: np.ndarray):
 
 def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(lib().oracle_threads())
 
 
 def lattice():

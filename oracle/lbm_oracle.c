@@ -52,6 +52,13 @@ static size_t at(const cfg_t* c, int q, int j, int i) {
 }
 
 int oracle_q(void) { return Q; }
+
+#ifdef _OPENMP
+#include <omp.h>
+int oracle_threads(void) { return omp_get_max_threads(); }
+#else
+int oracle_threads(void) { return 1; }
+#endif
 void oracle_lattice(int* cx, int* cy, int* opp, double* w) {
     for (int q = 0; q < Q; ++q) { cx[q] = CX[q]; cy[q] = CY[q]; opp[q] = OPP[q]; w[q] = WQ[q]; }
 }

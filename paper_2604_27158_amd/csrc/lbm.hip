@@ -203,46 +203,75 @@ struct StepArgs {
     double omega, guo, gx, gy, u_in, rho_out;
 };
 
-// Pull gather of f(t) at node (i, j) from the deviation store.
+// Pull gather of f(t) at node (i, j) from the deviation store: direction q reads
+// plane q at x - c_q, or, when link bit q-1 is set, plane opp(q) at x itself.
+// The nine streaming loads are issued unconditionally (every address is valid), so
+// they overlap the link-byte load instead of waiting for it; the few bounced
+// directions are re-read afterwards.  Offsets are formed per direction (an
+// indexed local array would be placed in scratch memory).
 template <typename R>
-__device__ __forceinline__ void gather(const float* __restrict__ src, const LatticeGeom& g,
-                                       unsigned lk, int i, int j, int n, R f[9]) {
+__device__ __forceinline__ void gather_stream(const float* __restrict__ src, const LatticeGeom& g,
+                                              int i, int j, int n, R f[9]) {
     const int im = i == 0 ? g.nx - 1 : i - 1, ip = i == g.nx - 1 ? 0 : i + 1;
     const int jm = j == 0 ? g.ny - 1 : j - 1, jp = j == g.ny - 1 ? 0 : j + 1;
     const int r0 = j * g.nx, rm = jm * g.nx, rp = jp * g.nx;
     const int N = g.N;
-    // pull source x - c_q for q = 0..8
-    const int s[9] = {n, r0 + im, rm + i, r0 + ip, rp + i, rm + im, rm + ip, rp + ip, rp + im};
     f[0] = (R)src[n];
-#pragma unroll
-    for (int q = 1; q < 9; ++q) {
-        const bool bb = (lk >> (q - 1)) & 1u;
-        const int off = bb ? opp_of(q) * N + n : q * N + s[q];
-        f[q] = (R)src[off];
-    }
+    f[1] = (R)src[1 * N + r0 + im];
+    f[2] = (R)src[2 * N + rm + i];
+    f[3] = (R)src[3 * N + r0 + ip];
+    f[4] = (R)src[4 * N + rp + i];
+    f[5] = (R)src[5 * N + rm + im];
+    f[6] = (R)src[6 * N + rm + ip];
+    f[7] = (R)src[7 * N + rp + ip];
+    f[8] = (R)src[8 * N + rp + im];
+}
+
+template <typename R>
+__device__ __forceinline__ void gather_bounce(const float* __restrict__ src, const LatticeGeom& g,
+                                              unsigned lk, int n, R f[9]) {
+    if (lk == 0u) return;
+    const int N = g.N;
+#define LBM_BOUNCE(Q) \
+    if ((lk >> (Q - 1)) & 1u) f[Q] = (R)src[opp_of(Q) * N + n];
+    LBM_BOUNCE(1) LBM_BOUNCE(2) LBM_BOUNCE(3) LBM_BOUNCE(4)
+    LBM_BOUNCE(5) LBM_BOUNCE(6) LBM_BOUNCE(7) LBM_BOUNCE(8)
+#undef LBM_BOUNCE
+}
+
+template <typename R>
+__device__ __forceinline__ void gather(const float* __restrict__ src, const LatticeGeom& g,
+                                       unsigned lk, int i, int j, int n, R f[9]) {
+    gather_stream<R>(src, g, i, j, n, f);
+    gather_bounce<R>(src, g, lk, n, f);
 }
 
 // Zou-He closures in deviation variables (w_1 = w_3, w_5 = w_7, w_6 = w_8 and
 // sum of the known weights = 1 make the shifted formulas identical in form).
+// Written branch-free (both closures evaluated, results selected) so the
+// population array stays in registers.
 template <typename R>
 __device__ __forceinline__ void zouhe(R f[9], int i, int nx, R u_in, R rho_out) {
-    if (i == 0) {
-        const R s = f[0] + f[2] + f[4] + R(2) * (f[3] + f[6] + f[7]);
-        const R rho = R(1) + (s + u_in) / (R(1) - u_in);
-        const R ru = rho * u_in;
-        const R h = R(0.5) * (f[2] - f[4]);
-        f[1] = f[3] + (R(2) / R(3)) * ru;
-        f[5] = f[7] - h + (R(1) / R(6)) * ru;
-        f[8] = f[6] + h + (R(1) / R(6)) * ru;
-    } else if (i == nx - 1) {
-        const R s = f[0] + f[2] + f[4] + R(2) * (f[1] + f[5] + f[8]);
-        const R ux = ((R(1) - rho_out) + s) / rho_out;
-        const R ru = rho_out * ux;
-        const R h = R(0.5) * (f[2] - f[4]);
-        f[3] = f[1] - (R(2) / R(3)) * ru;
-        f[6] = f[8] - h - (R(1) / R(6)) * ru;
-        f[7] = f[5] + h - (R(1) / R(6)) * ru;
-    }
+    const bool inl = i == 0, outl = i == nx - 1;
+    const R h = R(0.5) * (f[2] - f[4]);
+    // inlet x = 0: unknown f1, f5, f8 from u = (u_in, 0)
+    const R s_in = f[0] + f[2] + f[4] + R(2) * (f[3] + f[6] + f[7]);
+    const R ru_in = (R(1) + (s_in + u_in) / (R(1) - u_in)) * u_in;
+    const R f1 = f[3] + (R(2) / R(3)) * ru_in;
+    const R f5 = f[7] - h + (R(1) / R(6)) * ru_in;
+    const R f8 = f[6] + h + (R(1) / R(6)) * ru_in;
+    // outlet x = nx - 1: unknown f3, f6, f7 from rho = rho_out, u_y = 0
+    const R s_out = f[0] + f[2] + f[4] + R(2) * (f[1] + f[5] + f[8]);
+    const R ru_out = ((R(1) - rho_out) + s_out);  // rho_out * u_x
+    const R f3 = f[1] - (R(2) / R(3)) * ru_out;
+    const R f6 = f[8] - h - (R(1) / R(6)) * ru_out;
+    const R f7 = f[5] + h - (R(1) / R(6)) * ru_out;
+    f[1] = inl ? f1 : f[1];
+    f[5] = inl ? f5 : f[5];
+    f[8] = inl ? f8 : f[8];
+    f[3] = outl ? f3 : f[3];
+    f[6] = outl ? f6 : f[6];
+    f[7] = outl ? f7 : f[7];
 }
 
 template <typename R>
@@ -284,7 +313,7 @@ __device__ __forceinline__ float collide_q(R fq, const Moments<R>& m, R omega, R
 // One fused step t -> t+1 for one node per thread.  R is the register type of
 // the collision arithmetic (double by default; float for the all-FP32 variant);
 // the stores are float either way.
-template <bool ZH, bool FORCE, bool WDRHO, typename R>
+template <bool ZH, bool FORCE, bool WDRHO, bool NT, typename R>
 __global__ __launch_bounds__(256) void k_bgk_step(StepArgs a) {
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int by = b / a.g.gridx, bx = b - by * a.g.gridx;
@@ -292,24 +321,144 @@ __global__ __launch_bounds__(256) void k_bgk_step(StepArgs a) {
     if (i >= a.g.nx || j >= a.g.ny) return;
     const int n = j * a.g.nx + i;
     const unsigned lk = a.link[n];
-    if (is_solid(lk, a.mask, n)) return;
     R f[9];
-    gather<R>(a.src, a.g, lk, i, j, n, f);
+    gather_stream<R>(a.src, a.g, i, j, n, f);
+    if (is_solid(lk, a.mask, n)) return;
+    gather_bounce<R>(a.src, a.g, lk, n, f);
     if (ZH) zouhe<R>(f, i, a.g.nx, (R)a.u_in, (R)a.rho_out);
     const R gx = (R)a.gx, gy = (R)a.gy, om = (R)a.omega, guo = (R)a.guo;
     const Moments<R> m = moments<FORCE, R>(f, gx, gy);
     if (WDRHO) a.drho_out[n] = (float)m.drho;
     float* __restrict__ d = a.dst + n;
     const size_t N = (size_t)a.g.N;
-    d[0 * N] = collide_q<0, FORCE, R>(f[0], m, om, guo, gx, gy);
-    d[1 * N] = collide_q<1, FORCE, R>(f[1], m, om, guo, gx, gy);
-    d[2 * N] = collide_q<2, FORCE, R>(f[2], m, om, guo, gx, gy);
-    d[3 * N] = collide_q<3, FORCE, R>(f[3], m, om, guo, gx, gy);
-    d[4 * N] = collide_q<4, FORCE, R>(f[4], m, om, guo, gx, gy);
-    d[5 * N] = collide_q<5, FORCE, R>(f[5], m, om, guo, gx, gy);
-    d[6 * N] = collide_q<6, FORCE, R>(f[6], m, om, guo, gx, gy);
-    d[7 * N] = collide_q<7, FORCE, R>(f[7], m, om, guo, gx, gy);
-    d[8 * N] = collide_q<8, FORCE, R>(f[8], m, om, guo, gx, gy);
+    // Stores that overflow the last-level cache stream past it (non-temporal);
+    // a lattice whose two stores fit keeps them cached for the next step.
+#define LBM_STORE(Q)                                                                \
+    {                                                                              \
+        const float v_ = collide_q<Q, FORCE, R>(f[Q], m, om, guo, gx, gy);        \
+        if (NT) __builtin_nontemporal_store(v_, d + Q * N); else d[Q * N] = v_;    \
+    }
+    LBM_STORE(0) LBM_STORE(1) LBM_STORE(2) LBM_STORE(3) LBM_STORE(4)
+    LBM_STORE(5) LBM_STORE(6) LBM_STORE(7) LBM_STORE(8)
+#undef LBM_STORE
+}
+
+// Four-wide step (nx % 4 == 0): each lane owns four consecutive x nodes of one
+// row and a wavefront covers 256 nodes, so every plane is read and written with
+// aligned 16-byte accesses.  The +-x shifted populations come from the
+// neighbouring lane by a wavefront shuffle; the two values beyond the segment
+// ends are loaded explicitly.  Lanes past the row end are clamped onto the last
+// quad (every address stays valid) and store nothing.  Link bits arrive as one
+// 32-bit word per quad; the mask byte is read only for 0xFF links.  Solid nodes
+// store zeros (their slots are never read back).
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <bool ZH, bool FORCE, bool WDRHO, bool NT, typename R>
+__global__ __launch_bounds__(256) void k_bgk_step_v4(StepArgs a) {
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int by = b / a.g.gridx, bx = b - by * a.g.gridx;
+    const int lane = threadIdx.x;
+    const int j = by * TY + threadIdx.y;
+    if (j >= a.g.ny) return;  // uniform over the wavefront
+    const int nx = a.g.nx, ny = a.g.ny, N = a.g.N;
+    const int xw = bx * (4 * TX);
+    const int x0r = xw + 4 * lane;
+    const bool active = x0r < nx;
+    const int x0 = active ? x0r : nx - 4;
+    const int jm = j == 0 ? ny - 1 : j - 1, jp = j == ny - 1 ? 0 : j + 1;
+    const int r0 = j * nx, rm = jm * nx, rp = jp * nx;
+    const int xl = xw == 0 ? nx - 1 : xw - 1;
+    const int xr = x0 + 4 >= nx ? x0 + 4 - nx : x0 + 4;
+    const bool redge = lane == TX - 1 || x0 + 4 >= nx;
+    const int n0 = r0 + x0;
+    const unsigned lk4 = *reinterpret_cast<const unsigned*>(a.link + n0);
+    float v[9][4];
+#define LBM_LOAD0(Q, ROW)                                                              \
+    {                                                                                  \
+        const f4 t = *reinterpret_cast<const f4*>(a.src + (size_t)Q * N + (ROW) + x0); \
+        v[Q][0] = t.x; v[Q][1] = t.y; v[Q][2] = t.z; v[Q][3] = t.w;                   \
+    }
+#define LBM_LOADP(Q, ROW) /* c_x = +1: pull from x - 1 */                             \
+    {                                                                                  \
+        const float* p_ = a.src + (size_t)Q * N + (ROW);                               \
+        const f4 t = *reinterpret_cast<const f4*>(p_ + x0);                            \
+        float left = __shfl_up(t.w, 1, 64);                                            \
+        if (lane == 0) left = p_[xl];                                                  \
+        v[Q][0] = left; v[Q][1] = t.x; v[Q][2] = t.y; v[Q][3] = t.z;                  \
+    }
+#define LBM_LOADM(Q, ROW) /* c_x = -1: pull from x + 1 */                             \
+    {                                                                                  \
+        const float* p_ = a.src + (size_t)Q * N + (ROW);                               \
+        const f4 t = *reinterpret_cast<const f4*>(p_ + x0);                            \
+        float right = __shfl_down(t.x, 1, 64);                                         \
+        if (redge) right = p_[xr];                                                     \
+        v[Q][0] = t.y; v[Q][1] = t.z; v[Q][2] = t.w; v[Q][3] = right;                 \
+    }
+    LBM_LOAD0(0, r0)
+    LBM_LOADP(1, r0)
+    LBM_LOAD0(2, rm)
+    LBM_LOADM(3, r0)
+    LBM_LOAD0(4, rp)
+    LBM_LOADP(5, rm)
+    LBM_LOADM(6, rm)
+    LBM_LOADM(7, rp)
+    LBM_LOADP(8, rp)
+#undef LBM_LOAD0
+#undef LBM_LOADP
+#undef LBM_LOADM
+    // solids (0xFF link and mask set) and bounced directions
+    unsigned solid4 = 0;
+    if (lk4 != 0u) {
+        unsigned m4 = 0;
+        const bool any_ff = ((lk4 & 0xFFu) == 0xFFu) | (((lk4 >> 8) & 0xFFu) == 0xFFu) |
+                            (((lk4 >> 16) & 0xFFu) == 0xFFu) | ((lk4 >> 24) == 0xFFu);
+        if (any_ff) m4 = *reinterpret_cast<const unsigned*>(a.mask + n0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const unsigned lk = (lk4 >> (8 * k)) & 0xFFu;
+            const bool sol = lk == 0xFFu && ((m4 >> (8 * k)) & 0xFFu) != 0u;
+            solid4 |= (sol ? 1u : 0u) << k;
+            if (lk != 0u && !sol) {
+                const float* own = a.src + n0 + k;
+#define LBM_BB(Q) if ((lk >> (Q - 1)) & 1u) v[Q][k] = own[(size_t)opp_of(Q) * N];
+                LBM_BB(1) LBM_BB(2) LBM_BB(3) LBM_BB(4) LBM_BB(5) LBM_BB(6) LBM_BB(7) LBM_BB(8)
+#undef LBM_BB
+            }
+        }
+    }
+    const R gx = (R)a.gx, gy = (R)a.gy, om = (R)a.omega, guo = (R)a.guo;
+    float drho4[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        R f[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) f[q] = (R)v[q][k];
+        if (ZH) zouhe<R>(f, x0 + k, nx, (R)a.u_in, (R)a.rho_out);
+        const Moments<R> m = moments<FORCE, R>(f, gx, gy);
+        drho4[k] = (float)m.drho;
+        const bool sol = (solid4 >> k) & 1u;
+        v[0][k] = sol ? 0.0f : collide_q<0, FORCE, R>(f[0], m, om, guo, gx, gy);
+        v[1][k] = sol ? 0.0f : collide_q<1, FORCE, R>(f[1], m, om, guo, gx, gy);
+        v[2][k] = sol ? 0.0f : collide_q<2, FORCE, R>(f[2], m, om, guo, gx, gy);
+        v[3][k] = sol ? 0.0f : collide_q<3, FORCE, R>(f[3], m, om, guo, gx, gy);
+        v[4][k] = sol ? 0.0f : collide_q<4, FORCE, R>(f[4], m, om, guo, gx, gy);
+        v[5][k] = sol ? 0.0f : collide_q<5, FORCE, R>(f[5], m, om, guo, gx, gy);
+        v[6][k] = sol ? 0.0f : collide_q<6, FORCE, R>(f[6], m, om, guo, gx, gy);
+        v[7][k] = sol ? 0.0f : collide_q<7, FORCE, R>(f[7], m, om, guo, gx, gy);
+        v[8][k] = sol ? 0.0f : collide_q<8, FORCE, R>(f[8], m, om, guo, gx, gy);
+        if ((solid4 >> k) & 1u) drho4[k] = 0.0f;
+    }
+    if (!active) return;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        const f4 t = {v[q][0], v[q][1], v[q][2], v[q][3]};
+        f4* d = reinterpret_cast<f4*>(a.dst + (size_t)q * N + n0);
+        if (NT) __builtin_nontemporal_store(t, d); else *d = t;
+    }
+    if (WDRHO) {
+        const f4 t = {drho4[0], drho4[1], drho4[2], drho4[3]};
+        *reinterpret_cast<f4*>(a.drho_out + n0) = t;
+    }
 }
 
 struct MacroArgs {
@@ -429,6 +578,10 @@ struct lbm_ctx {
     hipGraphExec_t graph[2];
     int graph_chunk;
     int device;
+    bool nontemporal;
+    bool vec4;       // four-wide step kernel (nx % 4 == 0)
+    int gridx4;      // workgroups along x for the four-wide kernel
+    int nblocks4;
 };
 
 static bool finite_d(double x) { return std::isfinite(x); }
@@ -544,12 +697,44 @@ static int launch_step(lbm_ctx* c, bool write_drho) {
     const bool zh = c->cfg.bc_x == LBM_BC_ZOUHE;
     const bool force = c->cfg.gx != 0.0 || c->cfg.gy != 0.0;
     const bool f32 = c->cfg.arith == LBM_ARITH_FP32;
-    dim3 blk(TX, TY), grd(c->nblocks);
+    const bool nt = c->nontemporal;
     hipStream_t s = c->stream;
+    if (c->vec4) {
+        a.g.gridx = c->gridx4;
+        dim3 blk(TX, TY), grd(c->nblocks4);
 #define LBM_STEP_CASE(Z, F, W)                                                         \
     if (zh == Z && force == F && write_drho == W) {                                   \
-        if (f32) k_bgk_step<Z, F, W, float><<<grd, blk, 0, s>>>(a);                   \
-        else k_bgk_step<Z, F, W, double><<<grd, blk, 0, s>>>(a);                      \
+        if (f32) {                                                                    \
+            if (nt) k_bgk_step_v4<Z, F, W, true, float><<<grd, blk, 0, s>>>(a);       \
+            else k_bgk_step_v4<Z, F, W, false, float><<<grd, blk, 0, s>>>(a);         \
+        } else {                                                                      \
+            if (nt) k_bgk_step_v4<Z, F, W, true, double><<<grd, blk, 0, s>>>(a);      \
+            else k_bgk_step_v4<Z, F, W, false, double><<<grd, blk, 0, s>>>(a);        \
+        }                                                                             \
+    }
+        LBM_STEP_CASE(false, false, false)
+        LBM_STEP_CASE(false, false, true)
+        LBM_STEP_CASE(false, true, false)
+        LBM_STEP_CASE(false, true, true)
+        LBM_STEP_CASE(true, false, false)
+        LBM_STEP_CASE(true, false, true)
+        LBM_STEP_CASE(true, true, false)
+        LBM_STEP_CASE(true, true, true)
+#undef LBM_STEP_CASE
+        c->cur ^= 1;
+        ++c->steps;
+        return LBM_OK;
+    }
+    dim3 blk(TX, TY), grd(c->nblocks);
+#define LBM_STEP_CASE(Z, F, W)                                                         \
+    if (zh == Z && force == F && write_drho == W) {                                   \
+        if (f32) {                                                                    \
+            if (nt) k_bgk_step<Z, F, W, true, float><<<grd, blk, 0, s>>>(a);          \
+            else k_bgk_step<Z, F, W, false, float><<<grd, blk, 0, s>>>(a);            \
+        } else {                                                                      \
+            if (nt) k_bgk_step<Z, F, W, true, double><<<grd, blk, 0, s>>>(a);         \
+            else k_bgk_step<Z, F, W, false, double><<<grd, blk, 0, s>>>(a);           \
+        }                                                                             \
     }
     LBM_STEP_CASE(false, false, false)
     LBM_STEP_CASE(false, false, true)
@@ -620,12 +805,20 @@ extern "C" int lbm_init(lbm_ctx** out, const lbm_config* cfg, const uint8_t* d_m
     c->g.bc_x = cfg->bc_x;
     c->g.bc_y = cfg->bc_y;
     c->nblocks = c->g.gridx * ((cfg->ny + TY - 1) / TY);
+    // The four-wide kernel issues a quarter of the wavefronts; below ~4M nodes that
+    // leaves too few in flight to hide latency and the one-node kernel is faster.
+    c->vec4 = cfg->nx % 4 == 0 && cfg->nx >= 4 && ((uintptr_t)d_fA % 16 == 0) &&
+              ((uintptr_t)d_fB % 16 == 0) && (size_t)cfg->nx * cfg->ny >= ((size_t)1 << 22);
+    c->gridx4 = (cfg->nx + 4 * TX - 1) / (4 * TX);
+    c->nblocks4 = c->gridx4 * ((cfg->ny + TY - 1) / TY);
     c->f[0] = d_fA;
     c->f[1] = d_fB;
     c->cur = 0;
     c->stream = (hipStream_t)stream;
     c->graph_chunk = 32;
     const size_t N = (size_t)c->g.N;
+    // two stores above 128 MB cannot stay in the 256 MB last-level cache across a step
+    c->nontemporal = 2 * 9 * N * sizeof(float) > ((size_t)128 << 20);
 #define LBM_TRY(call)                                                                   \
     do {                                                                                \
         hipError_t e_ = (call);                                                         \

@@ -65,6 +65,7 @@ SIGNATURES = [
     ("lbm_get_populations", ctypes.c_int, [_p, _p]),
     ("lbm_set_populations", ctypes.c_int, [_p, _p]),
     ("lbm_info", ctypes.c_int, [_p, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
+    ("lbm_stream_copy", ctypes.c_int, [_p, _p, ctypes.c_size_t, _p]),
 ]
 
 
@@ -120,6 +121,13 @@ def mask_raster(nx: int, ny: int, shapes: np.ndarray, wrap_x: bool, wrap_y: bool
                               shapes.shape[0], mask.data_ptr(), stream_handle(stream)),
           "lbm_mask_raster")
     return mask
+
+
+def stream_copy(src, dst, stream=None):
+    """dst[:] = src[:] (float32 device tensors) with the library's copy kernel."""
+    lib = load()
+    check(lib.lbm_stream_copy(src.data_ptr(), dst.data_ptr(), src.numel(), stream_handle(stream)),
+          "lbm_stream_copy")
 
 
 class Lattice:
