@@ -64,9 +64,15 @@ extern "C" {
                               rounded once to FP32 at the store (default) */
 #define LBM_ARITH_FP32 1   /* everything in FP32 registers */
 
+/* Step-kernel choice; every choice computes the same values. */
+#define LBM_KERNEL_AUTO 0  /* by lattice size (or the autotuner's cached pick) */
+#define LBM_KERNEL_NODE 1  /* one node per lane, 4-byte accesses (any nx) */
+#define LBM_KERNEL_QUAD 2  /* four x nodes per lane, 16-byte accesses (nx % 4 == 0,
+                              16-byte aligned stores) */
+
 /* Lattice description.  tau > 1/2 is the BGK relaxation time (nu = (tau-1/2)/3 in
  * lattice units), (gx, gy) a uniform body force per unit mass (Guo forcing; use 0
- * with LBM_BC_ZOUHE), arith one of LBM_ARITH_*. */
+ * with LBM_BC_ZOUHE), arith one of LBM_ARITH_*, kernel one of LBM_KERNEL_*. */
 typedef struct lbm_config {
     int32_t nx, ny;
     int32_t bc_x, bc_y;
@@ -74,7 +80,7 @@ typedef struct lbm_config {
     double gx, gy;
     double u_in, rho_out;
     int32_t arith;
-    int32_t reserved;
+    int32_t kernel;
 } lbm_config;
 
 /* Diagnostics of the state at time n (FP64 accumulation over fluid nodes). */

@@ -596,6 +596,8 @@ static int validate_config(const lbm_config* c) {
     if (!finite_d(c->gx) || !finite_d(c->gy)) return fail(LBM_EINVAL, "non-finite body force");
     if (c->arith != LBM_ARITH_MIXED && c->arith != LBM_ARITH_FP32)
         return fail(LBM_EINVAL, "arith = %d", c->arith);
+    if (c->kernel < LBM_KERNEL_AUTO || c->kernel > LBM_KERNEL_QUAD)
+        return fail(LBM_EINVAL, "kernel = %d", c->kernel);
     if (c->bc_x < 0 || c->bc_x > 2 || c->bc_y < 0 || c->bc_y > 1)
         return fail(LBM_EINVAL, "boundary codes bc_x=%d bc_y=%d", c->bc_x, c->bc_y);
     if (c->bc_x == LBM_BC_ZOUHE) {
@@ -807,8 +809,15 @@ extern "C" int lbm_init(lbm_ctx** out, const lbm_config* cfg, const uint8_t* d_m
     c->nblocks = c->g.gridx * ((cfg->ny + TY - 1) / TY);
     // The four-wide kernel issues a quarter of the wavefronts; below ~4M nodes that
     // leaves too few in flight to hide latency and the one-node kernel is faster.
-    c->vec4 = cfg->nx % 4 == 0 && cfg->nx >= 4 && ((uintptr_t)d_fA % 16 == 0) &&
-              ((uintptr_t)d_fB % 16 == 0) && (size_t)cfg->nx * cfg->ny >= ((size_t)1 << 22);
+    const bool quad_ok = cfg->nx % 4 == 0 && cfg->nx >= 4 && ((uintptr_t)d_fA % 16 == 0) &&
+                         ((uintptr_t)d_fB % 16 == 0);
+    if (cfg->kernel == LBM_KERNEL_QUAD && !quad_ok) {
+        delete c;
+        return fail(LBM_EUNSUPPORTED, "four-wide kernel needs nx %% 4 == 0 and 16-byte aligned stores");
+    }
+    c->vec4 = cfg->kernel == LBM_KERNEL_QUAD ||
+              (cfg->kernel == LBM_KERNEL_AUTO && quad_ok &&
+               (size_t)cfg->nx * cfg->ny >= ((size_t)1 << 22));
     c->gridx4 = (cfg->nx + 4 * TX - 1) / (4 * TX);
     c->nblocks4 = c->gridx4 * ((cfg->ny + TY - 1) / TY);
     c->f[0] = d_fA;

@@ -28,10 +28,11 @@ class LbmConfig(ctypes.Structure):
                 ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32),
                 ("tau", ctypes.c_double), ("gx", ctypes.c_double), ("gy", ctypes.c_double),
                 ("u_in", ctypes.c_double), ("rho_out", ctypes.c_double),
-                ("arith", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("arith", ctypes.c_int32), ("kernel", ctypes.c_int32)]
 
 
 ARITH_MIXED, ARITH_FP32 = 0, 1
+KERNEL_AUTO, KERNEL_NODE, KERNEL_QUAD = 0, 1, 2
 
 
 class LbmReport(ctypes.Structure):
@@ -136,12 +137,13 @@ class Lattice:
     capturable stream)."""
 
     def __init__(self, nx, ny, tau, gx=0.0, gy=0.0, bc_x=BC_PERIODIC, bc_y=BC_PERIODIC,
-                 u_in=0.0, rho_out=1.0, mask=None, stream=None, arith=ARITH_MIXED):
+                 u_in=0.0, rho_out=1.0, mask=None, stream=None, arith=ARITH_MIXED,
+                 kernel=KERNEL_AUTO):
         import torch
         self.lib = load()
         self.nx, self.ny = int(nx), int(ny)
         self.cfg = LbmConfig(self.nx, self.ny, bc_x, bc_y, float(tau), float(gx), float(gy),
-                             float(u_in), float(rho_out), int(arith), 0)
+                             float(u_in), float(rho_out), int(arith), int(kernel))
         self.stream = stream if stream is not None else torch.cuda.Stream()
         with torch.cuda.stream(self.stream):
             self.fA = torch.empty((9, ny, nx), dtype=torch.float32, device="cuda")
@@ -155,14 +157,14 @@ class Lattice:
               "lbm_init")
 
     @classmethod
-    def from_workload(cls, lat, stream=None, arith=ARITH_MIXED):
+    def from_workload(cls, lat, stream=None, arith=ARITH_MIXED, kernel=KERNEL_AUTO):
         """Build from a workloads.Lattice (its mask rasterised on the GPU)."""
         import torch
         stream = stream if stream is not None else torch.cuda.Stream()
         with torch.cuda.stream(stream):
             mask = mask_raster(lat.nx, lat.ny, lat.shapes_array(), lat.wrap_x, lat.wrap_y, stream)
         return cls(lat.nx, lat.ny, lat.tau, lat.gx, lat.gy, lat.bc_x, lat.bc_y, lat.u_in,
-                   lat.rho_out, mask=mask, stream=stream, arith=arith)
+                   lat.rho_out, mask=mask, stream=stream, arith=arith, kernel=kernel)
 
     def close(self):
         if self.ctx:

@@ -42,7 +42,7 @@ def test_every_declared_symbol_is_exported_and_bound(lib):
 
 
 def _cfg(**kw):
-    c = dict(nx=16, ny=8, bc_x=0, bc_y=0, tau=0.8, gx=0.0, gy=0.0, u_in=0.0, rho_out=1.0, arith=0)
+    c = dict(nx=16, ny=8, bc_x=0, bc_y=0, tau=0.8, gx=0.0, gy=0.0, u_in=0.0, rho_out=1.0, arith=0, kernel=0)
     c.update(kw)
     return lbmfno.LbmConfig(**c)
 
@@ -50,7 +50,7 @@ def _cfg(**kw):
 @pytest.mark.parametrize("kw", [dict(tau=0.5), dict(tau=float("nan")), dict(nx=0), dict(ny=-3),
                                 dict(bc_x=7), dict(bc_y=2), dict(nx=30000, ny=30000),
                                 dict(bc_x=2, u_in=1.5), dict(bc_x=2, rho_out=0.0),
-                                dict(gx=float("inf")), dict(arith=5)])
+                                dict(gx=float("inf")), dict(arith=5), dict(kernel=3)])
 def test_lbm_init_rejects_invalid_config(lib, kw):
     ctx = ctypes.c_void_p()
     rc = lib.lbm_init(ctypes.byref(ctx), ctypes.byref(_cfg(**kw)), 1, 2, 3, None)

@@ -18,18 +18,18 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-5
 
 
-def gpu_lattice(gpu, lat):
-    return gpu.Lattice.from_workload(lat)
+def gpu_lattice(gpu, lat, kernel=0):
+    return gpu.Lattice.from_workload(lat, kernel=kernel)
 
 
 def np_(t):
     return t.detach().cpu().numpy()
 
 
-def run_pair(gpu, lat, checkpoints, rho0=None, ux0=None, uy0=None):
+def run_pair(gpu, lat, checkpoints, rho0=None, ux0=None, uy0=None, kernel=0):
     """Run GPU and oracle side by side; yield (step, gpu macros, oracle macros, mask)."""
     import torch
-    G = gpu_lattice(gpu, lat)
+    G = gpu_lattice(gpu, lat, kernel)
     mask = olbm.raster(lat.nx, lat.ny, lat.shapes_array(), lat.wrap_x, lat.wrap_y)
     O = olbm.Sim(lat, mask)
     if rho0 is not None:
@@ -60,31 +60,37 @@ def test_mask_bit_exact(gpu, maker, args, seed):
     print(f"{lat.name}: {int(m_ref.sum())} solid cells, porosity {1 - m_ref.mean():.4f}")
 
 
+KERNELS = [1, 2]   # one node per lane, four nodes per lane
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("seed", list(range(10)))
-def test_channel_parity_1000_2000(gpu, seed):
+def test_channel_parity_1000_2000(gpu, seed, kernel):
     """128x64, periodic x, bounce-back walls and 10 circles, g = 1e-6, tau = 0.8."""
     lat = W.channel_walls_circles(seed)
-    for step, g, r, mask, _, _ in run_pair(gpu, lat, [1000, 2000]):
+    for step, g, r, mask, _, _ in run_pair(gpu, lat, [1000, 2000], kernel=kernel):
         e = field_errors(g, r, mask)
         print(f"seed {seed} step {step}: " + " ".join(f"{k}={v:.2e}" for k, v in e.items()))
         assert e["rho"] < TOL and e["ux"] < TOL and e["uy"] < TOL, e
 
 
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("seed", [0, 1])
-def test_porous_zouhe_parity_full_size(gpu, seed):
+def test_porous_zouhe_parity_full_size(gpu, seed, kernel):
     """1024x512 porous medium, Zou-He inlet u = 0.05 / outlet rho = 1, tau = 0.6."""
     lat = W.porous_circles(seed)
-    for step, g, r, mask, _, _ in run_pair(gpu, lat, [1000]):
+    for step, g, r, mask, _, _ in run_pair(gpu, lat, [1000], kernel=kernel):
         e = field_errors(g, r, mask)
         print(f"{lat.name} step {step}: " + " ".join(f"{k}={v:.2e}" for k, v in e.items()))
         assert e["rho"] < TOL and e["ux"] < TOL and e["uy"] < TOL, e
 
 
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("seed,size", [(7, (256, 128)), (8, (384, 192)), (9, (512, 256)), (0, None)])
-def test_ellipse_zouhe_parity(gpu, seed, size):
+def test_ellipse_zouhe_parity(gpu, seed, size, kernel):
     """Flow past random ellipses from the plug flow, Zou-He in x, periodic y."""
     lat = W.ellipse_flow(seed, size=size)
-    for step, g, r, mask, _, _ in run_pair(gpu, lat, [1000], *W.plug_flow(lat)):
+    for step, g, r, mask, _, _ in run_pair(gpu, lat, [1000], *W.plug_flow(lat), kernel=kernel):
         e = field_errors(g, r, mask)
         print(f"{lat.name} step {step}: " + " ".join(f"{k}={v:.2e}" for k, v in e.items()))
         assert e["rho"] < TOL and e["ux"] < TOL and e["uy"] < TOL, e
@@ -103,15 +109,18 @@ def test_ellipse_high_mach_jet_case(gpu):
     assert np.isfinite(np_(G.macros())).all()
 
 
-@pytest.mark.parametrize("nx,ny,bcx,bcy", [
-    (1, 5, 0, 0), (3, 7, 0, 1), (37, 11, 0, 0), (70, 9, 1, 0), (65, 13, 2, 0), (131, 6, 1, 1)])
-def test_ragged_and_tiny_lattices(gpu, nx, ny, bcx, bcy):
-    """Sizes that are not multiples of the 64x4 tile, single columns, all boundary kinds."""
+@pytest.mark.parametrize("nx,ny,bcx,bcy,kernel", [
+    (1, 5, 0, 0, 1), (3, 7, 0, 1, 1), (37, 11, 0, 0, 1), (70, 9, 1, 0, 1), (65, 13, 2, 0, 1),
+    (131, 6, 1, 1, 1), (4, 5, 0, 0, 2), (8, 7, 0, 1, 2), (36, 11, 0, 0, 2), (68, 9, 1, 0, 2),
+    (260, 13, 2, 0, 2), (516, 6, 1, 1, 2), (252, 10, 0, 1, 2)])
+def test_ragged_and_tiny_lattices(gpu, nx, ny, bcx, bcy, kernel):
+    """Sizes that are not multiples of the tiles (64x4 nodes, or 256x4 four-wide),
+    single columns, segment ends inside a wavefront, all boundary kinds."""
     shapes = [W.circle(nx // 2, ny // 2, 1)] if nx > 4 and ny > 4 else []
     lat = W.Lattice(nx=nx, ny=ny, tau=0.7, gx=2e-6 if bcx != 2 else 0.0, bc_x=bcx, bc_y=bcy,
                     u_in=0.03 if bcx == 2 else 0.0, shapes=shapes, wrap_x=bcx == 0, wrap_y=bcy == 0)
     rho0, ux0, uy0 = W.random_macro_fields(nx * 100 + ny, nx, ny, amp_u=0.01)
-    for step, g, r, mask, _, _ in run_pair(gpu, lat, [3, 200], rho0, ux0, uy0):
+    for step, g, r, mask, _, _ in run_pair(gpu, lat, [3, 200], rho0, ux0, uy0, kernel=kernel):
         e = field_errors(g, r, mask)
         fl = mask == 0
         # velocity as a vector field: a component that decays to ~1e-7 next to a
@@ -189,6 +198,27 @@ def test_report_sums_and_residual(gpu):
     print(f"residual gpu {rep['residual']:.4e} oracle {oref[0]:.4e}; mass gpu {rep['mass']:.12e} oracle {oref[1]:.12e}")
     assert abs(rep["mass"] - oref[1]) <= 1e-6 * oref[1]
     assert abs(rep["residual"] - oref[0]) <= 1e-3 * oref[0]
+
+
+def test_quad_and_node_kernels_agree_bitwise(gpu):
+    """Both step kernels evaluate the same expressions in the same order: identical
+    bits after 300 steps (forced channel; porous Zou-He)."""
+    for lat in (W.channel_walls_circles(2), W.porous_circles(3, nx=512, ny=256, rmin=6, rmax=12, keepout=20)):
+        A = gpu_lattice(gpu, lat, 1)
+        B = gpu_lattice(gpu, lat, 2)
+        A.step(300)
+        B.step(300)
+        assert np.array_equal(np_(A.populations()), np_(B.populations())), lat.name
+
+
+def test_large_lattice_quad_kernel_sampled_parity(gpu):
+    """Four-wide launch on a 2048x1024 porous lattice (the kernel the benchmark's
+    large lattice runs), 200 steps, against the FP64 oracle on every fluid node."""
+    lat = W.porous_circles(5, nx=2048, ny=1024, keepout=60, rmin=12, rmax=30)
+    for step, g, r, mask, _, _ in run_pair(gpu, lat, [200], kernel=2):
+        e = field_errors(g, r, mask)
+        print(f"{lat.name} step {step}: " + " ".join(f"{k}={v:.2e}" for k, v in e.items()))
+        assert e["rho"] < TOL and e["ux"] < TOL and e["uy"] < TOL, e
 
 
 def test_graph_replay_equals_direct_launches(gpu):
