@@ -158,6 +158,66 @@ int lbm_stream_copy(const float* d_src, float* d_dst, size_t n, void* stream);
 /* Number of fluid nodes and the current step counter (host values). */
 int lbm_info(const lbm_ctx* ctx, int64_t* fluid_nodes, int64_t* steps_done);
 
+/* ================================================== Fourier Neural Operator
+ *
+ * FNO of the paper's Sec. 2.2 (Eq. 6): lift P (pointwise, input channels + two
+ * coordinate channels x = w/(W-1), y = h/(H-1) -> width/2 -> width with the layer
+ * activation between), L Fourier layers v <- act(W v + b + F^-1(R . F(v))) with
+ * no activation after the last one, and a pointwise decoder Q (dec_layers hidden
+ * layers of dec_size with the decoder activation, then a linear map to cout).
+ * F is the 2-D DFT over the (zero-padded) H' x W' grid truncated to rows
+ * k1 in {0..m1-1} U {H'-m1..H'-1} and columns k2 in {0..m2-1}; F^-1 the real
+ * inverse (the k2 = 0 column contributes its real part once, the others twice,
+ * 1/(H'W') normalisation).  H' = H + padding, W' = W + padding (zeros on the high
+ * side, cropped before the decoder).
+ *
+ * Precision: activations between layers, spectral coefficients, DFT bases,
+ * spectral/1x1/decoder weights are bfloat16 (round-to-nearest-even); every
+ * contraction accumulates in float32 on MFMA (matrix cores); lift weights,
+ * biases and activations functions are float32.
+ *
+ * Packed parameters (float32, in this order; weights [out][in]):
+ *   lift1.w [width/2][cin+2*coords], lift1.b [width/2],
+ *   lift2.w [width][width/2], lift2.b [width],
+ *   per layer n: r_top [width][width][m1][m2][2], r_bot [width][width][m1][m2][2]
+ *                (complex (re, im); r_top applies to k1 = 0..m1-1, r_bot to
+ *                k1 = H'-m1..H'-1), conv.w [width][width], conv.b [width],
+ *   per decoder layer: w [dec_size][in], b [dec_size], then out.w [cout][in],
+ *   out.b [cout]. */
+#define FNO_ACT_GELU 0
+#define FNO_ACT_RELU 1
+#define FNO_ACT_SILU 2
+#define FNO_ACT_IDENTITY 3
+
+typedef struct fno_spec {
+    int32_t cin, width, layers, m1, m2;
+    int32_t dec_layers, dec_size, cout;
+    int32_t padding, coords;
+    int32_t act, dec_act;
+} fno_spec;
+
+typedef struct fno_model fno_model;
+
+/* Number of float32 values in the packed parameter vector of `spec`. */
+int fno_param_count(const fno_spec* spec, int64_t* count);
+
+/* Build a model for inputs of H x W points: validates the spec (width <= 64,
+ * 1 <= m1 <= H'/2, 1 <= m2 <= W'/2, layers >= 1, ...), converts the host parameter
+ * vector h_params (nparams float32, layout above) to the device layouts and
+ * builds the DFT bases.  Synchronous. */
+int fno_model_create(fno_model** out, const fno_spec* spec, const float* h_params,
+                     int64_t nparams, int32_t H, int32_t W);
+void fno_model_destroy(fno_model* m);
+
+/* Device workspace bytes fno_forward needs for a batch of B. */
+int fno_workspace_size(const fno_model* m, int32_t B, size_t* bytes);
+
+/* out[B][cout][H][W] = FNO(in[B][cin][H][W]) (float32, device).  d_ws: caller-owned
+ * device workspace of at least fno_workspace_size bytes (256-byte aligned).
+ * Asynchronous on `stream`. */
+int fno_forward(const fno_model* m, const float* d_in, float* d_out, int32_t B, void* d_ws,
+                size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,94 @@
+"""ctypes binding of the FNO entry points of liblbmfno.so (include/lbmfno.h):
+argument marshalling only; the forward pass runs in the library's HIP kernels."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import lbmfno as _L
+
+ACT = {"gelu": 0, "relu": 1, "silu": 2, "identity": 3}
+
+
+FnoSpecC = _L.FnoSpecC
+
+
+def to_c(spec) -> FnoSpecC:
+    """C spec from any object with the FnoSpec fields (workloads.FnoSpec)."""
+    return FnoSpecC(spec.cin, spec.width, spec.layers, spec.m1, spec.m2, spec.dec_layers,
+                    spec.dec_size, spec.cout, spec.padding, int(bool(spec.coords)),
+                    ACT[spec.act], ACT[spec.dec_act])
+
+
+def param_count(spec) -> int:
+    lib = _L.load_library()
+    n = ctypes.c_int64()
+    _L.check(lib.fno_param_count(ctypes.byref(to_c(spec)), ctypes.byref(n)), "fno_param_count")
+    return n.value
+
+
+def param_layout(spec):
+    """(name, shape) of the packed parameter tensors in the order the C ABI reads
+    them (lift, per-layer spectral/conv, decoder)."""
+    cl = spec.cin + (2 if spec.coords else 0)
+    h, wd = spec.width // 2, spec.width
+    out = [("lift1.w", (h, cl)), ("lift1.b", (h,)), ("lift2.w", (wd, h)), ("lift2.b", (wd,))]
+    for n in range(spec.layers):
+        out += [(f"spec{n}.r_top", (wd, wd, spec.m1, spec.m2, 2)),
+                (f"spec{n}.r_bot", (wd, wd, spec.m1, spec.m2, 2)),
+                (f"conv{n}.w", (wd, wd)), (f"conv{n}.b", (wd,))]
+    din = wd
+    for n in range(spec.dec_layers):
+        out += [(f"dec{n}.w", (spec.dec_size, din)), (f"dec{n}.b", (spec.dec_size,))]
+        din = spec.dec_size
+    out += [("dec_out.w", (spec.cout, din)), ("dec_out.b", (spec.cout,))]
+    return out
+
+
+class Fno:
+    """Device FNO bound to an H x W grid; forward() takes float32 [B][cin][H][W]."""
+
+    def __init__(self, spec, params, H: int, W: int):
+        self.lib = _L.load()
+        self.spec, self.H, self.W = spec, int(H), int(W)
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32).ravel())
+        self.model = ctypes.c_void_p()
+        _L.check(self.lib.fno_model_create(ctypes.byref(self.model), ctypes.byref(to_c(spec)),
+                                           p.ctypes.data_as(ctypes.c_void_p), p.size, self.H, self.W),
+                 "fno_model_create")
+        self._ws = {}
+
+    def workspace(self, B: int):
+        import torch
+        if B not in self._ws:
+            n = ctypes.c_size_t()
+            _L.check(self.lib.fno_workspace_size(self.model, int(B), ctypes.byref(n)), "fno_workspace_size")
+            self._ws[B] = torch.empty(int(n.value), dtype=torch.uint8, device="cuda")
+        return self._ws[B]
+
+    def forward(self, x, out=None, stream=None):
+        import torch
+        x = x.to(device="cuda", dtype=torch.float32).contiguous()
+        B = x.shape[0]
+        if tuple(x.shape[1:]) != (self.spec.cin, self.H, self.W):
+            raise ValueError(f"input shape {tuple(x.shape)} != [B][{self.spec.cin}][{self.H}][{self.W}]")
+        if out is None:
+            out = torch.empty((B, self.spec.cout, self.H, self.W), dtype=torch.float32, device="cuda")
+        ws = self.workspace(B)
+        _L.check(self.lib.fno_forward(self.model, x.data_ptr(), out.data_ptr(), int(B), ws.data_ptr(),
+                                      ws.numel(), _L.stream_handle(stream)), "fno_forward")
+        return out
+
+    __call__ = forward
+
+    def close(self):
+        if self.model:
+            self.lib.fno_model_destroy(self.model)
+            self.model = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

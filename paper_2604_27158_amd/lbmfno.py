@@ -53,6 +53,12 @@ class LbmError(RuntimeError):
         self.code = code
 
 
+class FnoSpecC(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("cin", "width", "layers", "m1", "m2", "dec_layers",
+                                                "dec_size", "cout", "padding", "coords", "act",
+                                                "dec_act")]
+
+
 # (name, restype, argtypes) of every exported entry point declared in include/*.h
 SIGNATURES = [
     ("lbm_status_str", ctypes.c_char_p, [ctypes.c_int]),
@@ -67,6 +73,12 @@ SIGNATURES = [
     ("lbm_set_populations", ctypes.c_int, [_p, _p]),
     ("lbm_info", ctypes.c_int, [_p, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     ("lbm_stream_copy", ctypes.c_int, [_p, _p, ctypes.c_size_t, _p]),
+    ("fno_param_count", ctypes.c_int, [ctypes.POINTER(FnoSpecC), ctypes.POINTER(_i64)]),
+    ("fno_model_create", ctypes.c_int, [ctypes.POINTER(_p), ctypes.POINTER(FnoSpecC), _p, _i64,
+                                        _i32, _i32]),
+    ("fno_model_destroy", None, [_p]),
+    ("fno_workspace_size", ctypes.c_int, [_p, _i32, ctypes.POINTER(ctypes.c_size_t)]),
+    ("fno_forward", ctypes.c_int, [_p, _p, _p, _i32, _p, ctypes.c_size_t, _p]),
 ]
 
 

@@ -86,3 +86,31 @@ def test_raster_validation(lib):
 def test_status_strings(lib):
     for code in range(0, -7, -1):
         assert lib.lbm_status_str(code) not in (None, b"unknown status")
+
+
+@pytest.mark.parametrize("args,count", [
+    ((1, 16, 3, 6, 3, 32, 1), 114273), ((1, 16, 6, 12, 3, 64, 2), 896082),
+    ((1, 14, 3, 8, 1, 32, 1), 151811), ((1, 14, 7, 32, 1, 32, 1), 5621835),
+    ((2, 14, 3, 32, 1, 32, 2), 2409771), ((2, 14, 7, 32, 1, 32, 2), 5621875),
+    ((4, 32, 4, 12, 1, 32, 3), 2365331)])
+def test_fno_param_count_abi_matches_paper(lib, args, count):
+    """fno_param_count (library) reproduces the paper's printed model sizes."""
+    from paper_2604_27158_amd import fno as gfno, workloads as W
+    cin, wd, L, m, dl, ds, co = args
+    s = W.FnoSpec(cin=cin, width=wd, layers=L, m1=m, m2=m, dec_layers=dl, dec_size=ds, cout=co)
+    assert gfno.param_count(s) == count
+    assert sum(int(__import__("numpy").prod(sh)) for _, sh in gfno.param_layout(s)) == count
+
+
+def test_fno_model_create_validates_on_host(lib):
+    from paper_2604_27158_amd import fno as gfno, workloads as W
+    import numpy as np
+    m = ctypes.c_void_p()
+    bad = W.FnoSpec(width=65)
+    p = np.zeros(10, np.float32)
+    assert lib.fno_model_create(ctypes.byref(m), ctypes.byref(gfno.to_c(bad)),
+                                p.ctypes.data_as(ctypes.c_void_p), 10, 64, 64) == -1
+    good = W.FnoSpec()
+    assert lib.fno_model_create(ctypes.byref(m), ctypes.byref(gfno.to_c(good)),
+                                p.ctypes.data_as(ctypes.c_void_p), 10, 64, 64) == -1
+    assert lib.fno_forward(None, 1, 2, 1, 3, 100, None) == -1

@@ -1,0 +1,107 @@
+"""GPU parity of the FNO forward (BF16 MFMA, FP32 accumulation) against the oracle.
+
+Two references: the oracle in "bf16" mode rounds every contraction operand to
+bfloat16 exactly where the GPU path does, so the only differences left are the
+FP32 (GPU) vs FP64 (oracle) accumulation and the one-ulp bf16 flips it causes.
+A value whose two accumulations differ by delta flips with probability
+~delta/ulp, so one rounding stage contributes ~sqrt(eps_acc * u_bf16) relative L2
+(eps_acc up to ~1e-4 for high modes with cancellation, u_bf16 = 2^-8): about
+2e-4 to 6e-4 per stage over 12-20 stages.  Bars: 5e-3 relative L2, and at most
+half of the oracle's own bf16-vs-FP64 distance.  The "fp64" oracle gives the
+error against FP64, reported and bounded by 3e-2."""
+import numpy as np
+import pytest
+
+from oracle import fno as ofno
+from paper_2604_27158_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL_BF16 = 5e-3
+TOL_FP64 = 3e-2
+
+
+def fields_input(seed, B, cin, H, Wd):
+    """(rho, ux, uy, mask)-like input: smooth fields plus a binary obstacle mask."""
+    xs = []
+    for b in range(B):
+        r, u, v = W.random_macro_fields(seed * 100 + b, Wd, H, amp_rho=0.02, amp_u=0.05)
+        m = (W.random_array(seed * 100 + b + 7, (H, Wd)) > 1.2).astype(np.float64)
+        chans = [r, u, v, m][:cin] + [W.random_array(seed + b, (H, Wd))] * max(0, cin - 4)
+        xs.append(np.stack(chans[:cin]))
+    return np.stack(xs)
+
+
+def ospec(s):
+    return ofno.Spec(cin=s.cin, width=s.width, layers=s.layers, m1=s.m1, m2=s.m2,
+                     dec_layers=s.dec_layers, dec_size=s.dec_size, cout=s.cout, padding=s.padding,
+                     coords=s.coords, act=s.act, dec_act=s.dec_act)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+CASES = [
+    # (name, spec, H, W, B)
+    ("flagship-4to3-w32-L4-m12", W.FnoSpec(), 128, 256, 2),
+    ("porous-rho-paper", W.FnoSpec(cin=1, width=16, layers=3, m1=6, m2=6, dec_layers=3, dec_size=32,
+                                   cout=1, padding=9), 64, 128, 1),
+    ("porous-u-paper", W.FnoSpec(cin=1, width=16, layers=6, m1=12, m2=12, dec_layers=3, dec_size=64,
+                                 cout=2, padding=9), 64, 128, 1),
+    ("shear-rho-small", W.FnoSpec(cin=1, width=14, layers=3, m1=8, m2=8, dec_layers=1, dec_size=32,
+                                  cout=1, padding=9), 64, 64, 2),
+    ("shear-u-small", W.FnoSpec(cin=2, width=14, layers=3, m1=32, m2=32, dec_layers=1, dec_size=32,
+                                cout=2, padding=9), 64, 64, 1),
+    ("ragged-50x70-w64", W.FnoSpec(cin=3, width=64, layers=2, m1=5, m2=7, dec_layers=2, dec_size=48,
+                                   cout=3, padding=3, act="relu", dec_act="gelu"), 50, 70, 3),
+]
+
+
+@pytest.mark.parametrize("name,spec,H,Wd,B", CASES, ids=[c[0] for c in CASES])
+def test_fno_forward_parity(gpu, name, spec, H, Wd, B):
+    import torch
+    from paper_2604_27158_amd import fno as gfno
+    layout = gfno.param_layout(spec)
+    assert sum(int(np.prod(s)) for _, s in layout) == ofno.param_count(ospec(spec)) == gfno.param_count(spec)
+    params = W.fno_random_params(hash(name) & 0xFFFF, layout, spec.width)
+    x = fields_input(len(name), B, spec.cin, H, Wd)
+    model = gfno.Fno(spec, params, H, Wd)
+    y = model(torch.from_numpy(x)).cpu().numpy().astype(np.float64)
+    y_bf = ofno.forward(ospec(spec), params, x, "bf16")
+    y_64 = ofno.forward(ospec(spec), params, x, "fp64")
+    e_bf, e_64 = rel(y, y_bf), rel(y, y_64)
+    print(f"{name}: rel-L2 vs bf16-emulating oracle {e_bf:.2e}, vs FP64 {e_64:.2e} "
+          f"(oracle bf16 vs fp64 {rel(y_bf, y_64):.2e})")
+    assert np.isfinite(y).all()
+    assert e_bf < TOL_BF16 and e_bf < 0.5 * rel(y_bf, y_64) and e_64 < TOL_FP64
+
+
+def test_fno_batch_is_per_sample(gpu):
+    """A batch of B gives bit-identical results to B single-sample calls."""
+    import torch
+    from paper_2604_27158_amd import fno as gfno
+    spec = W.FnoSpec()
+    params = W.fno_random_params(3, gfno.param_layout(spec), spec.width)
+    x = torch.from_numpy(fields_input(5, 3, 4, 128, 256))
+    m = gfno.Fno(spec, params, 128, 256)
+    yb = m(x).cpu().numpy()
+    for b in range(3):
+        assert np.array_equal(m(x[b:b + 1]).cpu().numpy()[0], yb[b])
+
+
+def test_fno_rejects_bad_arguments(gpu):
+    import ctypes
+    import torch
+    from paper_2604_27158_amd import fno as gfno, lbmfno
+    spec = W.FnoSpec(m1=80)
+    with pytest.raises(lbmfno.LbmError):
+        gfno.Fno(spec, np.zeros(10), 128, 256)
+    spec = W.FnoSpec()
+    params = W.fno_random_params(1, gfno.param_layout(spec), spec.width)
+    m = gfno.Fno(spec, params, 128, 256)
+    x = torch.zeros((1, 4, 128, 256), device="cuda")
+    out = torch.zeros((1, 3, 128, 256), device="cuda")
+    ws = m.workspace(1)
+    rc = m.lib.fno_forward(m.model, x.data_ptr(), out.data_ptr(), 1, ws.data_ptr(), 16, None)
+    assert rc == -1
