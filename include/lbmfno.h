@@ -149,6 +149,21 @@ int lbm_get_populations(lbm_ctx* ctx, float* d_f);
  * [9][ny][nx], solid entries ignored); the step counter is kept. */
 int lbm_set_populations(lbm_ctx* ctx, const float* d_f);
 
+/* Statistics of macroscopic fields over the fluid nodes of ctx's mask. */
+typedef struct lbm_field_stats {
+    double mass;          /* sum rho (FP64) */
+    double max_speed;     /* max |u| */
+    int64_t nonfinite;    /* nodes with a NaN or Inf in rho, ux or uy */
+    int64_t fluid_nodes;
+} lbm_field_stats;
+
+/* Guard for fields about to be handed to the lattice (e.g. an FNO prediction,
+ * Sec. 2.3): mass, peak speed and non-finite count of float32 [ny][nx] fields
+ * over fluid nodes, reduced on the device in a fixed order (deterministic).
+ * Synchronises ctx's stream. */
+int lbm_check_fields(lbm_ctx* ctx, const float* d_rho, const float* d_ux, const float* d_uy,
+                     lbm_field_stats* out);
+
 /* Plain device-to-device copy of n float32 values (n a multiple of 4, 16-byte
  * aligned buffers) with 16-byte loads and stores: the achievable-bandwidth
  * reference against which the lattice kernels' traffic and counters are read.

@@ -554,6 +554,64 @@ __global__ __launch_bounds__(256) void k_reduce_final(const double* __restrict__
     if (t < 4) out[t] = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
 }
 
+// Field guard: per-workgroup (sum rho, max |u|, non-finite count), then a
+// fixed-order second pass.  Partials reuse the [nblocks][4] double scratch.
+__global__ __launch_bounds__(256) void k_field_stats(const uint8_t* __restrict__ mask, int N,
+                                                     const float* __restrict__ rho,
+                                                     const float* __restrict__ ux,
+                                                     const float* __restrict__ uy,
+                                                     double* __restrict__ partials) {
+    __shared__ double red[4][3];
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    double s = 0.0, mx = 0.0, bad = 0.0;
+    if (n < N && !mask[n]) {
+        const float r = rho[n], u = ux[n], v = uy[n];
+        const bool fin = isfinite(r) && isfinite(u) && isfinite(v);
+        if (fin) {
+            s = (double)r;
+            mx = sqrt((double)u * u + (double)v * v);
+        } else {
+            bad = 1.0;
+        }
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    s = wave_sum(s);
+    bad = wave_sum(bad);
+    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_down(mx, o, 64));
+    if (lane == 0) { red[wave][0] = s; red[wave][1] = mx; red[wave][2] = bad; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, m = 0.0, c = 0.0;
+        for (int w = 0; w < 4; ++w) { a += red[w][0]; m = fmax(m, red[w][1]); c += red[w][2]; }
+        partials[(size_t)blockIdx.x * 4 + 0] = a;
+        partials[(size_t)blockIdx.x * 4 + 1] = m;
+        partials[(size_t)blockIdx.x * 4 + 2] = c;
+        partials[(size_t)blockIdx.x * 4 + 3] = 0.0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_field_stats_final(const double* __restrict__ partials,
+                                                           int nb, double* __restrict__ out) {
+    __shared__ double red[4][3];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    double s = 0.0, m = 0.0, c = 0.0;
+    for (int b = t; b < nb; b += 256) {
+        s += partials[(size_t)b * 4];
+        m = fmax(m, partials[(size_t)b * 4 + 1]);
+        c += partials[(size_t)b * 4 + 2];
+    }
+    s = wave_sum(s);
+    c = wave_sum(c);
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_down(m, o, 64));
+    if (lane == 0) { red[wave][0] = s; red[wave][1] = m; red[wave][2] = c; }
+    __syncthreads();
+    if (t == 0) {
+        double a = 0.0, mm = 0.0, cc = 0.0;
+        for (int w = 0; w < 4; ++w) { a += red[w][0]; mm = fmax(mm, red[w][1]); cc += red[w][2]; }
+        out[0] = a; out[1] = mm; out[2] = cc; out[3] = 0.0;
+    }
+}
+
 }  // namespace lbmfno
 
 // ------------------------------------------------------------ host side
@@ -957,6 +1015,28 @@ extern "C" int lbm_get_populations(lbm_ctx* c, float* d_f) {
     if (!c) return fail(LBM_EINVAL, "ctx is NULL");
     if (!d_f) return fail(LBM_EINVAL, "d_f is NULL");
     return launch_macro(c, nullptr, nullptr, nullptr, 0, d_f, false);
+}
+
+extern "C" int lbm_check_fields(lbm_ctx* c, const float* d_rho, const float* d_ux,
+                                const float* d_uy, lbm_field_stats* out) {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (!d_rho || !d_ux || !d_uy || !out) return fail(LBM_EINVAL, "NULL argument");
+    const int N = c->g.N;
+    const int nb = (N + 255) / 256;
+    if (nb > c->nblocks) {
+        // the partials scratch holds nblocks rows; nblocks >= ceil(N / 256) always
+        return fail(LBM_EINVAL, "internal: partial buffer too small");
+    }
+    k_field_stats<<<nb, 256, 0, c->stream>>>(c->d_mask, N, d_rho, d_ux, d_uy, c->d_partials);
+    k_field_stats_final<<<1, 256, 0, c->stream>>>(c->d_partials, nb, c->d_out);
+    LBM_HIP(hipGetLastError());
+    LBM_HIP(hipMemcpyAsync(c->h_out, c->d_out, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    LBM_HIP(hipStreamSynchronize(c->stream));
+    out->mass = c->h_out[0];
+    out->max_speed = c->h_out[1];
+    out->nonfinite = (int64_t)c->h_out[2];
+    out->fluid_nodes = c->fluid;
+    return LBM_OK;
 }
 
 extern "C" int lbm_info(const lbm_ctx* c, int64_t* fluid_nodes, int64_t* steps_done) {

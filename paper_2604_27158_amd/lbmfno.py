@@ -53,6 +53,14 @@ class LbmError(RuntimeError):
         self.code = code
 
 
+class FieldStats(ctypes.Structure):
+    _fields_ = [("mass", ctypes.c_double), ("max_speed", ctypes.c_double),
+                ("nonfinite", ctypes.c_int64), ("fluid_nodes", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class FnoSpecC(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("cin", "width", "layers", "m1", "m2", "dec_layers",
                                                 "dec_size", "cout", "padding", "coords", "act",
@@ -73,6 +81,7 @@ SIGNATURES = [
     ("lbm_set_populations", ctypes.c_int, [_p, _p]),
     ("lbm_info", ctypes.c_int, [_p, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     ("lbm_stream_copy", ctypes.c_int, [_p, _p, ctypes.c_size_t, _p]),
+    ("lbm_check_fields", ctypes.c_int, [_p, _p, _p, _p, ctypes.POINTER(FieldStats)]),
     ("fno_param_count", ctypes.c_int, [ctypes.POINTER(FnoSpecC), ctypes.POINTER(_i64)]),
     ("fno_model_create", ctypes.c_int, [ctypes.POINTER(_p), ctypes.POINTER(FnoSpecC), _p, _i64,
                                         _i32, _i32]),
@@ -236,6 +245,14 @@ class Lattice:
             f = f.to(device="cuda", dtype=torch.float32).contiguous()
         self._keep_f = f
         check(self.lib.lbm_set_populations(self.ctx, f.data_ptr()), "lbm_set_populations")
+
+    def check_fields(self, rho, ux, uy):
+        """Mass, peak speed and non-finite count of fields over fluid nodes."""
+        self._after_caller()
+        st = FieldStats()
+        check(self.lib.lbm_check_fields(self.ctx, rho.data_ptr(), ux.data_ptr(), uy.data_ptr(),
+                                        ctypes.byref(st)), "lbm_check_fields")
+        return st.as_dict()
 
     def info(self):
         fl, st = _i64(), _i64()
