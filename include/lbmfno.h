@@ -173,6 +173,43 @@ int lbm_stream_copy(const float* d_src, float* d_dst, size_t n, void* stream);
 /* Number of fluid nodes and the current step counter (host values). */
 int lbm_info(const lbm_ctx* ctx, int64_t* fluid_nodes, int64_t* steps_done);
 
+/* ================================================================ batches
+ *
+ * Many independent trajectories of possibly different sizes advanced together:
+ * one launch per step covers every trajectory through a flattened tile table
+ * (trajectory, tile), and chunks of steps are replayed as a captured hipGraph, so
+ * 100 small lattices cost one launch per step instead of 100. */
+typedef struct lbm_traj_desc {
+    lbm_config cfg;        /* arith must be LBM_ARITH_MIXED; kernel is ignored */
+    const uint8_t* d_mask; /* uint8 [ny][nx], copied */
+    float* d_fA;           /* caller-owned stores of 9*nx*ny float32 each */
+    float* d_fB;
+} lbm_traj_desc;
+
+typedef struct lbm_batch lbm_batch;
+
+/* Create contexts for ntraj trajectories (h_desc: host array) on `stream`, then
+ * pick the step kernel by measurement: every admissible (one-node / four-wide,
+ * cached / non-temporal stores) variant is timed on the batch itself and the
+ * fastest kept (autotuner).  With tune_cache != NULL the choice is read from, or
+ * appended to, that text file (key: device architecture and batch geometry).
+ * Every trajectory is left at rest (rho = 1, u = 0).  Synchronous. */
+int lbm_batch_create(lbm_batch** out, const lbm_traj_desc* h_desc, int32_t ntraj,
+                     const char* tune_cache, void* stream);
+
+/* Advance every trajectory n steps (asynchronous).  Fails with LBM_EINVAL if a
+ * trajectory's context was stepped on its own since the last batch step. */
+int lbm_batch_step(lbm_batch* b, int32_t n);
+
+/* Context of trajectory i (owned by the batch; use it for lbm_reinit_from_macro,
+ * lbm_get_macro, lbm_get_populations, lbm_check_fields -- not for lbm_step). */
+int lbm_batch_context(lbm_batch* b, int32_t i, lbm_ctx** out);
+
+/* Human-readable autotuner decision ("tuned quad+nt 0.1 ms/step", "cached ..."). */
+const char* lbm_batch_choice(const lbm_batch* b);
+
+void lbm_batch_destroy(lbm_batch* b);
+
 /* ================================================== Fourier Neural Operator
  *
  * FNO of the paper's Sec. 2.2 (Eq. 6): lift P (pointwise, input channels + two

@@ -314,9 +314,7 @@ __device__ __forceinline__ float collide_q(R fq, const Moments<R>& m, R omega, R
 // the collision arithmetic (double by default; float for the all-FP32 variant);
 // the stores are float either way.
 template <bool ZH, bool FORCE, bool WDRHO, bool NT, typename R>
-__global__ __launch_bounds__(256) void k_bgk_step(StepArgs a) {
-    const int b = xcd_remap(blockIdx.x, gridDim.x);
-    const int by = b / a.g.gridx, bx = b - by * a.g.gridx;
+__device__ __forceinline__ void step_node(const StepArgs& a, int bx, int by) {
     const int i = bx * TX + threadIdx.x, j = by * TY + threadIdx.y;
     if (i >= a.g.nx || j >= a.g.ny) return;
     const int n = j * a.g.nx + i;
@@ -343,6 +341,13 @@ __global__ __launch_bounds__(256) void k_bgk_step(StepArgs a) {
 #undef LBM_STORE
 }
 
+template <bool ZH, bool FORCE, bool WDRHO, bool NT, typename R>
+__global__ __launch_bounds__(256) void k_bgk_step(StepArgs a) {
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int by = b / a.g.gridx;
+    step_node<ZH, FORCE, WDRHO, NT, R>(a, b - by * a.g.gridx, by);
+}
+
 // Four-wide step (nx % 4 == 0): each lane owns four consecutive x nodes of one
 // row and a wavefront covers 256 nodes, so every plane is read and written with
 // aligned 16-byte accesses.  The +-x shifted populations come from the
@@ -354,9 +359,7 @@ __global__ __launch_bounds__(256) void k_bgk_step(StepArgs a) {
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 template <bool ZH, bool FORCE, bool WDRHO, bool NT, typename R>
-__global__ __launch_bounds__(256) void k_bgk_step_v4(StepArgs a) {
-    const int b = xcd_remap(blockIdx.x, gridDim.x);
-    const int by = b / a.g.gridx, bx = b - by * a.g.gridx;
+__device__ __forceinline__ void step_quad(const StepArgs& a, int bx, int by) {
     const int lane = threadIdx.x;
     const int j = by * TY + threadIdx.y;
     if (j >= a.g.ny) return;  // uniform over the wavefront
@@ -458,6 +461,49 @@ __global__ __launch_bounds__(256) void k_bgk_step_v4(StepArgs a) {
     if (WDRHO) {
         const f4 t = {drho4[0], drho4[1], drho4[2], drho4[3]};
         *reinterpret_cast<f4*>(a.drho_out + n0) = t;
+    }
+}
+
+template <bool ZH, bool FORCE, bool WDRHO, bool NT, typename R>
+__global__ __launch_bounds__(256) void k_bgk_step_v4(StepArgs a) {
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int by = b / a.g.gridx;
+    step_quad<ZH, FORCE, WDRHO, NT, R>(a, b - by * a.g.gridx, by);
+}
+
+// Batched step: one launch advances every trajectory of a batch by one step.  The
+// flattened tile table lists (trajectory, tile x, tile y) for all trajectories;
+// each workgroup reads its tile and that trajectory's step arguments (uniform
+// over the workgroup, so the boundary / forcing branches do not diverge).
+// Trajectories of one launch share the kernel shape (QUAD) and store policy (NT).
+struct BatchTile {
+    int traj, bx, by, pad;
+};
+
+template <bool QUAD, bool NT>
+__global__ __launch_bounds__(256) void k_bgk_batch(const StepArgs* __restrict__ args,
+                                                   const BatchTile* __restrict__ tiles) {
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const BatchTile t = tiles[b];
+    const StepArgs a = args[t.traj];
+    const bool zh = a.g.bc_x == LBM_BC_ZOUHE;
+    const bool force = a.gx != 0.0 || a.gy != 0.0;
+    if (QUAD) {
+        if (zh) {
+            if (force) step_quad<true, true, false, NT, double>(a, t.bx, t.by);
+            else step_quad<true, false, false, NT, double>(a, t.bx, t.by);
+        } else {
+            if (force) step_quad<false, true, false, NT, double>(a, t.bx, t.by);
+            else step_quad<false, false, false, NT, double>(a, t.bx, t.by);
+        }
+    } else {
+        if (zh) {
+            if (force) step_node<true, true, false, NT, double>(a, t.bx, t.by);
+            else step_node<true, false, false, NT, double>(a, t.bx, t.by);
+        } else {
+            if (force) step_node<false, true, false, NT, double>(a, t.bx, t.by);
+            else step_node<false, false, false, NT, double>(a, t.bx, t.by);
+        }
     }
 }
 
@@ -1045,3 +1091,280 @@ extern "C" int lbm_info(const lbm_ctx* c, int64_t* fluid_nodes, int64_t* steps_d
     if (steps_done) *steps_done = c->steps;
     return LBM_OK;
 }
+
+// ================================================================== batches
+
+struct lbm_batch {
+    int n = 0;
+    std::vector<lbm_ctx*> ctx;
+    hipStream_t stream = nullptr;
+    StepArgs* d_args[2] = {nullptr, nullptr};
+    BatchTile* d_tiles = nullptr;
+    int ntiles = 0;
+    bool quad = false, nt = false;
+    int parity = 0;
+    int64_t steps = 0;
+    int chunk = 32;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    std::string choice;
+};
+
+static void batch_release(lbm_batch* b) {
+    if (!b) return;
+    for (int k = 0; k < 2; ++k) {
+        if (b->graph[k]) (void)hipGraphExecDestroy(b->graph[k]);
+        if (b->d_args[k]) (void)hipFree(b->d_args[k]);
+    }
+    if (b->d_tiles) (void)hipFree(b->d_tiles);
+    for (lbm_ctx* c : b->ctx) release(c);
+    delete b;
+}
+
+extern "C" void lbm_batch_destroy(lbm_batch* b) { batch_release(b); }
+
+static StepArgs step_args_for(const lbm_ctx* c, int parity) {
+    StepArgs a;
+    a.src = c->f[parity];
+    a.dst = c->f[parity ^ 1];
+    a.link = c->d_link;
+    a.mask = c->d_mask;
+    a.drho_out = c->d_drho;
+    a.g = c->g;
+    a.omega = 1.0 / c->cfg.tau;
+    a.guo = 1.0 - 0.5 / c->cfg.tau;
+    a.gx = c->cfg.gx;
+    a.gy = c->cfg.gy;
+    a.u_in = c->cfg.u_in;
+    a.rho_out = c->cfg.rho_out;
+    return a;
+}
+
+// Tile table for one kernel shape: trajectory-major, rows of tiles in order, so
+// that the XCD remap keeps each trajectory's tiles (which share halo rows) together.
+static int build_tiles(lbm_batch* b, bool quad) {
+    std::vector<BatchTile> t;
+    for (int i = 0; i < b->n; ++i) {
+        const lbm_ctx* c = b->ctx[i];
+        const int gx = quad ? c->gridx4 : c->g.gridx;
+        const int gy = (c->g.ny + TY - 1) / TY;
+        for (int y = 0; y < gy; ++y)
+            for (int x = 0; x < gx; ++x) t.push_back(BatchTile{i, x, y, 0});
+    }
+    if (b->d_tiles) (void)hipFree(b->d_tiles);
+    b->d_tiles = nullptr;
+    LBM_HIP(hipMalloc(&b->d_tiles, t.size() * sizeof(BatchTile)));
+    LBM_HIP(hipMemcpy(b->d_tiles, t.data(), t.size() * sizeof(BatchTile), hipMemcpyHostToDevice));
+    b->ntiles = (int)t.size();
+    b->quad = quad;
+    return LBM_OK;
+}
+
+static void launch_batch(lbm_batch* b, int parity) {
+    dim3 blk(TX, TY), grd(b->ntiles);
+    if (b->quad) {
+        if (b->nt) k_bgk_batch<true, true><<<grd, blk, 0, b->stream>>>(b->d_args[parity], b->d_tiles);
+        else k_bgk_batch<true, false><<<grd, blk, 0, b->stream>>>(b->d_args[parity], b->d_tiles);
+    } else {
+        if (b->nt) k_bgk_batch<false, true><<<grd, blk, 0, b->stream>>>(b->d_args[parity], b->d_tiles);
+        else k_bgk_batch<false, false><<<grd, blk, 0, b->stream>>>(b->d_args[parity], b->d_tiles);
+    }
+}
+
+static int reset_rest(lbm_batch* b) {
+    for (lbm_ctx* c : b->ctx) {
+        LBM_HIP(hipMemsetAsync(c->f[0], 0, 9 * (size_t)c->g.N * sizeof(float), b->stream));
+        c->cur = 0;
+        c->steps = 0;
+    }
+    b->parity = 0;
+    b->steps = 0;
+    return LBM_OK;
+}
+
+// Autotuner: time every admissible (kernel shape, store policy) pair on the batch
+// itself and keep the fastest.  Results are cached in a text file of
+// "<key> <quad> <nt>" lines keyed by device and batch geometry.
+static std::string batch_key(const lbm_batch* b) {
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        arch = prop.gcnArchName;
+    for (char& ch : arch)
+        if (ch == ' ' || ch == ':') ch = '_';
+    uint64_t h = 1469598103934665603ull;
+    for (const lbm_ctx* c : b->ctx) {
+        const uint64_t v[3] = {(uint64_t)c->g.nx, (uint64_t)c->g.ny, (uint64_t)c->cfg.bc_x};
+        for (uint64_t x : v) { h ^= x; h *= 1099511628211ull; }
+    }
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s:n%d:%016llx", arch.c_str(), b->n, (unsigned long long)h);
+    return buf;
+}
+
+static bool cache_lookup(const char* path, const std::string& key, bool* quad, bool* nt) {
+    if (!path) return false;
+    FILE* f = fopen(path, "r");
+    if (!f) return false;
+    char k[256];
+    int q = 0, t = 0;
+    bool found = false;
+    while (fscanf(f, "%255s %d %d", k, &q, &t) == 3)
+        if (key == k) { *quad = q != 0; *nt = t != 0; found = true; }
+    fclose(f);
+    return found;
+}
+
+static void cache_store(const char* path, const std::string& key, bool quad, bool nt) {
+    if (!path) return;
+    FILE* f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%s %d %d\n", key.c_str(), quad ? 1 : 0, nt ? 1 : 0);
+    fclose(f);
+}
+
+static int autotune(lbm_batch* b, bool quad_ok, const char* cache) {
+    const std::string key = batch_key(b);
+    bool q = false, t = false;
+    if (cache_lookup(cache, key, &q, &t) && (quad_ok || !q)) {
+        b->nt = t;
+        int rc = build_tiles(b, q);
+        if (rc) return rc;
+        b->choice = std::string("cached ") + (q ? "quad" : "node") + (t ? "+nt" : "");
+        return LBM_OK;
+    }
+    float best = 1e30f;
+    bool bq = false, bt = false;
+    hipEvent_t e0, e1;
+    LBM_HIP(hipEventCreate(&e0));
+    LBM_HIP(hipEventCreate(&e1));
+    for (int qi = quad_ok ? 1 : 0; qi >= 0; --qi) {
+        int rc = build_tiles(b, qi != 0);
+        if (rc) return rc;
+        for (int ti = 0; ti < 2; ++ti) {
+            b->nt = ti != 0;
+            for (int k = 0; k < 4; ++k) launch_batch(b, k & 1);  // warm-up (even count)
+            LBM_HIP(hipEventRecord(e0, b->stream));
+            for (int k = 0; k < 16; ++k) launch_batch(b, k & 1);
+            LBM_HIP(hipEventRecord(e1, b->stream));
+            LBM_HIP(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            LBM_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) { best = ms; bq = qi != 0; bt = b->nt; }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b->nt = bt;
+    int rc = build_tiles(b, bq);
+    if (rc) return rc;
+    char msg[96];
+    snprintf(msg, sizeof msg, "tuned %s%s %.4f ms/step", bq ? "quad" : "node", bt ? "+nt" : "", best / 16);
+    b->choice = msg;
+    cache_store(cache, key, bq, bt);
+    return reset_rest(b);
+}
+
+extern "C" int lbm_batch_create(lbm_batch** out, const lbm_traj_desc* h_desc, int32_t ntraj,
+                                const char* tune_cache, void* stream) {
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!h_desc || ntraj < 1) return fail(LBM_EINVAL, "ntraj = %d", ntraj);
+    for (int i = 0; i < ntraj; ++i) {
+        int rc = validate_config(&h_desc[i].cfg);
+        if (rc) return fail(rc, "trajectory %d: %s", i, lbm_last_error());
+        if (h_desc[i].cfg.arith != LBM_ARITH_MIXED)
+            return fail(LBM_EUNSUPPORTED, "trajectory %d: batches run the mixed-precision step", i);
+        if (!h_desc[i].d_mask || !h_desc[i].d_fA || !h_desc[i].d_fB)
+            return fail(LBM_EINVAL, "trajectory %d: NULL device buffer", i);
+    }
+    lbm_batch* b = new (std::nothrow) lbm_batch();
+    if (!b) return fail(LBM_ENOMEM, "batch allocation");
+    b->n = ntraj;
+    b->stream = (hipStream_t)stream;
+    bool quad_ok = true;
+    for (int i = 0; i < ntraj; ++i) {
+        lbm_ctx* c = nullptr;
+        lbm_config cfg = h_desc[i].cfg;
+        cfg.kernel = LBM_KERNEL_NODE;
+        int rc = lbm_init(&c, &cfg, h_desc[i].d_mask, h_desc[i].d_fA, h_desc[i].d_fB, stream);
+        if (rc) { batch_release(b); return rc; }
+        b->ctx.push_back(c);
+        quad_ok = quad_ok && cfg.nx % 4 == 0 && cfg.nx >= 4 &&
+                  (uintptr_t)h_desc[i].d_fA % 16 == 0 && (uintptr_t)h_desc[i].d_fB % 16 == 0;
+    }
+    std::vector<StepArgs> a0, a1;
+    for (lbm_ctx* c : b->ctx) {
+        a0.push_back(step_args_for(c, 0));
+        a1.push_back(step_args_for(c, 1));
+    }
+    for (int k = 0; k < 2; ++k) {
+        hipError_t e = hipMalloc(&b->d_args[k], ntraj * sizeof(StepArgs));
+        if (e == hipSuccess)
+            e = hipMemcpy(b->d_args[k], k ? a1.data() : a0.data(), ntraj * sizeof(StepArgs),
+                          hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            batch_release(b);
+            return fail(LBM_EHIP, "batch arguments: %s", hipGetErrorString(e));
+        }
+    }
+    int rc = autotune(b, quad_ok, tune_cache);
+    if (rc) { batch_release(b); return rc; }
+    *out = b;
+    return LBM_OK;
+}
+
+static int batch_build_graph(lbm_batch* b) {
+    const int start = b->parity;
+    hipGraph_t g = nullptr;
+    LBM_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < b->chunk; ++k) launch_batch(b, start ^ (k & 1));
+    hipError_t e = hipStreamEndCapture(b->stream, &g);
+    if (e != hipSuccess) return fail(LBM_EHIP, "batch graph capture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&b->graph[start], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        b->graph[start] = nullptr;
+        return fail(LBM_EHIP, "batch graph instantiate: %s", hipGetErrorString(e));
+    }
+    return LBM_OK;
+}
+
+extern "C" int lbm_batch_step(lbm_batch* b, int32_t n) {
+    if (!b) return fail(LBM_EINVAL, "batch is NULL");
+    if (n < 0) return fail(LBM_EINVAL, "n = %d < 0", n);
+    for (const lbm_ctx* c : b->ctx)
+        if (c->cur != b->parity)
+            return fail(LBM_EINVAL, "a trajectory was stepped outside the batch");
+    int left = n;
+    if (b->stream != nullptr) {
+        while (left >= b->chunk) {
+            if (!b->graph[b->parity]) {
+                int rc = batch_build_graph(b);
+                if (rc) return rc;
+            }
+            LBM_HIP(hipGraphLaunch(b->graph[b->parity], b->stream));
+            left -= b->chunk;  // even chunk: parity unchanged
+        }
+    }
+    for (int k = 0; k < left; ++k) {
+        launch_batch(b, b->parity);
+        b->parity ^= 1;
+    }
+    LBM_HIP(hipGetLastError());
+    b->steps += n;
+    for (lbm_ctx* c : b->ctx) {
+        c->cur = b->parity;
+        c->steps += n;
+    }
+    return LBM_OK;
+}
+
+extern "C" int lbm_batch_context(lbm_batch* b, int32_t i, lbm_ctx** out) {
+    if (!b || !out) return fail(LBM_EINVAL, "NULL argument");
+    if (i < 0 || i >= b->n) return fail(LBM_EINVAL, "trajectory %d of %d", i, b->n);
+    *out = b->ctx[i];
+    return LBM_OK;
+}
+
+extern "C" const char* lbm_batch_choice(const lbm_batch* b) { return b ? b->choice.c_str() : ""; }

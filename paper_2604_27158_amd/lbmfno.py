@@ -61,6 +61,10 @@ class FieldStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class TrajDesc(ctypes.Structure):
+    _fields_ = [("cfg", LbmConfig), ("d_mask", _p), ("d_fA", _p), ("d_fB", _p)]
+
+
 class FnoSpecC(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("cin", "width", "layers", "m1", "m2", "dec_layers",
                                                 "dec_size", "cout", "padding", "coords", "act",
@@ -82,6 +86,12 @@ SIGNATURES = [
     ("lbm_info", ctypes.c_int, [_p, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     ("lbm_stream_copy", ctypes.c_int, [_p, _p, ctypes.c_size_t, _p]),
     ("lbm_check_fields", ctypes.c_int, [_p, _p, _p, _p, ctypes.POINTER(FieldStats)]),
+    ("lbm_batch_create", ctypes.c_int, [ctypes.POINTER(_p), ctypes.POINTER(TrajDesc), _i32,
+                                        ctypes.c_char_p, _p]),
+    ("lbm_batch_step", ctypes.c_int, [_p, _i32]),
+    ("lbm_batch_context", ctypes.c_int, [_p, _i32, ctypes.POINTER(_p)]),
+    ("lbm_batch_choice", ctypes.c_char_p, [_p]),
+    ("lbm_batch_destroy", None, [_p]),
     ("fno_param_count", ctypes.c_int, [ctypes.POINTER(FnoSpecC), ctypes.POINTER(_i64)]),
     ("fno_model_create", ctypes.c_int, [ctypes.POINTER(_p), ctypes.POINTER(FnoSpecC), _p, _i64,
                                         _i32, _i32]),
@@ -187,7 +197,17 @@ class Lattice:
         return cls(lat.nx, lat.ny, lat.tau, lat.gx, lat.gy, lat.bc_x, lat.bc_y, lat.u_in,
                    lat.rho_out, mask=mask, stream=stream, arith=arith, kernel=kernel)
 
+    @classmethod
+    def _view(cls, lib, ctx, nx, ny, mask, stream, owner):
+        """Non-owning view of a context that belongs to a batch."""
+        obj = cls.__new__(cls)
+        obj.lib, obj.ctx, obj.nx, obj.ny = lib, ctx, nx, ny
+        obj.mask, obj.stream, obj._owner = mask, stream, owner
+        return obj
+
     def close(self):
+        if getattr(self, "_owner", None) is not None:
+            return
         if self.ctx:
             self.lib.lbm_destroy(self.ctx)
             self.ctx = _p()
@@ -261,3 +281,56 @@ class Lattice:
 
     def synchronize(self):
         self.stream.synchronize()
+
+
+class Batch:
+    """Many trajectories (workloads.Lattice list) stepped by one launch per step;
+    trajectory(i) returns a Lattice view for reinit / macros / field checks."""
+
+    def __init__(self, lats, tune_cache=None, stream=None):
+        import torch
+        self.lib = load()
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        self.lats = list(lats)
+        descs = (TrajDesc * len(self.lats))()
+        self._bufs = []
+        with torch.cuda.stream(self.stream):
+            for k, lat in enumerate(self.lats):
+                mask = mask_raster(lat.nx, lat.ny, lat.shapes_array(), lat.wrap_x, lat.wrap_y,
+                                   self.stream)
+                fA = torch.empty((9, lat.ny, lat.nx), dtype=torch.float32, device="cuda")
+                fB = torch.empty_like(fA)
+                self._bufs.append((mask, fA, fB))
+                descs[k].cfg = LbmConfig(lat.nx, lat.ny, lat.bc_x, lat.bc_y, float(lat.tau),
+                                         float(lat.gx), float(lat.gy), float(lat.u_in),
+                                         float(lat.rho_out), ARITH_MIXED, KERNEL_AUTO)
+                descs[k].d_mask, descs[k].d_fA, descs[k].d_fB = mask.data_ptr(), fA.data_ptr(), fB.data_ptr()
+        self.handle = _p()
+        cache = tune_cache.encode() if tune_cache else None
+        check(self.lib.lbm_batch_create(ctypes.byref(self.handle), descs, len(self.lats), cache,
+                                        self.stream.cuda_stream), "lbm_batch_create")
+        self.choice = self.lib.lbm_batch_choice(self.handle).decode()
+        self.nodes = sum(l.nx * l.ny for l in self.lats)
+
+    def step(self, n: int):
+        check(self.lib.lbm_batch_step(self.handle, int(n)), "lbm_batch_step")
+
+    def trajectory(self, i: int) -> "Lattice":
+        ctx = _p()
+        check(self.lib.lbm_batch_context(self.handle, int(i), ctypes.byref(ctx)), "lbm_batch_context")
+        lat = self.lats[i]
+        return Lattice._view(self.lib, ctx, lat.nx, lat.ny, self._bufs[i][0], self.stream, self)
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def close(self):
+        if self.handle:
+            self.lib.lbm_batch_destroy(self.handle)
+            self.handle = _p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

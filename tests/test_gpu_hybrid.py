@@ -14,7 +14,11 @@ def make(gpu, seed=1, scale=1.0):
     import torch
     G.reinit(*(torch.from_numpy(a) for a in W.plug_flow(lat)))
     spec = W.FnoSpec()
-    p = W.fno_random_params(seed, gfno.param_layout(spec), spec.width) * scale
+    layout = gfno.param_layout(spec)
+    p = W.fno_random_params(seed, layout, spec.width) * scale
+    # output bias of the density channel = 1: predictions stay near rest density
+    off = sum(int(np.prod(s)) for _, s in layout[:-1])
+    p[off] = 1.0
     f = gfno.Fno(spec, p, lat.ny, lat.nx)
     return lat, G, f
 
