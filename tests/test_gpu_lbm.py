@@ -77,7 +77,7 @@ def test_channel_parity_1000_2000(gpu, seed, kernel):
 @pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("seed", [0, 1])
 def test_porous_zouhe_parity_full_size(gpu, seed, kernel):
-    """1024x512 porous medium, Zou-He inlet u = 0.05 / outlet rho = 1, tau = 0.6."""
+    """1024x512 porous medium, Zou-He inlet u = 0.02 / outlet rho = 1, tau = 0.6."""
     lat = W.porous_circles(seed)
     for step, g, r, mask, _, _ in run_pair(gpu, lat, [1000], kernel=kernel):
         e = field_errors(g, r, mask)
