@@ -26,6 +26,11 @@
 
 #include "common.hpp"
 
+// No multiply-add contraction in the lattice kernels: every step kernel (one node
+// or four nodes per lane, single or batched) then evaluates the same sequence of
+// IEEE operations and gives bit-identical results, whichever the tuner picks.
+#pragma clang fp contract(off)
+
 namespace lbmfno {
 
 static thread_local std::string g_err;
@@ -134,12 +139,32 @@ __device__ __forceinline__ int push_target(const LatticeGeom& g, const uint8_t* 
     return mask[t] ? -1 : t;
 }
 
-// Deviation equilibrium f_eq_p - w_p = w_p [(rho - 1) + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u.u)].
+// c_q . (x, y) for the integer velocity c_q, as additions only: with contraction
+// off, a product by a literal 0 or 1 would otherwise be evaluated.
+template <int Q, typename R>
+__device__ __forceinline__ R cdot(R x, R y) {
+    constexpr int cx = cx_of(Q), cy = cy_of(Q);
+    R a = R(0);
+    if constexpr (cx == 1) a = x;
+    if constexpr (cx == -1) a = -x;
+    if constexpr (cy == 1) a = (cx == 0) ? y : a + y;
+    if constexpr (cy == -1) a = (cx == 0) ? -y : a - y;
+    return a;
+}
+
+// Deviation equilibrium f_eq_p - w_p = w_p [(rho - 1) + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u.u)],
+// with every multiply-add written as an explicit fma (one fixed operation order).
+// usq15 = 1.5 u.u.
+template <int P, typename R>
+__device__ __forceinline__ R feq_dev(R drho, R rho, R ux, R uy, R usq15) {
+    const R cu = cdot<P, R>(ux, uy);
+    const R t = fma(cu, fma(R(4.5), cu, R(3)), -usq15);
+    return (R)w_of_d(P) * fma(rho, t, drho);
+}
+
 template <int P, typename R>
 __device__ __forceinline__ R feq_dev(R drho, R rho, R ux, R uy) {
-    const R cu = (R)cx_of(P) * ux + (R)cy_of(P) * uy;
-    const R usq = R(1.5) * (ux * ux + uy * uy);
-    return (R)w_of_d(P) * (drho + rho * (R(3) * cu + R(4.5) * cu * cu - usq));
+    return feq_dev<P, R>(drho, rho, ux, uy, R(1.5) * fma(ux, ux, uy * uy));
 }
 
 __device__ __forceinline__ float feq_dev_rt(int p, double drho, double rho, double ux, double uy) {
@@ -287,27 +312,36 @@ __device__ __forceinline__ Moments<R> moments(const R f[9], R gx, R gy) {
     const R jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
     const R jy = (f[2] - f[4]) + (f[5] - f[8]) + (f[6] - f[7]);
     const R inv = R(1) / m.rho;
-    m.ux = jx * inv;
-    m.uy = jy * inv;
     if (FORCE) {
-        m.ux += R(0.5) * gx;
-        m.uy += R(0.5) * gy;
+        m.ux = fma(jx, inv, R(0.5) * gx);
+        m.uy = fma(jy, inv, R(0.5) * gy);
+    } else {
+        m.ux = jx * inv;
+        m.uy = jy * inv;
     }
     return m;
 }
 
+// Post-collision deviation of direction Q: f - omega (f - f_eq) (+ Guo term
+// guo w rho [3 (c - u).g + 9 (c.u)(c.g)]), usq15 = 1.5 u.u of the node.
 template <int Q, bool FORCE, typename R>
-__device__ __forceinline__ float collide_q(R fq, const Moments<R>& m, R omega, R guo, R gx, R gy) {
-    const R fe = feq_dev<Q>(m.drho, m.rho, m.ux, m.uy);
-    R out = fq - omega * (fq - fe);
+__device__ __forceinline__ float collide_q(R fq, const Moments<R>& m, R omega, R guo, R gx, R gy,
+                                           R usq15) {
+    const R fe = feq_dev<Q, R>(m.drho, m.rho, m.ux, m.uy, usq15);
+    R out = fma(-omega, fq - fe, fq);
     if (FORCE) {
-        constexpr R cxq = (R)cx_of(Q), cyq = (R)cy_of(Q);
-        const R cu = cxq * m.ux + cyq * m.uy;
-        const R cg = cxq * gx + cyq * gy;
-        const R t = R(3) * ((cxq - m.ux) * gx + (cyq - m.uy) * gy) + R(9) * cu * cg;
-        out += guo * (R)w_of_d(Q) * m.rho * t;
+        const R cu = cdot<Q, R>(m.ux, m.uy);
+        const R cg = cdot<Q, R>(gx, gy);
+        const R ug = fma(m.ux, gx, m.uy * gy);
+        const R t = fma(R(9) * cu, cg, R(3) * (cg - ug));
+        out = fma(guo * (R)w_of_d(Q) * m.rho, t, out);
     }
     return (float)out;
+}
+
+template <int Q, bool FORCE, typename R>
+__device__ __forceinline__ float collide_q(R fq, const Moments<R>& m, R omega, R guo, R gx, R gy) {
+    return collide_q<Q, FORCE, R>(fq, m, omega, guo, gx, gy, R(1.5) * fma(m.ux, m.ux, m.uy * m.uy));
 }
 
 // One fused step t -> t+1 for one node per thread.  R is the register type of
@@ -451,7 +485,15 @@ __device__ __forceinline__ void step_quad(const StepArgs& a, int bx, int by) {
         v[8][k] = sol ? 0.0f : collide_q<8, FORCE, R>(f[8], m, om, guo, gx, gy);
         if ((solid4 >> k) & 1u) drho4[k] = 0.0f;
     }
-    if (!active) return;
+    // a quad of four solid nodes stores nothing (its slots are never read); its
+    // loads above stay, since the neighbouring lanes' shuffles use them
+    if (!active || solid4 == 0xFu) {
+        if (WDRHO && active) {
+            const f4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+            *reinterpret_cast<f4*>(a.drho_out + n0) = z;
+        }
+        return;
+    }
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
         const f4 t = {v[q][0], v[q][1], v[q][2], v[q][3]};

@@ -1,0 +1,49 @@
+"""Fixed kernel sequences for hardware-counter runs (rocprofv3 --pmc).
+
+Launches the fused step of a workload as single launches (no graph replay, so
+every dispatch is visible to the counter collector) and the library's copy kernel
+on a buffer of known size, which calibrates the byte counters:
+
+    python -m paper_2604_27158_amd.profile_run --workload porous1024 --steps 50
+"""
+import argparse
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+COPY_FLOATS = 1 << 26   # 256 MiB per buffer: 512 MiB moved per copy launch
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="porous1024", choices=["porous1024", "large"])
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--copies", type=int, default=5)
+    args = ap.parse_args()
+    import torch
+    from paper_2604_27158_amd import lbmfno
+    from paper_2604_27158_amd import workloads as W
+    if args.workload == "porous1024":
+        lat = W.porous_circles(0)
+    else:
+        import bench
+        lat = bench.porous_large(0)
+    G = lbmfno.Lattice.from_workload(lat)
+    for _ in range(args.steps):
+        G.step(1)
+    G.synchronize()
+    fluid, _ = G.info()
+    a = torch.ones(COPY_FLOATS, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(args.copies):
+        lbmfno.stream_copy(a, b)
+    torch.cuda.synchronize()
+    print(f"profile_run: {lat.name} {args.steps} single steps, fluid {fluid} of {lat.nx * lat.ny}; "
+          f"{args.copies} copies of {COPY_FLOATS * 4} bytes", flush=True)
+
+
+if __name__ == "__main__":
+    main()
