@@ -44,6 +44,22 @@ def parse():
     return ap.parse_args()
 
 
+def profiled_traffic(name: str):
+    """HBM bytes per launch of the step kernel on workload `name`, from the
+    counter summary committed under profiles/, or None when the kernel source has
+    changed since the counters were taken (the summary records its hash)."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_2604_27158_amd", "csrc", "lbm.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for md in glob.glob(os.path.join(ROOT, "profiles", "*.md")):
+        for line in open(md):
+            f = line.split()
+            if len(f) == 5 and f[0] == "traffic_bytes_per_launch" and f[1] == name and f[3] == "source":
+                return float(f[2]) if f[4] == sha else None
+    return None
+
+
 def algorithmic_bytes(fluid: int, total: int) -> int:
     """Per fused step: a fluid node loads 9 and stores 9 float32 populations and
     reads its link byte (73 B); a solid node reads its link byte and mask byte."""
@@ -295,7 +311,7 @@ def main():
                    "porosity": fluid / N, "lattice_steps_per_bench_step": INNER,
                    "arith": "fp32 storage, fp64 collision registers"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic("porous1024x512"),
                      "kernel": "k_bgk_step<zouhe>", "bytes_per_launch": bytes_launch,
                      "launch_ms": kern_ms,
                      "note": "37.7 MB working set: resident in the 256 MB last-level cache"},
@@ -329,7 +345,8 @@ def main():
         ach = bb / (kb * 1e-3) / 1e9
         out["roofline_hbm_resident"] = {
             "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": ach / HBM_PEAK_GBS, "frac_of_copy": ach / copy_gbs, "traffic": None,
+            "frac": ach / HBM_PEAK_GBS, "frac_of_copy": ach / copy_gbs,
+            "traffic": profiled_traffic("porous8192x4096"),
             "workload": big.name, "glups": 100 * big.nx * big.ny / (msb * 1e6),
             "bytes_per_launch": bb, "launch_ms": kb}
         GB.close()
