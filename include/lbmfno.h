@@ -170,8 +170,42 @@ int lbm_check_fields(lbm_ctx* ctx, const float* d_rho, const float* d_ux, const 
  * Asynchronous on `stream`. */
 int lbm_stream_copy(const float* d_src, float* d_dst, size_t n, void* stream);
 
+/* Exact checkpoints: copy the current population store (9*nx*ny float32 in the
+ * library's internal pull/deviation layout) out to, or back from, a caller buffer.
+ * Restoring a saved store reproduces every later step bit for bit.  The step
+ * counter is not touched.  Asynchronous on ctx's stream. */
+size_t lbm_state_elems(const lbm_ctx* ctx);
+int lbm_save_state(lbm_ctx* ctx, float* d_out);
+int lbm_load_state(lbm_ctx* ctx, const float* d_in);
+
 /* Number of fluid nodes and the current step counter (host values). */
 int lbm_info(const lbm_ctx* ctx, int64_t* fluid_nodes, int64_t* steps_done);
+
+/* ================================================================ adjoint
+ *
+ * Reverse-mode derivatives of the lattice (the paper's solver is differentiable,
+ * Sec. 2.1): a rollout f(0) = f_eq(rho0, u0), f(n+1) = P C(f(n)), loss L(macros(f(N)))
+ * is differentiated by
+ *   lam_N = lbm_macro_vjp(f(N), dL/d macros),
+ *   lam_n = lbm_adjoint_step(f(n), lam_{n+1})  for n = N-1 .. 0,
+ *   dL/d(rho0, u0) = lbm_feq_vjp(rho0, u0, lam_0),
+ * with f(n) recomputed from checkpoints.  All arrays float32 device, populations
+ * [9][ny][nx] absolute (as from lbm_get_populations), fields [ny][nx]; solid
+ * nodes get zeros.  Periodic and wall boundaries only (Zou-He: LBM_EUNSUPPORTED). */
+
+/* lam_n = C'(f(n))^T P^T lam_{n+1}: P^T is the inverse of the streaming /
+ * bounce-back permutation, C' the per-node collision Jacobian (with the Guo term).
+ * d_lam_np1 and d_lam_n must differ.  Asynchronous on ctx's stream. */
+int lbm_adjoint_step(lbm_ctx* ctx, const float* d_f_n, const float* d_lam_np1, float* d_lam_n);
+
+/* lam_j = g_rho + g_u . d u / d f_j, d u / d f_j = (c_j - u + g/2) / rho, for
+ * upstream gradients (g_rho, g_ux, g_uy) of the macroscopic fields of f. */
+int lbm_macro_vjp(lbm_ctx* ctx, const float* d_f_n, const float* d_g_rho, const float* d_g_ux,
+                  const float* d_g_uy, float* d_lam);
+
+/* Gradient of the initial fields through f(0) = f_eq(rho, u) (Eq. 1). */
+int lbm_feq_vjp(lbm_ctx* ctx, const float* d_rho, const float* d_ux, const float* d_uy,
+                const float* d_lam, float* d_g_rho, float* d_g_ux, float* d_g_uy);
 
 /* ================================================================ batches
  *

@@ -1,0 +1,65 @@
+"""Differentiable lattice rollouts: a torch.autograd.Function whose forward and
+backward run in liblbmfno kernels (the paper's solver is fully differentiable,
+Sec. 2.1; the hybrid couples the FNO to it through f = f_eq(rho, u), Sec. 2.3).
+
+forward(rho0, ux0, uy0): f(0) = f_eq(rho0, u0), N lattice steps, returns the
+macroscopic fields of f(N).  The lattice store is checkpointed exactly every
+`ckpt_every` steps (device tensors), so recomputed states equal the forward's
+bit for bit and the gradient does not depend on the checkpoint interval.  backward: lam_N from the macro Jacobian, then
+segment by segment (last first) the segment's states are recomputed from its
+checkpoint and the step adjoint runs backwards through them; finally the
+gradient is pulled back through f_eq.  Memory: N / ckpt_every checkpoints plus
+ckpt_every states of one segment.
+"""
+from __future__ import annotations
+
+import torch
+
+
+class LatticeRollout(torch.autograd.Function):
+
+    @staticmethod
+    def forward(ctx, rho0, ux0, uy0, lattice, nsteps: int, ckpt_every: int = 50):
+        lat = lattice
+        lat.reinit(rho0, ux0, uy0)
+        ckpts = []
+        done = 0
+        while done < nsteps:
+            ckpts.append(lat.save_state())
+            k = min(ckpt_every, nsteps - done)
+            lat.step(k)
+            done += k
+        f_N = lat.populations()
+        out = lat.macros()
+        ctx.lat, ctx.nsteps, ctx.every = lat, int(nsteps), int(ckpt_every)
+        ctx.ckpts = ckpts
+        ctx.save_for_backward(rho0, ux0, uy0, f_N)
+        return out[0].clone(), out[1].clone(), out[2].clone()
+
+    @staticmethod
+    def backward(ctx, g_rho, g_ux, g_uy):
+        lat = ctx.lat
+        rho0, ux0, uy0, f_N = ctx.saved_tensors
+        zeros = torch.zeros_like(rho0)
+        g = [t if t is not None else zeros for t in (g_rho, g_ux, g_uy)]
+        lam = lat.macro_vjp(f_N, *g)
+        spare = torch.empty_like(lam)
+        nseg = len(ctx.ckpts)
+        for s in range(nseg - 1, -1, -1):
+            start = s * ctx.every
+            k = min(ctx.every, ctx.nsteps - start)
+            lat.load_state(ctx.ckpts[s])
+            states = [lat.populations()]
+            for _ in range(k - 1):
+                lat.step(1)
+                states.append(lat.populations())
+            for n in range(k - 1, -1, -1):
+                lat.adjoint_step(states[n], lam, out=spare)
+                lam, spare = spare, lam
+        gr = lat.feq_vjp(rho0, ux0, uy0, lam)
+        return gr[0], gr[1], gr[2], None, None, None
+
+
+def rollout(lattice, rho0, ux0, uy0, nsteps: int, ckpt_every: int = 50):
+    """Differentiable macros(f(nsteps)) of the lattice started at f_eq(rho0, u0)."""
+    return LatticeRollout.apply(rho0, ux0, uy0, lattice, nsteps, ckpt_every)

@@ -1410,3 +1410,222 @@ extern "C" int lbm_batch_context(lbm_batch* b, int32_t i, lbm_ctx** out) {
 }
 
 extern "C" const char* lbm_batch_choice(const lbm_batch* b) { return b ? b->choice.c_str() : ""; }
+
+namespace lbmfno {
+
+// ================================================================= adjoint
+//
+// Vector-Jacobian product of one step f(n+1) = P C(f(n)) (periodic and wall
+// boundaries): lam_n = C'(f(n))^T P^T lam_{n+1}.  P^T is the inverse of the pull
+// permutation: slot (q, y) was pulled by y + c_q when that node is fluid and inside
+// the domain (link bit opp(q)-1 of y clear), otherwise it bounced back into y as
+// opp(q).  C' is the per-node collision Jacobian with d rho / d f_j = 1 and
+// d u / d f_j = (c_j - u + g/2) / rho.  FP64 registers, float32 in and out.
+struct AdjArgs {
+    const float* __restrict__ f;      // pre-collision populations f(n), absolute
+    const float* __restrict__ lam1;   // lam_{n+1}
+    float* __restrict__ lam0;         // lam_n
+    const uint8_t* __restrict__ link;
+    const uint8_t* __restrict__ mask;
+    LatticeGeom g;
+    double omega, guo, gx, gy;
+};
+
+template <bool FORCE>
+__global__ __launch_bounds__(256) void k_adjoint_step(AdjArgs a) {
+    const int b = blockIdx.x;
+    const int by = b / a.g.gridx, bx = b - by * a.g.gridx;
+    const int i = bx * TX + threadIdx.x, j = by * TY + threadIdx.y;
+    if (i >= a.g.nx || j >= a.g.ny) return;
+    const int n = j * a.g.nx + i;
+    const size_t N = (size_t)a.g.N;
+    const unsigned lk = a.link[n];
+    if (is_solid(lk, a.mask, n)) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) a.lam0[q * N + n] = 0.0f;
+        return;
+    }
+    const int im = i == 0 ? a.g.nx - 1 : i - 1, ip = i == a.g.nx - 1 ? 0 : i + 1;
+    const int jm = j == 0 ? a.g.ny - 1 : j - 1, jp = j == a.g.ny - 1 ? 0 : j + 1;
+    const int r0 = j * a.g.nx, rm = jm * a.g.nx, rp = jp * a.g.nx;
+    // push target y + c_q for q = 1..8
+    double mu[9];
+    mu[0] = a.lam1[n];
+#define LBM_PUSH(Q, TGT)                                                                  \
+    mu[Q] = ((lk >> (opp_of(Q) - 1)) & 1u) ? (double)a.lam1[opp_of(Q) * N + n]           \
+                                           : (double)a.lam1[Q * N + (TGT)];
+    LBM_PUSH(1, r0 + ip)
+    LBM_PUSH(2, rp + i)
+    LBM_PUSH(3, r0 + im)
+    LBM_PUSH(4, rm + i)
+    LBM_PUSH(5, rp + ip)
+    LBM_PUSH(6, rp + im)
+    LBM_PUSH(7, rm + im)
+    LBM_PUSH(8, rm + ip)
+#undef LBM_PUSH
+    double f[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) f[q] = (double)a.f[q * N + n] - w_of_d(q);
+    const Moments<double> m = moments<FORCE, double>(f, a.gx, a.gy);
+    const double usq = fma(m.ux, m.ux, m.uy * m.uy);
+    const double gu = fma(a.gx, m.ux, a.gy * m.uy);
+    double A = 0.0, Bx = 0.0, By = 0.0;
+#define LBM_ADJ_ACC(Q)                                                                        \
+    {                                                                                         \
+        const double cu = cdot<Q, double>(m.ux, m.uy);                                        \
+        const double wq = w_of_d(Q);                                                          \
+        /* d f_eq / d rho and d f_eq / d u */                                                 \
+        const double dfr = wq * (1.0 + fma(cu, fma(4.5, cu, 3.0), -1.5 * usq));              \
+        const double k = wq * m.rho * fma(9.0, cu, 3.0);                                      \
+        double dfx = (double)cx_of(Q) * k - wq * m.rho * 3.0 * m.ux;                          \
+        double dfy = (double)cy_of(Q) * k - wq * m.rho * 3.0 * m.uy;                          \
+        double t = a.omega * dfr, tx = a.omega * dfx, ty = a.omega * dfy;                    \
+        if (FORCE) {                                                                          \
+            const double cg = cdot<Q, double>(a.gx, a.gy);                                    \
+            t += a.guo * wq * (3.0 * (cg - gu) + 9.0 * cu * cg);                              \
+            tx += a.guo * wq * m.rho * (-3.0 * a.gx + 9.0 * (double)cx_of(Q) * cg);           \
+            ty += a.guo * wq * m.rho * (-3.0 * a.gy + 9.0 * (double)cy_of(Q) * cg);           \
+        }                                                                                     \
+        A = fma(mu[Q], t, A);                                                                 \
+        Bx = fma(mu[Q], tx, Bx);                                                              \
+        By = fma(mu[Q], ty, By);                                                              \
+    }
+    LBM_ADJ_ACC(0) LBM_ADJ_ACC(1) LBM_ADJ_ACC(2) LBM_ADJ_ACC(3) LBM_ADJ_ACC(4)
+    LBM_ADJ_ACC(5) LBM_ADJ_ACC(6) LBM_ADJ_ACC(7) LBM_ADJ_ACC(8)
+#undef LBM_ADJ_ACC
+    const double inv = 1.0 / m.rho;
+    const double vx = m.ux - 0.5 * a.gx, vy = m.uy - 0.5 * a.gy;  // (sum c f) / rho
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        const double dux = ((double)cx_of(q) - vx) * inv, duy = ((double)cy_of(q) - vy) * inv;
+        a.lam0[q * N + n] = (float)((1.0 - a.omega) * mu[q] + A + Bx * dux + By * duy);
+    }
+}
+
+// lam = d L / d f(n) from upstream gradients of the macroscopic fields of f(n):
+// lam_j = g_rho + g_u . (c_j - u + g/2) / rho (solids: 0).
+__global__ __launch_bounds__(256) void k_macro_vjp(const float* __restrict__ fpop,
+                                                   const uint8_t* __restrict__ mask, int N,
+                                                   double gx, double gy,
+                                                   const float* __restrict__ grho,
+                                                   const float* __restrict__ gux,
+                                                   const float* __restrict__ guy,
+                                                   float* __restrict__ lam) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const size_t NN = (size_t)N;
+    if (mask[n]) {
+        for (int q = 0; q < 9; ++q) lam[q * NN + n] = 0.0f;
+        return;
+    }
+    double rho = 0.0, jx = 0.0, jy = 0.0;
+    for (int q = 0; q < 9; ++q) {
+        const double v = fpop[q * NN + n];
+        rho += v;
+        jx += cx_of(q) * v;
+        jy += cy_of(q) * v;
+    }
+    const double vx = jx / rho, vy = jy / rho;
+    const double ar = grho[n], ax = gux[n], ay = guy[n];
+    (void)gx; (void)gy;  // u - g/2 = (sum c f)/rho: the half force cancels
+    for (int q = 0; q < 9; ++q)
+        lam[q * NN + n] = (float)(ar + (ax * (cx_of(q) - vx) + ay * (cy_of(q) - vy)) / rho);
+}
+
+// Pull-back through f(0) = f_eq(rho, u): g_rho = sum_q lam_q d f_eq_q / d rho,
+// g_u = sum_q lam_q d f_eq_q / d u (solids: 0).
+__global__ __launch_bounds__(256) void k_feq_vjp(const uint8_t* __restrict__ mask, int N,
+                                                 const float* __restrict__ rho,
+                                                 const float* __restrict__ ux,
+                                                 const float* __restrict__ uy,
+                                                 const float* __restrict__ lam,
+                                                 float* __restrict__ grho, float* __restrict__ gux,
+                                                 float* __restrict__ guy) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    if (mask[n]) { grho[n] = 0.0f; gux[n] = 0.0f; guy[n] = 0.0f; return; }
+    const size_t NN = (size_t)N;
+    const double r = rho[n], u = ux[n], v = uy[n];
+    const double usq = fma(u, u, v * v);
+    double a = 0.0, bx = 0.0, by = 0.0;
+    for (int q = 0; q < 9; ++q) {
+        const double l = lam[q * NN + n];
+        const double cu = cx_of(q) * u + cy_of(q) * v;
+        const double wq = w_of_d(q);
+        a = fma(l, wq * (1.0 + fma(cu, fma(4.5, cu, 3.0), -1.5 * usq)), a);
+        const double k = wq * r * fma(9.0, cu, 3.0);
+        bx = fma(l, cx_of(q) * k - 3.0 * wq * r * u, bx);
+        by = fma(l, cy_of(q) * k - 3.0 * wq * r * v, by);
+    }
+    grho[n] = (float)a;
+    gux[n] = (float)bx;
+    guy[n] = (float)by;
+}
+
+}  // namespace lbmfno
+
+using namespace lbmfno;
+
+extern "C" int lbm_adjoint_step(lbm_ctx* c, const float* d_f_n, const float* d_lam_np1,
+                                float* d_lam_n) {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (!d_f_n || !d_lam_np1 || !d_lam_n) return fail(LBM_EINVAL, "NULL buffer");
+    if (d_lam_np1 == d_lam_n) return fail(LBM_EINVAL, "lam_{n+1} and lam_n must differ");
+    if (c->cfg.bc_x == LBM_BC_ZOUHE)
+        return fail(LBM_EUNSUPPORTED, "adjoint of Zou-He columns is not implemented");
+    AdjArgs a;
+    a.f = d_f_n;
+    a.lam1 = d_lam_np1;
+    a.lam0 = d_lam_n;
+    a.link = c->d_link;
+    a.mask = c->d_mask;
+    a.g = c->g;
+    a.omega = 1.0 / c->cfg.tau;
+    a.guo = 1.0 - 0.5 / c->cfg.tau;
+    a.gx = c->cfg.gx;
+    a.gy = c->cfg.gy;
+    dim3 blk(TX, TY), grd(c->nblocks);
+    if (a.gx != 0.0 || a.gy != 0.0) k_adjoint_step<true><<<grd, blk, 0, c->stream>>>(a);
+    else k_adjoint_step<false><<<grd, blk, 0, c->stream>>>(a);
+    LBM_HIP(hipGetLastError());
+    return LBM_OK;
+}
+
+extern "C" int lbm_macro_vjp(lbm_ctx* c, const float* d_f_n, const float* d_g_rho,
+                             const float* d_g_ux, const float* d_g_uy, float* d_lam) {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (!d_f_n || !d_g_rho || !d_g_ux || !d_g_uy || !d_lam) return fail(LBM_EINVAL, "NULL buffer");
+    const int N = c->g.N;
+    k_macro_vjp<<<(N + 255) / 256, 256, 0, c->stream>>>(d_f_n, c->d_mask, N, c->cfg.gx, c->cfg.gy,
+                                                        d_g_rho, d_g_ux, d_g_uy, d_lam);
+    LBM_HIP(hipGetLastError());
+    return LBM_OK;
+}
+
+extern "C" int lbm_feq_vjp(lbm_ctx* c, const float* d_rho, const float* d_ux, const float* d_uy,
+                           const float* d_lam, float* d_g_rho, float* d_g_ux, float* d_g_uy) {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (!d_rho || !d_ux || !d_uy || !d_lam || !d_g_rho || !d_g_ux || !d_g_uy)
+        return fail(LBM_EINVAL, "NULL buffer");
+    const int N = c->g.N;
+    k_feq_vjp<<<(N + 255) / 256, 256, 0, c->stream>>>(c->d_mask, N, d_rho, d_ux, d_uy, d_lam,
+                                                      d_g_rho, d_g_ux, d_g_uy);
+    LBM_HIP(hipGetLastError());
+    return LBM_OK;
+}
+
+extern "C" size_t lbm_state_elems(const lbm_ctx* c) { return c ? 9 * (size_t)c->g.N : 0; }
+
+extern "C" int lbm_save_state(lbm_ctx* c, float* d_out) {
+    if (!c || !d_out) return fail(LBM_EINVAL, "NULL argument");
+    LBM_HIP(hipMemcpyAsync(d_out, c->f[c->cur], 9 * (size_t)c->g.N * sizeof(float),
+                           hipMemcpyDeviceToDevice, c->stream));
+    return LBM_OK;
+}
+
+extern "C" int lbm_load_state(lbm_ctx* c, const float* d_in) {
+    if (!c || !d_in) return fail(LBM_EINVAL, "NULL argument");
+    LBM_HIP(hipMemcpyAsync(c->f[c->cur], d_in, 9 * (size_t)c->g.N * sizeof(float),
+                           hipMemcpyDeviceToDevice, c->stream));
+    return LBM_OK;
+}

@@ -86,6 +86,12 @@ SIGNATURES = [
     ("lbm_info", ctypes.c_int, [_p, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     ("lbm_stream_copy", ctypes.c_int, [_p, _p, ctypes.c_size_t, _p]),
     ("lbm_check_fields", ctypes.c_int, [_p, _p, _p, _p, ctypes.POINTER(FieldStats)]),
+    ("lbm_adjoint_step", ctypes.c_int, [_p, _p, _p, _p]),
+    ("lbm_state_elems", ctypes.c_size_t, [_p]),
+    ("lbm_save_state", ctypes.c_int, [_p, _p]),
+    ("lbm_load_state", ctypes.c_int, [_p, _p]),
+    ("lbm_macro_vjp", ctypes.c_int, [_p, _p, _p, _p, _p, _p]),
+    ("lbm_feq_vjp", ctypes.c_int, [_p, _p, _p, _p, _p, _p, _p, _p]),
     ("lbm_batch_create", ctypes.c_int, [ctypes.POINTER(_p), ctypes.POINTER(TrajDesc), _i32,
                                         ctypes.c_char_p, _p]),
     ("lbm_batch_step", ctypes.c_int, [_p, _i32]),
@@ -273,6 +279,54 @@ class Lattice:
         check(self.lib.lbm_check_fields(self.ctx, rho.data_ptr(), ux.data_ptr(), uy.data_ptr(),
                                         ctypes.byref(st)), "lbm_check_fields")
         return st.as_dict()
+
+    def save_state(self):
+        """Exact copy of the current store (a device tensor)."""
+        import torch
+        with torch.cuda.stream(self.stream):
+            out = torch.empty(int(self.lib.lbm_state_elems(self.ctx)), dtype=torch.float32, device="cuda")
+        check(self.lib.lbm_save_state(self.ctx, out.data_ptr()), "lbm_save_state")
+        return out
+
+    def load_state(self, saved):
+        self._after_caller()
+        self._keep_state = saved
+        check(self.lib.lbm_load_state(self.ctx, saved.data_ptr()), "lbm_load_state")
+
+    def adjoint_step(self, f_n, lam_np1, out=None):
+        """lam_n = C'(f(n))^T P^T lam_{n+1} (float32 [9][ny][nx] device tensors)."""
+        import torch
+        self._after_caller()
+        if out is None:
+            with torch.cuda.stream(self.stream):
+                out = torch.empty_like(lam_np1)
+        check(self.lib.lbm_adjoint_step(self.ctx, f_n.data_ptr(), lam_np1.data_ptr(), out.data_ptr()),
+              "lbm_adjoint_step")
+        self._before_caller()
+        return out
+
+    def macro_vjp(self, f_n, g_rho, g_ux, g_uy):
+        import torch
+        self._after_caller()
+        with torch.cuda.stream(self.stream):
+            lam = torch.empty_like(f_n)
+            g = [t.to(device="cuda", dtype=torch.float32).contiguous() for t in (g_rho, g_ux, g_uy)]
+        check(self.lib.lbm_macro_vjp(self.ctx, f_n.data_ptr(), g[0].data_ptr(), g[1].data_ptr(),
+                                     g[2].data_ptr(), lam.data_ptr()), "lbm_macro_vjp")
+        self._before_caller()
+        return lam
+
+    def feq_vjp(self, rho, ux, uy, lam):
+        import torch
+        self._after_caller()
+        with torch.cuda.stream(self.stream):
+            fields = [t.to(device="cuda", dtype=torch.float32).contiguous() for t in (rho, ux, uy)]
+            out = torch.empty((3, self.ny, self.nx), dtype=torch.float32, device="cuda")
+        check(self.lib.lbm_feq_vjp(self.ctx, fields[0].data_ptr(), fields[1].data_ptr(),
+                                   fields[2].data_ptr(), lam.data_ptr(), out[0].data_ptr(),
+                                   out[1].data_ptr(), out[2].data_ptr()), "lbm_feq_vjp")
+        self._before_caller()
+        return out
 
     def info(self):
         fl, st = _i64(), _i64()
