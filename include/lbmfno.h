@@ -304,6 +304,57 @@ int fno_workspace_size(const fno_model* m, int32_t B, size_t* bytes);
 int fno_forward(const fno_model* m, const float* d_in, float* d_out, int32_t B, void* d_ws,
                 size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------- FNO training
+ * Training of the surrogate on lattice-generated samples (Sec. 2.2: FNO models
+ * trained by minimising the mean squared error of the predicted fields, AdamW).
+ * The gradient is the exact backward pass of the forward composition above with
+ * every bfloat16 rounding treated as the identity (straight-through); backward
+ * contractions use the same BF16-operand / FP32-accumulation policy, weight
+ * gradients are reduced in FP32 partials summed in FP64 in a fixed order
+ * (deterministic run to run). */
+
+/* Device workspace bytes fno_forward_train / fno_backward need for a batch of B
+ * (activations saved by the forward for the backward, plus backward scratch).
+ * LBM_EUNSUPPORTED for more than 32 Fourier layers. */
+int fno_train_workspace_size(const fno_model* m, int32_t B, size_t* bytes);
+
+/* fno_forward that also saves, in d_ws, what fno_backward reads.  d_ws (256-byte
+ * aligned, >= fno_train_workspace_size bytes) must then be passed unchanged to
+ * fno_backward with the same d_in and B.  Asynchronous on `stream`. */
+int fno_forward_train(const fno_model* m, const float* d_in, float* d_out, int32_t B,
+                      void* d_ws, size_t ws_bytes, void* stream);
+
+/* Gradient of a scalar loss w.r.t. the packed parameters (layout above):
+ * d_dout[B][cout][H][W] = dLoss/d out (float32, device); writes every element of
+ * d_grad[fno_param_count] (float32, device; overwritten, not accumulated).
+ * Uses the activations the last fno_forward_train saved in d_ws (and overwrites
+ * its backward scratch).  Asynchronous on `stream`. */
+int fno_backward(const fno_model* m, const float* d_in, const float* d_dout, int32_t B,
+                 void* d_ws, size_t ws_bytes, float* d_grad, void* stream);
+
+/* Mean squared error of n float32 values: *h_loss = sum e^2 / n with
+ * e = out - tgt taken in float32, squares and sum in FP64 (fixed order);
+ * d_dout = 2 e / n (float32).  d_ws: device scratch of
+ * at least (ceil(n / 256) + 1) * 8 bytes.  Synchronises `stream` (returns the
+ * loss on the host). */
+int fno_mse(const float* d_out, const float* d_tgt, size_t n, float* d_dout, void* d_ws,
+            size_t ws_bytes, double* h_loss, void* stream);
+
+/* Refresh the model's device weights from packed float32 parameters on the device
+ * (d_params[fno_param_count]; converted exactly as fno_model_create converts host
+ * parameters: bf16 round-to-nearest-even for contraction weights, float32 for lift
+ * and biases).  Asynchronous on `stream`; forwards queued later on the same
+ * stream see the new weights. */
+int fno_set_params(fno_model* m, const float* d_params, void* stream);
+
+/* One AdamW step (decoupled weight decay) over n float32 device values:
+ *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;
+ *   p = p (1 - lr wd) - lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps).
+ * step >= 1 counts calls so far including this one.  Asynchronous on `stream`. */
+int fno_adamw(float* d_p, const float* d_g, float* d_m, float* d_v, int64_t n, double lr,
+              double beta1, double beta2, double eps, double weight_decay, int64_t step,
+              void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -77,8 +77,15 @@ struct FnoDev {
     const __bf16* decw;     // per decoder layer [DSP][in_p], then out [CoutP][DSP]
     const float* decb;      // per decoder layer [DSP], then out [cout]
     const __bf16 *EwT, *BinvT, *EcolA, *EcolB;
+    const __bf16* WcT;      // [L][CP][CP], WcT[i][o] = Wc[o][i] (backward)
+    const __bf16* B1;       // [Wpad][KKp] unit-coefficient inverse row basis (backward)
     // workspace
     __bf16 *v0, *v1, *T, *Z;
+    // training forward: saved activations (NULL in plain inference)
+    float* sv_a1;     // lift pre-activation [B][H][W][32]
+    float* sv_X;      // column-DFT coefficients of this layer [B][m2][R2][CP]
+    float* sv_pre;    // Fourier-layer pre-activation [B][Hp][Wpad][CP]
+    float* sv_dec;    // decoder pre-activations, per layer [B][H][W][DSP]
 };
 
 // ---------------------------------------------------------------- kernels
@@ -106,6 +113,7 @@ __global__ __launch_bounds__(256) void k_fno_lift(FnoDev d, const float* __restr
         for (int k = 0; k < d.half; ++k) {
             float s = d.lift1b[k];
             for (int c = 0; c < d.cl; ++c) s = fmaf(d.lift1w[k * d.cl + c], z[c], s);
+            if (d.sv_a1) d.sv_a1[(((size_t)b * d.H + h) * d.W + w) * 32 + k] = s;
             hid[k] = act_f(d.act, s);
         }
         for (int c = 0; c < d.width; ++c) {
@@ -187,8 +195,12 @@ __global__ __launch_bounds__(256) void k_fno_col(FnoDev d, int layer) {
         acc = mma_tile(d.EcolA + (size_t)mi * 32 * H2, H2, Ts + (size_t)ni * 32 * H2, H2, H2, acc);
         const int c = ni * 32 + acc_col();
 #pragma unroll
-        for (int r = 0; r < 16; ++r)
-            xs[(mi * 32 + acc_row(r)) * d.CP + c] = from_bf16(to_bf16(acc[r]));
+        for (int r = 0; r < 16; ++r) {
+            const float xv = from_bf16(to_bf16(acc[r]));
+            xs[(mi * 32 + acc_row(r)) * d.CP + c] = xv;
+            if (d.sv_X)
+                d.sv_X[(((size_t)b * d.m2 + k2) * d.R2 + mi * 32 + acc_row(r)) * d.CP + c] = xv;
+        }
     }
     for (int i = tid; i < d.CP * d.R2; i += blockDim.x) ys[i] = to_bf16(0.0f);
     __syncthreads();
@@ -259,6 +271,7 @@ __global__ __launch_bounds__(256) void k_fno_rowinv(FnoDev d, const __bf16* __re
         for (int r = 0; r < 16; ++r) {
             const int w = mi * 32 + acc_row(r);
             float val = acc[r] + bo;
+            if (d.sv_pre) d.sv_pre[rowoff + (size_t)w * d.CP + o] = w < d.Wp ? val : 0.0f;
             if (!last) val = act_f(d.act, val);
             if (w >= d.Wp) val = 0.0f;
             vout[rowoff + (size_t)w * d.CP + o] = to_bf16(val);
@@ -293,6 +306,7 @@ __global__ __launch_bounds__(256) void k_fno_dec(FnoDev d, const __bf16* __restr
 #pragma unroll
                 for (int i = 0; i < MAXD; ++i)
                     if (i < din) acc = fmaf(from_bf16(wp[s * din + i]), a[i], acc);
+                if (d.sv_dec) d.sv_dec[((size_t)l * total + idx) * d.DSP + s] = acc;
                 acc = from_bf16(to_bf16(act_f(d.dec_act, acc)));
                 if (s >= d.dec_size) acc = 0.0f;
             }
@@ -324,6 +338,11 @@ struct fno_model {
     FnoDev d;            // sizes and parameter pointers (workspace filled per call)
     std::vector<void*> allocs;
     int device;
+    int64_t nparams;
+    // device index maps: element j of a device weight array takes packed parameter
+    // map[j] (or 0 when map[j] < 0); used to refresh weights from device params
+    struct Map { void* dst; const int32_t* map; int64_t n; bool bf16; };
+    std::vector<Map> maps;
 };
 
 static int rup(int x, int m) { return (x + m - 1) / m * m; }
@@ -390,6 +409,86 @@ static int upload(fno_model* m, const std::vector<T>& h, const T** out) {
         if (e != hipSuccess) return fail(LBM_EHIP, "hipMemcpy: %s", hipGetErrorString(e));
     }
     *out = reinterpret_cast<const T*>(p);
+    return LBM_OK;
+}
+
+static int build_param_maps(fno_model* m, const FnoDev& d) {
+    const fno_spec& s = m->spec;
+    const int wd = s.width, CP = d.CP, half = d.half, cl = d.cl;
+    int64_t off = 0;
+    const int64_t o_l1w = off; off += (int64_t)half * cl;
+    const int64_t o_l1b = off; off += half;
+    const int64_t o_l2w = off; off += (int64_t)wd * half;
+    const int64_t o_l2b = off; off += wd;
+    std::vector<int32_t> l1w(half * cl), l1b(half), l2w(wd * half), l2b(wd);
+    for (int i = 0; i < half * cl; ++i) l1w[i] = (int32_t)(o_l1w + i);
+    for (int i = 0; i < half; ++i) l1b[i] = (int32_t)(o_l1b + i);
+    for (int i = 0; i < wd * half; ++i) l2w[i] = (int32_t)(o_l2w + i);
+    for (int i = 0; i < wd; ++i) l2b[i] = (int32_t)(o_l2b + i);
+    std::vector<int32_t> Rm((size_t)s.layers * s.m2 * d.K1 * CP * CP * 2, -1);
+    std::vector<int32_t> Wc((size_t)s.layers * CP * CP, -1), WcT((size_t)s.layers * CP * CP, -1);
+    std::vector<int32_t> bc((size_t)s.layers * CP, -1);
+    const int64_t blk = (int64_t)wd * wd * s.m1 * s.m2 * 2;
+    for (int l = 0; l < s.layers; ++l) {
+        const int64_t top = off, bot = off + blk;
+        off += 2 * blk;
+        for (int i = 0; i < wd; ++i)
+            for (int o = 0; o < wd; ++o)
+                for (int a = 0; a < s.m1; ++a)
+                    for (int k2 = 0; k2 < s.m2; ++k2)
+                        for (int ri = 0; ri < 2; ++ri) {
+                            const int64_t src = ((((int64_t)i * wd + o) * s.m1 + a) * s.m2 + k2) * 2 + ri;
+                            for (int hf = 0; hf < 2; ++hf) {
+                                const int k = hf * s.m1 + a;
+                                const size_t dst = (((((size_t)l * s.m2 + k2) * d.K1 + k) * CP + o) * CP + i) * 2 + ri;
+                                Rm[dst] = (int32_t)((hf ? bot : top) + src);
+                            }
+                        }
+        for (int o = 0; o < wd; ++o)
+            for (int i = 0; i < wd; ++i) {
+                Wc[((size_t)l * CP + o) * CP + i] = (int32_t)(off + o * wd + i);
+                WcT[((size_t)l * CP + i) * CP + o] = (int32_t)(off + o * wd + i);
+            }
+        off += (int64_t)wd * wd;
+        for (int o = 0; o < wd; ++o) bc[(size_t)l * CP + o] = (int32_t)(off + o);
+        off += wd;
+    }
+    std::vector<int32_t> decw, decb;
+    int din = wd, dinp = CP;
+    for (int l = 0; l < s.dec_layers; ++l) {
+        const size_t base = decw.size();
+        decw.resize(base + (size_t)d.DSP * dinp, -1);
+        for (int o = 0; o < s.dec_size; ++o)
+            for (int i = 0; i < din; ++i) decw[base + (size_t)o * dinp + i] = (int32_t)(off + o * din + i);
+        off += (int64_t)s.dec_size * din;
+        const size_t bb = decb.size();
+        decb.resize(bb + d.DSP, -1);
+        for (int o = 0; o < s.dec_size; ++o) decb[bb + o] = (int32_t)(off + o);
+        off += s.dec_size;
+        din = s.dec_size;
+        dinp = d.DSP;
+    }
+    {
+        const size_t base = decw.size();
+        decw.resize(base + (size_t)s.cout * dinp, -1);
+        for (int o = 0; o < s.cout; ++o)
+            for (int i = 0; i < din; ++i) decw[base + (size_t)o * dinp + i] = (int32_t)(off + o * din + i);
+        off += (int64_t)s.cout * din;
+        for (int o = 0; o < s.cout; ++o) decb.push_back((int32_t)(off + o));
+        off += s.cout;
+    }
+    m->nparams = off;
+    struct Item { const void* dst; std::vector<int32_t>* v; bool bf; };
+    Item items[] = {{d.lift1w, &l1w, false}, {d.lift1b, &l1b, false}, {d.lift2w, &l2w, false},
+                    {d.lift2b, &l2b, false}, {d.Rmix, &Rm, true}, {d.Wc, &Wc, true},
+                    {d.WcT, &WcT, true}, {d.bc, &bc, false}, {d.decw, &decw, true},
+                    {d.decb, &decb, false}};
+    for (const Item& it : items) {
+        const int32_t* dm = nullptr;
+        int rc = upload(m, *it.v, &dm);
+        if (rc) return rc;
+        m->maps.push_back({const_cast<void*>(it.dst), dm, (int64_t)it.v->size(), it.bf});
+    }
     return LBM_OK;
 }
 
@@ -470,6 +569,11 @@ extern "C" int fno_model_create(fno_model** out, const fno_spec* spec, const flo
         for (int o = 0; o < wd; ++o) bc[(size_t)l * CP + o] = p[o];
         p += wd;
     }
+    std::vector<uint16_t> WcT((size_t)s.layers * CP * CP, 0);
+    for (int l = 0; l < s.layers; ++l)
+        for (int o = 0; o < CP; ++o)
+            for (int i = 0; i < CP; ++i)
+                WcT[((size_t)l * CP + i) * CP + o] = Wc[((size_t)l * CP + o) * CP + i];
     std::vector<uint16_t> decw;
     std::vector<float> decb;
     int din = wd, dinp = CP;
@@ -497,7 +601,8 @@ extern "C" int fno_model_create(fno_model** out, const fno_spec* spec, const flo
     }
     // ---- DFT bases (angles reduced exactly in integers, values in double, RNE to bf16)
     const double two_pi = 6.283185307179586476925286766559;
-    std::vector<uint16_t> EwT((size_t)d.KKp * d.Wpad, 0), BinvT((size_t)d.Wpad * d.KKp, 0);
+    std::vector<uint16_t> EwT((size_t)d.KKp * d.Wpad, 0), BinvT((size_t)d.Wpad * d.KKp, 0),
+        B1((size_t)d.Wpad * d.KKp, 0);
     const double inv_hw = 1.0 / ((double)d.Hp * d.Wp);
     for (int k2 = 0; k2 < s.m2; ++k2)
         for (int w = 0; w < d.Wp; ++w) {
@@ -508,6 +613,8 @@ extern "C" int fno_model_create(fno_model** out, const fno_spec* spec, const flo
             const double ck = (k2 == 0 ? 1.0 : 2.0) * inv_hw;
             BinvT[(size_t)w * d.KKp + 2 * k2] = host_bf16(ck * c);
             BinvT[(size_t)w * d.KKp + 2 * k2 + 1] = host_bf16(-ck * sn);
+            B1[(size_t)w * d.KKp + 2 * k2] = host_bf16(c);
+            B1[(size_t)w * d.KKp + 2 * k2 + 1] = host_bf16(-sn);
         }
     const int H2 = 2 * d.Hpad;
     std::vector<uint16_t> EcolA((size_t)d.R2 * H2, 0), EcolB((size_t)H2 * d.R2, 0);
@@ -529,12 +636,12 @@ extern "C" int fno_model_create(fno_model** out, const fno_spec* spec, const flo
     }
     // ---- upload
     const float *f1, *f2, *f3, *f4, *f5, *f6;
-    const uint16_t *u1, *u2, *u3, *u4, *u5, *u6, *u7;
+    const uint16_t *u1, *u2, *u3, *u4, *u5, *u6, *u7, *u8, *u9;
     if ((rc = upload(m, l1w, &f1)) || (rc = upload(m, l1b, &f2)) || (rc = upload(m, l2w, &f3)) ||
         (rc = upload(m, l2b, &f4)) || (rc = upload(m, bc, &f5)) || (rc = upload(m, decb, &f6)) ||
         (rc = upload(m, Rmix, &u1)) || (rc = upload(m, Wc, &u2)) || (rc = upload(m, decw, &u3)) ||
         (rc = upload(m, EwT, &u4)) || (rc = upload(m, BinvT, &u5)) || (rc = upload(m, EcolA, &u6)) ||
-        (rc = upload(m, EcolB, &u7)))
+        (rc = upload(m, EcolB, &u7)) || (rc = upload(m, WcT, &u8)) || (rc = upload(m, B1, &u9)))
         return bail(rc);
     d.lift1w = f1; d.lift1b = f2; d.lift2w = f3; d.lift2b = f4; d.bc = f5; d.decb = f6;
     d.Rmix = reinterpret_cast<const __bf16*>(u1);
@@ -544,6 +651,10 @@ extern "C" int fno_model_create(fno_model** out, const fno_spec* spec, const flo
     d.BinvT = reinterpret_cast<const __bf16*>(u5);
     d.EcolA = reinterpret_cast<const __bf16*>(u6);
     d.EcolB = reinterpret_cast<const __bf16*>(u7);
+    d.WcT = reinterpret_cast<const __bf16*>(u8);
+    d.B1 = reinterpret_cast<const __bf16*>(u9);
+    int rc2 = build_param_maps(m, d);
+    if (rc2) return bail(rc2);
     m->d = d;
     *out = m;
     return LBM_OK;
@@ -603,6 +714,631 @@ extern "C" int fno_forward(const fno_model* m, const float* d_in, float* d_out, 
     const int maxd = std::max(d.CP, d.DSP);
     if (maxd <= 32) k_fno_dec<32><<<(unsigned)((nout + 255) / 256), 256, 0, st>>>(d, cur, d_out);
     else k_fno_dec<64><<<(unsigned)((nout + 255) / 256), 256, 0, st>>>(d, cur, d_out);
+    LBM_HIP(hipGetLastError());
+    return LBM_OK;
+}
+
+// ================================================================ training
+//
+// Backward pass of the FNO (reverse order of the forward), AdamW and the device
+// parameter refresh.  Spectral layer, with pre = s + Wc v + b, s = Re-inverse(R X),
+// X = DFT(v):
+//   dY = (c_k2 / (H'W')) DFT(dpre)              (c_0 = 1, c_k2>0 = 2)
+//   dX[i] = sum_o dY[o] conj(R[i][o]),  dR[i][o] = sum_b conj(X[i]) dY[o]
+//   dv = sum_k Re(dX e^{+i theta}) + Wc^T dpre  (unit-coefficient real inverse)
+// The transforms reuse the forward kernels (BF16 operands on MFMA, FP32
+// accumulation); pointwise backward and every weight-gradient reduction run in
+// FP32 with a fixed summation order (deterministic).
+
+namespace lbmfno {
+
+__device__ __forceinline__ float act_grad(int kind, float x) {
+    switch (kind) {
+        case FNO_ACT_GELU: {
+            const float cdf = 0.5f * (1.0f + erff(x * 0.70710678118654752f));
+            const float pdf = 0.39894228040143268f * expf(-0.5f * x * x);
+            return cdf + x * pdf;
+        }
+        case FNO_ACT_RELU: return x > 0.0f ? 1.0f : 0.0f;
+        case FNO_ACT_SILU: {
+            const float sg = 1.0f / (1.0f + expf(-x));
+            return sg * (1.0f + x * (1.0f - sg));
+        }
+        default: return 1.0f;
+    }
+}
+
+struct FnoBwd {
+    float* dv;         // [B][Hp][Wpad][CP] gradient w.r.t. the current layer's output
+    float* dpre;       // [B][Hp][Wpad][CP]
+    __bf16* dpre_bf;   // same, bf16 (transform / MFMA operand)
+    float* dY;         // [B][m2][R2][CP]
+    float* dec_in;     // [dec_layers + 1][P0][MAXD]
+    float* dec_da;     // [dec_layers][P0][DSP]
+    float* d_out_cl;   // [P0][8] output gradient, channels last
+    float* l_dv0;      // [P0][64]
+    float* l_h1;       // [P0][32]
+    float* l_da1;      // [P0][32]
+    float* l_z;        // [P0][8]
+    float* partials;   // reduction scratch
+    float* grad;       // packed gradient (float32, parameter layout)
+};
+
+__global__ __launch_bounds__(256) void k_fill_f32(float* __restrict__ p, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0f;
+}
+
+// d out = 2 (out - target) / n, and per-workgroup partial sums of (out - target)^2.
+__global__ __launch_bounds__(256) void k_fno_mse(const float* __restrict__ out,
+                                                 const float* __restrict__ tgt, size_t n,
+                                                 float* __restrict__ dout,
+                                                 double* __restrict__ partials) {
+    __shared__ double red[4];
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double e2 = 0.0;
+    if (i < n) {
+        const float e = out[i] - tgt[i];
+        dout[i] = 2.0f * e / (float)n;
+        e2 = (double)e * e;
+    }
+    for (int o = 32; o > 0; o >>= 1) e2 += __shfl_down(e2, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e2;
+    __syncthreads();
+    if (threadIdx.x == 0) partials[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+__global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ p, int n,
+                                                      double* __restrict__ out) {
+    __shared__ double red[4];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) s += p[i];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) *out = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+// Decoder backward for one output point; writes the reduction inputs and the
+// gradient w.r.t. the last latent layer (dv, channels last).
+template <int MAXD>
+__global__ __launch_bounds__(256) void k_fno_dec_bwd(FnoDev d, FnoBwd g, const __bf16* __restrict__ v,
+                                                     const float* __restrict__ dout) {
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t total = (size_t)d.B * d.H * d.W;
+    if (idx >= total) return;
+    const int w = (int)(idx % d.W);
+    const int h = (int)((idx / d.W) % d.H);
+    const int b = (int)(idx / ((size_t)d.W * d.H));
+    const size_t vpt = ((size_t)b * d.Hp + h) * d.Wpad + w;
+    float a[MAXD];
+#pragma unroll
+    for (int i = 0; i < MAXD; ++i) a[i] = i < d.CP ? from_bf16(v[vpt * d.CP + i]) : 0.0f;
+    // forward recomputation: layer inputs from the saved pre-activations
+    int din = d.CP;
+    const __bf16* wl[4];
+    const __bf16* wp = d.decw;
+    for (int l = 0; l < d.dec_layers; ++l) {
+        wl[l] = wp;
+        float* in = g.dec_in + ((size_t)l * total + idx) * MAXD;
+#pragma unroll
+        for (int i = 0; i < MAXD; ++i) in[i] = a[i];
+#pragma unroll
+        for (int s = 0; s < MAXD; ++s)
+            a[s] = s < d.dec_size ? from_bf16(to_bf16(act_f(d.dec_act, d.sv_dec[((size_t)l * total + idx) * d.DSP + s]))) : 0.0f;
+        wp += (size_t)d.DSP * din;
+        din = d.DSP;
+    }
+    {
+        float* in = g.dec_in + ((size_t)d.dec_layers * total + idx) * MAXD;
+#pragma unroll
+        for (int i = 0; i < MAXD; ++i) in[i] = a[i];
+    }
+    // output layer: dh = Wout^T dout
+    float go[8];
+    for (int o = 0; o < 8; ++o) {
+        go[o] = o < d.cout ? dout[(((size_t)b * d.cout + o) * d.H + h) * d.W + w] : 0.0f;
+        g.d_out_cl[idx * 8 + o] = go[o];
+    }
+    float dh[MAXD];
+#pragma unroll
+    for (int i = 0; i < MAXD; ++i) {
+        float s = 0.0f;
+        if (i < din)
+            for (int o = 0; o < d.cout; ++o) s = fmaf(go[o], from_bf16(wp[o * din + i]), s);
+        dh[i] = s;
+    }
+    for (int l = d.dec_layers - 1; l >= 0; --l) {
+        const int dinl = l == 0 ? d.CP : d.DSP;
+        float da[MAXD];
+#pragma unroll
+        for (int s = 0; s < MAXD; ++s) {
+            float v_ = 0.0f;
+            if (s < d.dec_size) v_ = dh[s] * act_grad(d.dec_act, d.sv_dec[((size_t)l * total + idx) * d.DSP + s]);
+            da[s] = v_;
+            if (s < d.DSP) g.dec_da[((size_t)l * total + idx) * d.DSP + s] = v_;
+        }
+#pragma unroll
+        for (int c = 0; c < MAXD; ++c) {
+            float s2 = 0.0f;
+            if (c < dinl)
+#pragma unroll
+                for (int s = 0; s < MAXD; ++s)
+                    if (s < d.dec_size) s2 = fmaf(da[s], from_bf16(wl[l][s * dinl + c]), s2);
+            dh[c] = s2;
+        }
+    }
+    for (int c = 0; c < d.CP; ++c) g.dv[vpt * d.CP + c] = c < d.width ? dh[c] : 0.0f;
+}
+
+// Deterministic outer-product reduction G[n][m] = sum_p A[p][n] X[p][m] (and, with
+// want_bias, bias[n] = sum_p A[p][n]) over P points: per-workgroup partials of a
+// 256-point chunk, then a fixed-order pass over the chunks.
+template <typename TX>
+__global__ __launch_bounds__(256) void k_outer_partial(const float* __restrict__ A, int lda,
+                                                       const TX* __restrict__ X, int ldx, size_t P,
+                                                       int N, int M, float* __restrict__ partials) {
+    const int M1 = M + 1;
+    const size_t p0 = (size_t)blockIdx.x * 256;
+    const size_t p1 = p0 + 256 < P ? p0 + 256 : P;
+    for (int t = threadIdx.x; t < N * M1; t += blockDim.x) {
+        const int n = t / M1, m = t % M1;
+        float acc = 0.0f;
+        for (size_t p = p0; p < p1; ++p) {
+            const float av = A[p * lda + n];
+            const float xv = m < M ? (float)X[p * ldx + m] : 1.0f;
+            acc = fmaf(av, xv, acc);
+        }
+        partials[(size_t)blockIdx.x * N * M1 + t] = acc;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_outer_final(const float* __restrict__ partials, int nchunks,
+                                                     int N, int M, float* __restrict__ gw,
+                                                     float* __restrict__ gb) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int M1 = M + 1;
+    if (t >= N * M1) return;
+    double s = 0.0;
+    for (int c = 0; c < nchunks; ++c) s += partials[(size_t)c * N * M1 + t];
+    const int n = t / M1, m = t % M1;
+    if (m < M) gw[n * M + m] = (float)s;
+    else if (gb) gb[n] = (float)s;
+}
+
+// dpre = dv * act'(pre) (identity for the last layer); zero outside w < W'.
+__global__ __launch_bounds__(256) void k_fno_act_bwd(FnoDev d, FnoBwd g, const float* __restrict__ pre,
+                                                     int last) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t total = (size_t)d.B * d.Hp * d.Wpad * d.CP;
+    if (i >= total) return;
+    const int w = (int)((i / d.CP) % d.Wpad);
+    float v = w < d.Wp ? g.dv[i] : 0.0f;
+    if (!last) v *= act_grad(d.act, pre[i]);
+    g.dpre[i] = v;
+    g.dpre_bf[i] = to_bf16(v);
+}
+
+// Backward column step for one (sample, k2): dY = scale * DFT_H(T), complex
+// mixing with conj(R), inverse column DFT of dX into Z.
+__global__ __launch_bounds__(256) void k_fno_col_bwd(FnoDev d, FnoBwd g, int layer) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    float* xs = reinterpret_cast<float*>(smem);
+    __bf16* ys = reinterpret_cast<__bf16*>(smem + sizeof(float) * d.R2 * d.CP);
+    const int b = blockIdx.x / d.m2, k2 = blockIdx.x % d.m2;
+    const int tid = threadIdx.x, wave = tid >> 6, nw = blockDim.x >> 6;
+    const int H2 = 2 * d.Hpad, Nt = d.CP / 32;
+    const float scale = (k2 == 0 ? 1.0f : 2.0f) / ((float)d.Hp * (float)d.Wp);
+    const __bf16* Ts = d.T + ((size_t)b * d.m2 + k2) * d.CP * H2;
+    for (int t = wave; t < (d.R2 / 32) * Nt; t += nw) {
+        const int mi = t / Nt, ni = t % Nt;
+        f32x16 acc = {};
+        acc = mma_tile(d.EcolA + (size_t)mi * 32 * H2, H2, Ts + (size_t)ni * 32 * H2, H2, H2, acc);
+        const int c = ni * 32 + acc_col();
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int row = mi * 32 + acc_row(r);
+            const float y = acc[r] * scale;
+            xs[row * d.CP + c] = y;
+            g.dY[(((size_t)b * d.m2 + k2) * d.R2 + row) * d.CP + c] = y;
+        }
+    }
+    for (int i = tid; i < d.CP * d.R2; i += blockDim.x) ys[i] = to_bf16(0.0f);
+    __syncthreads();
+    const __bf16* R = d.Rmix + ((size_t)layer * d.m2 + k2) * d.K1 * d.CP * d.CP * 2;
+    for (int idx = tid; idx < d.K1 * d.CP; idx += blockDim.x) {
+        const int k = idx / d.CP, i = idx % d.CP;
+        const float* yr = xs + k * d.CP;
+        const float* yi = xs + (d.K1 + k) * d.CP;
+        float sr = 0.0f, si = 0.0f;
+        for (int o = 0; o < d.CP; ++o) {
+            const __bf16* Rp = R + (((size_t)k * d.CP + o) * d.CP + i) * 2;
+            const float rr = from_bf16(Rp[0]), rim = from_bf16(Rp[1]);
+            sr = fmaf(yr[o], rr, sr);
+            sr = fmaf(yi[o], rim, sr);
+            si = fmaf(-yr[o], rim, si);
+            si = fmaf(yi[o], rr, si);
+        }
+        ys[i * d.R2 + k] = to_bf16(sr);
+        ys[i * d.R2 + d.K1 + k] = to_bf16(si);
+    }
+    __syncthreads();
+    for (int t = wave; t < (H2 / 32) * Nt; t += nw) {
+        const int mi = t / Nt, ni = t % Nt;
+        f32x16 acc = {};
+        acc = mma_tile(d.EcolB + (size_t)mi * 32 * d.R2, d.R2, ys + ni * 32 * d.R2, d.R2, d.R2, acc);
+        const int o = ni * 32 + acc_col();
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int q = mi * 32 + acc_row(r);
+            const int ri = q >= d.Hpad ? 1 : 0, h = q - ri * d.Hpad;
+            if (h < d.Hp)
+                d.Z[(((size_t)b * d.Hp + h) * d.CP + o) * d.KKp + 2 * k2 + ri] = to_bf16(acc[r]);
+        }
+    }
+    if (k2 == 0) {
+        const int padw = d.KKp - 2 * d.m2;
+        for (int i = tid; i < d.Hp * d.CP * padw; i += blockDim.x) {
+            const int p = i % padw, ho = i / padw;
+            d.Z[((size_t)b * d.Hp * d.CP + ho) * d.KKp + 2 * d.m2 + p] = to_bf16(0.0f);
+        }
+    }
+}
+
+// dv[w][i] = sum_kk B1[w][kk] Z[i][kk] + sum_o dpre[w][o] Wc[o][i], per (b, h) row.
+__global__ __launch_bounds__(256) void k_fno_rowinv_bwd(FnoDev d, FnoBwd g, int layer) {
+    const int b = blockIdx.x / d.Hp, h = blockIdx.x % d.Hp;
+    const int tid = threadIdx.x, wave = tid >> 6, nw = blockDim.x >> 6;
+    const size_t rowoff = ((size_t)b * d.Hp + h) * d.Wpad * d.CP;
+    const __bf16* Zrow = d.Z + ((size_t)b * d.Hp + h) * d.CP * d.KKp;
+    const __bf16* WcT = d.WcT + (size_t)layer * d.CP * d.CP;
+    const int Mt = d.Wpad / 32, Nt = d.CP / 32;
+    for (int t = wave; t < Mt * Nt; t += nw) {
+        const int mi = t / Nt, ni = t % Nt;
+        f32x16 acc = {};
+        acc = mma_tile(d.B1 + (size_t)mi * 32 * d.KKp, d.KKp, Zrow + (size_t)ni * 32 * d.KKp, d.KKp,
+                       d.KKp, acc);
+        acc = mma_tile(g.dpre_bf + rowoff + (size_t)mi * 32 * d.CP, d.CP, WcT + (size_t)ni * 32 * d.CP,
+                       d.CP, d.CP, acc);
+        const int i = ni * 32 + acc_col();
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int w = mi * 32 + acc_row(r);
+            g.dv[rowoff + (size_t)w * d.CP + i] = (w < d.Wp && i < d.width) ? acc[r] : 0.0f;
+        }
+    }
+}
+
+// dR of one layer into the packed gradient: thread per (k2, kept row k, o, i).
+__global__ __launch_bounds__(256) void k_fno_dR(FnoDev d, FnoBwd g, const float* __restrict__ X,
+                                                float* __restrict__ gtop, float* __restrict__ gbot) {
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int wd = d.width;
+    const size_t total = (size_t)d.m2 * d.K1 * wd * wd;
+    if (idx >= total) return;
+    const int i = (int)(idx % wd);
+    const int o = (int)((idx / wd) % wd);
+    const int k = (int)((idx / ((size_t)wd * wd)) % d.K1);
+    const int k2 = (int)(idx / ((size_t)wd * wd * d.K1));
+    double sr = 0.0, si = 0.0;
+    for (int b = 0; b < d.B; ++b) {
+        const size_t base = ((size_t)b * d.m2 + k2) * d.R2;
+        const double xr = X[(base + k) * d.CP + i], xi = X[(base + d.K1 + k) * d.CP + i];
+        const double yr = g.dY[(base + k) * d.CP + o], yi = g.dY[(base + d.K1 + k) * d.CP + o];
+        sr += xr * yr + xi * yi;
+        si += xr * yi - xi * yr;
+    }
+    const int a = k < d.m1 ? k : k - d.m1;
+    float* dst = k < d.m1 ? gtop : gbot;
+    const size_t off = ((((size_t)i * wd + o) * d.m1 + a) * d.m2 + k2) * 2;
+    dst[off] = (float)sr;
+    dst[off + 1] = (float)si;
+}
+
+// Lift backward for one input point: dh1 = P2^T dv0, da1 = dh1 act'(a1); writes
+// the reduction inputs (dv0, h1, da1, z).
+__global__ __launch_bounds__(256) void k_fno_lift_bwd(FnoDev d, FnoBwd g, const float* __restrict__ x) {
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t total = (size_t)d.B * d.H * d.W;
+    if (idx >= total) return;
+    const int w = (int)(idx % d.W);
+    const int h = (int)((idx / d.W) % d.H);
+    const int b = (int)(idx / ((size_t)d.W * d.H));
+    const size_t vpt = ((size_t)b * d.Hp + h) * d.Wpad + w;
+    float dv0[64];
+    for (int c = 0; c < d.width; ++c) {
+        dv0[c] = g.dv[vpt * d.CP + c];
+        g.l_dv0[idx * 64 + c] = dv0[c];
+    }
+    for (int k = 0; k < d.half; ++k) {
+        const float a1 = d.sv_a1[idx * 32 + k];
+        float s = 0.0f;
+        for (int c = 0; c < d.width; ++c) s = fmaf(dv0[c], d.lift2w[c * d.half + k], s);
+        g.l_h1[idx * 32 + k] = act_f(d.act, a1);
+        g.l_da1[idx * 32 + k] = s * act_grad(d.act, a1);
+    }
+    for (int c = 0; c < d.cin; ++c) g.l_z[idx * 8 + c] = x[(((size_t)b * d.cin + c) * d.H + h) * d.W + w];
+    if (d.coords) {
+        g.l_z[idx * 8 + d.cin] = d.W > 1 ? (float)w / (float)(d.W - 1) : 0.0f;
+        g.l_z[idx * 8 + d.cin + 1] = d.H > 1 ? (float)h / (float)(d.H - 1) : 0.0f;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_param_map(const float* __restrict__ params,
+                                                   const int32_t* __restrict__ map, int64_t n,
+                                                   void* __restrict__ dst, int bf) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int32_t src = map[j];
+    const float v = src >= 0 ? params[src] : 0.0f;
+    if (bf) reinterpret_cast<__bf16*>(dst)[j] = to_bf16(v);
+    else reinterpret_cast<float*>(dst)[j] = v;
+}
+
+__global__ __launch_bounds__(256) void k_adamw(float* __restrict__ p, const float* __restrict__ gr,
+                                               float* __restrict__ m, float* __restrict__ v, int64_t n,
+                                               float lr, float b1, float b2, float eps, float wd,
+                                               float c1, float c2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = gr[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    float pi = p[i] * (1.0f - lr * wd);
+    pi -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    p[i] = pi;
+}
+
+}  // namespace lbmfno
+
+// ------------------------------------------------------------ training host
+
+struct TrainLayout {
+    size_t v, pre, X, a1, dec, dv, dpre, dpre_bf, dY, dec_in, dec_da, dout, ldv0, lh1, lda1, lz,
+        partials, T, Z, total;
+    int maxd;
+    size_t P0, Pl;
+};
+
+static TrainLayout train_layout(const FnoDev& d, int B) {
+    auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+    TrainLayout t;
+    t.maxd = std::max(d.CP, d.DSP) <= 32 ? 32 : 64;
+    t.Pl = (size_t)B * d.Hp * d.Wpad;
+    t.P0 = (size_t)B * d.H * d.W;
+    const size_t lat = t.Pl * d.CP;
+    t.v = al(lat * 2);
+    t.pre = al(lat * 4);
+    t.X = al((size_t)B * d.m2 * d.R2 * d.CP * 4);
+    t.a1 = al(t.P0 * 32 * 4);
+    t.dec = al((size_t)std::max(d.dec_layers, 1) * t.P0 * std::max(d.DSP, 1) * 4);
+    t.dv = al(lat * 4);
+    t.dpre = al(lat * 4);
+    t.dpre_bf = al(lat * 2);
+    t.dY = t.X;
+    t.dec_in = al((size_t)(d.dec_layers + 1) * t.P0 * t.maxd * 4);
+    t.dec_da = al((size_t)std::max(d.dec_layers, 1) * t.P0 * std::max(d.DSP, 1) * 4);
+    t.dout = al(t.P0 * 8 * 4);
+    t.ldv0 = al(t.P0 * 64 * 4);
+    t.lh1 = al(t.P0 * 32 * 4);
+    t.lda1 = al(t.P0 * 32 * 4);
+    t.lz = al(t.P0 * 8 * 4);
+    const size_t chunks = (std::max(t.Pl, t.P0) + 255) / 256;
+    t.partials = al(chunks * 64 * 65 * 4 + 4096 * 8);
+    t.T = al((size_t)B * d.m2 * d.CP * 2 * d.Hpad * 2);
+    t.Z = al((size_t)B * d.Hp * d.CP * d.KKp * 2);
+    t.total = (d.L + 1) * t.v + d.L * t.pre + d.L * t.X + t.a1 + t.dec + t.dv + t.dpre + t.dpre_bf +
+              t.dY + t.dec_in + t.dec_da + t.dout + t.ldv0 + t.lh1 + t.lda1 + t.lz + t.partials +
+              t.T + t.Z;
+    return t;
+}
+
+struct TrainPtrs {
+    __bf16* v[33];
+    float* pre[32];
+    float* X[32];
+    float *a1, *dec;
+    FnoBwd g;
+    __bf16 *T, *Z;
+};
+
+static TrainPtrs train_ptrs(const FnoDev& d, const TrainLayout& t, void* ws) {
+    unsigned char* p = static_cast<unsigned char*>(ws);
+    TrainPtrs r{};
+    for (int l = 0; l <= d.L; ++l) { r.v[l] = reinterpret_cast<__bf16*>(p); p += t.v; }
+    for (int l = 0; l < d.L; ++l) { r.pre[l] = reinterpret_cast<float*>(p); p += t.pre; }
+    for (int l = 0; l < d.L; ++l) { r.X[l] = reinterpret_cast<float*>(p); p += t.X; }
+    r.a1 = reinterpret_cast<float*>(p); p += t.a1;
+    r.dec = reinterpret_cast<float*>(p); p += t.dec;
+    r.g.dv = reinterpret_cast<float*>(p); p += t.dv;
+    r.g.dpre = reinterpret_cast<float*>(p); p += t.dpre;
+    r.g.dpre_bf = reinterpret_cast<__bf16*>(p); p += t.dpre_bf;
+    r.g.dY = reinterpret_cast<float*>(p); p += t.dY;
+    r.g.dec_in = reinterpret_cast<float*>(p); p += t.dec_in;
+    r.g.dec_da = reinterpret_cast<float*>(p); p += t.dec_da;
+    r.g.d_out_cl = reinterpret_cast<float*>(p); p += t.dout;
+    r.g.l_dv0 = reinterpret_cast<float*>(p); p += t.ldv0;
+    r.g.l_h1 = reinterpret_cast<float*>(p); p += t.lh1;
+    r.g.l_da1 = reinterpret_cast<float*>(p); p += t.lda1;
+    r.g.l_z = reinterpret_cast<float*>(p); p += t.lz;
+    r.g.partials = reinterpret_cast<float*>(p); p += t.partials;
+    r.T = reinterpret_cast<__bf16*>(p); p += t.T;
+    r.Z = reinterpret_cast<__bf16*>(p); p += t.Z;
+    return r;
+}
+
+extern "C" int fno_train_workspace_size(const fno_model* m, int32_t B, size_t* bytes) {
+    if (!m || !bytes) return fail(LBM_EINVAL, "NULL argument");
+    if (B < 1) return fail(LBM_EINVAL, "B = %d", B);
+    if (m->d.L > 32) return fail(LBM_EUNSUPPORTED, "training supports up to 32 layers");
+    *bytes = train_layout(m->d, B).total;
+    return LBM_OK;
+}
+
+static int check_train_args(const fno_model* m, int32_t B, void* ws, size_t ws_bytes) {
+    if (!m) return fail(LBM_EINVAL, "model is NULL");
+    if (!ws) return fail(LBM_EINVAL, "workspace is NULL");
+    if (B < 1 || (int64_t)B * m->d.Hp * m->d.Wpad > ((int64_t)1 << 31) / 64) return fail(LBM_EINVAL, "B = %d", B);
+    if ((uintptr_t)ws % 256) return fail(LBM_EINVAL, "workspace not 256-byte aligned");
+    if (m->d.L > 32) return fail(LBM_EUNSUPPORTED, "training supports up to 32 layers");
+    const size_t need = train_layout(m->d, B).total;
+    if (ws_bytes < need) return fail(LBM_EINVAL, "training workspace %zu < %zu bytes", ws_bytes, need);
+    return LBM_OK;
+}
+
+extern "C" int fno_forward_train(const fno_model* m, const float* d_in, float* d_out, int32_t B,
+                                 void* d_ws, size_t ws_bytes, void* stream) {
+    int rc = check_train_args(m, B, d_ws, ws_bytes);
+    if (rc) return rc;
+    if (!d_in || !d_out) return fail(LBM_EINVAL, "NULL buffer");
+    FnoDev d = m->d;
+    d.B = B;
+    const TrainLayout t = train_layout(d, B);
+    TrainPtrs P = train_ptrs(d, t, d_ws);
+    hipStream_t st = (hipStream_t)stream;
+    d.T = P.T;
+    d.Z = P.Z;
+    d.v0 = P.v[0];
+    d.sv_a1 = P.a1;
+    k_fno_lift<<<(unsigned)((t.Pl + 255) / 256), 256, 0, st>>>(d, d_in);
+    d.sv_a1 = nullptr;
+    const size_t lds_row = (size_t)d.CP * d.Wpad * 2;
+    const size_t lds_col = (size_t)d.R2 * d.CP * 4 + (size_t)d.CP * d.R2 * 2;
+    for (int l = 0; l < d.L; ++l) {
+        k_fno_rowfwd<<<B * d.Hpad, 256, lds_row, st>>>(d, P.v[l]);
+        d.sv_X = P.X[l];
+        k_fno_col<<<B * d.m2, 256, lds_col, st>>>(d, l);
+        d.sv_X = nullptr;
+        d.sv_pre = P.pre[l];
+        k_fno_rowinv<<<B * d.Hp, 256, 0, st>>>(d, P.v[l], P.v[l + 1], l, l == d.L - 1);
+        d.sv_pre = nullptr;
+    }
+    d.sv_dec = P.dec;
+    const size_t nout = t.P0;
+    if (t.maxd == 32) k_fno_dec<32><<<(unsigned)((nout + 255) / 256), 256, 0, st>>>(d, P.v[d.L], d_out);
+    else k_fno_dec<64><<<(unsigned)((nout + 255) / 256), 256, 0, st>>>(d, P.v[d.L], d_out);
+    LBM_HIP(hipGetLastError());
+    return LBM_OK;
+}
+
+static void outer_reduce(hipStream_t st, float* partials, const float* A, int lda, const void* X,
+                         bool xbf, int ldx, size_t P, int N, int M, float* gw, float* gb) {
+    const unsigned chunks = (unsigned)((P + 255) / 256);
+    if (xbf)
+        k_outer_partial<__bf16><<<chunks, 256, 0, st>>>(A, lda, static_cast<const __bf16*>(X), ldx, P, N, M, partials);
+    else
+        k_outer_partial<float><<<chunks, 256, 0, st>>>(A, lda, static_cast<const float*>(X), ldx, P, N, M, partials);
+    const int n = N * (M + 1);
+    k_outer_final<<<(n + 255) / 256, 256, 0, st>>>(partials, (int)chunks, N, M, gw, gb);
+}
+
+extern "C" int fno_backward(const fno_model* m, const float* d_in, const float* d_dout, int32_t B,
+                            void* d_ws, size_t ws_bytes, float* d_grad, void* stream) {
+    int rc = check_train_args(m, B, d_ws, ws_bytes);
+    if (rc) return rc;
+    if (!d_in || !d_dout || !d_grad) return fail(LBM_EINVAL, "NULL buffer");
+    FnoDev d = m->d;
+    d.B = B;
+    const TrainLayout t = train_layout(d, B);
+    TrainPtrs P = train_ptrs(d, t, d_ws);
+    FnoBwd g = P.g;
+    g.grad = d_grad;
+    d.T = P.T;
+    d.Z = P.Z;
+    d.sv_dec = P.dec;
+    d.sv_a1 = P.a1;
+    hipStream_t st = (hipStream_t)stream;
+    const fno_spec& s = m->spec;
+    // packed offsets
+    const int wd = s.width, half = d.half, cl = d.cl;
+    const size_t o_l1w = 0, o_l1b = o_l1w + (size_t)half * cl, o_l2w = o_l1b + half,
+                 o_l2b = o_l2w + (size_t)wd * half, o_layers = o_l2b + wd;
+    const size_t blk = (size_t)wd * wd * s.m1 * s.m2 * 2, per_layer = 2 * blk + (size_t)wd * wd + wd;
+    size_t o_dec = o_layers + (size_t)s.layers * per_layer;
+    // decoder
+    const size_t lat = t.Pl * d.CP;
+    k_fill_f32<<<(unsigned)((lat + 255) / 256), 256, 0, st>>>(g.dv, lat);
+    if (t.maxd == 32) k_fno_dec_bwd<32><<<(unsigned)((t.P0 + 255) / 256), 256, 0, st>>>(d, g, P.v[d.L], d_dout);
+    else k_fno_dec_bwd<64><<<(unsigned)((t.P0 + 255) / 256), 256, 0, st>>>(d, g, P.v[d.L], d_dout);
+    {
+        size_t off = o_dec;
+        int din = wd;
+        std::vector<size_t> wofs, bofs;
+        std::vector<int> dins;
+        for (int l = 0; l < s.dec_layers; ++l) {
+            wofs.push_back(off); off += (size_t)s.dec_size * din;
+            bofs.push_back(off); off += s.dec_size;
+            dins.push_back(din);
+            din = s.dec_size;
+        }
+        const size_t ow = off, ob = off + (size_t)s.cout * din;
+        outer_reduce(st, g.partials, g.d_out_cl, 8, g.dec_in + (size_t)s.dec_layers * t.P0 * t.maxd, false,
+                     t.maxd, t.P0, s.cout, din, d_grad + ow, d_grad + ob);
+        for (int l = 0; l < s.dec_layers; ++l)
+            outer_reduce(st, g.partials, g.dec_da + (size_t)l * t.P0 * d.DSP, d.DSP,
+                         g.dec_in + (size_t)l * t.P0 * t.maxd, false, t.maxd, t.P0, s.dec_size, dins[l],
+                         d_grad + wofs[l], d_grad + bofs[l]);
+    }
+    // Fourier layers, last first
+    const size_t lds_row = (size_t)d.CP * d.Wpad * 2;
+    const size_t lds_col = (size_t)d.R2 * d.CP * 4 + (size_t)d.CP * d.R2 * 2;
+    for (int l = d.L - 1; l >= 0; --l) {
+        const size_t lo = o_layers + (size_t)l * per_layer;
+        k_fno_act_bwd<<<(unsigned)((lat + 255) / 256), 256, 0, st>>>(d, g, P.pre[l], l == d.L - 1);
+        outer_reduce(st, g.partials, g.dpre, d.CP, P.v[l], true, d.CP, t.Pl, wd, wd,
+                     d_grad + lo + 2 * blk, d_grad + lo + 2 * blk + (size_t)wd * wd);
+        k_fno_rowfwd<<<B * d.Hpad, 256, lds_row, st>>>(d, g.dpre_bf);
+        k_fno_col_bwd<<<B * d.m2, 256, lds_col, st>>>(d, g, l);
+        const size_t nR = (size_t)s.m2 * d.K1 * wd * wd;
+        k_fno_dR<<<(unsigned)((nR + 255) / 256), 256, 0, st>>>(d, g, P.X[l], d_grad + lo, d_grad + lo + blk);
+        k_fno_rowinv_bwd<<<B * d.Hp, 256, 0, st>>>(d, g, l);  // dv = dLoss / d v_l
+    }
+    // lift
+    k_fno_lift_bwd<<<(unsigned)((t.P0 + 255) / 256), 256, 0, st>>>(d, g, d_in);
+    outer_reduce(st, g.partials, g.l_dv0, 64, g.l_h1, false, 32, t.P0, wd, half, d_grad + o_l2w, d_grad + o_l2b);
+    outer_reduce(st, g.partials, g.l_da1, 32, g.l_z, false, 8, t.P0, half, cl, d_grad + o_l1w, d_grad + o_l1b);
+    LBM_HIP(hipGetLastError());
+    return LBM_OK;
+}
+
+extern "C" int fno_mse(const float* d_out, const float* d_tgt, size_t n, float* d_dout, void* d_ws,
+                       size_t ws_bytes, double* h_loss, void* stream) {
+    if (!d_out || !d_tgt || !d_dout || !d_ws || !h_loss) return fail(LBM_EINVAL, "NULL argument");
+    if (n == 0) return fail(LBM_EINVAL, "n = 0");
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    if (ws_bytes < ((size_t)nb + 1) * sizeof(double)) return fail(LBM_EINVAL, "workspace too small");
+    hipStream_t st = (hipStream_t)stream;
+    double* part = static_cast<double*>(d_ws);
+    k_fno_mse<<<nb, 256, 0, st>>>(d_out, d_tgt, n, d_dout, part);
+    k_sum_partials<<<1, 256, 0, st>>>(part, (int)nb, part + nb);
+    LBM_HIP(hipGetLastError());
+    LBM_HIP(hipMemcpyAsync(h_loss, part + nb, sizeof(double), hipMemcpyDeviceToHost, st));
+    LBM_HIP(hipStreamSynchronize(st));
+    *h_loss /= (double)n;
+    return LBM_OK;
+}
+
+extern "C" int fno_set_params(fno_model* m, const float* d_params, void* stream) {
+    if (!m || !d_params) return fail(LBM_EINVAL, "NULL argument");
+    hipStream_t st = (hipStream_t)stream;
+    for (const fno_model::Map& mp : m->maps)
+        k_param_map<<<(unsigned)((mp.n + 255) / 256), 256, 0, st>>>(d_params, mp.map, mp.n, mp.dst, mp.bf16 ? 1 : 0);
+    LBM_HIP(hipGetLastError());
+    return LBM_OK;
+}
+
+extern "C" int fno_adamw(float* d_p, const float* d_g, float* d_m, float* d_v, int64_t n, double lr,
+                         double beta1, double beta2, double eps, double weight_decay, int64_t step,
+                         void* stream) {
+    if (!d_p || !d_g || !d_m || !d_v) return fail(LBM_EINVAL, "NULL buffer");
+    if (n < 0 || step < 1 || !(lr >= 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1))
+        return fail(LBM_EINVAL, "AdamW arguments");
+    const float c1 = (float)(1.0 - std::pow(beta1, (double)step));
+    const float c2 = (float)(1.0 - std::pow(beta2, (double)step));
+    k_adamw<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(
+        d_p, d_g, d_m, d_v, n, (float)lr, (float)beta1, (float)beta2, (float)eps, (float)weight_decay, c1, c2);
     LBM_HIP(hipGetLastError());
     return LBM_OK;
 }

@@ -92,3 +92,108 @@ class Fno:
             self.close()
         except Exception:
             pass
+
+
+class Trainer:
+    """AdamW training of an Fno on device-resident samples: forward (saving
+    activations), MSE loss, backward, AdamW and the weight refresh all run in the
+    library's kernels on `stream` (argument marshalling only here)."""
+
+    def __init__(self, fno: Fno, params, lr: float = 1e-3, betas=(0.9, 0.999), eps: float = 1e-8,
+                 weight_decay: float = 1e-4, stream=None):
+        import torch
+        self.fno, self.lib = fno, fno.lib
+        self.stream = stream
+        self.p = torch.as_tensor(np.asarray(params, dtype=np.float32).ravel()).to("cuda")
+        n = param_count(fno.spec)
+        if self.p.numel() != n:
+            raise ValueError(f"expected {n} parameters, got {self.p.numel()}")
+        self.g = torch.zeros_like(self.p)
+        self.m = torch.zeros_like(self.p)
+        self.v = torch.zeros_like(self.p)
+        self.lr, self.betas, self.eps, self.wd = float(lr), betas, float(eps), float(weight_decay)
+        self.t = 0
+        self._ws = {}
+        self._mse_ws = None
+        self._dout = {}
+        _L.check(self.lib.fno_set_params(fno.model, self.p.data_ptr(), _L.stream_handle(stream)),
+                 "fno_set_params")
+
+    def workspace(self, B: int):
+        import torch
+        if B not in self._ws:
+            n = ctypes.c_size_t()
+            _L.check(self.lib.fno_train_workspace_size(self.fno.model, int(B), ctypes.byref(n)),
+                     "fno_train_workspace_size")
+            self._ws[B] = torch.empty(int(n.value), dtype=torch.uint8, device="cuda")
+        return self._ws[B]
+
+    def _check_x(self, x):
+        import torch
+        s = self.fno.spec
+        if x.dtype != torch.float32 or not x.is_cuda or not x.is_contiguous():
+            raise ValueError("x must be a contiguous float32 CUDA tensor")
+        if tuple(x.shape[1:]) != (s.cin, self.fno.H, self.fno.W):
+            raise ValueError(f"input shape {tuple(x.shape)}")
+
+    def forward(self, x, out=None):
+        import torch
+        self._check_x(x)
+        B = x.shape[0]
+        if out is None:
+            out = torch.empty((B, self.fno.spec.cout, self.fno.H, self.fno.W), dtype=torch.float32,
+                              device="cuda")
+        ws = self.workspace(B)
+        _L.check(self.lib.fno_forward_train(self.fno.model, x.data_ptr(), out.data_ptr(), int(B),
+                                            ws.data_ptr(), ws.numel(), _L.stream_handle(self.stream)),
+                 "fno_forward_train")
+        return out
+
+    def backward(self, x, dout):
+        """Gradient (into self.g) for the activations the last forward() saved."""
+        self._check_x(x)
+        B = x.shape[0]
+        ws = self.workspace(B)
+        _L.check(self.lib.fno_backward(self.fno.model, x.data_ptr(), dout.contiguous().data_ptr(),
+                                       int(B), ws.data_ptr(), ws.numel(), self.g.data_ptr(),
+                                       _L.stream_handle(self.stream)), "fno_backward")
+        return self.g
+
+    def mse(self, out, target):
+        """(loss, dLoss/dout) of the mean squared error."""
+        import torch
+        n = out.numel()
+        if target.shape != out.shape or target.dtype != torch.float32:
+            raise ValueError("target must match out (float32)")
+        nb = (n + 255) // 256 + 1
+        if self._mse_ws is None or self._mse_ws.numel() < nb:
+            self._mse_ws = torch.empty(nb, dtype=torch.float64, device="cuda")
+        key = tuple(out.shape)
+        if key not in self._dout:
+            self._dout[key] = torch.empty_like(out)
+        loss = ctypes.c_double()
+        _L.check(self.lib.fno_mse(out.data_ptr(), target.contiguous().data_ptr(), n,
+                                  self._dout[key].data_ptr(), self._mse_ws.data_ptr(),
+                                  self._mse_ws.numel() * 8, ctypes.byref(loss),
+                                  _L.stream_handle(self.stream)), "fno_mse")
+        return loss.value, self._dout[key]
+
+    def adamw(self):
+        self.t += 1
+        _L.check(self.lib.fno_adamw(self.p.data_ptr(), self.g.data_ptr(), self.m.data_ptr(),
+                                    self.v.data_ptr(), self.p.numel(), self.lr, self.betas[0],
+                                    self.betas[1], self.eps, self.wd, self.t,
+                                    _L.stream_handle(self.stream)), "fno_adamw")
+        _L.check(self.lib.fno_set_params(self.fno.model, self.p.data_ptr(),
+                                         _L.stream_handle(self.stream)), "fno_set_params")
+
+    def step(self, x, target):
+        """One optimisation step on a batch; returns the batch loss before the update."""
+        out = self.forward(x)
+        loss, dout = self.mse(out, target)
+        self.backward(x, dout)
+        self.adamw()
+        return loss
+
+    def params(self):
+        return self.p.detach().cpu().numpy().astype(np.float64)

@@ -104,6 +104,14 @@ SIGNATURES = [
     ("fno_model_destroy", None, [_p]),
     ("fno_workspace_size", ctypes.c_int, [_p, _i32, ctypes.POINTER(ctypes.c_size_t)]),
     ("fno_forward", ctypes.c_int, [_p, _p, _p, _i32, _p, ctypes.c_size_t, _p]),
+    ("fno_train_workspace_size", ctypes.c_int, [_p, _i32, ctypes.POINTER(ctypes.c_size_t)]),
+    ("fno_forward_train", ctypes.c_int, [_p, _p, _p, _i32, _p, ctypes.c_size_t, _p]),
+    ("fno_backward", ctypes.c_int, [_p, _p, _p, _i32, _p, ctypes.c_size_t, _p, _p]),
+    ("fno_mse", ctypes.c_int, [_p, _p, ctypes.c_size_t, _p, _p, ctypes.c_size_t,
+                               ctypes.POINTER(ctypes.c_double), _p]),
+    ("fno_set_params", ctypes.c_int, [_p, _p, _p]),
+    ("fno_adamw", ctypes.c_int, [_p, _p, _p, _p, _i64, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_double, ctypes.c_double, ctypes.c_double, _i64, _p]),
 ]
 
 
