@@ -164,6 +164,25 @@ typedef struct lbm_field_stats {
 int lbm_check_fields(lbm_ctx* ctx, const float* d_rho, const float* d_ux, const float* d_uy,
                      lbm_field_stats* out);
 
+/* Distance of macroscopic fields from a reference over the fluid nodes of ctx's
+ * mask (the convergence measures of the porous steady-state study, Sec. 3.1):
+ * relative L1 norms sum|a - ref| / sum|ref| of rho, ux and uy, and the pressure
+ * drop dp = c_s^2 (mean rho on column x = 0 - mean rho on column x = nx - 1) of
+ * both sets with its relative error.  A ratio with a zero denominator is 0 when
+ * the numerator is 0 and +Inf otherwise; dp is 0 when an end column has no fluid. */
+typedef struct lbm_field_error {
+    double rel_l1_rho, rel_l1_ux, rel_l1_uy;
+    double dp, dp_ref, rel_dp;
+} lbm_field_error;
+
+/* Compare float32 [ny][nx] device fields (d_drho = rho - 1, as lbm_get_macro
+ * writes with rho_minus_one = 1; velocities in lattice units) with reference
+ * fields of the same form.  FP64 sums in a fixed order (deterministic);
+ * synchronises ctx's stream. */
+int lbm_compare_fields(lbm_ctx* ctx, const float* d_drho, const float* d_ux, const float* d_uy,
+                       const float* d_drho_ref, const float* d_ux_ref, const float* d_uy_ref,
+                       lbm_field_error* out);
+
 /* Plain device-to-device copy of n float32 values (n a multiple of 4, 16-byte
  * aligned buffers) with 16-byte loads and stores: the achievable-bandwidth
  * reference against which the lattice kernels' traffic and counters are read.

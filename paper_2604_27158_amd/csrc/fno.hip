@@ -79,6 +79,8 @@ struct FnoDev {
     const __bf16 *EwT, *BinvT, *EcolA, *EcolB;
     const __bf16* WcT;      // [L][CP][CP], WcT[i][o] = Wc[o][i] (backward)
     const __bf16* B1;       // [Wpad][KKp] unit-coefficient inverse row basis (backward)
+    const __bf16* decwT;    // hidden decoder layers transposed, [din_p][DSP] each (backward)
+    int DKP;                // decoder LDS row stride (bf16 elements)
     // workspace
     __bf16 *v0, *v1, *T, *Z;
     // training forward: saved activations (NULL in plain inference)
@@ -100,35 +102,51 @@ __global__ __launch_bounds__(256) void k_fno_lift(FnoDev d, const float* __restr
     const int h = (int)((idx / d.Wpad) % d.Hp);
     const int b = (int)(idx / ((size_t)d.Wpad * d.Hp));
     __bf16* out = d.v0 + idx * d.CP;
-    float z[8];
-    float hid[32];
     float o[64];
-    const bool inside = h < d.H && w < d.W;
-    if (inside) {
-        for (int c = 0; c < d.cin; ++c) z[c] = x[(((size_t)b * d.cin + c) * d.H + h) * d.W + w];
+#pragma unroll
+    for (int c = 0; c < 64; ++c) o[c] = 0.0f;
+    if (h < d.H && w < d.W) {
+        float z[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) z[c] = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 6; ++c)
+            if (c < d.cin) z[c] = x[(((size_t)b * d.cin + c) * d.H + h) * d.W + w];
         if (d.coords) {
-            z[d.cin] = d.W > 1 ? (float)w / (float)(d.W - 1) : 0.0f;
-            z[d.cin + 1] = d.H > 1 ? (float)h / (float)(d.H - 1) : 0.0f;
+            const float xc = d.W > 1 ? (float)w / (float)(d.W - 1) : 0.0f;
+            const float yc = d.H > 1 ? (float)h / (float)(d.H - 1) : 0.0f;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                if (c == d.cin) z[c] = xc;
+                if (c == d.cin + 1) z[c] = yc;
+            }
         }
+        const size_t pt = ((size_t)b * d.H + h) * d.W + w;
+#pragma unroll
+        for (int c = 0; c < 64; ++c)
+            if (c < d.width) o[c] = d.lift2b[c];
         for (int k = 0; k < d.half; ++k) {
             float s = d.lift1b[k];
-            for (int c = 0; c < d.cl; ++c) s = fmaf(d.lift1w[k * d.cl + c], z[c], s);
-            if (d.sv_a1) d.sv_a1[(((size_t)b * d.H + h) * d.W + w) * 32 + k] = s;
-            hid[k] = act_f(d.act, s);
-        }
-        for (int c = 0; c < d.width; ++c) {
-            float s = d.lift2b[c];
-            for (int k = 0; k < d.half; ++k) s = fmaf(d.lift2w[c * d.half + k], hid[k], s);
-            o[c] = s;
+            const float* w1 = d.lift1w + (size_t)k * d.cl;
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                if (c < d.cl) s = fmaf(w1[c], z[c], s);
+            if (d.sv_a1) d.sv_a1[pt * 32 + k] = s;
+            const float hk = act_f(d.act, s);
+            // o[c] += W2[c][k] * hid[k], accumulated over k in order
+#pragma unroll
+            for (int c = 0; c < 64; ++c)
+                if (c < d.width) o[c] = fmaf(d.lift2w[(size_t)c * d.half + k], hk, o[c]);
         }
     }
-    for (int c0 = 0; c0 < d.CP; c0 += 8) {
-        bf16x8 t;
-        for (int e = 0; e < 8; ++e) {
-            const int c = c0 + e;
-            t[e] = to_bf16(inside && c < d.width ? o[c] : 0.0f);
+#pragma unroll
+    for (int c0 = 0; c0 < 64; c0 += 8) {
+        if (c0 < d.CP) {
+            bf16x8 t;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) t[e] = to_bf16(o[c0 + e]);
+            *reinterpret_cast<bf16x8*>(out + c0) = t;
         }
-        *reinterpret_cast<bf16x8*>(out + c0) = t;
     }
 }
 
@@ -279,51 +297,86 @@ __global__ __launch_bounds__(256) void k_fno_rowinv(FnoDev d, const __bf16* __re
     }
 }
 
-// Decoder: per output point, dec_layers hidden layers (bf16 operands, float32
-// sums, decoder activation, rounded to bf16) and the output layer (float32 out).
-template <int MAXD>
+// Decoder on MFMA.  Each wave takes 32 consecutive output points; a layer's input
+// (bf16, channels contiguous) sits in LDS and is multiplied by the layer's
+// [DSP][din_p] weights, both operands contiguous along the input channels; bias,
+// activation and the bf16 rounding run in the accumulator epilogue, which writes
+// the next layer's input back to LDS.  The output layer (cout <= 8 rows) is a
+// per-point dot product over the last LDS row (float32 out).
+constexpr int DEC_PTS = 32;
+
+__device__ __forceinline__ size_t dec_point_offset(const FnoDev& d, size_t pt) {
+    const size_t w = pt % d.W, h = (pt / d.W) % d.H, b = pt / ((size_t)d.W * d.H);
+    return (b * d.Hp + h) * d.Wpad + w;
+}
+
+__device__ __forceinline__ size_t dec_out_offset(const FnoDev& d, size_t pt, int o) {
+    const size_t hw = (size_t)d.H * d.W, b = pt / hw;
+    return (b * d.cout + o) * hw + pt % hw;
+}
+
+__device__ __forceinline__ void dec_stage_input(const FnoDev& d, const __bf16* __restrict__ v,
+                                                size_t pt0, size_t total, __bf16* buf, int lane) {
+    const int c8n = d.CP / 8;
+    for (int e = lane; e < DEC_PTS * c8n; e += 64) {
+        const int pp = e / c8n, c8 = e % c8n;
+        const size_t pt = pt0 + pp;
+        bf16x8 t;
+        if (pt < total) {
+            t = *reinterpret_cast<const bf16x8*>(v + dec_point_offset(d, pt) * d.CP + 8 * c8);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) t[k] = to_bf16(0.0f);
+        }
+        *reinterpret_cast<bf16x8*>(buf + pp * d.DKP + 8 * c8) = t;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_fno_dec(FnoDev d, const __bf16* __restrict__ v,
                                                  float* __restrict__ out) {
-    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int KP = d.DKP;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __bf16* bufA = reinterpret_cast<__bf16*>(smem) + (size_t)wave * 2 * DEC_PTS * KP;
+    __bf16* bufB = bufA + DEC_PTS * KP;
     const size_t total = (size_t)d.B * d.H * d.W;
-    if (idx >= total) return;
-    const int w = (int)(idx % d.W);
-    const int h = (int)((idx / d.W) % d.H);
-    const int b = (int)(idx / ((size_t)d.W * d.H));
-    const __bf16* vin = v + (((size_t)b * d.Hp + h) * d.Wpad + w) * d.CP;
-    float a[MAXD], c[MAXD];
-#pragma unroll
-    for (int i = 0; i < MAXD; ++i) a[i] = i < d.CP ? from_bf16(vin[i]) : 0.0f;
+    const size_t pt0 = ((size_t)blockIdx.x * 4 + wave) * DEC_PTS;
+    dec_stage_input(d, v, pt0, total, bufA, lane);
+    __syncthreads();
     int din = d.CP;
     const __bf16* wp = d.decw;
     const float* bp = d.decb;
     for (int l = 0; l < d.dec_layers; ++l) {
+        for (int nt = 0; nt < d.DSP / 32; ++nt) {
+            f32x16 acc = {};
+            acc = mma_tile(bufA, KP, wp + (size_t)nt * 32 * din, din, din, acc);
+            const int su = nt * 32 + acc_col();
+            const float bs = bp[su];
 #pragma unroll
-        for (int s = 0; s < MAXD; ++s) {
-            float acc = 0.0f;
-            if (s < d.DSP) {
-                acc = bp[s];
-#pragma unroll
-                for (int i = 0; i < MAXD; ++i)
-                    if (i < din) acc = fmaf(from_bf16(wp[s * din + i]), a[i], acc);
-                if (d.sv_dec) d.sv_dec[((size_t)l * total + idx) * d.DSP + s] = acc;
-                acc = from_bf16(to_bf16(act_f(d.dec_act, acc)));
-                if (s >= d.dec_size) acc = 0.0f;
+            for (int r = 0; r < 16; ++r) {
+                const int pp = acc_row(r);
+                const size_t pt = pt0 + pp;
+                const float val = acc[r] + bs;
+                if (d.sv_dec && pt < total) d.sv_dec[((size_t)l * total + pt) * d.DSP + su] = val;
+                const float a = su < d.dec_size ? act_f(d.dec_act, val) : 0.0f;
+                bufB[pp * KP + su] = to_bf16(a);
             }
-            c[s] = acc;
         }
-#pragma unroll
-        for (int i = 0; i < MAXD; ++i) a[i] = c[i];
+        __syncthreads();
+        __bf16* t = bufA; bufA = bufB; bufB = t;
         wp += (size_t)d.DSP * din;
         bp += d.DSP;
         din = d.DSP;
     }
-    for (int o = 0; o < d.cout; ++o) {
-        float acc = bp[o];
-#pragma unroll
-        for (int i = 0; i < MAXD; ++i)
-            if (i < din) acc = fmaf(from_bf16(wp[o * din + i]), a[i], acc);
-        out[(((size_t)b * d.cout + o) * d.H + h) * d.W + w] = acc;
+    const int pp = lane & 31;
+    const size_t pt = pt0 + pp;
+    if (pt < total) {
+        for (int o = lane >> 5; o < d.cout; o += 2) {
+            float acc = bp[o];
+            for (int i = 0; i < din; ++i)
+                acc = fmaf(from_bf16(wp[o * din + i]), from_bf16(bufA[pp * KP + i]), acc);
+            out[dec_out_offset(d, pt, o)] = acc;
+        }
     }
 }
 
@@ -346,6 +399,11 @@ struct fno_model {
 };
 
 static int rup(int x, int m) { return (x + m - 1) / m * m; }
+
+// dynamic LDS of the decoder kernels: 4 waves x (two bf16 rows of 32 points) or
+// (one bf16 + one float row of 32 points)
+static size_t dec_lds(const FnoDev& d) { return (size_t)4 * 2 * DEC_PTS * d.DKP * 2; }
+static size_t dec_bwd_lds(const FnoDev& d) { return (size_t)4 * DEC_PTS * d.DKP * (2 + 4); }
 
 static uint16_t host_bf16(double v) {
     float f = (float)v;
@@ -453,13 +511,18 @@ static int build_param_maps(fno_model* m, const FnoDev& d) {
         for (int o = 0; o < wd; ++o) bc[(size_t)l * CP + o] = (int32_t)(off + o);
         off += wd;
     }
-    std::vector<int32_t> decw, decb;
+    std::vector<int32_t> decw, decb, decwT;
     int din = wd, dinp = CP;
     for (int l = 0; l < s.dec_layers; ++l) {
         const size_t base = decw.size();
         decw.resize(base + (size_t)d.DSP * dinp, -1);
+        const size_t tb = decwT.size();
+        decwT.resize(tb + (size_t)dinp * d.DSP, -1);
         for (int o = 0; o < s.dec_size; ++o)
-            for (int i = 0; i < din; ++i) decw[base + (size_t)o * dinp + i] = (int32_t)(off + o * din + i);
+            for (int i = 0; i < din; ++i) {
+                decw[base + (size_t)o * dinp + i] = (int32_t)(off + o * din + i);
+                decwT[tb + (size_t)i * d.DSP + o] = (int32_t)(off + o * din + i);
+            }
         off += (int64_t)s.dec_size * din;
         const size_t bb = decb.size();
         decb.resize(bb + d.DSP, -1);
@@ -482,7 +545,7 @@ static int build_param_maps(fno_model* m, const FnoDev& d) {
     Item items[] = {{d.lift1w, &l1w, false}, {d.lift1b, &l1b, false}, {d.lift2w, &l2w, false},
                     {d.lift2b, &l2b, false}, {d.Rmix, &Rm, true}, {d.Wc, &Wc, true},
                     {d.WcT, &WcT, true}, {d.bc, &bc, false}, {d.decw, &decw, true},
-                    {d.decb, &decb, false}};
+                    {d.decb, &decb, false}, {d.decwT, &decwT, true}};
     for (const Item& it : items) {
         const int32_t* dm = nullptr;
         int rc = upload(m, *it.v, &dm);
@@ -524,6 +587,7 @@ extern "C" int fno_model_create(fno_model** out, const fno_spec* spec, const flo
     d.dec_layers = s.dec_layers;
     d.dec_size = s.dec_size;
     d.DSP = s.dec_layers > 0 ? rup(s.dec_size, 32) : 0;
+    d.DKP = std::max(d.CP, d.DSP) + 8;
     d.cout = s.cout;
     d.act = s.act; d.dec_act = s.dec_act;
     if ((size_t)d.CP * d.Wpad * 2 > 64 * 1024) return fail(LBM_EUNSUPPORTED, "row of %d x %d too large for LDS", d.Wpad, d.CP);
@@ -599,6 +663,20 @@ extern "C" int fno_model_create(fno_model** out, const fno_spec* spec, const flo
         for (int o = 0; o < s.cout; ++o) decb.push_back(p[o]);
         p += s.cout;
     }
+    // hidden decoder layers transposed: [din_p][DSP] per layer
+    std::vector<uint16_t> decwT;
+    {
+        size_t base = 0;
+        int dinp2 = CP;
+        for (int l = 0; l < s.dec_layers; ++l) {
+            const size_t tb = decwT.size();
+            decwT.resize(tb + (size_t)dinp2 * d.DSP, 0);
+            for (int o = 0; o < d.DSP; ++o)
+                for (int i = 0; i < dinp2; ++i) decwT[tb + (size_t)i * d.DSP + o] = decw[base + (size_t)o * dinp2 + i];
+            base += (size_t)d.DSP * dinp2;
+            dinp2 = d.DSP;
+        }
+    }
     // ---- DFT bases (angles reduced exactly in integers, values in double, RNE to bf16)
     const double two_pi = 6.283185307179586476925286766559;
     std::vector<uint16_t> EwT((size_t)d.KKp * d.Wpad, 0), BinvT((size_t)d.Wpad * d.KKp, 0),
@@ -636,12 +714,13 @@ extern "C" int fno_model_create(fno_model** out, const fno_spec* spec, const flo
     }
     // ---- upload
     const float *f1, *f2, *f3, *f4, *f5, *f6;
-    const uint16_t *u1, *u2, *u3, *u4, *u5, *u6, *u7, *u8, *u9;
+    const uint16_t *u1, *u2, *u3, *u4, *u5, *u6, *u7, *u8, *u9, *u10;
     if ((rc = upload(m, l1w, &f1)) || (rc = upload(m, l1b, &f2)) || (rc = upload(m, l2w, &f3)) ||
         (rc = upload(m, l2b, &f4)) || (rc = upload(m, bc, &f5)) || (rc = upload(m, decb, &f6)) ||
         (rc = upload(m, Rmix, &u1)) || (rc = upload(m, Wc, &u2)) || (rc = upload(m, decw, &u3)) ||
         (rc = upload(m, EwT, &u4)) || (rc = upload(m, BinvT, &u5)) || (rc = upload(m, EcolA, &u6)) ||
-        (rc = upload(m, EcolB, &u7)) || (rc = upload(m, WcT, &u8)) || (rc = upload(m, B1, &u9)))
+        (rc = upload(m, EcolB, &u7)) || (rc = upload(m, WcT, &u8)) || (rc = upload(m, B1, &u9)) ||
+        (rc = upload(m, decwT, &u10)))
         return bail(rc);
     d.lift1w = f1; d.lift1b = f2; d.lift2w = f3; d.lift2b = f4; d.bc = f5; d.decb = f6;
     d.Rmix = reinterpret_cast<const __bf16*>(u1);
@@ -653,6 +732,7 @@ extern "C" int fno_model_create(fno_model** out, const fno_spec* spec, const flo
     d.EcolB = reinterpret_cast<const __bf16*>(u7);
     d.WcT = reinterpret_cast<const __bf16*>(u8);
     d.B1 = reinterpret_cast<const __bf16*>(u9);
+    d.decwT = reinterpret_cast<const __bf16*>(u10);
     int rc2 = build_param_maps(m, d);
     if (rc2) return bail(rc2);
     m->d = d;
@@ -711,9 +791,7 @@ extern "C" int fno_forward(const fno_model* m, const float* d_in, float* d_out, 
         __bf16* t = cur; cur = nxt; nxt = t;
     }
     const size_t nout = (size_t)B * d.H * d.W;
-    const int maxd = std::max(d.CP, d.DSP);
-    if (maxd <= 32) k_fno_dec<32><<<(unsigned)((nout + 255) / 256), 256, 0, st>>>(d, cur, d_out);
-    else k_fno_dec<64><<<(unsigned)((nout + 255) / 256), 256, 0, st>>>(d, cur, d_out);
+    k_fno_dec<<<(unsigned)((nout + 4 * DEC_PTS - 1) / (4 * DEC_PTS)), 256, dec_lds(d), st>>>(d, cur, d_out);
     LBM_HIP(hipGetLastError());
     return LBM_OK;
 }
@@ -756,10 +834,10 @@ struct FnoBwd {
     float* dec_in;     // [dec_layers + 1][P0][MAXD]
     float* dec_da;     // [dec_layers][P0][DSP]
     float* d_out_cl;   // [P0][8] output gradient, channels last
-    float* l_dv0;      // [P0][64]
-    float* l_h1;       // [P0][32]
-    float* l_da1;      // [P0][32]
-    float* l_z;        // [P0][8]
+    float* l_dv0;      // [P0][width]
+    float* l_h1;       // [P0][width / 2]
+    float* l_da1;      // [P0][width / 2]
+    float* l_z;        // [P0][lift input channels]
     float* partials;   // reduction scratch
     float* grad;       // packed gradient (float32, parameter layout)
 };
@@ -799,111 +877,197 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__
     if (threadIdx.x == 0) *out = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
-// Decoder backward for one output point; writes the reduction inputs and the
-// gradient w.r.t. the last latent layer (dv, channels last).
-template <int MAXD>
+// Decoder backward, same tiling as the forward: the layer inputs are recomputed
+// from the saved pre-activations (written out as float for the weight gradients),
+// the output layer's transpose is a per-point sum over cout, and every hidden
+// layer's input gradient dh_prev = da * W_l is an MFMA product with the
+// transposed weights [din_p][DSP] (da rounded to bf16).  Writes dv (channels last).
 __global__ __launch_bounds__(256) void k_fno_dec_bwd(FnoDev d, FnoBwd g, const __bf16* __restrict__ v,
-                                                     const float* __restrict__ dout) {
-    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+                                                     const float* __restrict__ dout, int maxd) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int KP = d.DKP;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __bf16* buf = reinterpret_cast<__bf16*>(smem) + (size_t)wave * DEC_PTS * KP;
+    float* dh = reinterpret_cast<float*>(smem + (size_t)4 * DEC_PTS * KP * 2) + (size_t)wave * DEC_PTS * KP;
     const size_t total = (size_t)d.B * d.H * d.W;
-    if (idx >= total) return;
-    const int w = (int)(idx % d.W);
-    const int h = (int)((idx / d.W) % d.H);
-    const int b = (int)(idx / ((size_t)d.W * d.H));
-    const size_t vpt = ((size_t)b * d.Hp + h) * d.Wpad + w;
-    float a[MAXD];
-#pragma unroll
-    for (int i = 0; i < MAXD; ++i) a[i] = i < d.CP ? from_bf16(v[vpt * d.CP + i]) : 0.0f;
-    // forward recomputation: layer inputs from the saved pre-activations
-    int din = d.CP;
-    const __bf16* wl[4];
-    const __bf16* wp = d.decw;
-    for (int l = 0; l < d.dec_layers; ++l) {
-        wl[l] = wp;
-        float* in = g.dec_in + ((size_t)l * total + idx) * MAXD;
-#pragma unroll
-        for (int i = 0; i < MAXD; ++i) in[i] = a[i];
-#pragma unroll
-        for (int s = 0; s < MAXD; ++s)
-            a[s] = s < d.dec_size ? from_bf16(to_bf16(act_f(d.dec_act, d.sv_dec[((size_t)l * total + idx) * d.DSP + s]))) : 0.0f;
-        wp += (size_t)d.DSP * din;
-        din = d.DSP;
+    const size_t pt0 = ((size_t)blockIdx.x * 4 + wave) * DEC_PTS;
+    // layer inputs (float, row stride maxd) for the weight gradients
+    for (int e = lane; e < DEC_PTS * maxd; e += 64) {
+        const int pp = e / maxd, i = e % maxd;
+        const size_t pt = pt0 + pp;
+        if (pt >= total) continue;
+        g.dec_in[pt * maxd + i] = i < d.CP ? from_bf16(v[dec_point_offset(d, pt) * d.CP + i]) : 0.0f;
+        for (int l = 0; l < d.dec_layers; ++l) {
+            float a = 0.0f;
+            if (i < d.dec_size)
+                a = from_bf16(to_bf16(act_f(d.dec_act, d.sv_dec[((size_t)l * total + pt) * d.DSP + i])));
+            g.dec_in[((size_t)(l + 1) * total + pt) * maxd + i] = a;
+        }
     }
-    {
-        float* in = g.dec_in + ((size_t)d.dec_layers * total + idx) * MAXD;
-#pragma unroll
-        for (int i = 0; i < MAXD; ++i) in[i] = a[i];
+    // output layer: d out (channels last copy) and dh = Wout^T d out
+    const int dinL = d.dec_layers > 0 ? d.DSP : d.CP;
+    const __bf16* wout = d.decw + (d.dec_layers > 0 ? (size_t)d.DSP * d.CP +
+                                                          (size_t)(d.dec_layers - 1) * d.DSP * d.DSP : 0);
+    for (int e = lane; e < DEC_PTS * 8; e += 64) {
+        const int pp = e >> 3, o = e & 7;
+        const size_t pt = pt0 + pp;
+        if (pt < total) g.d_out_cl[pt * 8 + o] = o < d.cout ? dout[dec_out_offset(d, pt, o)] : 0.0f;
     }
-    // output layer: dh = Wout^T dout
-    float go[8];
-    for (int o = 0; o < 8; ++o) {
-        go[o] = o < d.cout ? dout[(((size_t)b * d.cout + o) * d.H + h) * d.W + w] : 0.0f;
-        g.d_out_cl[idx * 8 + o] = go[o];
+    for (int e = lane; e < DEC_PTS * dinL; e += 64) {
+        const int pp = e / dinL, i = e % dinL;
+        const size_t pt = pt0 + pp;
+        float t = 0.0f;
+        if (pt < total)
+            for (int o = 0; o < d.cout; ++o) t = fmaf(dout[dec_out_offset(d, pt, o)], from_bf16(wout[o * dinL + i]), t);
+        dh[pp * KP + i] = t;
     }
-    float dh[MAXD];
-#pragma unroll
-    for (int i = 0; i < MAXD; ++i) {
-        float s = 0.0f;
-        if (i < din)
-            for (int o = 0; o < d.cout; ++o) s = fmaf(go[o], from_bf16(wp[o * din + i]), s);
-        dh[i] = s;
-    }
+    __syncthreads();
     for (int l = d.dec_layers - 1; l >= 0; --l) {
+        for (int e = lane; e < DEC_PTS * d.DSP; e += 64) {
+            const int pp = e / d.DSP, su = e % d.DSP;
+            const size_t pt = pt0 + pp;
+            float da = 0.0f;
+            if (pt < total && su < d.dec_size)
+                da = dh[pp * KP + su] * act_grad(d.dec_act, d.sv_dec[((size_t)l * total + pt) * d.DSP + su]);
+            if (pt < total) g.dec_da[((size_t)l * total + pt) * d.DSP + su] = da;
+            buf[pp * KP + su] = to_bf16(da);
+        }
+        __syncthreads();
         const int dinl = l == 0 ? d.CP : d.DSP;
-        float da[MAXD];
+        const __bf16* wt = d.decwT + (l == 0 ? 0 : (size_t)d.CP * d.DSP + (size_t)(l - 1) * d.DSP * d.DSP);
+        for (int ct = 0; ct < dinl / 32; ++ct) {
+            f32x16 acc = {};
+            acc = mma_tile(buf, KP, wt + (size_t)ct * 32 * d.DSP, d.DSP, d.DSP, acc);
+            const int c = ct * 32 + acc_col();
 #pragma unroll
-        for (int s = 0; s < MAXD; ++s) {
-            float v_ = 0.0f;
-            if (s < d.dec_size) v_ = dh[s] * act_grad(d.dec_act, d.sv_dec[((size_t)l * total + idx) * d.DSP + s]);
-            da[s] = v_;
-            if (s < d.DSP) g.dec_da[((size_t)l * total + idx) * d.DSP + s] = v_;
+            for (int r = 0; r < 16; ++r) dh[acc_row(r) * KP + c] = acc[r];
         }
-#pragma unroll
-        for (int c = 0; c < MAXD; ++c) {
-            float s2 = 0.0f;
-            if (c < dinl)
-#pragma unroll
-                for (int s = 0; s < MAXD; ++s)
-                    if (s < d.dec_size) s2 = fmaf(da[s], from_bf16(wl[l][s * dinl + c]), s2);
-            dh[c] = s2;
-        }
+        __syncthreads();
     }
-    for (int c = 0; c < d.CP; ++c) g.dv[vpt * d.CP + c] = c < d.width ? dh[c] : 0.0f;
+    // dv of the last latent layer
+    for (int e = lane; e < DEC_PTS * d.CP; e += 64) {
+        const int pp = e / d.CP, c = e % d.CP;
+        const size_t pt = pt0 + pp;
+        if (pt < total) g.dv[dec_point_offset(d, pt) * d.CP + c] = c < d.width ? dh[pp * KP + c] : 0.0f;
+    }
 }
 
-// Deterministic outer-product reduction G[n][m] = sum_p A[p][n] X[p][m] (and, with
-// want_bias, bias[n] = sum_p A[p][n]) over P points: per-workgroup partials of a
-// 256-point chunk, then a fixed-order pass over the chunks.
+// Deterministic outer-product reduction G[n][m] = sum_p A[p][n] X[p][m] (and
+// bias[n] = sum_p A[p][n]) over P points, N, M <= 64.  Each workgroup takes a fixed
+// set of 64-point stages (grid-stride), staged through LDS as float; a thread owns
+// a 4 x 4 block of (n, m) and, when the tensor is narrow, the 256 threads form G
+// groups that take every G-th point of a stage.  Group sums are combined in a fixed
+// order, then one partial per workgroup is written; k_outer_final adds the
+// partials in FP64 in a fixed order.
+constexpr int OUT_TP = 64;
+constexpr int OUT_MAX_BLOCKS = 2048;
+
 template <typename TX>
 __global__ __launch_bounds__(256) void k_outer_partial(const float* __restrict__ A, int lda,
                                                        const TX* __restrict__ X, int ldx, size_t P,
                                                        int N, int M, float* __restrict__ partials) {
-    const int M1 = M + 1;
-    const size_t p0 = (size_t)blockIdx.x * 256;
-    const size_t p1 = p0 + 256 < P ? p0 + 256 : P;
-    for (int t = threadIdx.x; t < N * M1; t += blockDim.x) {
-        const int n = t / M1, m = t % M1;
-        float acc = 0.0f;
-        for (size_t p = p0; p < p1; ++p) {
-            const float av = A[p * lda + n];
-            const float xv = m < M ? (float)X[p * ldx + m] : 1.0f;
-            acc = fmaf(av, xv, acc);
+    __shared__ __align__(16) float As[OUT_TP][64];
+    __shared__ __align__(16) float Xs[OUT_TP][64];
+    const int tid = threadIdx.x;
+    const int tn = (N + 3) >> 2, tm = (M + 3) >> 2, T = tn * tm, G = 256 / T;
+    const int g = tid / T, r = tid % T, ty = r / tm, tx = r % tm;
+    const bool active = g < G;
+    float acc[4][4] = {};
+    float bacc[4] = {};
+    // columns >= N (M) stay zero; only the valid columns are loaded per stage
+    for (int i = tid; i < OUT_TP * 64; i += 256) {
+        As[i >> 6][i & 63] = 0.0f;
+        Xs[i >> 6][i & 63] = 0.0f;
+    }
+    const size_t nstage = (P + OUT_TP - 1) / OUT_TP;
+    for (size_t st = blockIdx.x; st < nstage; st += gridDim.x) {
+        const size_t p0 = st * OUT_TP;
+        __syncthreads();
+        for (int i = tid; i < OUT_TP * N; i += 256) {
+            const int pp = i / N, c = i - pp * N;
+            const size_t p = p0 + pp;
+            As[pp][c] = p < P ? A[p * lda + c] : 0.0f;
         }
-        partials[(size_t)blockIdx.x * N * M1 + t] = acc;
+        for (int i = tid; i < OUT_TP * M; i += 256) {
+            const int pp = i / M, c = i - pp * M;
+            const size_t p = p0 + pp;
+            Xs[pp][c] = p < P ? (float)X[p * ldx + c] : 0.0f;
+        }
+        __syncthreads();
+        if (active) {
+            for (int pp = g; pp < OUT_TP; pp += G) {
+                const float4 a = *reinterpret_cast<const float4*>(&As[pp][4 * ty]);
+                const float4 x = *reinterpret_cast<const float4*>(&Xs[pp][4 * tx]);
+                const float av[4] = {a.x, a.y, a.z, a.w}, xv[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(av[i], xv[j], acc[i][j]);
+                    bacc[i] += av[i];
+                }
+            }
+        }
+    }
+    // combine the G groups in a fixed order through LDS (reusing As / Xs: 2 x 16 KB)
+    __syncthreads();
+    float* red = &As[0][0];  // [G][T][16] <= 256 * 16 floats
+    float* bred = &Xs[0][0]; // [G][T][4]
+    if (active) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) red[((size_t)g * T + r) * 16 + i * 4 + j] = acc[i][j];
+            bred[((size_t)g * T + r) * 4 + i] = bacc[i];
+        }
+    }
+    __syncthreads();
+    const int M1 = M + 1;
+    float* out = partials + (size_t)blockIdx.x * N * M1;
+    for (int e = tid; e < N * M1; e += 256) {
+        const int n = e / M1, m = e % M1;
+        const int ry = n >> 2, i = n & 3;
+        float t = 0.0f;
+        if (m < M) {
+            const int rr = ry * tm + (m >> 2), j = m & 3;
+            for (int q = 0; q < G; ++q) t += red[((size_t)q * T + rr) * 16 + i * 4 + j];
+        } else {
+            const int rr = ry * tm;   // bias sums: the tx = 0 thread of row block ry
+            for (int q = 0; q < G; ++q) t += bred[((size_t)q * T + rr) * 4 + i];
+        }
+        out[e] = t;
     }
 }
 
+// Second pass: 64 outputs per workgroup, the four waves each sum a contiguous
+// quarter of the partials in FP64, combined in a fixed order.
 __global__ __launch_bounds__(256) void k_outer_final(const float* __restrict__ partials, int nchunks,
                                                      int N, int M, float* __restrict__ gw,
                                                      float* __restrict__ gb) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ double red[4][64];
     const int M1 = M + 1;
-    if (t >= N * M1) return;
-    double s = 0.0;
-    for (int c = 0; c < nchunks; ++c) s += partials[(size_t)c * N * M1 + t];
-    const int n = t / M1, m = t % M1;
-    if (m < M) gw[n * M + m] = (float)s;
-    else if (gb) gb[n] = (float)s;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int t = blockIdx.x * 64 + lane;
+    const int q0 = (nchunks * wave) / 4, q1 = (nchunks * (wave + 1)) / 4;
+    double s8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (t < N * M1) {
+        int c = q0;
+        for (; c + 8 <= q1; c += 8) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) s8[j] += partials[(size_t)(c + j) * N * M1 + t];
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            if (c + j < q1) s8[j] += partials[(size_t)(c + j) * N * M1 + t];
+    }
+    const double s = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
+    red[wave][lane] = s;
+    __syncthreads();
+    if (wave == 0 && t < N * M1) {
+        const double v = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+        const int n = t / M1, m = t % M1;
+        if (m < M) gw[n * M + m] = (float)v;
+        else if (gb) gb[n] = (float)v;
+    }
 }
 
 // dpre = dv * act'(pre) (identity for the last layer); zero outside w < W'.
@@ -1045,22 +1209,29 @@ __global__ __launch_bounds__(256) void k_fno_lift_bwd(FnoDev d, FnoBwd g, const 
     const int h = (int)((idx / d.W) % d.H);
     const int b = (int)(idx / ((size_t)d.W * d.H));
     const size_t vpt = ((size_t)b * d.Hp + h) * d.Wpad + w;
-    float dv0[64];
+    float s[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) s[k] = 0.0f;
     for (int c = 0; c < d.width; ++c) {
-        dv0[c] = g.dv[vpt * d.CP + c];
-        g.l_dv0[idx * 64 + c] = dv0[c];
+        const float dv = g.dv[vpt * d.CP + c];
+        g.l_dv0[idx * d.width + c] = dv;
+        const float* w2 = d.lift2w + (size_t)c * d.half;
+#pragma unroll
+        for (int k = 0; k < 32; ++k)
+            if (k < d.half) s[k] = fmaf(dv, w2[k], s[k]);
     }
-    for (int k = 0; k < d.half; ++k) {
-        const float a1 = d.sv_a1[idx * 32 + k];
-        float s = 0.0f;
-        for (int c = 0; c < d.width; ++c) s = fmaf(dv0[c], d.lift2w[c * d.half + k], s);
-        g.l_h1[idx * 32 + k] = act_f(d.act, a1);
-        g.l_da1[idx * 32 + k] = s * act_grad(d.act, a1);
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+        if (k < d.half) {
+            const float a1 = d.sv_a1[idx * 32 + k];
+            g.l_h1[idx * d.half + k] = act_f(d.act, a1);
+            g.l_da1[idx * d.half + k] = s[k] * act_grad(d.act, a1);
+        }
     }
-    for (int c = 0; c < d.cin; ++c) g.l_z[idx * 8 + c] = x[(((size_t)b * d.cin + c) * d.H + h) * d.W + w];
+    for (int c = 0; c < d.cin; ++c) g.l_z[idx * d.cl + c] = x[(((size_t)b * d.cin + c) * d.H + h) * d.W + w];
     if (d.coords) {
-        g.l_z[idx * 8 + d.cin] = d.W > 1 ? (float)w / (float)(d.W - 1) : 0.0f;
-        g.l_z[idx * 8 + d.cin + 1] = d.H > 1 ? (float)h / (float)(d.H - 1) : 0.0f;
+        g.l_z[idx * d.cl + d.cin] = d.W > 1 ? (float)w / (float)(d.W - 1) : 0.0f;
+        g.l_z[idx * d.cl + d.cin + 1] = d.H > 1 ? (float)h / (float)(d.H - 1) : 0.0f;
     }
 }
 
@@ -1125,8 +1296,7 @@ static TrainLayout train_layout(const FnoDev& d, int B) {
     t.lh1 = al(t.P0 * 32 * 4);
     t.lda1 = al(t.P0 * 32 * 4);
     t.lz = al(t.P0 * 8 * 4);
-    const size_t chunks = (std::max(t.Pl, t.P0) + 255) / 256;
-    t.partials = al(chunks * 64 * 65 * 4 + 4096 * 8);
+    t.partials = al((size_t)OUT_MAX_BLOCKS * 64 * 65 * 4 + 4096 * 8);
     t.T = al((size_t)B * d.m2 * d.CP * 2 * d.Hpad * 2);
     t.Z = al((size_t)B * d.Hp * d.CP * d.KKp * 2);
     t.total = (d.L + 1) * t.v + d.L * t.pre + d.L * t.X + t.a1 + t.dec + t.dv + t.dpre + t.dpre_bf +
@@ -1217,21 +1387,20 @@ extern "C" int fno_forward_train(const fno_model* m, const float* d_in, float* d
     }
     d.sv_dec = P.dec;
     const size_t nout = t.P0;
-    if (t.maxd == 32) k_fno_dec<32><<<(unsigned)((nout + 255) / 256), 256, 0, st>>>(d, P.v[d.L], d_out);
-    else k_fno_dec<64><<<(unsigned)((nout + 255) / 256), 256, 0, st>>>(d, P.v[d.L], d_out);
+    k_fno_dec<<<(unsigned)((nout + 4 * DEC_PTS - 1) / (4 * DEC_PTS)), 256, dec_lds(d), st>>>(d, P.v[d.L], d_out);
     LBM_HIP(hipGetLastError());
     return LBM_OK;
 }
 
 static void outer_reduce(hipStream_t st, float* partials, const float* A, int lda, const void* X,
                          bool xbf, int ldx, size_t P, int N, int M, float* gw, float* gb) {
-    const unsigned chunks = (unsigned)((P + 255) / 256);
+    const unsigned chunks = (unsigned)std::min<size_t>((P + OUT_TP - 1) / OUT_TP, OUT_MAX_BLOCKS);
     if (xbf)
         k_outer_partial<__bf16><<<chunks, 256, 0, st>>>(A, lda, static_cast<const __bf16*>(X), ldx, P, N, M, partials);
     else
         k_outer_partial<float><<<chunks, 256, 0, st>>>(A, lda, static_cast<const float*>(X), ldx, P, N, M, partials);
     const int n = N * (M + 1);
-    k_outer_final<<<(n + 255) / 256, 256, 0, st>>>(partials, (int)chunks, N, M, gw, gb);
+    k_outer_final<<<(n + 63) / 64, 256, 0, st>>>(partials, (int)chunks, N, M, gw, gb);
 }
 
 extern "C" int fno_backward(const fno_model* m, const float* d_in, const float* d_dout, int32_t B,
@@ -1260,8 +1429,8 @@ extern "C" int fno_backward(const fno_model* m, const float* d_in, const float* 
     // decoder
     const size_t lat = t.Pl * d.CP;
     k_fill_f32<<<(unsigned)((lat + 255) / 256), 256, 0, st>>>(g.dv, lat);
-    if (t.maxd == 32) k_fno_dec_bwd<32><<<(unsigned)((t.P0 + 255) / 256), 256, 0, st>>>(d, g, P.v[d.L], d_dout);
-    else k_fno_dec_bwd<64><<<(unsigned)((t.P0 + 255) / 256), 256, 0, st>>>(d, g, P.v[d.L], d_dout);
+    k_fno_dec_bwd<<<(unsigned)((t.P0 + 4 * DEC_PTS - 1) / (4 * DEC_PTS)), 256, dec_bwd_lds(d), st>>>(
+        d, g, P.v[d.L], d_dout, t.maxd);
     {
         size_t off = o_dec;
         int din = wd;
@@ -1297,8 +1466,8 @@ extern "C" int fno_backward(const fno_model* m, const float* d_in, const float* 
     }
     // lift
     k_fno_lift_bwd<<<(unsigned)((t.P0 + 255) / 256), 256, 0, st>>>(d, g, d_in);
-    outer_reduce(st, g.partials, g.l_dv0, 64, g.l_h1, false, 32, t.P0, wd, half, d_grad + o_l2w, d_grad + o_l2b);
-    outer_reduce(st, g.partials, g.l_da1, 32, g.l_z, false, 8, t.P0, half, cl, d_grad + o_l1w, d_grad + o_l1b);
+    outer_reduce(st, g.partials, g.l_dv0, wd, g.l_h1, false, half, t.P0, wd, half, d_grad + o_l2w, d_grad + o_l2b);
+    outer_reduce(st, g.partials, g.l_da1, half, g.l_z, false, cl, t.P0, half, cl, d_grad + o_l1w, d_grad + o_l1b);
     LBM_HIP(hipGetLastError());
     return LBM_OK;
 }
@@ -1324,7 +1493,8 @@ extern "C" int fno_set_params(fno_model* m, const float* d_params, void* stream)
     if (!m || !d_params) return fail(LBM_EINVAL, "NULL argument");
     hipStream_t st = (hipStream_t)stream;
     for (const fno_model::Map& mp : m->maps)
-        k_param_map<<<(unsigned)((mp.n + 255) / 256), 256, 0, st>>>(d_params, mp.map, mp.n, mp.dst, mp.bf16 ? 1 : 0);
+        if (mp.n > 0)
+            k_param_map<<<(unsigned)((mp.n + 255) / 256), 256, 0, st>>>(d_params, mp.map, mp.n, mp.dst, mp.bf16 ? 1 : 0);
     LBM_HIP(hipGetLastError());
     return LBM_OK;
 }

@@ -700,6 +700,76 @@ __global__ __launch_bounds__(256) void k_field_stats_final(const double* __restr
     }
 }
 
+// Plain float copy / zero fill, grid-stride.  Used instead of hipMemcpyAsync /
+// hipMemsetAsync wherever a captured graph may be the next work on the stream:
+// a graph launched right behind an asynchronous fill has been seen to start
+// before the fill completed; kernels are ordered with graph launches.
+__global__ __launch_bounds__(256) void k_copy_f32(const float* __restrict__ src, float* __restrict__ dst,
+                                                  size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = src ? src[i] : 0.0f;
+}
+
+static unsigned copy_grid(size_t n) {
+    const size_t b = (n + 255) / 256;
+    return (unsigned)(b < 8192 ? (b ? b : 1) : 8192);
+}
+
+// Field comparison: per-workgroup FP64 partial sums over fluid nodes of
+// |a - ref| and |ref| for rho (= 1 + drho), ux, uy, and of drho, drho_ref and the
+// fluid-node count on the first and last columns (pressure drop); grid-stride,
+// then a fixed-order second pass (deterministic).
+constexpr int CMP_VALUES = 12;
+constexpr int CMP_BLOCKS = 512;
+
+__global__ __launch_bounds__(256) void k_compare(const uint8_t* __restrict__ mask, int nx, int N,
+                                                 const float* __restrict__ drho,
+                                                 const float* __restrict__ ux,
+                                                 const float* __restrict__ uy,
+                                                 const float* __restrict__ drho_ref,
+                                                 const float* __restrict__ ux_ref,
+                                                 const float* __restrict__ uy_ref,
+                                                 double* __restrict__ partials) {
+    __shared__ double red[4][CMP_VALUES];
+    double s[CMP_VALUES];
+#pragma unroll
+    for (int k = 0; k < CMP_VALUES; ++k) s[k] = 0.0;
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < N; n += gridDim.x * blockDim.x) {
+        if (mask[n]) continue;
+        const double r = drho[n], rr = drho_ref[n];
+        const double u = ux[n], ur = ux_ref[n], v = uy[n], vr = uy_ref[n];
+        s[0] += fabs(r - rr);
+        s[1] += fabs(1.0 + rr);
+        s[2] += fabs(u - ur);
+        s[3] += fabs(ur);
+        s[4] += fabs(v - vr);
+        s[5] += fabs(vr);
+        const int i = n % nx;
+        if (i == 0) { s[6] += r; s[7] += rr; s[8] += 1.0; }
+        if (i == nx - 1) { s[9] += r; s[10] += rr; s[11] += 1.0; }
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < CMP_VALUES; ++k) {
+        const double t = wave_sum(s[k]);
+        if (lane == 0) red[wave][k] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < CMP_VALUES) {
+        const int k = threadIdx.x;
+        partials[(size_t)blockIdx.x * CMP_VALUES + k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+    }
+}
+
+__global__ __launch_bounds__(64) void k_compare_final(const double* __restrict__ partials, int nb,
+                                                      double* __restrict__ out) {
+    const int k = threadIdx.x;
+    if (k >= CMP_VALUES) return;
+    double t = 0.0;
+    for (int b = 0; b < nb; ++b) t += partials[(size_t)b * CMP_VALUES + k];
+    out[k] = t;
+}
+
 }  // namespace lbmfno
 
 // ------------------------------------------------------------ host side
@@ -716,8 +786,9 @@ struct lbm_ctx {
     uint8_t* d_mask;
     float* d_drho;
     double* d_partials;
-    double* d_out;
-    double* h_out;
+    double* d_cmp;      // [CMP_BLOCKS][CMP_VALUES] field-comparison partials
+    double* d_out;      // [16] reduction results
+    double* h_out;      // [16] pinned copy
     int nblocks;
     int64_t fluid;
     int64_t steps;
@@ -821,6 +892,7 @@ static void release(lbm_ctx* c) {
     if (c->d_mask) (void)hipFree(c->d_mask);
     if (c->d_drho) (void)hipFree(c->d_drho);
     if (c->d_partials) (void)hipFree(c->d_partials);
+    if (c->d_cmp) (void)hipFree(c->d_cmp);
     if (c->d_out) (void)hipFree(c->d_out);
     if (c->h_out) (void)hipHostFree(c->h_out);
     delete c;
@@ -990,8 +1062,9 @@ extern "C" int lbm_init(lbm_ctx** out, const lbm_config* cfg, const uint8_t* d_m
     LBM_TRY(hipMemcpyAsync(c->d_mask, d_mask, N, hipMemcpyDeviceToDevice, c->stream));
     LBM_TRY(hipMalloc(&c->d_drho, N * sizeof(float)));
     LBM_TRY(hipMalloc(&c->d_partials, (size_t)c->nblocks * 4 * sizeof(double)));
-    LBM_TRY(hipMalloc(&c->d_out, 4 * sizeof(double)));
-    LBM_TRY(hipHostMalloc(&c->h_out, 4 * sizeof(double), hipHostMallocDefault));
+    LBM_TRY(hipMalloc(&c->d_cmp, (size_t)CMP_BLOCKS * CMP_VALUES * sizeof(double)));
+    LBM_TRY(hipMalloc(&c->d_out, 16 * sizeof(double)));
+    LBM_TRY(hipHostMalloc(&c->h_out, 16 * sizeof(double), hipHostMallocDefault));
     dim3 blk(256), grd((cfg->nx + 255) / 256, cfg->ny);
     k_links<<<grd, blk, 0, c->stream>>>(cfg->nx, cfg->ny, cfg->bc_x, cfg->bc_y, c->d_mask, c->d_link);
     LBM_TRY(hipGetLastError());
@@ -1127,6 +1200,33 @@ extern "C" int lbm_check_fields(lbm_ctx* c, const float* d_rho, const float* d_u
     return LBM_OK;
 }
 
+extern "C" int lbm_compare_fields(lbm_ctx* c, const float* d_drho, const float* d_ux,
+                                  const float* d_uy, const float* d_drho_ref, const float* d_ux_ref,
+                                  const float* d_uy_ref, lbm_field_error* out) {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (!d_drho || !d_ux || !d_uy || !d_drho_ref || !d_ux_ref || !d_uy_ref || !out)
+        return fail(LBM_EINVAL, "NULL argument");
+    const int N = c->g.N;
+    const int nb = std::min(CMP_BLOCKS, (N + 255) / 256);
+    k_compare<<<nb, 256, 0, c->stream>>>(c->d_mask, c->cfg.nx, N, d_drho, d_ux, d_uy, d_drho_ref,
+                                         d_ux_ref, d_uy_ref, c->d_cmp);
+    k_compare_final<<<1, 64, 0, c->stream>>>(c->d_cmp, nb, c->d_out);
+    LBM_HIP(hipGetLastError());
+    LBM_HIP(hipMemcpyAsync(c->h_out, c->d_out, CMP_VALUES * sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream));
+    LBM_HIP(hipStreamSynchronize(c->stream));
+    const double* h = c->h_out;
+    auto ratio = [](double a, double b) { return b > 0.0 ? a / b : (a > 0.0 ? INFINITY : 0.0); };
+    out->rel_l1_rho = ratio(h[0], h[1]);
+    out->rel_l1_ux = ratio(h[2], h[3]);
+    out->rel_l1_uy = ratio(h[4], h[5]);
+    const double cs2 = 1.0 / 3.0;
+    out->dp = (h[8] > 0 && h[11] > 0) ? cs2 * (h[6] / h[8] - h[9] / h[11]) : 0.0;
+    out->dp_ref = (h[8] > 0 && h[11] > 0) ? cs2 * (h[7] / h[8] - h[10] / h[11]) : 0.0;
+    out->rel_dp = ratio(fabs(out->dp - out->dp_ref), fabs(out->dp_ref));
+    return LBM_OK;
+}
+
 extern "C" int lbm_info(const lbm_ctx* c, int64_t* fluid_nodes, int64_t* steps_done) {
     if (!c) return fail(LBM_EINVAL, "ctx is NULL");
     if (fluid_nodes) *fluid_nodes = c->fluid;
@@ -1214,10 +1314,13 @@ static void launch_batch(lbm_batch* b, int parity) {
 
 static int reset_rest(lbm_batch* b) {
     for (lbm_ctx* c : b->ctx) {
-        LBM_HIP(hipMemsetAsync(c->f[0], 0, 9 * (size_t)c->g.N * sizeof(float), b->stream));
+        const size_t n = 9 * (size_t)c->g.N;
+        k_copy_f32<<<copy_grid(n), 256, 0, b->stream>>>(nullptr, c->f[0], n);
         c->cur = 0;
         c->steps = 0;
     }
+    LBM_HIP(hipGetLastError());
+    LBM_HIP(hipStreamSynchronize(b->stream));
     b->parity = 0;
     b->steps = 0;
     return LBM_OK;
@@ -1618,14 +1721,16 @@ extern "C" size_t lbm_state_elems(const lbm_ctx* c) { return c ? 9 * (size_t)c->
 
 extern "C" int lbm_save_state(lbm_ctx* c, float* d_out) {
     if (!c || !d_out) return fail(LBM_EINVAL, "NULL argument");
-    LBM_HIP(hipMemcpyAsync(d_out, c->f[c->cur], 9 * (size_t)c->g.N * sizeof(float),
-                           hipMemcpyDeviceToDevice, c->stream));
+    const size_t n = 9 * (size_t)c->g.N;
+    k_copy_f32<<<copy_grid(n), 256, 0, c->stream>>>(c->f[c->cur], d_out, n);
+    LBM_HIP(hipGetLastError());
     return LBM_OK;
 }
 
 extern "C" int lbm_load_state(lbm_ctx* c, const float* d_in) {
     if (!c || !d_in) return fail(LBM_EINVAL, "NULL argument");
-    LBM_HIP(hipMemcpyAsync(c->f[c->cur], d_in, 9 * (size_t)c->g.N * sizeof(float),
-                           hipMemcpyDeviceToDevice, c->stream));
+    const size_t n = 9 * (size_t)c->g.N;
+    k_copy_f32<<<copy_grid(n), 256, 0, c->stream>>>(d_in, c->f[c->cur], n);
+    LBM_HIP(hipGetLastError());
     return LBM_OK;
 }

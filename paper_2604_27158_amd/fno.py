@@ -76,6 +76,13 @@ class Fno:
         if out is None:
             out = torch.empty((B, self.spec.cout, self.H, self.W), dtype=torch.float32, device="cuda")
         ws = self.workspace(B)
+        cur = torch.cuda.current_stream()
+        if stream is not None and stream != cur:
+            # run on `stream` after the caller's pending work; mark the tensors as
+            # used there so that the allocator does not recycle them early
+            stream.wait_stream(cur)
+            for t in (x, out):
+                t.record_stream(stream)
         _L.check(self.lib.fno_forward(self.model, x.data_ptr(), out.data_ptr(), int(B), ws.data_ptr(),
                                       ws.numel(), _L.stream_handle(stream)), "fno_forward")
         return out

@@ -61,6 +61,14 @@ class FieldStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class FieldError(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("rel_l1_rho", "rel_l1_ux", "rel_l1_uy", "dp", "dp_ref",
+                                                 "rel_dp")]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class TrajDesc(ctypes.Structure):
     _fields_ = [("cfg", LbmConfig), ("d_mask", _p), ("d_fA", _p), ("d_fB", _p)]
 
@@ -86,6 +94,7 @@ SIGNATURES = [
     ("lbm_info", ctypes.c_int, [_p, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     ("lbm_stream_copy", ctypes.c_int, [_p, _p, ctypes.c_size_t, _p]),
     ("lbm_check_fields", ctypes.c_int, [_p, _p, _p, _p, ctypes.POINTER(FieldStats)]),
+    ("lbm_compare_fields", ctypes.c_int, [_p, _p, _p, _p, _p, _p, _p, ctypes.POINTER(FieldError)]),
     ("lbm_adjoint_step", ctypes.c_int, [_p, _p, _p, _p]),
     ("lbm_state_elems", ctypes.c_size_t, [_p]),
     ("lbm_save_state", ctypes.c_int, [_p, _p]),
@@ -246,11 +255,30 @@ class Lattice:
         import torch
         torch.cuda.current_stream().wait_stream(self.stream)
 
+    def _hand_over(self, *outs):
+        """Outputs written on the lattice stream and returned to the caller: the
+        caller's stream waits for them, and the allocator is told that the caller's
+        stream uses them (else a block freed by the caller could be handed to the
+        next lattice-stream allocation while the caller still reads it)."""
+        import torch
+        self._before_caller()
+        cur = torch.cuda.current_stream()
+        for t in outs:
+            t.record_stream(cur)
+
+    def _take_inputs(self, *ins):
+        """Inputs from the caller's stream that lattice kernels read: the lattice
+        stream waits for the caller, and the inputs are marked as used on it."""
+        self._after_caller()
+        for t in ins:
+            t.record_stream(self.stream)
+
     def reinit(self, rho, ux, uy):
         import torch
         self._after_caller()
         with torch.cuda.stream(self.stream):
             rho, ux, uy = (t.to(device="cuda", dtype=torch.float32).contiguous() for t in (rho, ux, uy))
+        self._take_inputs(rho, ux, uy)
         self._keep = (rho, ux, uy)
         check(self.lib.lbm_reinit_from_macro(self.ctx, rho.data_ptr(), ux.data_ptr(), uy.data_ptr()),
               "lbm_reinit_from_macro")
@@ -261,7 +289,7 @@ class Lattice:
             out = torch.empty((3, self.ny, self.nx), dtype=torch.float32, device="cuda")
         check(self.lib.lbm_get_macro(self.ctx, out[0].data_ptr(), out[1].data_ptr(),
                                      out[2].data_ptr(), int(rho_minus_one)), "lbm_get_macro")
-        self._before_caller()
+        self._hand_over(out)
         return out
 
     def populations(self):
@@ -269,7 +297,7 @@ class Lattice:
         with torch.cuda.stream(self.stream):
             out = torch.empty((9, self.ny, self.nx), dtype=torch.float32, device="cuda")
         check(self.lib.lbm_get_populations(self.ctx, out.data_ptr()), "lbm_get_populations")
-        self._before_caller()
+        self._hand_over(out)
         return out
 
     def set_populations(self, f):
@@ -277,16 +305,27 @@ class Lattice:
         self._after_caller()
         with torch.cuda.stream(self.stream):
             f = f.to(device="cuda", dtype=torch.float32).contiguous()
+        self._take_inputs(f)
         self._keep_f = f
         check(self.lib.lbm_set_populations(self.ctx, f.data_ptr()), "lbm_set_populations")
 
     def check_fields(self, rho, ux, uy):
         """Mass, peak speed and non-finite count of fields over fluid nodes."""
-        self._after_caller()
+        self._take_inputs(rho, ux, uy)
         st = FieldStats()
         check(self.lib.lbm_check_fields(self.ctx, rho.data_ptr(), ux.data_ptr(), uy.data_ptr(),
                                         ctypes.byref(st)), "lbm_check_fields")
         return st.as_dict()
+
+    def compare(self, fields, ref):
+        """lbm_compare_fields of [3][ny][nx] (rho - 1, ux, uy) device tensors."""
+        fields, ref = fields.contiguous(), ref.contiguous()
+        self._take_inputs(fields, ref)
+        e = FieldError()
+        check(self.lib.lbm_compare_fields(self.ctx, fields[0].data_ptr(), fields[1].data_ptr(),
+                                          fields[2].data_ptr(), ref[0].data_ptr(), ref[1].data_ptr(),
+                                          ref[2].data_ptr(), ctypes.byref(e)), "lbm_compare_fields")
+        return e.as_dict()
 
     def save_state(self):
         """Exact copy of the current store (a device tensor)."""
@@ -294,46 +333,49 @@ class Lattice:
         with torch.cuda.stream(self.stream):
             out = torch.empty(int(self.lib.lbm_state_elems(self.ctx)), dtype=torch.float32, device="cuda")
         check(self.lib.lbm_save_state(self.ctx, out.data_ptr()), "lbm_save_state")
+        self._hand_over(out)
         return out
 
     def load_state(self, saved):
-        self._after_caller()
+        self._take_inputs(saved)
         self._keep_state = saved
         check(self.lib.lbm_load_state(self.ctx, saved.data_ptr()), "lbm_load_state")
 
     def adjoint_step(self, f_n, lam_np1, out=None):
         """lam_n = C'(f(n))^T P^T lam_{n+1} (float32 [9][ny][nx] device tensors)."""
         import torch
-        self._after_caller()
+        self._take_inputs(f_n, lam_np1)
         if out is None:
             with torch.cuda.stream(self.stream):
                 out = torch.empty_like(lam_np1)
+        else:
+            self._take_inputs(out)
         check(self.lib.lbm_adjoint_step(self.ctx, f_n.data_ptr(), lam_np1.data_ptr(), out.data_ptr()),
               "lbm_adjoint_step")
-        self._before_caller()
+        self._hand_over(out)
         return out
 
     def macro_vjp(self, f_n, g_rho, g_ux, g_uy):
         import torch
-        self._after_caller()
         with torch.cuda.stream(self.stream):
             lam = torch.empty_like(f_n)
             g = [t.to(device="cuda", dtype=torch.float32).contiguous() for t in (g_rho, g_ux, g_uy)]
+        self._take_inputs(f_n, *g)
         check(self.lib.lbm_macro_vjp(self.ctx, f_n.data_ptr(), g[0].data_ptr(), g[1].data_ptr(),
                                      g[2].data_ptr(), lam.data_ptr()), "lbm_macro_vjp")
-        self._before_caller()
+        self._hand_over(lam)
         return lam
 
     def feq_vjp(self, rho, ux, uy, lam):
         import torch
-        self._after_caller()
         with torch.cuda.stream(self.stream):
             fields = [t.to(device="cuda", dtype=torch.float32).contiguous() for t in (rho, ux, uy)]
             out = torch.empty((3, self.ny, self.nx), dtype=torch.float32, device="cuda")
+        self._take_inputs(*fields, lam)
         check(self.lib.lbm_feq_vjp(self.ctx, fields[0].data_ptr(), fields[1].data_ptr(),
                                    fields[2].data_ptr(), lam.data_ptr(), out[0].data_ptr(),
                                    out[1].data_ptr(), out[2].data_ptr()), "lbm_feq_vjp")
-        self._before_caller()
+        self._hand_over(out)
         return out
 
     def info(self):

@@ -34,6 +34,58 @@ def test_batch_equals_single_lattices(gpu, tmp_path):
         assert np.array_equal(a, b), lat.name
 
 
+def test_batch_from_rest_steps_graph_first(gpu):
+    """Regression: a batch stepped from rest straight into graph replay (no other
+    launch between the tuner's reset and the first graph) matches single lattices
+    bit for bit.  The reset used to be an asynchronous fill that the first graph
+    could overtake."""
+    lats = [W.porous_circles(100000 + s, nx=512, ny=256, rmin=8, rmax=20, phi_lo=0.75, phi_hi=0.9,
+                             keepout=20) for s in range(3)]
+    for n in (3, 20):
+        B = gpu.Batch((lats * 7)[:n])
+        B.step(1000)
+        for i, lat in enumerate(lats):
+            G = gpu.Lattice.from_workload(lat)
+            G.step(1000)
+            assert np.array_equal(B.trajectory(i).populations().cpu().numpy(),
+                                  G.populations().cpu().numpy()), (n, lat.name)
+        B.close()
+
+
+def test_macros_handed_to_caller_stream_are_not_recycled(gpu):
+    """Regression: fields read from several trajectories back to back and consumed
+    on the caller's stream (no synchronisation in between) each keep their own
+    values.  The outputs live on the lattice stream; without marking them as used
+    by the caller's stream, the allocator handed a just-freed block to the next
+    read before the caller's copy of the previous one had run."""
+    import torch
+    lats = [W.porous_circles(100000 + s, nx=512, ny=256, rmin=8, rmax=20, phi_lo=0.75, phi_hi=0.9,
+                             keepout=20) for s in range(4)]
+    B = gpu.Batch(lats)
+    B.step(200)
+    got = [B.trajectory(i).macros(rho_minus_one=True).clone() for i in range(len(lats))]
+    torch.cuda.synchronize()
+    for i, lat in enumerate(lats):
+        G = gpu.Lattice.from_workload(lat)
+        G.step(200)
+        assert torch.equal(got[i], G.macros(rho_minus_one=True)), lat.name
+
+
+def test_load_state_then_graph_steps(gpu):
+    """Restoring a saved state and replaying graph chunks right away reproduces the
+    uninterrupted run bit for bit."""
+    lat = W.porous_circles(5, nx=512, ny=256, rmin=8, rmax=20, phi_lo=0.75, phi_hi=0.9, keepout=20)
+    G = gpu.Lattice.from_workload(lat)
+    G.step(100)
+    s = G.save_state()
+    G.step(640)
+    want = G.populations().cpu().numpy()
+    for _ in range(3):
+        G.load_state(s)
+        G.step(640)
+        assert np.array_equal(G.populations().cpu().numpy(), want)
+
+
 def test_batch_oracle_parity_sampled(gpu):
     """Five sampled trajectories of a 100-trajectory batch, 1000 steps, vs FP64."""
     lats = [W.ellipse_flow(s) for s in range(100)]
