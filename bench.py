@@ -41,6 +41,8 @@ def parse():
                     help="only the main workload (for profiler runs)")
     ap.add_argument("--steady-max", type=int, default=400_000,
                     help="step budget of the time-to-steady run")
+    ap.add_argument("--steady-seeds", type=int, default=20,
+                    help="porous geometries in the FNO-initialised time-to-steady study")
     return ap.parse_args()
 
 
@@ -252,6 +254,42 @@ def bench_steady(out, lat, max_steps):
                                    "residual_every_10k": [h[1] for h in hist[9::10]]}
 
 
+# speed-ups (%) of FNO initialisation over plain LBM printed in the paper's
+# steady-convergence table (RTX A4000; geometric means over 20 trajectories)
+PAPER_STEADY_SPEEDUP = {"u@0.0001": 32.7, "v@0.0001": 11.7, "rho@0.0001": 70.0, "dp@0.0001": 42.5,
+                        "u@1e-05": 8.57, "rho@1e-05": 50.0, "dp@1e-05": 28.4, "rho@1e-06": 38.1,
+                        "rho@2e-07": 31.4}
+
+
+def bench_time_to_steady(out, seeds):
+    """Hybrid (FNO-initialised) vs plain time-to-steady on 512 x 256 porous
+    geometries held out from training: outputs (223 lattice steps each) to each
+    tolerance against each run's own steady reference, and the wall time on this
+    GPU including the two FNO calls and the re-initialisation."""
+    from paper_2604_27158_amd import steady_init as S
+    if not os.path.exists(S.DEFAULT_WEIGHTS):
+        out["time_to_steady_fno"] = {"skipped": "trained surrogate weights not present"}
+        return
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    res = S.time_to_steady_study(S.SteadyInit(), list(S.TEST_SEEDS)[:seeds], outputs=500, log=log)
+    rows = {}
+    for r in res["table"]:
+        key = f"{r['quantity']}@{r['tol']:g}"
+        rows[key] = {"lbm_outputs": r["lbm"], "fno_outputs": r["fno"], "steady_init_outputs": r["steady"],
+                     "reached_lbm_fno": [r["lbm_reached"], r["fno_reached"]],
+                     "paired_seeds": r["paired_seeds"],
+                     "speedup_pct": r["speedup_pct"], "time_speedup_pct": r.get("time_speedup_pct"),
+                     "seconds_lbm": r.get("seconds_lbm"), "seconds_fno": r.get("seconds_fno"),
+                     "paper_speedup_pct": PAPER_STEADY_SPEEDUP.get(key)}
+    lat = S.geometry(S.TEST_SEEDS[0])
+    out["time_to_steady_fno"] = {
+        "workload": f"porous {lat.nx}x{lat.ny}, r 8-20, phi U(0.75,0.9), u_in {lat.u_in}, tau {lat.tau:.4f}",
+        "seeds": len(res["seeds"]), "output_every_steps": res["output_every"], "outputs": res["outputs"],
+        "reference": res["reference"], "seconds_per_lattice_step": res["seconds_per_step"],
+        "seconds_fno_init": res["seconds_fno_init"],
+        "median_final_state_fno_vs_lbm": res["median_final_state_fno_vs_lbm"], "rows": rows}
+
+
 def cpu_baseline(lat, seconds):
     """FP64 oracle (C, OpenMP over rows) on this host: MLUPS on a bounded number of
     steps of the same workload; returns (dict, oracle Sim after those steps)."""
@@ -357,6 +395,7 @@ def main():
         bench_hybrid(out, model)
         bench_batch(out)
         bench_steady(out, lat, args.steady_max)
+        bench_time_to_steady(out, args.steady_seeds)
     if not args.no_cpu_baseline:
         cb, sim, mask, nsteps = cpu_baseline(lat, args.cpu_seconds)
         out["cpu_baseline"] = cb

@@ -48,30 +48,21 @@ DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weig
 
 
 GAP = 2   # minimum free cells between obstacle discs
+# Reynolds number of the paper's porous setup on the domain height,
+# U L / nu = 0.5 * 1.0 / 0.01 = 50, at inlet speed 0.01: nu = 0.01 * 256 / 50
+U_IN = 0.01
+TAU = 0.5 + 3.0 * U_IN * NY / 50.0
 
 
 def geometry(seed: int) -> W.Lattice:
     """Porous medium at 512 x 256: the porous generator with the obstacle radii of
     the 1024 x 512 case (8-20 cells), inlet/outlet keep-out halved, and the porosity
-    range of the paper's porous-media setup, phi ~ U(0.75, 0.9).  The paper gives no
+    range of the paper's porous-media setup, phi ~ U(0.75, 0.9); inlet speed and
+    viscosity give its Reynolds number on the domain height, 50.  The paper gives no
     obstacle sizes; obstacles of 16-40 cells are resolved by the surrogates' 6 and
     12 retained modes (about 20 cells at this grid), smaller ones are not."""
     return W.porous_circles(seed, nx=NX, ny=NY, rmin=8, rmax=20, phi_lo=0.75, phi_hi=0.9,
-                            gap=GAP, keepout=20)
-
-
-def steady_run(lat, steps: int, stream=None):
-    """(mask as float32 [ny][nx], fields [3][ny][nx] = (rho - 1, ux, uy)) after
-    `steps` lattice steps from rest."""
-    import torch
-    from paper_2604_27158_amd import lbmfno
-    G = lbmfno.Lattice.from_workload(lat, stream=stream)
-    G.step(steps)
-    f = G.macros(rho_minus_one=True)
-    with torch.cuda.stream(G.stream):
-        m = G.mask.to(torch.float32)
-    G.synchronize()
-    return m, f
+                            gap=GAP, keepout=20, u_in=U_IN, tau=TAU)
 
 
 def make_dataset(seeds, steps: int, log=None, per_launch: int = 100):
@@ -87,7 +78,14 @@ def make_dataset(seeds, steps: int, log=None, per_launch: int = 100):
     for k0 in range(0, len(seeds), per_launch):
         lats = [geometry(s) for s in seeds[k0:k0 + per_launch]]
         batch = lbmfno.Batch(lats)
-        batch.step(steps)
+        batch.step(steps - OUTPUT_EVERY)
+        prev = [batch.trajectory(i).macros(rho_minus_one=True) for i in range(min(len(lats), 8))]
+        batch.step(OUTPUT_EVERY)
+        if log and k0 == 0:
+            ch = [batch.trajectory(i).compare(batch.trajectory(i).macros(rho_minus_one=True), p)["rel_l1_ux"]
+                  for i, p in enumerate(prev)]
+            log(f"dataset: relative L1 change of ux over the last {OUTPUT_EVERY} of {steps} steps, "
+                f"median of {len(ch)}: {float(np.median(ch)):.2e}")
         for i in range(len(lats)):
             view = batch.trajectory(i)
             f = view.macros(rho_minus_one=True)
@@ -125,7 +123,8 @@ def train_model(spec, X, Y, Xv, Yv, epochs: int, batch: int = 8, lr: float = 1e-
                 decay: float = 0.85, decay_every: int = 10, weight_decay: float = 1e-2,
                 seed: int = 0, log=None):
     """AdamW training of one model on device tensors (targets already normalised).
-    Returns (packed parameters, [(epoch, train loss, validation loss)])."""
+    Returns (the parameters of the epoch with the lowest validation loss,
+    [(epoch, train loss, validation loss)])."""
     import torch
     from paper_2604_27158_amd import fno as gfno
     params = W.fno_random_params(seed, gfno.param_layout(spec), spec.width)
@@ -134,6 +133,7 @@ def train_model(spec, X, Y, Xv, Yv, epochs: int, batch: int = 8, lr: float = 1e-
     n = X.shape[0]
     g = torch.Generator().manual_seed(seed)
     hist = []
+    best = (float("inf"), None)
     t0 = time.perf_counter()
     for ep in range(epochs):
         tr.lr = lr * decay ** (ep // decay_every)
@@ -147,10 +147,12 @@ def train_model(spec, X, Y, Xv, Yv, epochs: int, batch: int = 8, lr: float = 1e-
             cnt += 1
         vl = evaluate(tr, Xv, Yv, batch)
         hist.append((ep, tot / max(cnt, 1), vl))
+        if vl < best[0]:
+            best = (vl, tr.params())
         if log:
             log(f"{spec.cout}-output model: epoch {ep + 1}/{epochs} train {tot / max(cnt, 1):.4e} "
                 f"val {vl:.4e} lr {tr.lr:.2e} ({time.perf_counter() - t0:.0f} s)")
-    return tr.params(), hist
+    return best[1], hist
 
 
 def evaluate(tr, X, Y, batch: int = 8) -> float:
@@ -188,40 +190,6 @@ class SteadyInit:
         return rho, u[0, 0], u[0, 1]
 
 
-def reference_state(lat, steps: int, stream=None):
-    """Steady reference: mean of the last 10 outputs (output interval 223 steps) after
-    `steps` steps from rest; fields as (rho - 1, ux, uy), plus the density residual."""
-    import torch
-    from paper_2604_27158_amd import lbmfno
-    G = lbmfno.Lattice.from_workload(lat, stream=stream)
-    G.step(steps - 10 * OUTPUT_EVERY)
-    acc = None
-    for _ in range(10):
-        G.step(OUTPUT_EVERY - 1)
-        rep = G.step(1, report=True)
-        f = G.macros(rho_minus_one=True)
-        with torch.cuda.stream(G.stream):
-            acc = f.double() if acc is None else acc + f.double()
-    with torch.cuda.stream(G.stream):
-        ref = (acc / 10.0).to(torch.float32)
-    G.synchronize()
-    return ref, rep["residual"]
-
-
-def convergence(lat, ref, outputs: int, init=None, stream=None):
-    """Errors after each output interval: list of lbm_compare_fields dicts, from the
-    naive start or from init fields (rho, ux, uy) given by a callable(lattice)."""
-    from paper_2604_27158_amd import lbmfno
-    G = lbmfno.Lattice.from_workload(lat, stream=stream)
-    if init is not None:
-        G.reinit(*init(G))
-    errs = []
-    for _ in range(outputs):
-        G.step(OUTPUT_EVERY)
-        errs.append(G.compare(G.macros(rho_minus_one=True), ref))
-    return errs
-
-
 def outputs_to_tolerance(errs, key: str, eps: float):
     """First output index (1-based) at which errs[k][key] <= eps and stays so for the
     rest of the recorded run; None if never."""
@@ -241,33 +209,87 @@ def geo_mean(xs):
     return float(np.exp(np.mean(np.log(xs)))) if xs else None
 
 
-def time_to_steady_study(init: "SteadyInit", seeds, ref_steps: int = 80000, outputs: int = 250,
-                         log=None):
-    """Outputs (of 223 lattice steps) needed to reach each tolerance for u, v, rho and
-    the pressure drop from three starts -- rest (plain lattice), the FNO prediction,
-    and the steady reference itself -- per seed and as geometric means over seeds,
-    plus the wall time per lattice step and of the FNO start (two models + reinit)."""
+def run_outputs(lats, inits, outputs: int, log=None, tag=""):
+    """Run trajectories side by side in one batch for `outputs` output intervals;
+    inits[i] is None (rest: rho = 1, u = 0) or a callable(view) giving (rho, ux,
+    uy) to re-initialise from.  Returns (batch, fields [n][outputs][3][ny][nx] as
+    (rho - 1, ux, uy) on the device)."""
     import torch
     from paper_2604_27158_amd import lbmfno
+    batch = lbmfno.Batch(lats)
+    n = len(lats)
+    for i, init in enumerate(inits):
+        if init is not None:
+            view = batch.trajectory(i)
+            view.reinit(*init(view))
+    store = torch.empty((n, outputs, 3, NY, NX), dtype=torch.float32, device="cuda")
+    t0 = time.perf_counter()
+    for o in range(outputs):
+        batch.step(OUTPUT_EVERY)
+        for i in range(n):
+            store[i, o].copy_(batch.trajectory(i).macros(rho_minus_one=True))
+        if log and (o + 1) % 50 == 0:
+            torch.cuda.synchronize()
+            log(f"{tag}: {o + 1}/{outputs} outputs of {n} trajectories ({time.perf_counter() - t0:.1f} s)")
+    torch.cuda.synchronize()
+    return batch, store
+
+
+def own_reference(store_i):
+    """The paper's steady reference of one trajectory: the mean of its last 10 outputs."""
+    return store_i[-10:].double().mean(dim=0).to(store_i.dtype).contiguous()
+
+
+def time_to_steady_study(init: "SteadyInit", seeds, outputs: int = 500, log=None):
+    """Outputs (of 223 lattice steps) each start needs to bring u, v, rho and the
+    pressure drop within each tolerance of its own steady reference (the mean of
+    its last 10 outputs): rest (plain lattice), the FNO prediction, and the plain
+    run's converged fields ("steady" start); per seed and as geometric means over
+    seeds; the distance between the starts' final states; and the wall time per
+    lattice step and of the FNO start (two models + equilibrium re-initialisation)."""
+    import torch
+    from paper_2604_27158_amd import lbmfno
+    seeds = list(seeds)
+    lats = [geometry(s) for s in seeds]
+    ns = len(seeds)
+    # rest and FNO starts side by side
+    batch, store = run_outputs(lats + lats, [None] * ns + [init.predict] * ns, outputs, log, "lbm+fno")
+    refs = {"lbm": [own_reference(store[i]) for i in range(ns)],
+            "fno": [own_reference(store[ns + i]) for i in range(ns)]}
+    errs = {"lbm": [], "fno": []}
+    for i in range(ns):
+        for name, j in (("lbm", i), ("fno", ns + i)):
+            view = batch.trajectory(j)
+            errs[name].append([view.compare(store[j, o], refs[name][i]) for o in range(outputs)])
+    final_gap = [batch.trajectory(i).compare(refs["fno"][i], refs["lbm"][i]) for i in range(ns)]
+    last_change = {name: [batch.trajectory(j).compare(store[j, -1], store[j, -2])
+                          for j in (range(ns) if name == "lbm" else range(ns, 2 * ns))]
+                   for name in ("lbm", "fno")}
+    batch.close()
+    del store
+    torch.cuda.empty_cache()
+    # "steady" start from the plain run's converged fields
+    steady_fields = [(refs["lbm"][i][0] + 1.0, refs["lbm"][i][1], refs["lbm"][i][2]) for i in range(ns)]
+    batch, store = run_outputs(lats, [(lambda v, f=f: f) for f in steady_fields], outputs, log, "steady")
+    refs["steady"] = [own_reference(store[i]) for i in range(ns)]
+    errs["steady"] = [[batch.trajectory(i).compare(store[i, o], refs["steady"][i]) for o in range(outputs)]
+                      for i in range(ns)]
+    batch.close()
+    del store
+    torch.cuda.empty_cache()
     per_seed = []
-    stream = torch.cuda.Stream()
-    for s in seeds:
-        lat = geometry(s)
-        ref, res = reference_state(lat, ref_steps, stream)
-        runs = {
-            "lbm": convergence(lat, ref, outputs, None, stream),
-            "fno": convergence(lat, ref, outputs, init.predict, stream),
-            "steady": convergence(lat, ref, outputs,
-                                  lambda G: (ref[0] + 1.0, ref[1], ref[2]), stream),
-        }
-        rec = {"seed": s, "residual": res, "first_output_error": {}}
-        for name, errs in runs.items():
-            rec[name] = {q: {str(e): outputs_to_tolerance(errs, key, e) for e in TOLERANCES}
+    for i, sd in enumerate(seeds):
+        rec = {"seed": sd, "name": lats[i].name,
+               "final_state_fno_vs_lbm": {q: final_gap[i][key] for q, key in QUANTITIES},
+               "last_output_change": {n: {q: last_change[n][i][key] for q, key in QUANTITIES}
+                                      for n in last_change}}
+        for name in ("lbm", "fno", "steady"):
+            rec[name] = {q: {str(e): outputs_to_tolerance(errs[name][i], key, e) for e in TOLERANCES}
                          for q, key in QUANTITIES}
-            rec["first_output_error"][name] = {q: errs[0][key] for q, key in QUANTITIES}
+            rec["first_output_" + name] = {q: errs[name][i][0][key] for q, key in QUANTITIES}
         per_seed.append(rec)
         if log:
-            log(f"steady study seed {s}: residual {res:.2e}; outputs to 1e-4 (lbm/fno/steady) " +
+            log(f"seed {sd}: outputs to 1e-4 (lbm/fno/steady) " +
                 ", ".join(f"{q} {rec['lbm'][q]['0.0001']}/{rec['fno'][q]['0.0001']}/{rec['steady'][q]['0.0001']}"
                           for q, _ in QUANTITIES))
     table = []
@@ -278,14 +300,19 @@ def time_to_steady_study(init: "SteadyInit", seeds, ref_steps: int = 80000, outp
                 vals = [r[name][q][str(e)] for r in per_seed]
                 row[name] = geo_mean(vals)
                 row[name + "_reached"] = sum(v is not None for v in vals)
-            if row["lbm"] and row["fno"] and row["lbm_reached"] == row["fno_reached"] == len(per_seed):
-                row["speedup_pct"] = 100.0 * (row["lbm"] - row["fno"]) / row["lbm"]
+            # speed-up over the seeds where both the rest and the FNO start reach e
+            pairs = [(r["lbm"][q][str(e)], r["fno"][q][str(e)]) for r in per_seed
+                     if r["lbm"][q][str(e)] is not None and r["fno"][q][str(e)] is not None]
+            row["paired_seeds"] = len(pairs)
+            if pairs:
+                gl, gf = geo_mean([p[0] for p in pairs]), geo_mean([p[1] for p in pairs])
+                row["lbm_paired"], row["fno_paired"] = gl, gf
+                row["speedup_pct"] = 100.0 * (gl - gf) / gl
             else:
                 row["speedup_pct"] = None
             table.append(row)
-    # wall-clock costs on this GPU
-    lat = geometry(seeds[0])
-    G = lbmfno.Lattice.from_workload(lat, stream=stream)
+    # wall-clock costs on this GPU: one lattice on its own, and the FNO start
+    G = lbmfno.Lattice.from_workload(lats[0])
     G.step(1000)
     G.synchronize()
     t0 = time.perf_counter()
@@ -301,14 +328,16 @@ def time_to_steady_study(init: "SteadyInit", seeds, ref_steps: int = 80000, outp
     G.synchronize()
     t_init = (time.perf_counter() - t0) / 10
     for row in table:
-        if row["lbm"] is not None and row["fno"] is not None:
-            t_l = row["lbm"] * OUTPUT_EVERY * t_step
-            t_f = row["fno"] * OUTPUT_EVERY * t_step + t_init
+        if row["speedup_pct"] is not None:
+            t_l = row["lbm_paired"] * OUTPUT_EVERY * t_step
+            t_f = row["fno_paired"] * OUTPUT_EVERY * t_step + t_init
             row["seconds_lbm"], row["seconds_fno"] = t_l, t_f
             row["time_speedup_pct"] = 100.0 * (t_l - t_f) / t_l
-    return {"seeds": list(seeds), "output_every": OUTPUT_EVERY, "ref_steps": ref_steps,
-            "outputs_recorded": outputs, "seconds_per_step": t_step,
-            "seconds_fno_init": t_init, "table": table, "per_seed": per_seed}
+    gaps = {q: float(np.median([r["final_state_fno_vs_lbm"][q] for r in per_seed])) for q, _ in QUANTITIES}
+    return {"seeds": seeds, "output_every": OUTPUT_EVERY, "outputs": outputs,
+            "reference": "mean of each trajectory's last 10 outputs",
+            "seconds_per_step": t_step, "seconds_fno_init": t_init,
+            "median_final_state_fno_vs_lbm": gaps, "table": table, "per_seed": per_seed}
 
 
 def log_print(msg):
@@ -329,12 +358,14 @@ def main():
     e.add_argument("--weights", default=DEFAULT_WEIGHTS)
     e.add_argument("--seeds", type=int, default=len(TEST_SEEDS))
     e.add_argument("--json", default=None)
+    e.add_argument("--outputs", type=int, default=500)
     args = ap.parse_args()
     if args.cmd == "eval":
         import json
         from paper_2604_27158_amd import lbmfno
         lbmfno.load()
-        res = time_to_steady_study(SteadyInit(args.weights), list(TEST_SEEDS)[:args.seeds], log=log_print)
+        res = time_to_steady_study(SteadyInit(args.weights), list(TEST_SEEDS)[:args.seeds],
+                                   outputs=args.outputs, log=log_print)
         for row in res["table"]:
             log_print(json.dumps({k: v for k, v in row.items()}))
         if args.json:
