@@ -22,6 +22,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "common.hpp"
@@ -344,35 +345,107 @@ __device__ __forceinline__ float collide_q(R fq, const Moments<R>& m, R omega, R
     return collide_q<Q, FORCE, R>(fq, m, omega, guo, gx, gy, R(1.5) * fma(m.ux, m.ux, m.uy * m.uy));
 }
 
-// One fused step t -> t+1 for one node per thread.  R is the register type of
-// the collision arithmetic (double by default; float for the all-FP32 variant);
-// the stores are float either way.
+// Register arithmetic "lean" (LBM_ARITH_LEAN): FP32 everywhere except where the
+// rounding would act as a force.  Rounding the velocity to FP32 before the linear
+// equilibrium term w (drho + 3 rho c.u) gives every node a momentum bias that is
+// nearly constant in time for slowly varying flow, i.e. a spurious body force.  So
+// the moment sums stay FP32, u is formed in FP64 (reciprocal of rho from the FP32
+// v_rcp refined by one FP64 Newton step: relative error ~1e-14), and the linear term
+// is evaluated in FP64 and rounded once; the quadratic terms, the forcing and the
+// relaxation are FP32.
+struct Lean {};
+
+template <int Q, bool FORCE>
+__device__ __forceinline__ float collide_q_lean(float fq, double dr64, double rho3, double ux, double uy,
+                                                float rho, float ux32, float uy32, float usq15,
+                                                float omega, float guo, float gx, float gy) {
+    const float lin = (float)(w_of_d(Q) * fma(rho3, cdot<Q, double>(ux, uy), dr64));
+    const float cu = cdot<Q, float>(ux32, uy32);
+    const float quad = w_of(Q) * rho * fmaf(4.5f * cu, cu, -usq15);
+    const float fe = lin + quad;
+    float out = fmaf(-omega, fq - fe, fq);
+    if (FORCE) {
+        const float cg = cdot<Q, float>(gx, gy);
+        const float ug = fmaf(ux32, gx, uy32 * gy);
+        const float t = fmaf(9.0f * cu, cg, 3.0f * (cg - ug));
+        out = fmaf(guo * w_of(Q) * rho, t, out);
+    }
+    return out;
+}
+
+// Boundary closure, moments and collision of one fluid node in arithmetic R
+// (float, double or Lean) on its gathered float populations v (replaced by the
+// post-collision deviations); returns drho.  Every step kernel calls this, so all
+// of them evaluate one operation sequence.
+template <bool ZH, bool FORCE, typename R>
+__device__ __forceinline__ float collide_node(float v[9], int x, int nx, const StepArgs& a) {
+    if constexpr (std::is_same<R, Lean>::value) {
+        if (ZH) zouhe<float>(v, x, nx, (float)a.u_in, (float)a.rho_out);
+        const float dr = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7])) + v[8];
+        const float jx = (v[1] - v[3]) + (v[5] - v[6]) + (v[8] - v[7]);
+        const float jy = (v[2] - v[4]) + (v[5] - v[8]) + (v[6] - v[7]);
+        const double dr64 = (double)dr, rho64 = 1.0 + dr64;
+        const double r0 = (double)__builtin_amdgcn_rcpf((float)rho64);
+        const double inv = fma(r0, fma(-rho64, r0, 1.0), r0);
+        double ux, uy;
+        if (FORCE) {
+            ux = fma((double)jx, inv, 0.5 * a.gx);
+            uy = fma((double)jy, inv, 0.5 * a.gy);
+        } else {
+            ux = (double)jx * inv;
+            uy = (double)jy * inv;
+        }
+        const double rho3 = 3.0 * rho64;
+        const float rho = (float)rho64, ux32 = (float)ux, uy32 = (float)uy;
+        const float usq15 = 1.5f * fmaf(ux32, ux32, uy32 * uy32);
+        const float om = (float)a.omega, guo = (float)a.guo, gx = (float)a.gx, gy = (float)a.gy;
+#define LBM_LEAN(Q) v[Q] = collide_q_lean<Q, FORCE>(v[Q], dr64, rho3, ux, uy, rho, ux32, uy32, usq15, om, guo, gx, gy);
+        LBM_LEAN(0) LBM_LEAN(1) LBM_LEAN(2) LBM_LEAN(3) LBM_LEAN(4)
+        LBM_LEAN(5) LBM_LEAN(6) LBM_LEAN(7) LBM_LEAN(8)
+#undef LBM_LEAN
+        return dr;
+    } else {
+        R f[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) f[q] = (R)v[q];
+        if (ZH) zouhe<R>(f, x, nx, (R)a.u_in, (R)a.rho_out);
+        const R gx = (R)a.gx, gy = (R)a.gy, om = (R)a.omega, guo = (R)a.guo;
+        const Moments<R> m = moments<FORCE, R>(f, gx, gy);
+        v[0] = collide_q<0, FORCE, R>(f[0], m, om, guo, gx, gy);
+        v[1] = collide_q<1, FORCE, R>(f[1], m, om, guo, gx, gy);
+        v[2] = collide_q<2, FORCE, R>(f[2], m, om, guo, gx, gy);
+        v[3] = collide_q<3, FORCE, R>(f[3], m, om, guo, gx, gy);
+        v[4] = collide_q<4, FORCE, R>(f[4], m, om, guo, gx, gy);
+        v[5] = collide_q<5, FORCE, R>(f[5], m, om, guo, gx, gy);
+        v[6] = collide_q<6, FORCE, R>(f[6], m, om, guo, gx, gy);
+        v[7] = collide_q<7, FORCE, R>(f[7], m, om, guo, gx, gy);
+        v[8] = collide_q<8, FORCE, R>(f[8], m, om, guo, gx, gy);
+        return (float)m.drho;
+    }
+}
+
+// One fused step t -> t+1 for one node per thread.  R selects the collision
+// arithmetic (Lean by default, double or float); the stores are float either way.
 template <bool ZH, bool FORCE, bool WDRHO, bool NT, typename R>
 __device__ __forceinline__ void step_node(const StepArgs& a, int bx, int by) {
     const int i = bx * TX + threadIdx.x, j = by * TY + threadIdx.y;
     if (i >= a.g.nx || j >= a.g.ny) return;
     const int n = j * a.g.nx + i;
     const unsigned lk = a.link[n];
-    R f[9];
-    gather_stream<R>(a.src, a.g, i, j, n, f);
+    float f[9];
+    gather_stream<float>(a.src, a.g, i, j, n, f);
     if (is_solid(lk, a.mask, n)) return;
-    gather_bounce<R>(a.src, a.g, lk, n, f);
-    if (ZH) zouhe<R>(f, i, a.g.nx, (R)a.u_in, (R)a.rho_out);
-    const R gx = (R)a.gx, gy = (R)a.gy, om = (R)a.omega, guo = (R)a.guo;
-    const Moments<R> m = moments<FORCE, R>(f, gx, gy);
-    if (WDRHO) a.drho_out[n] = (float)m.drho;
+    gather_bounce<float>(a.src, a.g, lk, n, f);
+    const float drho = collide_node<ZH, FORCE, R>(f, i, a.g.nx, a);
+    if (WDRHO) a.drho_out[n] = drho;
     float* __restrict__ d = a.dst + n;
     const size_t N = (size_t)a.g.N;
     // Stores that overflow the last-level cache stream past it (non-temporal);
     // a lattice whose two stores fit keeps them cached for the next step.
-#define LBM_STORE(Q)                                                                \
-    {                                                                              \
-        const float v_ = collide_q<Q, FORCE, R>(f[Q], m, om, guo, gx, gy);        \
-        if (NT) __builtin_nontemporal_store(v_, d + Q * N); else d[Q * N] = v_;    \
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        if (NT) __builtin_nontemporal_store(f[q], d + q * N); else d[q * N] = f[q];
     }
-    LBM_STORE(0) LBM_STORE(1) LBM_STORE(2) LBM_STORE(3) LBM_STORE(4)
-    LBM_STORE(5) LBM_STORE(6) LBM_STORE(7) LBM_STORE(8)
-#undef LBM_STORE
 }
 
 template <bool ZH, bool FORCE, bool WDRHO, bool NT, typename R>
@@ -380,6 +453,87 @@ __global__ __launch_bounds__(256) void k_bgk_step(StepArgs a) {
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int by = b / a.g.gridx;
     step_node<ZH, FORCE, WDRHO, NT, R>(a, b - by * a.g.gridx, by);
+}
+
+// Two fused steps per launch (temporal blocking).  A workgroup owns a TX x PAIR_RY
+// tile (64 x 4 nodes: measured fastest against 64 x 8 and 64 x 16 on cache-resident
+// and HBM-resident lattices alike, the many small workgroups hiding more latency
+// than the larger tiles save in ring recomputation).  Step n -> n+1 runs on the tile and a one-node ring around it (the nodes
+// the tile pulls from), gathering from the store in global memory as the one-step
+// kernel does and keeping the post-collision values in LDS; step n+1 -> n+2 then
+// runs on the tile, pulling from LDS, and only its result is stored.  Both steps
+// call collide_node on the same float inputs, so the result is bit-identical to
+// two one-step launches, while the store traffic and the launch count per step
+// halve.  Ring nodes outside a non-periodic axis, and solid ring nodes, are never
+// pulled (their links bounce) and are skipped; on a periodic axis the ring wraps.
+constexpr int PAIR_RY = 4;
+constexpr int PAIR_LW = TX + 2, PAIR_LN = PAIR_LW * (PAIR_RY + 2);
+
+template <bool ZH, bool FORCE, bool NT, typename R>
+__device__ __forceinline__ void step_pair(const StepArgs& a, int bx, int by, float* __restrict__ P) {
+    const int x0 = bx * TX, y0 = by * PAIR_RY;
+    const int nx = a.g.nx, ny = a.g.ny;
+    const int tid = threadIdx.y * TX + threadIdx.x;
+    for (int e = tid; e < PAIR_LN; e += TX * TY) {
+        const int ly = e / PAIR_LW, lx = e - ly * PAIR_LW;
+        int i = x0 - 1 + lx, j = y0 - 1 + ly;
+        if (i < 0 || i >= nx) {
+            if (a.g.bc_x != LBM_BC_PERIODIC) continue;
+            i = ((i % nx) + nx) % nx;
+        }
+        if (j < 0 || j >= ny) {
+            if (a.g.bc_y != LBM_BC_PERIODIC) continue;
+            j = ((j % ny) + ny) % ny;
+        }
+        const int n = j * nx + i;
+        const unsigned lk = a.link[n];
+        if (is_solid(lk, a.mask, n)) continue;
+        float f[9];
+        gather_stream<float>(a.src, a.g, i, j, n, f);
+        gather_bounce<float>(a.src, a.g, lk, n, f);
+        (void)collide_node<ZH, FORCE, R>(f, i, nx, a);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) P[q * PAIR_LN + e] = f[q];
+    }
+    __syncthreads();
+    const size_t N = (size_t)a.g.N;
+    for (int r = threadIdx.y; r < PAIR_RY; r += TY) {
+        const int i = x0 + threadIdx.x, j = y0 + r;
+        if (i >= nx || j >= ny) continue;
+        const int n = j * nx + i;
+        const unsigned lk = a.link[n];
+        if (is_solid(lk, a.mask, n)) continue;
+        const int c = (r + 1) * PAIR_LW + threadIdx.x + 1;
+        float f[9];
+        f[0] = P[0 * PAIR_LN + c];
+        f[1] = P[1 * PAIR_LN + c - 1];
+        f[2] = P[2 * PAIR_LN + c - PAIR_LW];
+        f[3] = P[3 * PAIR_LN + c + 1];
+        f[4] = P[4 * PAIR_LN + c + PAIR_LW];
+        f[5] = P[5 * PAIR_LN + c - PAIR_LW - 1];
+        f[6] = P[6 * PAIR_LN + c - PAIR_LW + 1];
+        f[7] = P[7 * PAIR_LN + c + PAIR_LW + 1];
+        f[8] = P[8 * PAIR_LN + c + PAIR_LW - 1];
+        if (lk != 0u) {
+#define LBM_BB2(Q) if ((lk >> (Q - 1)) & 1u) f[Q] = P[opp_of(Q) * PAIR_LN + c];
+            LBM_BB2(1) LBM_BB2(2) LBM_BB2(3) LBM_BB2(4) LBM_BB2(5) LBM_BB2(6) LBM_BB2(7) LBM_BB2(8)
+#undef LBM_BB2
+        }
+        (void)collide_node<ZH, FORCE, R>(f, i, nx, a);
+        float* __restrict__ d = a.dst + n;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            if (NT) __builtin_nontemporal_store(f[q], d + q * N); else d[q * N] = f[q];
+        }
+    }
+}
+
+template <bool ZH, bool FORCE, bool NT, typename R>
+__global__ __launch_bounds__(256) void k_bgk_step2(StepArgs a) {
+    __shared__ float P[9 * PAIR_LN];
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int by = b / a.g.gridx;
+    step_pair<ZH, FORCE, NT, R>(a, b - by * a.g.gridx, by, P);
 }
 
 // Four-wide step (nx % 4 == 0): each lane owns four consecutive x nodes of one
@@ -463,27 +617,17 @@ __device__ __forceinline__ void step_quad(const StepArgs& a, int bx, int by) {
             }
         }
     }
-    const R gx = (R)a.gx, gy = (R)a.gy, om = (R)a.omega, guo = (R)a.guo;
     float drho4[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        R f[9];
+        float f[9];
 #pragma unroll
-        for (int q = 0; q < 9; ++q) f[q] = (R)v[q][k];
-        if (ZH) zouhe<R>(f, x0 + k, nx, (R)a.u_in, (R)a.rho_out);
-        const Moments<R> m = moments<FORCE, R>(f, gx, gy);
-        drho4[k] = (float)m.drho;
+        for (int q = 0; q < 9; ++q) f[q] = v[q][k];
+        drho4[k] = collide_node<ZH, FORCE, R>(f, x0 + k, nx, a);
         const bool sol = (solid4 >> k) & 1u;
-        v[0][k] = sol ? 0.0f : collide_q<0, FORCE, R>(f[0], m, om, guo, gx, gy);
-        v[1][k] = sol ? 0.0f : collide_q<1, FORCE, R>(f[1], m, om, guo, gx, gy);
-        v[2][k] = sol ? 0.0f : collide_q<2, FORCE, R>(f[2], m, om, guo, gx, gy);
-        v[3][k] = sol ? 0.0f : collide_q<3, FORCE, R>(f[3], m, om, guo, gx, gy);
-        v[4][k] = sol ? 0.0f : collide_q<4, FORCE, R>(f[4], m, om, guo, gx, gy);
-        v[5][k] = sol ? 0.0f : collide_q<5, FORCE, R>(f[5], m, om, guo, gx, gy);
-        v[6][k] = sol ? 0.0f : collide_q<6, FORCE, R>(f[6], m, om, guo, gx, gy);
-        v[7][k] = sol ? 0.0f : collide_q<7, FORCE, R>(f[7], m, om, guo, gx, gy);
-        v[8][k] = sol ? 0.0f : collide_q<8, FORCE, R>(f[8], m, om, guo, gx, gy);
-        if ((solid4 >> k) & 1u) drho4[k] = 0.0f;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) v[q][k] = sol ? 0.0f : f[q];
+        if (sol) drho4[k] = 0.0f;
     }
     // a quad of four solid nodes stores nothing (its slots are never read); its
     // loads above stay, since the neighbouring lanes' shuffles use them
@@ -532,20 +676,40 @@ __global__ __launch_bounds__(256) void k_bgk_batch(const StepArgs* __restrict__ 
     const bool force = a.gx != 0.0 || a.gy != 0.0;
     if (QUAD) {
         if (zh) {
-            if (force) step_quad<true, true, false, NT, double>(a, t.bx, t.by);
-            else step_quad<true, false, false, NT, double>(a, t.bx, t.by);
+            if (force) step_quad<true, true, false, NT, Lean>(a, t.bx, t.by);
+            else step_quad<true, false, false, NT, Lean>(a, t.bx, t.by);
         } else {
-            if (force) step_quad<false, true, false, NT, double>(a, t.bx, t.by);
-            else step_quad<false, false, false, NT, double>(a, t.bx, t.by);
+            if (force) step_quad<false, true, false, NT, Lean>(a, t.bx, t.by);
+            else step_quad<false, false, false, NT, Lean>(a, t.bx, t.by);
         }
     } else {
         if (zh) {
-            if (force) step_node<true, true, false, NT, double>(a, t.bx, t.by);
-            else step_node<true, false, false, NT, double>(a, t.bx, t.by);
+            if (force) step_node<true, true, false, NT, Lean>(a, t.bx, t.by);
+            else step_node<true, false, false, NT, Lean>(a, t.bx, t.by);
         } else {
-            if (force) step_node<false, true, false, NT, double>(a, t.bx, t.by);
-            else step_node<false, false, false, NT, double>(a, t.bx, t.by);
+            if (force) step_node<false, true, false, NT, Lean>(a, t.bx, t.by);
+            else step_node<false, false, false, NT, Lean>(a, t.bx, t.by);
         }
+    }
+}
+
+// Batched two-step launch: k_bgk_step2's tile step over the trajectory-major tile
+// table (its 64 x 4 tiles are the one-node kernel's).
+template <bool NT>
+__global__ __launch_bounds__(256) void k_bgk_batch2(const StepArgs* __restrict__ args,
+                                                    const BatchTile* __restrict__ tiles) {
+    __shared__ float P[9 * PAIR_LN];
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const BatchTile t = tiles[b];
+    const StepArgs a = args[t.traj];
+    const bool zh = a.g.bc_x == LBM_BC_ZOUHE;
+    const bool force = a.gx != 0.0 || a.gy != 0.0;
+    if (zh) {
+        if (force) step_pair<true, true, NT, Lean>(a, t.bx, t.by, P);
+        else step_pair<true, false, NT, Lean>(a, t.bx, t.by, P);
+    } else {
+        if (force) step_pair<false, true, NT, Lean>(a, t.bx, t.by, P);
+        else step_pair<false, false, NT, Lean>(a, t.bx, t.by, P);
     }
 }
 
@@ -797,6 +961,7 @@ struct lbm_ctx {
     int device;
     bool nontemporal;
     bool vec4;       // four-wide step kernel (nx % 4 == 0)
+    bool pair;       // two steps per launch (k_bgk_step2)
     int gridx4;      // workgroups along x for the four-wide kernel
     int nblocks4;
 };
@@ -811,9 +976,9 @@ static int validate_config(const lbm_config* c) {
     if (!(c->tau > 0.5) || !finite_d(c->tau))
         return fail(LBM_EINVAL, "tau = %g must be finite and > 1/2", c->tau);
     if (!finite_d(c->gx) || !finite_d(c->gy)) return fail(LBM_EINVAL, "non-finite body force");
-    if (c->arith != LBM_ARITH_MIXED && c->arith != LBM_ARITH_FP32)
+    if (c->arith != LBM_ARITH_MIXED && c->arith != LBM_ARITH_FP32 && c->arith != LBM_ARITH_LEAN)
         return fail(LBM_EINVAL, "arith = %d", c->arith);
-    if (c->kernel < LBM_KERNEL_AUTO || c->kernel > LBM_KERNEL_QUAD)
+    if (c->kernel < LBM_KERNEL_AUTO || c->kernel > LBM_KERNEL_PAIR)
         return fail(LBM_EINVAL, "kernel = %d", c->kernel);
     if (c->bc_x < 0 || c->bc_x > 2 || c->bc_y < 0 || c->bc_y > 1)
         return fail(LBM_EINVAL, "boundary codes bc_x=%d bc_y=%d", c->bc_x, c->bc_y);
@@ -916,21 +1081,23 @@ static int launch_step(lbm_ctx* c, bool write_drho) {
     a.rho_out = c->cfg.rho_out;
     const bool zh = c->cfg.bc_x == LBM_BC_ZOUHE;
     const bool force = c->cfg.gx != 0.0 || c->cfg.gy != 0.0;
-    const bool f32 = c->cfg.arith == LBM_ARITH_FP32;
+    const int ar = c->cfg.arith;
     const bool nt = c->nontemporal;
     hipStream_t s = c->stream;
     if (c->vec4) {
         a.g.gridx = c->gridx4;
         dim3 blk(TX, TY), grd(c->nblocks4);
-#define LBM_STEP_CASE(Z, F, W)                                                         \
-    if (zh == Z && force == F && write_drho == W) {                                   \
-        if (f32) {                                                                    \
-            if (nt) k_bgk_step_v4<Z, F, W, true, float><<<grd, blk, 0, s>>>(a);       \
-            else k_bgk_step_v4<Z, F, W, false, float><<<grd, blk, 0, s>>>(a);         \
-        } else {                                                                      \
-            if (nt) k_bgk_step_v4<Z, F, W, true, double><<<grd, blk, 0, s>>>(a);      \
-            else k_bgk_step_v4<Z, F, W, false, double><<<grd, blk, 0, s>>>(a);        \
-        }                                                                             \
+#define LBM_STEP_ARITH(R)                                                              \
+    {                                                                                 \
+        if (nt) k_bgk_step_v4<Z, F, W, true, R><<<grd, blk, 0, s>>>(a);               \
+        else k_bgk_step_v4<Z, F, W, false, R><<<grd, blk, 0, s>>>(a);                 \
+    }
+#define LBM_STEP_CASE(Z_, F_, W_)                                                      \
+    if (zh == Z_ && force == F_ && write_drho == W_) {                                \
+        constexpr bool Z = Z_, F = F_, W = W_;                                        \
+        if (ar == LBM_ARITH_FP32) LBM_STEP_ARITH(float)                               \
+        else if (ar == LBM_ARITH_MIXED) LBM_STEP_ARITH(double)                        \
+        else LBM_STEP_ARITH(Lean)                                                     \
     }
         LBM_STEP_CASE(false, false, false)
         LBM_STEP_CASE(false, false, true)
@@ -941,20 +1108,23 @@ static int launch_step(lbm_ctx* c, bool write_drho) {
         LBM_STEP_CASE(true, true, false)
         LBM_STEP_CASE(true, true, true)
 #undef LBM_STEP_CASE
+#undef LBM_STEP_ARITH
         c->cur ^= 1;
         ++c->steps;
         return LBM_OK;
     }
     dim3 blk(TX, TY), grd(c->nblocks);
-#define LBM_STEP_CASE(Z, F, W)                                                         \
-    if (zh == Z && force == F && write_drho == W) {                                   \
-        if (f32) {                                                                    \
-            if (nt) k_bgk_step<Z, F, W, true, float><<<grd, blk, 0, s>>>(a);          \
-            else k_bgk_step<Z, F, W, false, float><<<grd, blk, 0, s>>>(a);            \
-        } else {                                                                      \
-            if (nt) k_bgk_step<Z, F, W, true, double><<<grd, blk, 0, s>>>(a);         \
-            else k_bgk_step<Z, F, W, false, double><<<grd, blk, 0, s>>>(a);           \
-        }                                                                             \
+#define LBM_STEP_ARITH(R)                                                              \
+    {                                                                                 \
+        if (nt) k_bgk_step<Z, F, W, true, R><<<grd, blk, 0, s>>>(a);                  \
+        else k_bgk_step<Z, F, W, false, R><<<grd, blk, 0, s>>>(a);                    \
+    }
+#define LBM_STEP_CASE(Z_, F_, W_)                                                      \
+    if (zh == Z_ && force == F_ && write_drho == W_) {                                \
+        constexpr bool Z = Z_, F = F_, W = W_;                                        \
+        if (ar == LBM_ARITH_FP32) LBM_STEP_ARITH(float)                               \
+        else if (ar == LBM_ARITH_MIXED) LBM_STEP_ARITH(double)                        \
+        else LBM_STEP_ARITH(Lean)                                                     \
     }
     LBM_STEP_CASE(false, false, false)
     LBM_STEP_CASE(false, false, true)
@@ -965,8 +1135,53 @@ static int launch_step(lbm_ctx* c, bool write_drho) {
     LBM_STEP_CASE(true, true, false)
     LBM_STEP_CASE(true, true, true)
 #undef LBM_STEP_CASE
+#undef LBM_STEP_ARITH
     c->cur ^= 1;
     ++c->steps;
+    return LBM_OK;
+}
+
+// Two steps in one launch (k_bgk_step2): store parity flips once.
+static int launch_step2(lbm_ctx* c) {
+    StepArgs a;
+    a.src = c->f[c->cur];
+    a.dst = c->f[c->cur ^ 1];
+    a.link = c->d_link;
+    a.mask = c->d_mask;
+    a.drho_out = c->d_drho;
+    a.g = c->g;
+    a.omega = 1.0 / c->cfg.tau;
+    a.guo = 1.0 - 0.5 / c->cfg.tau;
+    a.gx = c->cfg.gx;
+    a.gy = c->cfg.gy;
+    a.u_in = c->cfg.u_in;
+    a.rho_out = c->cfg.rho_out;
+    const bool zh = c->cfg.bc_x == LBM_BC_ZOUHE;
+    const bool force = c->cfg.gx != 0.0 || c->cfg.gy != 0.0;
+    const int ar = c->cfg.arith;
+    const bool nt = c->nontemporal;
+    hipStream_t s = c->stream;
+    dim3 blk(TX, TY), grd(c->g.gridx * ((c->g.ny + PAIR_RY - 1) / PAIR_RY));
+#define LBM_STEP2_ARITH(R)                                                             \
+    {                                                                                 \
+        if (nt) k_bgk_step2<Z, F, true, R><<<grd, blk, 0, s>>>(a);                    \
+        else k_bgk_step2<Z, F, false, R><<<grd, blk, 0, s>>>(a);                      \
+    }
+#define LBM_STEP2_CASE(Z_, F_)                                                         \
+    if (zh == Z_ && force == F_) {                                                    \
+        constexpr bool Z = Z_, F = F_;                                                \
+        if (ar == LBM_ARITH_FP32) LBM_STEP2_ARITH(float)                              \
+        else if (ar == LBM_ARITH_MIXED) LBM_STEP2_ARITH(double)                       \
+        else LBM_STEP2_ARITH(Lean)                                                    \
+    }
+    LBM_STEP2_CASE(false, false)
+    LBM_STEP2_CASE(false, true)
+    LBM_STEP2_CASE(true, false)
+    LBM_STEP2_CASE(true, true)
+#undef LBM_STEP2_CASE
+#undef LBM_STEP2_ARITH
+    c->cur ^= 1;
+    c->steps += 2;
     return LBM_OK;
 }
 
@@ -1033,9 +1248,12 @@ extern "C" int lbm_init(lbm_ctx** out, const lbm_config* cfg, const uint8_t* d_m
         delete c;
         return fail(LBM_EUNSUPPORTED, "four-wide kernel needs nx %% 4 == 0 and 16-byte aligned stores");
     }
-    c->vec4 = cfg->kernel == LBM_KERNEL_QUAD ||
-              (cfg->kernel == LBM_KERNEL_AUTO && quad_ok &&
-               (size_t)cfg->nx * cfg->ny >= ((size_t)1 << 22));
+    // Two steps per launch beat every one-step kernel from ~100k nodes up (measured
+    // on 512x256, 1024x512 and 8192x4096); below that the lattice is launch-bound
+    // and the one-node kernel is used.
+    c->pair = cfg->kernel == LBM_KERNEL_PAIR ||
+              (cfg->kernel == LBM_KERNEL_AUTO && (size_t)cfg->nx * cfg->ny >= ((size_t)1 << 16));
+    c->vec4 = cfg->kernel == LBM_KERNEL_QUAD;
     c->gridx4 = (cfg->nx + 4 * TX - 1) / (4 * TX);
     c->nblocks4 = c->gridx4 * ((cfg->ny + TY - 1) / TY);
     c->f[0] = d_fA;
@@ -1110,7 +1328,11 @@ static int build_graph(lbm_ctx* c) {
     const int64_t steps0 = c->steps;
     hipGraph_t graph = nullptr;
     LBM_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-    for (int k = 0; k < c->graph_chunk; ++k) launch_step(c, false);
+    if (c->pair) {
+        for (int k = 0; k < c->graph_chunk; k += 2) launch_step2(c);
+    } else {
+        for (int k = 0; k < c->graph_chunk; ++k) launch_step(c, false);
+    }
     hipError_t e = hipStreamEndCapture(c->stream, &graph);
     c->cur = start;
     c->steps = steps0;
@@ -1129,8 +1351,8 @@ extern "C" int lbm_step(lbm_ctx* c, int32_t n, lbm_report* rep) {
     if (n < 0) return fail(LBM_EINVAL, "n = %d < 0", n);
     if (rep && n < 1) return fail(LBM_EINVAL, "a report needs n >= 1");
     int plain = rep ? n - 1 : n;
-    // Replay graph-captured chunks of plain steps on a non-default stream; the
-    // chunk length is even, so the store parity is unchanged by a replay.
+    // Replay graph-captured chunks of plain steps on a non-default stream; a
+    // chunk flips the store parity an even number of times.
     if (c->stream != nullptr) {
         while (plain >= c->graph_chunk) {
             if (!c->graph[c->cur]) {
@@ -1142,6 +1364,8 @@ extern "C" int lbm_step(lbm_ctx* c, int32_t n, lbm_report* rep) {
             plain -= c->graph_chunk;
         }
     }
+    if (c->pair)
+        for (; plain >= 2; plain -= 2) launch_step2(c);
     for (int k = 0; k < plain; ++k) launch_step(c, false);
     LBM_HIP(hipGetLastError());
     if (!rep) return LBM_OK;
@@ -1227,6 +1451,14 @@ extern "C" int lbm_compare_fields(lbm_ctx* c, const float* d_drho, const float* 
     return LBM_OK;
 }
 
+extern "C" const char* lbm_step_kernel(const lbm_ctx* c) {
+    if (!c) return "";
+    const bool lean = c->cfg.arith == LBM_ARITH_LEAN, f32 = c->cfg.arith == LBM_ARITH_FP32;
+    if (c->pair) return lean ? "pair/lean" : f32 ? "pair/fp32" : "pair/mixed";
+    if (c->vec4) return lean ? "quad/lean" : f32 ? "quad/fp32" : "quad/mixed";
+    return lean ? "node/lean" : f32 ? "node/fp32" : "node/mixed";
+}
+
 extern "C" int lbm_info(const lbm_ctx* c, int64_t* fluid_nodes, int64_t* steps_done) {
     if (!c) return fail(LBM_EINVAL, "ctx is NULL");
     if (fluid_nodes) *fluid_nodes = c->fluid;
@@ -1244,6 +1476,7 @@ struct lbm_batch {
     BatchTile* d_tiles = nullptr;
     int ntiles = 0;
     bool quad = false, nt = false;
+    bool pair = false;      // two steps per launch (k_bgk_batch2 on the one-node tiles)
     int parity = 0;
     int64_t steps = 0;
     int chunk = 32;
@@ -1301,6 +1534,12 @@ static int build_tiles(lbm_batch* b, bool quad) {
     return LBM_OK;
 }
 
+static void launch_batch2(lbm_batch* b, int parity) {
+    dim3 blk(TX, TY), grd(b->ntiles);
+    if (b->nt) k_bgk_batch2<true><<<grd, blk, 0, b->stream>>>(b->d_args[parity], b->d_tiles);
+    else k_bgk_batch2<false><<<grd, blk, 0, b->stream>>>(b->d_args[parity], b->d_tiles);
+}
+
 static void launch_batch(lbm_batch* b, int parity) {
     dim3 blk(TX, TY), grd(b->ntiles);
     if (b->quad) {
@@ -1347,7 +1586,7 @@ static std::string batch_key(const lbm_batch* b) {
     return buf;
 }
 
-static bool cache_lookup(const char* path, const std::string& key, bool* quad, bool* nt) {
+static bool cache_lookup(const char* path, const std::string& key, int* shape, bool* nt) {
     if (!path) return false;
     FILE* f = fopen(path, "r");
     if (!f) return false;
@@ -1355,56 +1594,74 @@ static bool cache_lookup(const char* path, const std::string& key, bool* quad, b
     int q = 0, t = 0;
     bool found = false;
     while (fscanf(f, "%255s %d %d", k, &q, &t) == 3)
-        if (key == k) { *quad = q != 0; *nt = t != 0; found = true; }
+        if (key == k) { *shape = q; *nt = t != 0; found = true; }
     fclose(f);
     return found;
 }
 
-static void cache_store(const char* path, const std::string& key, bool quad, bool nt) {
+static void cache_store(const char* path, const std::string& key, int shape, bool nt) {
     if (!path) return;
     FILE* f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%s %d %d\n", key.c_str(), quad ? 1 : 0, nt ? 1 : 0);
+    fprintf(f, "%s %d %d\n", key.c_str(), shape, nt ? 1 : 0);
     fclose(f);
+}
+
+// Kernel shapes of a batch: 0 one node per lane, 1 four nodes per lane, 2 two steps
+// per launch (on the one-node tiles).
+static const char* shape_name(int shape) { return shape == 1 ? "quad" : shape == 2 ? "pair" : "node"; }
+
+static int set_shape(lbm_batch* b, int shape) {
+    b->pair = shape == 2;
+    return build_tiles(b, shape == 1);
 }
 
 static int autotune(lbm_batch* b, bool quad_ok, const char* cache) {
     const std::string key = batch_key(b);
-    bool q = false, t = false;
-    if (cache_lookup(cache, key, &q, &t) && (quad_ok || !q)) {
+    int q = 0;
+    bool t = false;
+    if (cache_lookup(cache, key, &q, &t) && q >= 0 && q <= 2 && (quad_ok || q != 1)) {
         b->nt = t;
-        int rc = build_tiles(b, q);
+        int rc = set_shape(b, q);
         if (rc) return rc;
-        b->choice = std::string("cached ") + (q ? "quad" : "node") + (t ? "+nt" : "");
+        b->choice = std::string("cached ") + shape_name(q) + (t ? "+nt" : "");
         return LBM_OK;
     }
     float best = 1e30f;
-    bool bq = false, bt = false;
+    int bq = 0;
+    bool bt = false;
     hipEvent_t e0, e1;
     LBM_HIP(hipEventCreate(&e0));
     LBM_HIP(hipEventCreate(&e1));
-    for (int qi = quad_ok ? 1 : 0; qi >= 0; --qi) {
-        int rc = build_tiles(b, qi != 0);
+    for (int qi = 2; qi >= 0; --qi) {
+        if (qi == 1 && !quad_ok) continue;
+        int rc = set_shape(b, qi);
         if (rc) return rc;
         for (int ti = 0; ti < 2; ++ti) {
             b->nt = ti != 0;
-            for (int k = 0; k < 4; ++k) launch_batch(b, k & 1);  // warm-up (even count)
+            // 16 timed launches (32 steps for the two-step shape), after an even warm-up
+            for (int k = 0; k < 4; ++k) {
+                if (b->pair) launch_batch2(b, k & 1); else launch_batch(b, k & 1);
+            }
             LBM_HIP(hipEventRecord(e0, b->stream));
-            for (int k = 0; k < 16; ++k) launch_batch(b, k & 1);
+            for (int k = 0; k < 16; ++k) {
+                if (b->pair) launch_batch2(b, k & 1); else launch_batch(b, k & 1);
+            }
             LBM_HIP(hipEventRecord(e1, b->stream));
             LBM_HIP(hipEventSynchronize(e1));
             float ms = 0.0f;
             LBM_HIP(hipEventElapsedTime(&ms, e0, e1));
-            if (ms < best) { best = ms; bq = qi != 0; bt = b->nt; }
+            ms /= b->pair ? 32.0f : 16.0f;   // per lattice step
+            if (ms < best) { best = ms; bq = qi; bt = b->nt; }
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     b->nt = bt;
-    int rc = build_tiles(b, bq);
+    int rc = set_shape(b, bq);
     if (rc) return rc;
     char msg[96];
-    snprintf(msg, sizeof msg, "tuned %s%s %.4f ms/step", bq ? "quad" : "node", bt ? "+nt" : "", best / 16);
+    snprintf(msg, sizeof msg, "tuned %s%s %.4f ms/step", shape_name(bq), bt ? "+nt" : "", best);
     b->choice = msg;
     cache_store(cache, key, bq, bt);
     return reset_rest(b);
@@ -1418,8 +1675,8 @@ extern "C" int lbm_batch_create(lbm_batch** out, const lbm_traj_desc* h_desc, in
     for (int i = 0; i < ntraj; ++i) {
         int rc = validate_config(&h_desc[i].cfg);
         if (rc) return fail(rc, "trajectory %d: %s", i, lbm_last_error());
-        if (h_desc[i].cfg.arith != LBM_ARITH_MIXED)
-            return fail(LBM_EUNSUPPORTED, "trajectory %d: batches run the mixed-precision step", i);
+        if (h_desc[i].cfg.arith != LBM_ARITH_LEAN)
+            return fail(LBM_EUNSUPPORTED, "trajectory %d: batches run the LBM_ARITH_LEAN step", i);
         if (!h_desc[i].d_mask || !h_desc[i].d_fA || !h_desc[i].d_fB)
             return fail(LBM_EINVAL, "trajectory %d: NULL device buffer", i);
     }
@@ -1463,7 +1720,11 @@ static int batch_build_graph(lbm_batch* b) {
     const int start = b->parity;
     hipGraph_t g = nullptr;
     LBM_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-    for (int k = 0; k < b->chunk; ++k) launch_batch(b, start ^ (k & 1));
+    if (b->pair) {
+        for (int k = 0; k < b->chunk / 2; ++k) launch_batch2(b, start ^ (k & 1));
+    } else {
+        for (int k = 0; k < b->chunk; ++k) launch_batch(b, start ^ (k & 1));
+    }
     hipError_t e = hipStreamEndCapture(b->stream, &g);
     if (e != hipSuccess) return fail(LBM_EHIP, "batch graph capture: %s", hipGetErrorString(e));
     e = hipGraphInstantiate(&b->graph[start], g, nullptr, nullptr, 0);
@@ -1489,7 +1750,13 @@ extern "C" int lbm_batch_step(lbm_batch* b, int32_t n) {
                 if (rc) return rc;
             }
             LBM_HIP(hipGraphLaunch(b->graph[b->parity], b->stream));
-            left -= b->chunk;  // even chunk: parity unchanged
+            left -= b->chunk;  // an even number of parity flips
+        }
+    }
+    if (b->pair) {
+        for (; left >= 2; left -= 2) {
+            launch_batch2(b, b->parity);
+            b->parity ^= 1;
         }
     }
     for (int k = 0; k < left; ++k) {

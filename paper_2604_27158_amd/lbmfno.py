@@ -31,8 +31,8 @@ class LbmConfig(ctypes.Structure):
                 ("arith", ctypes.c_int32), ("kernel", ctypes.c_int32)]
 
 
-ARITH_MIXED, ARITH_FP32 = 0, 1
-KERNEL_AUTO, KERNEL_NODE, KERNEL_QUAD = 0, 1, 2
+ARITH_MIXED, ARITH_FP32, ARITH_LEAN = 0, 1, 2
+KERNEL_AUTO, KERNEL_NODE, KERNEL_QUAD, KERNEL_PAIR = 0, 1, 2, 3
 
 
 class LbmReport(ctypes.Structure):
@@ -93,6 +93,7 @@ SIGNATURES = [
     ("lbm_set_populations", ctypes.c_int, [_p, _p]),
     ("lbm_info", ctypes.c_int, [_p, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     ("lbm_stream_copy", ctypes.c_int, [_p, _p, ctypes.c_size_t, _p]),
+    ("lbm_step_kernel", ctypes.c_char_p, [_p]),
     ("lbm_check_fields", ctypes.c_int, [_p, _p, _p, _p, ctypes.POINTER(FieldStats)]),
     ("lbm_compare_fields", ctypes.c_int, [_p, _p, _p, _p, _p, _p, _p, ctypes.POINTER(FieldError)]),
     ("lbm_adjoint_step", ctypes.c_int, [_p, _p, _p, _p]),
@@ -191,7 +192,7 @@ class Lattice:
     capturable stream)."""
 
     def __init__(self, nx, ny, tau, gx=0.0, gy=0.0, bc_x=BC_PERIODIC, bc_y=BC_PERIODIC,
-                 u_in=0.0, rho_out=1.0, mask=None, stream=None, arith=ARITH_MIXED,
+                 u_in=0.0, rho_out=1.0, mask=None, stream=None, arith=ARITH_LEAN,
                  kernel=KERNEL_AUTO):
         import torch
         self.lib = load()
@@ -211,7 +212,7 @@ class Lattice:
               "lbm_init")
 
     @classmethod
-    def from_workload(cls, lat, stream=None, arith=ARITH_MIXED, kernel=KERNEL_AUTO):
+    def from_workload(cls, lat, stream=None, arith=ARITH_LEAN, kernel=KERNEL_AUTO):
         """Build from a workloads.Lattice (its mask rasterised on the GPU)."""
         import torch
         stream = stream if stream is not None else torch.cuda.Stream()
@@ -378,6 +379,10 @@ class Lattice:
         self._hand_over(out)
         return out
 
+    def step_kernel(self) -> str:
+        """"<shape>/<arith>" of the step kernel this lattice runs (lbm_step_kernel)."""
+        return self.lib.lbm_step_kernel(self.ctx).decode()
+
     def info(self):
         fl, st = _i64(), _i64()
         check(self.lib.lbm_info(self.ctx, ctypes.byref(fl), ctypes.byref(st)), "lbm_info")
@@ -407,7 +412,7 @@ class Batch:
                 self._bufs.append((mask, fA, fB))
                 descs[k].cfg = LbmConfig(lat.nx, lat.ny, lat.bc_x, lat.bc_y, float(lat.tau),
                                          float(lat.gx), float(lat.gy), float(lat.u_in),
-                                         float(lat.rho_out), ARITH_MIXED, KERNEL_AUTO)
+                                         float(lat.rho_out), ARITH_LEAN, KERNEL_AUTO)
                 descs[k].d_mask, descs[k].d_fA, descs[k].d_fB = mask.data_ptr(), fA.data_ptr(), fB.data_ptr()
         self.handle = _p()
         cache = tune_cache.encode() if tune_cache else None

@@ -1,8 +1,9 @@
 """Fixed kernel sequences for hardware-counter runs (rocprofv3 --pmc).
 
-Launches the fused step of a workload as single launches (no graph replay, so
-every dispatch is visible to the counter collector) and the library's copy kernel
-on a buffer of known size, which calibrates the byte counters:
+Launches the step kernel of a workload directly (no graph replay, so every
+dispatch is visible to the counter collector; two steps per call, i.e. one launch
+of the two-step kernel the workload runs by default) and the library's copy
+kernel on a buffer of known size, which calibrates the byte counters:
 
     python -m paper_2604_27158_amd.profile_run --workload porous1024 --steps 50
 """
@@ -32,8 +33,8 @@ def main():
         import bench
         lat = bench.porous_large(0)
     G = lbmfno.Lattice.from_workload(lat)
-    for _ in range(args.steps):
-        G.step(1)
+    for _ in range(args.steps // 2):
+        G.step(2)
     G.synchronize()
     fluid, _ = G.info()
     a = torch.ones(COPY_FLOATS, dtype=torch.float32, device="cuda")
@@ -41,7 +42,7 @@ def main():
     for _ in range(args.copies):
         lbmfno.stream_copy(a, b)
     torch.cuda.synchronize()
-    print(f"profile_run: {lat.name} {args.steps} single steps, fluid {fluid} of {lat.nx * lat.ny}; "
+    print(f"profile_run: {lat.name} {args.steps} steps ({G.step_kernel()}), fluid {fluid} of {lat.nx * lat.ny}; "
           f"{args.copies} copies of {COPY_FLOATS * 4} bytes", flush=True)
 
 
