@@ -204,3 +204,33 @@ class Trainer:
 
     def params(self):
         return self.p.detach().cpu().numpy().astype(np.float64)
+
+
+def fold_affine(spec, params, in_scale, in_shift, out_scale, out_shift):
+    """Packed parameters of the network on raw channels, given one trained on
+    normalised ones: inputs z' = (z - in_shift) / in_scale (per input channel; the
+    coordinate channels pass unchanged) folded into the lift's first layer, outputs
+    y = out_scale * o + out_shift folded into the decoder's last layer."""
+    p = np.array(params, dtype=np.float64, copy=True)
+    off, o = {}, 0
+    for name, shp in param_layout(spec):
+        off[name] = (o, shp)
+        o += int(np.prod(shp))
+    o1, (h, cl) = off["lift1.w"]
+    w1 = p[o1:o1 + h * cl].reshape(h, cl)
+    ob1, _ = off["lift1.b"]
+    b1 = p[ob1:ob1 + h]
+    sc = np.ones(cl)
+    sh = np.zeros(cl)
+    sc[:spec.cin] = in_scale
+    sh[:spec.cin] = in_shift
+    b1 -= (w1 * (sh / sc)[None, :]).sum(axis=1)
+    w1 /= sc[None, :]
+    ow, (co, din) = off["dec_out.w"]
+    ob, _ = off["dec_out.b"]
+    wo = p[ow:ow + co * din].reshape(co, din)
+    bo = p[ob:ob + co]
+    wo *= np.asarray(out_scale, dtype=np.float64)[:, None]
+    bo *= np.asarray(out_scale, dtype=np.float64)
+    bo += np.asarray(out_shift, dtype=np.float64)
+    return p

@@ -131,29 +131,8 @@ def fold(params: np.ndarray, s_r: float, s_u: float) -> np.ndarray:
     layer, and the output map (rho, ux, uy) = (1 + s_r o0, s_u o1, s_u o2) folded into
     the decoder's last layer."""
     from paper_2604_27158_amd import fno as gfno
-    p = np.array(params, dtype=np.float64, copy=True)
-    off = {}
-    o = 0
-    for name, shp in gfno.param_layout(SPEC):
-        off[name] = (o, shp)
-        o += int(np.prod(shp))
-    o1, (h, cl) = off["lift1.w"]
-    w1 = p[o1:o1 + h * cl].reshape(h, cl)
-    ob1, _ = off["lift1.b"]
-    b1 = p[ob1:ob1 + h]
-    scale_in = np.ones(cl)
-    scale_in[0], scale_in[1], scale_in[2] = 1.0 / s_r, 1.0 / s_u, 1.0 / s_u
-    b1 -= w1[:, 0] / s_r           # the -1 of rho - 1
-    w1 *= scale_in[None, :]
-    ow, (co, din) = off["dec_out.w"]
-    ob, _ = off["dec_out.b"]
-    wo = p[ow:ow + co * din].reshape(co, din)
-    bo = p[ob:ob + co]
-    sc = np.array([s_r, s_u, s_u])
-    wo *= sc[:, None]
-    bo *= sc
-    bo[0] += 1.0
-    return p
+    return gfno.fold_affine(SPEC, params, [s_r, s_u, s_u, 1.0], [1.0, 0.0, 0.0, 0.0],
+                            [s_r, s_u, s_u], [1.0, 0.0, 0.0])
 
 
 def train(X, Y, Xv, Yv, epochs: int, batch: int = 16, lr: float = 1e-2, seed: int = 3, log=None):

@@ -234,6 +234,43 @@ def periodic_box(nx: int, ny: int, tau: float, gx: float = 0.0, gy: float = 0.0,
                    name=f"box{nx}x{ny}")
 
 
+# Double shear layer (the paper's unsteady case, Sec. 3.2.1, Eqs. 9-10): a periodic
+# unit square at n x n, U = 1 m/s, nu = 0.001 m^2/s, outputs every 223 lattice steps
+# over a 3 s horizon of 30 outputs.  Lattice units: dt = 3 s / (30 * 223),
+# dx = 1/n, so u_lat = U dt / dx and nu_lat = nu dt / dx^2.
+SHEAR_DT_OUT = 223
+SHEAR_OUTPUTS = 30
+
+
+def shear_units(n: int = 128):
+    """(u_lat, tau) of the double shear layer at n x n."""
+    dt = 3.0 / (SHEAR_OUTPUTS * SHEAR_DT_OUT)
+    dx = 1.0 / n
+    u_lat = 1.0 * dt / dx
+    nu_lat = 0.001 * dt / (dx * dx)
+    return u_lat, 0.5 + 3.0 * nu_lat
+
+
+def double_shear_layer(seed: int, n: int = 128, re_lo: float = 8.0, re_hi: float = 50.0):
+    """(Lattice, rho, ux, uy) of one double-shear-layer trajectory.  u = U tanh(A1 (y1 - y))
+    for y >= 1/2 and U tanh(A2 (y - y2)) below, v = 0.1 U sin(2 pi (x + 1/4)), rho = 1,
+    node (i, j) at (x, y) = (i/n, j/n).  Randomised: the layer centres y1 ~ U(0.7, 0.8),
+    y2 ~ U(0.2, 0.3), and each layer's Reynolds number on its thickness 1/A,
+    Re = U / (A nu) ~ U(8, 50), so A = U / (Re nu)."""
+    rng = SplitMix64(seed)
+    y1, y2 = rng.uniform(0.7, 0.8), rng.uniform(0.2, 0.3)
+    re1, re2 = rng.uniform(re_lo, re_hi), rng.uniform(re_lo, re_hi)
+    a1, a2 = 1.0 / (re1 * 0.001), 1.0 / (re2 * 0.001)
+    u_lat, tau = shear_units(n)
+    y, x = np.mgrid[0:n, 0:n].astype(np.float64) / n
+    ux = np.where(y >= 0.5, np.tanh(a1 * (y1 - y)), np.tanh(a2 * (y - y2))) * u_lat
+    uy = 0.1 * u_lat * np.sin(2.0 * np.pi * (x + 0.25))
+    rho = np.ones((n, n))
+    lat = periodic_box(n, n, tau, seed=seed)
+    lat.name = f"shear{n}-Re{re1:.0f}-{re2:.0f}-s{seed}"
+    return lat, rho, ux, uy
+
+
 def random_macro_fields(seed: int, nx: int, ny: int, amp_rho: float = 1e-2,
                         amp_u: float = 2e-2, modes: int = 3):
     """Smooth random (rho, ux, uy) fields: rho = 1 + small band-limited perturbation,

@@ -1,0 +1,69 @@
+"""Host logic of the double-shear-layer study: the initial condition of Eqs. 9-10
+in lattice units, the 1:k hybrid cadence, and the error measures."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2604_27158_amd import shear as S
+from paper_2604_27158_amd import workloads as W
+
+
+def test_lattice_units_match_the_paper_setup():
+    u_lat, tau = W.shear_units(128)
+    dt = 3.0 / (30 * 223)                   # 30 outputs of 223 steps cover 3 s
+    assert u_lat == pytest.approx(1.0 * dt * 128)
+    assert (tau - 0.5) / 3.0 == pytest.approx(0.001 * dt * 128 ** 2)
+    assert u_lat / math.sqrt(1.0 / 3.0) < 0.1   # Mach number
+
+
+def test_initial_condition_profile():
+    lat, r, u, v = W.double_shear_layer(3, 128)
+    u_lat, tau = W.shear_units(128)
+    assert (lat.nx, lat.ny, lat.bc_x, lat.bc_y) == (128, 128, W.BC_PERIODIC, W.BC_PERIODIC)
+    assert lat.tau == pytest.approx(tau) and np.all(r == 1.0)
+    # the middle band flows one way, the outer bands the other
+    assert u[64, 0] > 0.99 * u_lat and u[2, 0] < -0.99 * u_lat and u[125, 0] < -0.99 * u_lat
+    # v = 0.1 U sin(2 pi (x + 1/4)) does not depend on y
+    x = np.arange(128) / 128
+    assert np.allclose(v, 0.1 * u_lat * np.sin(2 * np.pi * (x + 0.25))[None, :])
+    # u depends on y only, and its two zero crossings sit in the randomised ranges
+    assert np.allclose(u, u[:, :1])
+    crossings = np.nonzero(np.diff(np.sign(u[:, 0])))[0] / 128
+    assert len(crossings) == 2 and 0.19 < crossings[0] < 0.31 and 0.69 < crossings[1] < 0.81
+
+
+def test_layer_thickness_follows_the_reynolds_range():
+    """The steepest slope of a tanh layer is U A with A = U / (Re nu), Re in [8, 50]."""
+    for seed in range(5):
+        _, _, u, _ = W.double_shear_layer(seed, 1024)
+        u_lat, _ = W.shear_units(1024)
+        slope = np.abs(np.diff(u[:, 0])).max() * 1024 / u_lat     # per metre, in units of U
+        assert 1.0 / (50 * 0.001) * 0.9 <= slope <= 1.0 / (8 * 0.001) * 1.01
+
+
+@pytest.mark.parametrize("k,n_fno", [(1, 15), (2, 10), (3, 8)])
+def test_hybrid_cadence(k, n_fno):
+    assert sum(S.is_fno_interval(t, k) for t in range(S.OUTPUTS)) == n_fno
+    assert S.is_fno_interval(0, k)
+
+
+def test_vorticity_of_a_shear_wave():
+    """u = sin(2 pi y / N): dv/dx - du/dy = -(2 pi/N) cos(2 pi y/N) sin(2 pi/N)/(2 pi/N)
+    with central differences."""
+    n = 64
+    y = np.arange(n)[:, None] * np.ones((1, n))
+    f = np.stack([np.ones((n, n)), np.sin(2 * np.pi * y / n), np.zeros((n, n))])
+    k = 2 * np.pi / n
+    assert np.allclose(S.vorticity(f), -np.cos(k * y) * np.sin(k), atol=1e-13)
+
+
+def test_errors():
+    rng = np.random.default_rng(0)
+    ref = rng.standard_normal((3, 16, 16))
+    assert S.errors(ref, ref) == (0.0, 0.0)
+    mse, vort = S.errors(ref + 0.1, ref)
+    assert mse == pytest.approx(0.01) and vort == pytest.approx(0.0, abs=1e-14)
+    bad = ref.copy()
+    bad[0, 0, 0] = np.nan
+    assert S.errors(bad, ref) == (float("inf"), float("inf"))
