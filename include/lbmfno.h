@@ -337,6 +337,18 @@ int fno_workspace_size(const fno_model* m, int32_t B, size_t* bytes);
 int fno_forward(const fno_model* m, const float* d_in, float* d_out, int32_t B, void* d_ws,
                 size_t ws_bytes, void* stream);
 
+/* fno_forward replayed from a HIP graph: the first call for an (d_in, d_out, B,
+ * d_ws) tuple captures the forward's launches on a stream private to the model
+ * and instantiates them; later calls with the same tuple only launch that graph
+ * on `stream` (one launch instead of 3 L + 2), which is what a batch-1 surrogate
+ * step inside a hybrid loop needs.  A call with another tuple re-captures.  The
+ * captured graph reads the model's weights through their device pointers, so
+ * fno_set_params refreshes also reach it.  Same arguments, results and errors as
+ * fno_forward (bitwise equal outputs); the model is not reentrant: calls on one
+ * model from several threads must be serialised by the caller. */
+int fno_forward_graph(fno_model* m, const float* d_in, float* d_out, int32_t B, void* d_ws,
+                      size_t ws_bytes, void* stream);
+
 /* ---------------------------------------------------------------- FNO training
  * Training of the surrogate on lattice-generated samples (Sec. 2.2: FNO models
  * trained by minimising the mean squared error of the predicted fields, AdamW).

@@ -27,6 +27,7 @@
 namespace lbmfno {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 // One 32x32 tile C += A[32 x K] * Bt[32 x K]^T, A and Bt row-major with K
@@ -95,6 +96,14 @@ struct FnoDev {
 // Lift: x (cin channels, float32) + coordinates -> width/2 (act) -> width, rounded
 // to bf16, written channels-last; the zero-padded region and w >= W' hold zeros.
 __global__ __launch_bounds__(256) void k_fno_lift(FnoDev d, const float* __restrict__ x) {
+    // weights staged in LDS once per workgroup (uniform per-weight global loads
+    // would serialise behind the runtime channel-count guards)
+    __shared__ float w1s[32 * 8], b1s[32], w2s[64 * 32], b2s[64];
+    for (int t = threadIdx.x; t < d.half * d.cl; t += blockDim.x) w1s[t] = d.lift1w[t];
+    for (int t = threadIdx.x; t < d.half; t += blockDim.x) b1s[t] = d.lift1b[t];
+    for (int t = threadIdx.x; t < d.width * d.half; t += blockDim.x) w2s[t] = d.lift2w[t];
+    for (int t = threadIdx.x; t < d.width; t += blockDim.x) b2s[t] = d.lift2b[t];
+    __syncthreads();
     const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t total = (size_t)d.B * d.Hp * d.Wpad;
     if (idx >= total) return;
@@ -124,10 +133,10 @@ __global__ __launch_bounds__(256) void k_fno_lift(FnoDev d, const float* __restr
         const size_t pt = ((size_t)b * d.H + h) * d.W + w;
 #pragma unroll
         for (int c = 0; c < 64; ++c)
-            if (c < d.width) o[c] = d.lift2b[c];
+            if (c < d.width) o[c] = b2s[c];
         for (int k = 0; k < d.half; ++k) {
-            float s = d.lift1b[k];
-            const float* w1 = d.lift1w + (size_t)k * d.cl;
+            float s = b1s[k];
+            const float* w1 = w1s + k * d.cl;
 #pragma unroll
             for (int c = 0; c < 8; ++c)
                 if (c < d.cl) s = fmaf(w1[c], z[c], s);
@@ -136,7 +145,7 @@ __global__ __launch_bounds__(256) void k_fno_lift(FnoDev d, const float* __restr
             // o[c] += W2[c][k] * hid[k], accumulated over k in order
 #pragma unroll
             for (int c = 0; c < 64; ++c)
-                if (c < d.width) o[c] = fmaf(d.lift2w[(size_t)c * d.half + k], hk, o[c]);
+                if (c < d.width) o[c] = fmaf(w2s[c * d.half + k], hk, o[c]);
         }
     }
 #pragma unroll
@@ -223,19 +232,27 @@ __global__ __launch_bounds__(256) void k_fno_col(FnoDev d, int layer) {
     for (int i = tid; i < d.CP * d.R2; i += blockDim.x) ys[i] = to_bf16(0.0f);
     __syncthreads();
     // Y[k][o] = sum_i X[k][i] R[i][o][k][k2] (complex), k over the 2 m1 kept rows
+    // Only the width real channels take part: the padded channels of X are zero and
+    // so are R's padded rows and columns, and ys was cleared above.  Weights are read
+    // two complex values (8 bytes) at a time; width is even.
     const __bf16* R = d.Rmix + ((size_t)layer * d.m2 + k2) * d.K1 * d.CP * d.CP * 2;
-    for (int idx = tid; idx < d.K1 * d.CP; idx += blockDim.x) {
-        const int k = idx / d.CP, o = idx % d.CP;
+    for (int idx = tid; idx < d.K1 * d.width; idx += blockDim.x) {
+        const int k = idx / d.width, o = idx % d.width;
         const float* xr = xs + k * d.CP;
         const float* xi = xs + (d.K1 + k) * d.CP;
-        const __bf16* Rk = R + ((size_t)k * d.CP + o) * d.CP * 2;
+        const bf16x4* Rk = reinterpret_cast<const bf16x4*>(R + ((size_t)k * d.CP + o) * d.CP * 2);
         float sr = 0.0f, si = 0.0f;
-        for (int i = 0; i < d.CP; ++i) {
-            const float rr = from_bf16(Rk[2 * i]), rim = from_bf16(Rk[2 * i + 1]);
-            sr = fmaf(xr[i], rr, sr);
-            sr = fmaf(-xi[i], rim, sr);
-            si = fmaf(xr[i], rim, si);
-            si = fmaf(xi[i], rr, si);
+        for (int i = 0; i < d.width; i += 2) {
+            const bf16x4 r4 = Rk[i >> 1];
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const float rr = from_bf16(r4[2 * e]), rim = from_bf16(r4[2 * e + 1]);
+                const float a = xr[i + e], c = xi[i + e];
+                sr = fmaf(a, rr, sr);
+                sr = fmaf(-c, rim, sr);
+                si = fmaf(a, rim, si);
+                si = fmaf(c, rr, si);
+            }
         }
         ys[o * d.R2 + k] = to_bf16(sr);
         ys[o * d.R2 + d.K1 + k] = to_bf16(si);
@@ -396,6 +413,14 @@ struct fno_model {
     // map[j] (or 0 when map[j] < 0); used to refresh weights from device params
     struct Map { void* dst; const int32_t* map; int64_t n; bool bf16; };
     std::vector<Map> maps;
+    // replayable forward: the launches of one (input, output, B, workspace) tuple
+    // captured once on a private stream
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t fwd_exec = nullptr;
+    const void* g_in = nullptr;
+    const void* g_out = nullptr;
+    const void* g_ws = nullptr;
+    int32_t g_B = 0;
 };
 
 static int rup(int x, int m) { return (x + m - 1) / m * m; }
@@ -452,6 +477,8 @@ extern "C" int fno_param_count(const fno_spec* spec, int64_t* count) {
 
 extern "C" void fno_model_destroy(fno_model* m) {
     if (!m) return;
+    if (m->fwd_exec) (void)hipGraphExecDestroy(m->fwd_exec);
+    if (m->cap_stream) (void)hipStreamDestroy(m->cap_stream);
     for (void* p : m->allocs) (void)hipFree(p);
     delete m;
 }
@@ -761,8 +788,8 @@ extern "C" int fno_workspace_size(const fno_model* m, int32_t B, size_t* bytes) 
     return LBM_OK;
 }
 
-extern "C" int fno_forward(const fno_model* m, const float* d_in, float* d_out, int32_t B,
-                           void* d_ws, size_t ws_bytes, void* stream) {
+static int check_forward(const fno_model* m, const float* d_in, float* d_out, int32_t B,
+                         void* d_ws, size_t ws_bytes) {
     if (!m) return fail(LBM_EINVAL, "model is NULL");
     if (!d_in || !d_out || !d_ws) return fail(LBM_EINVAL, "NULL device buffer");
     if (B < 1 || (int64_t)B * m->d.Hp * m->d.Wpad > ((int64_t)1 << 31) / 64)
@@ -772,12 +799,20 @@ extern "C" int fno_forward(const fno_model* m, const float* d_in, float* d_out, 
     d.B = B;
     const WsLayout L = ws_layout(d, B);
     if (ws_bytes < L.total) return fail(LBM_EINVAL, "workspace %zu < %zu bytes", ws_bytes, L.total);
+    return LBM_OK;
+}
+
+// the forward's launches (arguments already checked)
+static void launch_forward(const fno_model* m, const float* d_in, float* d_out, int32_t B,
+                           void* d_ws, hipStream_t st) {
+    FnoDev d = m->d;
+    d.B = B;
+    const WsLayout L = ws_layout(d, B);
     unsigned char* ws = static_cast<unsigned char*>(d_ws);
     d.v0 = reinterpret_cast<__bf16*>(ws);
     d.v1 = reinterpret_cast<__bf16*>(ws + L.v);
     d.T = reinterpret_cast<__bf16*>(ws + 2 * L.v);
     d.Z = reinterpret_cast<__bf16*>(ws + 2 * L.v + L.T);
-    hipStream_t st = (hipStream_t)stream;
     const size_t npts = (size_t)B * d.Hp * d.Wpad;
     k_fno_lift<<<(unsigned)((npts + 255) / 256), 256, 0, st>>>(d, d_in);
     const size_t lds_row = (size_t)d.CP * d.Wpad * 2;
@@ -792,7 +827,44 @@ extern "C" int fno_forward(const fno_model* m, const float* d_in, float* d_out, 
     }
     const size_t nout = (size_t)B * d.H * d.W;
     k_fno_dec<<<(unsigned)((nout + 4 * DEC_PTS - 1) / (4 * DEC_PTS)), 256, dec_lds(d), st>>>(d, cur, d_out);
+}
+
+extern "C" int fno_forward(const fno_model* m, const float* d_in, float* d_out, int32_t B,
+                           void* d_ws, size_t ws_bytes, void* stream) {
+    int rc = check_forward(m, d_in, d_out, B, d_ws, ws_bytes);
+    if (rc) return rc;
+    launch_forward(m, d_in, d_out, B, d_ws, (hipStream_t)stream);
     LBM_HIP(hipGetLastError());
+    return LBM_OK;
+}
+
+extern "C" int fno_forward_graph(fno_model* m, const float* d_in, float* d_out, int32_t B,
+                                 void* d_ws, size_t ws_bytes, void* stream) {
+    int rc = check_forward(m, d_in, d_out, B, d_ws, ws_bytes);
+    if (rc) return rc;
+    if (!m->fwd_exec || m->g_in != d_in || m->g_out != d_out || m->g_ws != d_ws || m->g_B != B) {
+        if (m->fwd_exec) {
+            LBM_HIP(hipGraphExecDestroy(m->fwd_exec));
+            m->fwd_exec = nullptr;
+        }
+        if (!m->cap_stream) LBM_HIP(hipStreamCreateWithFlags(&m->cap_stream, hipStreamNonBlocking));
+        hipGraph_t graph = nullptr;
+        LBM_HIP(hipStreamBeginCapture(m->cap_stream, hipStreamCaptureModeThreadLocal));
+        launch_forward(m, d_in, d_out, B, d_ws, m->cap_stream);
+        hipError_t e = hipStreamEndCapture(m->cap_stream, &graph);
+        if (e != hipSuccess) return fail(LBM_EHIP, "graph capture: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&m->fwd_exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            m->fwd_exec = nullptr;
+            return fail(LBM_EHIP, "graph instantiate: %s", hipGetErrorString(e));
+        }
+        m->g_in = d_in;
+        m->g_out = d_out;
+        m->g_ws = d_ws;
+        m->g_B = B;
+    }
+    LBM_HIP(hipGraphLaunch(m->fwd_exec, (hipStream_t)stream));
     return LBM_OK;
 }
 
@@ -1110,12 +1182,13 @@ __global__ __launch_bounds__(256) void k_fno_col_bwd(FnoDev d, FnoBwd g, int lay
     for (int i = tid; i < d.CP * d.R2; i += blockDim.x) ys[i] = to_bf16(0.0f);
     __syncthreads();
     const __bf16* R = d.Rmix + ((size_t)layer * d.m2 + k2) * d.K1 * d.CP * d.CP * 2;
-    for (int idx = tid; idx < d.K1 * d.CP; idx += blockDim.x) {
-        const int k = idx / d.CP, i = idx % d.CP;
+    // padded channels of R are zero: only the width real ones take part
+    for (int idx = tid; idx < d.K1 * d.width; idx += blockDim.x) {
+        const int k = idx / d.width, i = idx % d.width;
         const float* yr = xs + k * d.CP;
         const float* yi = xs + (d.K1 + k) * d.CP;
         float sr = 0.0f, si = 0.0f;
-        for (int o = 0; o < d.CP; ++o) {
+        for (int o = 0; o < d.width; ++o) {
             const __bf16* Rp = R + (((size_t)k * d.CP + o) * d.CP + i) * 2;
             const float rr = from_bf16(Rp[0]), rim = from_bf16(Rp[1]);
             sr = fmaf(yr[o], rr, sr);

@@ -67,7 +67,10 @@ class Fno:
             self._ws[B] = torch.empty(int(n.value), dtype=torch.uint8, device="cuda")
         return self._ws[B]
 
-    def forward(self, x, out=None, stream=None):
+    def forward(self, x, out=None, stream=None, graph=False):
+        """out = FNO(x) on `stream` (the current stream by default).  graph=True
+        replays the launches from a HIP graph captured for this (x, out, B)
+        tuple; keep x and out the same tensors from call to call to reuse it."""
         import torch
         x = x.to(device="cuda", dtype=torch.float32).contiguous()
         B = x.shape[0]
@@ -83,8 +86,9 @@ class Fno:
             stream.wait_stream(cur)
             for t in (x, out):
                 t.record_stream(stream)
-        _L.check(self.lib.fno_forward(self.model, x.data_ptr(), out.data_ptr(), int(B), ws.data_ptr(),
-                                      ws.numel(), _L.stream_handle(stream)), "fno_forward")
+        fn = self.lib.fno_forward_graph if graph else self.lib.fno_forward
+        _L.check(fn(self.model, x.data_ptr(), out.data_ptr(), int(B), ws.data_ptr(), ws.numel(),
+                    _L.stream_handle(stream)), "fno_forward")
         return out
 
     __call__ = forward

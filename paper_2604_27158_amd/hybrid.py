@@ -96,7 +96,7 @@ class HybridRunner:
             self.x[0, :3].copy_(macros)
             self.x[0, 3].copy_(self.maskf)
             for k in range(self.k_fno):
-                self.fno.forward(self.x, out=self.y, stream=self.lat.stream)
+                self.fno.forward(self.x, out=self.y, stream=self.lat.stream, graph=True)
                 if k + 1 < self.k_fno:
                     self.x[0, :3].copy_(self.y[0])
         return self.y[0]

@@ -114,6 +114,7 @@ SIGNATURES = [
     ("fno_model_destroy", None, [_p]),
     ("fno_workspace_size", ctypes.c_int, [_p, _i32, ctypes.POINTER(ctypes.c_size_t)]),
     ("fno_forward", ctypes.c_int, [_p, _p, _p, _i32, _p, ctypes.c_size_t, _p]),
+    ("fno_forward_graph", ctypes.c_int, [_p, _p, _p, _i32, _p, ctypes.c_size_t, _p]),
     ("fno_train_workspace_size", ctypes.c_int, [_p, _i32, ctypes.POINTER(ctypes.c_size_t)]),
     ("fno_forward_train", ctypes.c_int, [_p, _p, _p, _i32, _p, ctypes.c_size_t, _p]),
     ("fno_backward", ctypes.c_int, [_p, _p, _p, _i32, _p, ctypes.c_size_t, _p, _p]),
@@ -284,10 +285,19 @@ class Lattice:
         check(self.lib.lbm_reinit_from_macro(self.ctx, rho.data_ptr(), ux.data_ptr(), uy.data_ptr()),
               "lbm_reinit_from_macro")
 
-    def macros(self, rho_minus_one: bool = False):
+    def macros(self, rho_minus_one: bool = False, out=None):
+        """(rho, ux, uy) [3][ny][nx] float32; written into `out` (a contiguous device
+        tensor of that shape) when given, else into a new tensor."""
         import torch
-        with torch.cuda.stream(self.stream):
-            out = torch.empty((3, self.ny, self.nx), dtype=torch.float32, device="cuda")
+        if out is None:
+            with torch.cuda.stream(self.stream):
+                out = torch.empty((3, self.ny, self.nx), dtype=torch.float32, device="cuda")
+        else:
+            if (tuple(out.shape) != (3, self.ny, self.nx) or out.dtype != torch.float32
+                    or not out.is_cuda or not out.is_contiguous()):
+                raise ValueError("out must be a contiguous float32 device tensor [3][ny][nx]")
+            self._after_caller()   # the caller's pending use of `out` comes first
+            out.record_stream(self.stream)
         check(self.lib.lbm_get_macro(self.ctx, out[0].data_ptr(), out[1].data_ptr(),
                                      out[2].data_ptr(), int(rho_minus_one)), "lbm_get_macro")
         self._hand_over(out)

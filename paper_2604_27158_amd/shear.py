@@ -131,19 +131,30 @@ class Surrogate:
     """Both trained models of a group on the 128 x 128 grid.  step(fields) maps raw
     (rho, ux, uy) [3][N][N] (device) one Delta T ahead."""
 
-    def __init__(self, group: str, path: str | None = None):
+    def __init__(self, group: str, path: str | None = None, graph: bool = True):
+        import torch
         from paper_2604_27158_amd import fno as gfno
         spec_r, spec_u = GROUPS[group]
         with np.load(path or weights_path(group), allow_pickle=False) as z:
             self.rho = gfno.Fno(spec_r, z["rho_params"], N, N)
             self.u = gfno.Fno(spec_u, z["u_params"], N, N)
         self.group = group
+        self.graph = graph
+        # fixed input and output buffers: the two forwards replay captured graphs
+        self.x = torch.empty((3, N, N), dtype=torch.float32, device="cuda")
+        self.y = torch.empty((3, N, N), dtype=torch.float32, device="cuda")
 
-    def step(self, fields):
-        import torch
-        r = self.rho.forward(fields[0:1].reshape(1, 1, N, N).contiguous())
-        u = self.u.forward(fields[1:3].reshape(1, 2, N, N).contiguous())
-        return torch.cat([r[0], u[0]], dim=0)
+    def step(self, fields=None):
+        """One Delta T ahead from raw (rho, ux, uy) [3][N][N] on the device; with
+        fields=None the input is what the caller already wrote into self.x (for
+        instance Lattice.macros(out=sur.x)).  Returns self.y, which the next step
+        overwrites."""
+        if fields is not None and fields.data_ptr() != self.x.data_ptr():
+            self.x.copy_(fields)
+        x, y = self.x, self.y
+        self.rho.forward(x[0:1].view(1, 1, N, N), out=y[0:1].view(1, 1, N, N), graph=self.graph)
+        self.u.forward(x[1:3].view(1, 2, N, N), out=y[1:3].view(1, 2, N, N), graph=self.graph)
+        return y
 
 
 def vorticity(f):
@@ -220,7 +231,8 @@ def timed_runs(sur: Surrogate, seed: int, reps: int = 3):
         t = 0
         while t < OUTPUTS:
             if is_fno_interval(t, k):
-                y = sur.step(G.macros())
+                G.macros(out=sur.x)
+                y = sur.step()
                 G.reinit(y[0], y[1], y[2])
                 t += 1
             else:

@@ -114,3 +114,4 @@ def test_fno_model_create_validates_on_host(lib):
     assert lib.fno_model_create(ctypes.byref(m), ctypes.byref(gfno.to_c(good)),
                                 p.ctypes.data_as(ctypes.c_void_p), 10, 64, 64) == -1
     assert lib.fno_forward(None, 1, 2, 1, 3, 100, None) == -1
+    assert lib.fno_forward_graph(None, 1, 2, 1, 3, 100, None) == -1

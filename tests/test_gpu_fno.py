@@ -107,3 +107,30 @@ def test_fno_rejects_bad_arguments(gpu):
     ws = m.workspace(1)
     rc = m.lib.fno_forward(m.model, x.data_ptr(), out.data_ptr(), 1, ws.data_ptr(), 16, None)
     assert rc == -1
+
+
+@pytest.mark.parametrize("name", ["shear-u-small", "ragged-50x70-w64"])
+def test_fno_graph_forward_matches_eager(gpu, name):
+    """The graph-replayed forward gives bit-identical outputs to the eager one: on
+    replays with new input contents, after a change of output buffer (re-capture)
+    and of batch size, with eager work and synchronisations in between."""
+    import torch
+    from paper_2604_27158_amd import fno as gfno
+    _, spec, H, Wd, _ = next(c for c in CASES if c[0] == name)
+    params = W.fno_random_params(zlib.crc32(name.encode()) & 0xFFFF, gfno.param_layout(spec), spec.width)
+    m = gfno.Fno(spec, params, H, Wd)
+    x = torch.from_numpy(fields_input(11, 2, spec.cin, H, Wd)).float().cuda()
+    xs = x[0:1].clone()
+    out = torch.empty((1, spec.cout, H, Wd), device="cuda")
+    for rep in range(3):
+        xs.copy_(x[rep % 2:rep % 2 + 1] * (1.0 + 0.01 * rep))
+        want = m(xs.clone()).clone()
+        m.forward(xs, out=out, graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(out, want), rep
+    out2 = torch.empty_like(out)
+    m.forward(xs, out=out2, graph=True)
+    assert torch.equal(out2, m(xs))
+    outb = torch.empty((2, spec.cout, H, Wd), device="cuda")
+    m.forward(x, out=outb, graph=True)
+    assert torch.equal(outb, m(x))
