@@ -70,11 +70,11 @@ extern "C" {
                               force in slowly varying flow */
 
 /* Step-kernel choice; every choice computes the same values. */
-#define LBM_KERNEL_AUTO 0  /* by lattice size (or the autotuner's cached pick) */
+#define LBM_KERNEL_AUTO 0  /* LBM_KERNEL_PAIR (batches: the autotuner's cached pick) */
 #define LBM_KERNEL_NODE 1  /* one node per lane, 4-byte accesses (any nx) */
 #define LBM_KERNEL_QUAD 2  /* four x nodes per lane, 16-byte accesses (nx % 4 == 0,
                               16-byte aligned stores) */
-#define LBM_KERNEL_PAIR 3  /* two steps per launch: a 64 x 16 tile and its one-node
+#define LBM_KERNEL_PAIR 3  /* two steps per launch: a 64 x 4 tile and its one-node
                               ring advance one step into LDS, then the tile advances
                               again from LDS (temporal blocking; half the store
                               traffic per step).  Any nx. */

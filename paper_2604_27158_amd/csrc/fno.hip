@@ -40,10 +40,34 @@ __device__ __forceinline__ f32x16 mma_tile(const __bf16* A, int lda, const __bf1
     const int row = lane & 31, kh = lane >> 5;
     const __bf16* a = A + row * lda + 8 * kh;
     const __bf16* b = Bt + row * ldb + 8 * kh;
-    for (int k0 = 0; k0 < K; k0 += 16) {
-        const bf16x8 av = *reinterpret_cast<const bf16x8*>(a + k0);
-        const bf16x8 bv = *reinterpret_cast<const bf16x8*>(b + k0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+    // groups of four k-steps: the next group's operands are requested before the
+    // current group's products, so that at most one memory latency per group is
+    // exposed (these tiles are latency-bound at batch 1: few waves per CU)
+    constexpr int U = 4;
+    bf16x8 av[U], bv[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j)
+        if (16 * j < K) {
+            av[j] = *reinterpret_cast<const bf16x8*>(a + 16 * j);
+            bv[j] = *reinterpret_cast<const bf16x8*>(b + 16 * j);
+        }
+    for (int k0 = 0; k0 < K; k0 += 16 * U) {
+        bf16x8 an[U], bn[U];
+        const int k1 = k0 + 16 * U;
+#pragma unroll
+        for (int j = 0; j < U; ++j)
+            if (k1 + 16 * j < K) {
+                an[j] = *reinterpret_cast<const bf16x8*>(a + k1 + 16 * j);
+                bn[j] = *reinterpret_cast<const bf16x8*>(b + k1 + 16 * j);
+            }
+#pragma unroll
+        for (int j = 0; j < U; ++j)
+            if (k0 + 16 * j < K) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[j], bv[j], acc, 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            av[j] = an[j];
+            bv[j] = bn[j];
+        }
     }
     return acc;
 }
@@ -96,13 +120,23 @@ struct FnoDev {
 // Lift: x (cin channels, float32) + coordinates -> width/2 (act) -> width, rounded
 // to bf16, written channels-last; the zero-padded region and w >= W' hold zeros.
 __global__ __launch_bounds__(256) void k_fno_lift(FnoDev d, const float* __restrict__ x) {
-    // weights staged in LDS once per workgroup (uniform per-weight global loads
-    // would serialise behind the runtime channel-count guards)
-    __shared__ float w1s[32 * 8], b1s[32], w2s[64 * 32], b2s[64];
-    for (int t = threadIdx.x; t < d.half * d.cl; t += blockDim.x) w1s[t] = d.lift1w[t];
-    for (int t = threadIdx.x; t < d.half; t += blockDim.x) b1s[t] = d.lift1b[t];
-    for (int t = threadIdx.x; t < d.width * d.half; t += blockDim.x) w2s[t] = d.lift2w[t];
-    for (int t = threadIdx.x; t < d.width; t += blockDim.x) b2s[t] = d.lift2b[t];
+    // weights staged in LDS once per workgroup, zero-padded to the register tile
+    // (8 inputs, 64 outputs) so that the point loop has no channel-count branches
+    // and reads each weight row with 16-byte broadcasts
+    __shared__ __align__(16) float w1s[32][8];
+    __shared__ __align__(16) float w2t[32][64];  // w2t[k][c] = W2[c][k]
+    __shared__ __align__(16) float b2s[64];
+    __shared__ float b1s[32];
+    for (int t = threadIdx.x; t < 32 * 8; t += blockDim.x) {
+        const int k = t / 8, c = t % 8;
+        w1s[k][c] = (k < d.half && c < d.cl) ? d.lift1w[k * d.cl + c] : 0.0f;
+    }
+    for (int t = threadIdx.x; t < 32 * 64; t += blockDim.x) {
+        const int k = t / 64, c = t % 64;
+        w2t[k][c] = (k < d.half && c < d.width) ? d.lift2w[c * d.half + k] : 0.0f;
+    }
+    for (int t = threadIdx.x; t < 64; t += blockDim.x) b2s[t] = t < d.width ? d.lift2b[t] : 0.0f;
+    for (int t = threadIdx.x; t < 32; t += blockDim.x) b1s[t] = t < d.half ? d.lift1b[t] : 0.0f;
     __syncthreads();
     const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t total = (size_t)d.B * d.Hp * d.Wpad;
@@ -132,21 +166,21 @@ __global__ __launch_bounds__(256) void k_fno_lift(FnoDev d, const float* __restr
         }
         const size_t pt = ((size_t)b * d.H + h) * d.W + w;
 #pragma unroll
-        for (int c = 0; c < 64; ++c)
-            if (c < d.width) o[c] = b2s[c];
+        for (int c = 0; c < 64; ++c) o[c] = b2s[c];
         for (int k = 0; k < d.half; ++k) {
+            // padded inputs carry zero weights and zero values: exact no-ops
             float s = b1s[k];
-            const float* w1 = w1s + k * d.cl;
 #pragma unroll
-            for (int c = 0; c < 8; ++c)
-                if (c < d.cl) s = fmaf(w1[c], z[c], s);
+            for (int c = 0; c < 8; ++c) s = fmaf(w1s[k][c], z[c], s);
             if (d.sv_a1) d.sv_a1[pt * 32 + k] = s;
             const float hk = act_f(d.act, s);
             // o[c] += W2[c][k] * hid[k], accumulated over k in order
 #pragma unroll
-            for (int c = 0; c < 64; ++c)
-                if (c < d.width) o[c] = fmaf(w2s[c * d.half + k], hk, o[c]);
+            for (int c = 0; c < 64; ++c) o[c] = fmaf(w2t[k][c], hk, o[c]);
         }
+#pragma unroll
+        for (int c = 0; c < 64; ++c)
+            if (c >= d.width) o[c] = 0.0f;  // padded channels stay zero
     }
 #pragma unroll
     for (int c0 = 0; c0 < 64; c0 += 8) {
@@ -204,7 +238,7 @@ __global__ __launch_bounds__(256) void k_fno_rowfwd(FnoDev d, const __bf16* __re
 }
 
 // Column forward DFT, per-mode complex mixing and column inverse DFT for one
-// (sample, k2).  Also zeroes Z's padded coefficient columns (k2 == 0 group).
+// (sample, k2).  Also clears a share of Z's padded coefficient columns.
 __global__ __launch_bounds__(256) void k_fno_col(FnoDev d, int layer) {
     extern __shared__ __align__(16) unsigned char smem[];
     float* xs = reinterpret_cast<float*>(smem);                                  // [R2][CP]
@@ -273,13 +307,12 @@ __global__ __launch_bounds__(256) void k_fno_col(FnoDev d, int layer) {
                 d.Z[(((size_t)b * d.Hp + h) * d.CP + o) * d.KKp + 2 * k2 + ri] = to_bf16(acc[r]);
         }
     }
-    if (k2 == 0) {
-        const int padw = d.KKp - 2 * d.m2;
-        for (int i = tid; i < d.Hp * d.CP * padw; i += blockDim.x) {
-            const int p = i % padw, ho = i / padw;
-            d.Z[((size_t)b * d.Hp * d.CP + ho) * d.KKp + 2 * d.m2 + p] = to_bf16(0.0f);
-        }
-    }
+    // Z's padded coefficient columns p (2 m2 <= 2 m2 + p < KKp) are cleared by the
+    // groups with k2 == p mod m2, spread so that no one group serialises the clear
+    const int padw = d.KKp - 2 * d.m2;
+    for (int p = k2; p < padw; p += d.m2)
+        for (int i = tid; i < d.Hp * d.CP; i += blockDim.x)
+            d.Z[((size_t)b * d.Hp * d.CP + i) * d.KKp + 2 * d.m2 + p] = to_bf16(0.0f);
 }
 
 // Row inverse DFT + 1x1 convolution + bias (+ activation) for one (b, h).
@@ -1213,13 +1246,12 @@ __global__ __launch_bounds__(256) void k_fno_col_bwd(FnoDev d, FnoBwd g, int lay
                 d.Z[(((size_t)b * d.Hp + h) * d.CP + o) * d.KKp + 2 * k2 + ri] = to_bf16(acc[r]);
         }
     }
-    if (k2 == 0) {
-        const int padw = d.KKp - 2 * d.m2;
-        for (int i = tid; i < d.Hp * d.CP * padw; i += blockDim.x) {
-            const int p = i % padw, ho = i / padw;
-            d.Z[((size_t)b * d.Hp * d.CP + ho) * d.KKp + 2 * d.m2 + p] = to_bf16(0.0f);
-        }
-    }
+    // Z's padded coefficient columns p (2 m2 <= 2 m2 + p < KKp) are cleared by the
+    // groups with k2 == p mod m2, spread so that no one group serialises the clear
+    const int padw = d.KKp - 2 * d.m2;
+    for (int p = k2; p < padw; p += d.m2)
+        for (int i = tid; i < d.Hp * d.CP; i += blockDim.x)
+            d.Z[((size_t)b * d.Hp * d.CP + i) * d.KKp + 2 * d.m2 + p] = to_bf16(0.0f);
 }
 
 // dv[w][i] = sum_kk B1[w][kk] Z[i][kk] + sum_o dpre[w][o] Wc[o][i], per (b, h) row.

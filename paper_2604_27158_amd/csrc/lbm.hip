@@ -1248,11 +1248,10 @@ extern "C" int lbm_init(lbm_ctx** out, const lbm_config* cfg, const uint8_t* d_m
         delete c;
         return fail(LBM_EUNSUPPORTED, "four-wide kernel needs nx %% 4 == 0 and 16-byte aligned stores");
     }
-    // Two steps per launch beat every one-step kernel from ~100k nodes up (measured
-    // on 512x256, 1024x512 and 8192x4096); below that the lattice is launch-bound
-    // and the one-node kernel is used.
-    c->pair = cfg->kernel == LBM_KERNEL_PAIR ||
-              (cfg->kernel == LBM_KERNEL_AUTO && (size_t)cfg->nx * cfg->ny >= ((size_t)1 << 16));
+    // Two steps per launch beat every one-step kernel at every size measured
+    // (128x128, 512x256, 1024x512, 8192x4096): on large lattices by halving the
+    // store traffic, on small, latency-bound ones by halving the launches.
+    c->pair = cfg->kernel == LBM_KERNEL_PAIR || cfg->kernel == LBM_KERNEL_AUTO;
     c->vec4 = cfg->kernel == LBM_KERNEL_QUAD;
     c->gridx4 = (cfg->nx + 4 * TX - 1) / (4 * TX);
     c->nblocks4 = c->gridx4 * ((cfg->ny + TY - 1) / TY);

@@ -102,7 +102,13 @@ class HybridRunner:
         return self.y[0]
 
     def cycle(self):
-        """One cycle: K FNO calls (guarded), re-initialisation, n_lbm lattice steps."""
+        """One cycle: K FNO calls (guarded), re-initialisation, n_lbm lattice steps,
+        all issued on the lattice's stream (no cross-stream waits inside a cycle)."""
+        import torch
+        with torch.cuda.stream(self.lat.stream):
+            self._cycle()
+
+    def _cycle(self):
         macros = self.lat.macros()
         ref = self.lat.check_fields(macros[0], macros[1], macros[2])
         pred = self._fno_rollout(macros)

@@ -251,11 +251,15 @@ class Lattice:
 
     def _after_caller(self):
         import torch
-        self.stream.wait_stream(torch.cuda.current_stream())
+        cur = torch.cuda.current_stream()
+        if cur != self.stream:   # a caller already on the lattice stream is ordered
+            self.stream.wait_stream(cur)
 
     def _before_caller(self):
         import torch
-        torch.cuda.current_stream().wait_stream(self.stream)
+        cur = torch.cuda.current_stream()
+        if cur != self.stream:
+            cur.wait_stream(self.stream)
 
     def _hand_over(self, *outs):
         """Outputs written on the lattice stream and returned to the caller: the

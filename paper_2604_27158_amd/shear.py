@@ -199,16 +199,18 @@ def rollouts(sur: Surrogate, seed: int):
     hyb = {}
     for k in HYBRIDS:
         H = lbmfno.Lattice.from_workload(lat)
-        H.reinit(ic[0], ic[1], ic[2])
         out = []
-        for t in range(OUTPUTS):
-            if is_fno_interval(t, k):
-                y = sur.step(H.macros())
-                H.reinit(y[0], y[1], y[2])
-                out.append(y.cpu().numpy().astype(np.float64))
-            else:
-                H.step(DT)
-                out.append(H.macros().cpu().numpy().astype(np.float64))
+        with torch.cuda.stream(H.stream):
+            H.reinit(ic[0], ic[1], ic[2])
+            for t in range(OUTPUTS):
+                if is_fno_interval(t, k):
+                    H.macros(out=sur.x)
+                    y = sur.step()
+                    H.reinit(y[0], y[1], y[2])
+                    out.append(y.cpu().numpy().astype(np.float64))
+                else:
+                    H.step(DT)
+                    out.append(H.macros().cpu().numpy().astype(np.float64))
         hyb[k] = out
     return ref, pure, hyb
 
@@ -223,24 +225,28 @@ def timed_runs(sur: Surrogate, seed: int, reps: int = 3):
     G = lbmfno.Lattice.from_workload(lat)
 
     def plain():
-        G.reinit(ic[0], ic[1], ic[2])
-        G.step(OUTPUTS * DT)
+        with torch.cuda.stream(G.stream):
+            G.reinit(ic[0], ic[1], ic[2])
+            G.step(OUTPUTS * DT)
 
     def hybrid(k):
-        G.reinit(ic[0], ic[1], ic[2])
-        t = 0
-        while t < OUTPUTS:
-            if is_fno_interval(t, k):
-                G.macros(out=sur.x)
-                y = sur.step()
-                G.reinit(y[0], y[1], y[2])
-                t += 1
-            else:
-                n = 1
-                while t + n < OUTPUTS and not is_fno_interval(t + n, k):
-                    n += 1
-                G.step(n * DT)
-                t += n
+        # the surrogate runs on the lattice's stream: the hybrid's alternation
+        # needs no cross-stream waits
+        with torch.cuda.stream(G.stream):
+            G.reinit(ic[0], ic[1], ic[2])
+            t = 0
+            while t < OUTPUTS:
+                if is_fno_interval(t, k):
+                    G.macros(out=sur.x)
+                    y = sur.step()
+                    G.reinit(y[0], y[1], y[2])
+                    t += 1
+                else:
+                    n = 1
+                    while t + n < OUTPUTS and not is_fno_interval(t + n, k):
+                        n += 1
+                    G.step(n * DT)
+                    t += n
 
     def clock(fn):
         fn()
