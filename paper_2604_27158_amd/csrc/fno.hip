@@ -6,7 +6,8 @@
 //   v  [Hp][Wpad][CP]   bf16  activations, channels last (CP = width rounded up to
 //                             32, Wpad = W' rounded up to 32; w >= W' is zero)
 //   T  [m2][CP][2][Hpad] bf16 row-DFT coefficients (re, im) with h fastest
-//   Z  [Hp][CP][KKp]    bf16  column-inverse coefficients, (k2, re/im) fastest
+//   Z  [2 m2][Hp][CP]   bf16  column-inverse coefficients, row kk = 2 k2 + (re/im),
+//                             channels fastest (each mode group stores whole rows)
 // Every contraction is arranged so that both MFMA operands are contiguous along
 // the summed index, i.e. each lane fetches its eight bf16 as one 16-byte load:
 //   row forward   T[kk][c]   = sum_w  EwT[kk][w]   * vt[c][w]     (vt staged in LDS)
@@ -14,6 +15,7 @@
 //   mixing        Y[k][o]    = sum_i  X[k][i] R[i][o]              (complex, per mode)
 //   column inv    Zc[q][o]   = sum_r  EcolB[q][r]  * Y[o][r]
 //   row inverse   s[w][o]    = sum_kk BinvT[w][kk] * Z[o][kk] + sum_i v[w][i] * Wc[o][i]
+//                                (Z of the row transposed into LDS, kk >= 2 m2 zero)
 // followed by bias and the activation, rounded to bf16 in the epilogue.
 #include <hip/hip_runtime.h>
 
@@ -238,7 +240,7 @@ __global__ __launch_bounds__(256) void k_fno_rowfwd(FnoDev d, const __bf16* __re
 }
 
 // Column forward DFT, per-mode complex mixing and column inverse DFT for one
-// (sample, k2).  Also clears a share of Z's padded coefficient columns.
+// (sample, k2).
 __global__ __launch_bounds__(256) void k_fno_col(FnoDev d, int layer) {
     extern __shared__ __align__(16) unsigned char smem[];
     float* xs = reinterpret_cast<float*>(smem);                                  // [R2][CP]
@@ -304,15 +306,29 @@ __global__ __launch_bounds__(256) void k_fno_col(FnoDev d, int layer) {
             const int q = mi * 32 + acc_row(r);
             const int ri = q >= d.Hpad ? 1 : 0, h = q - ri * d.Hpad;
             if (h < d.Hp)
-                d.Z[(((size_t)b * d.Hp + h) * d.CP + o) * d.KKp + 2 * k2 + ri] = to_bf16(acc[r]);
+                d.Z[(((size_t)b * 2 * d.m2 + 2 * k2 + ri) * d.Hp + h) * d.CP + o] = to_bf16(acc[r]);
         }
     }
-    // Z's padded coefficient columns p (2 m2 <= 2 m2 + p < KKp) are cleared by the
-    // groups with k2 == p mod m2, spread so that no one group serialises the clear
-    const int padw = d.KKp - 2 * d.m2;
-    for (int p = k2; p < padw; p += d.m2)
-        for (int i = tid; i < d.Hp * d.CP; i += blockDim.x)
-            d.Z[((size_t)b * d.Hp * d.CP + i) * d.KKp + 2 * d.m2 + p] = to_bf16(0.0f);
+}
+
+// Z coefficients of row (b, h) transposed into LDS, zs[o][kk] with row stride
+// KKp + 8, and the padded coefficient columns kk >= 2 m2 set to zero.  Reads are
+// 16-byte channel vectors of whole Z rows.
+__device__ __forceinline__ void stage_z(const FnoDev& d, int b, int h, __bf16* zs) {
+    const int KKs = d.KKp + 8, nvec = d.CP / 8;
+    for (int i = threadIdx.x; i < d.KKp * nvec; i += blockDim.x) {
+        const int kk = i / nvec, o0 = 8 * (i % nvec);
+        bf16x8 t;
+        if (kk < 2 * d.m2) {
+            t = *reinterpret_cast<const bf16x8*>(d.Z + (((size_t)b * 2 * d.m2 + kk) * d.Hp + h) * d.CP + o0);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) t[e] = to_bf16(0.0f);
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) zs[(o0 + e) * KKs + kk] = t[e];
+    }
+    __syncthreads();
 }
 
 // Row inverse DFT + 1x1 convolution + bias (+ activation) for one (b, h).
@@ -322,15 +338,18 @@ __global__ __launch_bounds__(256) void k_fno_rowinv(FnoDev d, const __bf16* __re
     const int tid = threadIdx.x, wave = tid >> 6, nw = blockDim.x >> 6;
     const size_t rowoff = ((size_t)b * d.Hp + h) * d.Wpad * d.CP;
     const __bf16* vrow = v + rowoff;
-    const __bf16* Zrow = d.Z + ((size_t)b * d.Hp + h) * d.CP * d.KKp;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __bf16* zs = reinterpret_cast<__bf16*>(smem);  // [CP][KKp + 8]
+    stage_z(d, b, h, zs);
+    const int KKs = d.KKp + 8;
     const __bf16* Wc = d.Wc + (size_t)layer * d.CP * d.CP;
     const float* bias = d.bc + (size_t)layer * d.CP;
     const int Mt = d.Wpad / 32, Nt = d.CP / 32;
     for (int t = wave; t < Mt * Nt; t += nw) {
         const int mi = t / Nt, ni = t % Nt;
         f32x16 acc = {};
-        acc = mma_tile(d.BinvT + (size_t)mi * 32 * d.KKp, d.KKp, Zrow + (size_t)ni * 32 * d.KKp,
-                       d.KKp, d.KKp, acc);
+        acc = mma_tile(d.BinvT + (size_t)mi * 32 * d.KKp, d.KKp, zs + (size_t)ni * 32 * KKs, KKs,
+                       d.KKp, acc);
         acc = mma_tile(vrow + (size_t)mi * 32 * d.CP, d.CP, Wc + (size_t)ni * 32 * d.CP, d.CP,
                        d.CP, acc);
         const int o = ni * 32 + acc_col();
@@ -462,6 +481,8 @@ static int rup(int x, int m) { return (x + m - 1) / m * m; }
 // (one bf16 + one float row of 32 points)
 static size_t dec_lds(const FnoDev& d) { return (size_t)4 * 2 * DEC_PTS * d.DKP * 2; }
 static size_t dec_bwd_lds(const FnoDev& d) { return (size_t)4 * DEC_PTS * d.DKP * (2 + 4); }
+// dynamic LDS of the row-inverse kernels: the row's Z transposed, [CP][KKp + 8] bf16
+static size_t zs_lds(const FnoDev& d) { return (size_t)d.CP * (d.KKp + 8) * 2; }
 
 static uint16_t host_bf16(double v) {
     float f = (float)v;
@@ -653,6 +674,7 @@ extern "C" int fno_model_create(fno_model** out, const fno_spec* spec, const flo
     if ((size_t)d.CP * d.Wpad * 2 > 64 * 1024) return fail(LBM_EUNSUPPORTED, "row of %d x %d too large for LDS", d.Wpad, d.CP);
     if (((size_t)d.R2 * d.CP * 4 + (size_t)d.CP * d.R2 * 2) > 64 * 1024)
         return fail(LBM_EUNSUPPORTED, "mode block too large for LDS");
+    if (zs_lds(d) > 64 * 1024) return fail(LBM_EUNSUPPORTED, "row coefficients too large for LDS");
     fno_model* m = new (std::nothrow) fno_model();
     if (!m) return fail(LBM_ENOMEM, "model allocation");
     m->spec = s;
@@ -809,7 +831,7 @@ static WsLayout ws_layout(const FnoDev& d, int B) {
     WsLayout L;
     L.v = al((size_t)B * d.Hp * d.Wpad * d.CP * 2);
     L.T = al((size_t)B * d.m2 * d.CP * 2 * d.Hpad * 2);
-    L.Z = al((size_t)B * d.Hp * d.CP * d.KKp * 2);
+    L.Z = al((size_t)B * 2 * d.m2 * d.Hp * d.CP * 2);
     L.total = 2 * L.v + L.T + L.Z;
     return L;
 }
@@ -855,7 +877,7 @@ static void launch_forward(const fno_model* m, const float* d_in, float* d_out, 
     for (int l = 0; l < d.L; ++l) {
         k_fno_rowfwd<<<B * d.Hpad, 256, lds_row, st>>>(d, cur);
         k_fno_col<<<B * d.m2, 256, lds_col, st>>>(d, l);
-        k_fno_rowinv<<<B * d.Hp, 256, 0, st>>>(d, cur, nxt, l, l == d.L - 1);
+        k_fno_rowinv<<<B * d.Hp, 256, zs_lds(d), st>>>(d, cur, nxt, l, l == d.L - 1);
         __bf16* t = cur; cur = nxt; nxt = t;
     }
     const size_t nout = (size_t)B * d.H * d.W;
@@ -1243,15 +1265,9 @@ __global__ __launch_bounds__(256) void k_fno_col_bwd(FnoDev d, FnoBwd g, int lay
             const int q = mi * 32 + acc_row(r);
             const int ri = q >= d.Hpad ? 1 : 0, h = q - ri * d.Hpad;
             if (h < d.Hp)
-                d.Z[(((size_t)b * d.Hp + h) * d.CP + o) * d.KKp + 2 * k2 + ri] = to_bf16(acc[r]);
+                d.Z[(((size_t)b * 2 * d.m2 + 2 * k2 + ri) * d.Hp + h) * d.CP + o] = to_bf16(acc[r]);
         }
     }
-    // Z's padded coefficient columns p (2 m2 <= 2 m2 + p < KKp) are cleared by the
-    // groups with k2 == p mod m2, spread so that no one group serialises the clear
-    const int padw = d.KKp - 2 * d.m2;
-    for (int p = k2; p < padw; p += d.m2)
-        for (int i = tid; i < d.Hp * d.CP; i += blockDim.x)
-            d.Z[((size_t)b * d.Hp * d.CP + i) * d.KKp + 2 * d.m2 + p] = to_bf16(0.0f);
 }
 
 // dv[w][i] = sum_kk B1[w][kk] Z[i][kk] + sum_o dpre[w][o] Wc[o][i], per (b, h) row.
@@ -1259,13 +1275,16 @@ __global__ __launch_bounds__(256) void k_fno_rowinv_bwd(FnoDev d, FnoBwd g, int 
     const int b = blockIdx.x / d.Hp, h = blockIdx.x % d.Hp;
     const int tid = threadIdx.x, wave = tid >> 6, nw = blockDim.x >> 6;
     const size_t rowoff = ((size_t)b * d.Hp + h) * d.Wpad * d.CP;
-    const __bf16* Zrow = d.Z + ((size_t)b * d.Hp + h) * d.CP * d.KKp;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __bf16* zs = reinterpret_cast<__bf16*>(smem);  // [CP][KKp + 8]
+    stage_z(d, b, h, zs);
+    const int KKs = d.KKp + 8;
     const __bf16* WcT = d.WcT + (size_t)layer * d.CP * d.CP;
     const int Mt = d.Wpad / 32, Nt = d.CP / 32;
     for (int t = wave; t < Mt * Nt; t += nw) {
         const int mi = t / Nt, ni = t % Nt;
         f32x16 acc = {};
-        acc = mma_tile(d.B1 + (size_t)mi * 32 * d.KKp, d.KKp, Zrow + (size_t)ni * 32 * d.KKp, d.KKp,
+        acc = mma_tile(d.B1 + (size_t)mi * 32 * d.KKp, d.KKp, zs + (size_t)ni * 32 * KKs, KKs,
                        d.KKp, acc);
         acc = mma_tile(g.dpre_bf + rowoff + (size_t)mi * 32 * d.CP, d.CP, WcT + (size_t)ni * 32 * d.CP,
                        d.CP, d.CP, acc);
@@ -1403,7 +1422,7 @@ static TrainLayout train_layout(const FnoDev& d, int B) {
     t.lz = al(t.P0 * 8 * 4);
     t.partials = al((size_t)OUT_MAX_BLOCKS * 64 * 65 * 4 + 4096 * 8);
     t.T = al((size_t)B * d.m2 * d.CP * 2 * d.Hpad * 2);
-    t.Z = al((size_t)B * d.Hp * d.CP * d.KKp * 2);
+    t.Z = al((size_t)B * 2 * d.m2 * d.Hp * d.CP * 2);
     t.total = (d.L + 1) * t.v + d.L * t.pre + d.L * t.X + t.a1 + t.dec + t.dv + t.dpre + t.dpre_bf +
               t.dY + t.dec_in + t.dec_da + t.dout + t.ldv0 + t.lh1 + t.lda1 + t.lz + t.partials +
               t.T + t.Z;
@@ -1487,7 +1506,7 @@ extern "C" int fno_forward_train(const fno_model* m, const float* d_in, float* d
         k_fno_col<<<B * d.m2, 256, lds_col, st>>>(d, l);
         d.sv_X = nullptr;
         d.sv_pre = P.pre[l];
-        k_fno_rowinv<<<B * d.Hp, 256, 0, st>>>(d, P.v[l], P.v[l + 1], l, l == d.L - 1);
+        k_fno_rowinv<<<B * d.Hp, 256, zs_lds(d), st>>>(d, P.v[l], P.v[l + 1], l, l == d.L - 1);
         d.sv_pre = nullptr;
     }
     d.sv_dec = P.dec;
@@ -1567,7 +1586,7 @@ extern "C" int fno_backward(const fno_model* m, const float* d_in, const float* 
         k_fno_col_bwd<<<B * d.m2, 256, lds_col, st>>>(d, g, l);
         const size_t nR = (size_t)s.m2 * d.K1 * wd * wd;
         k_fno_dR<<<(unsigned)((nR + 255) / 256), 256, 0, st>>>(d, g, P.X[l], d_grad + lo, d_grad + lo + blk);
-        k_fno_rowinv_bwd<<<B * d.Hp, 256, 0, st>>>(d, g, l);  // dv = dLoss / d v_l
+        k_fno_rowinv_bwd<<<B * d.Hp, 256, zs_lds(d), st>>>(d, g, l);  // dv = dLoss / d v_l
     }
     // lift
     k_fno_lift_bwd<<<(unsigned)((t.P0 + 255) / 256), 256, 0, st>>>(d, g, d_in);
