@@ -185,46 +185,32 @@ def bench_fno(out):
     return model
 
 
-def bench_hybrid(out, model):
-    """Hybrid super-time-stepping vs plain lattice steps on a 256x128 flow past
-    ellipses: 20 cycles of (5 FNO calls of dt = 100, re-initialisation, 200 steps)
-    against 14 000 plain steps.  Weights are random, so only the timing and step
-    accounting are meaningful here; the guard is relaxed to accept every finite
-    prediction and the FNO output density bias is set to 1."""
-    import torch
-    from paper_2604_27158_amd import lbmfno, hybrid as H
-    from paper_2604_27158_amd import workloads as W
-    lat = W.ellipse_flow(1, size=(256, 128))
-    init = [torch.from_numpy(a) for a in W.plug_flow(lat)]
-    P = lbmfno.Lattice.from_workload(lat)
-    P.reinit(*init)
-    P.step(200)
-    P.synchronize()
-    t0 = time.perf_counter()
-    P.step(14000)
-    P.synchronize()
-    t_plain = time.perf_counter() - t0
-    G = lbmfno.Lattice.from_workload(lat)
-    G.reinit(*init)
-    R = H.HybridRunner(G, model, dt_fno=100, k_fno=5, n_lbm=200,
-                       guard=H.Guard(max_speed=1e30, mass_rel_tol=1e30))
-    R.run(1)
-    G.reinit(*init)
-    R = H.HybridRunner(G, model, dt_fno=100, k_fno=5, n_lbm=200,
-                       guard=H.Guard(max_speed=1e30, mass_rel_tol=1e30))
-    G.synchronize()
-    t0 = time.perf_counter()
-    log = R.run(20)
-    G.synchronize()
-    t_h = time.perf_counter() - t0
-    step_ms = t_plain / 14000 * 1e3
-    fno_ms = out.get("fno", {}).get("B1", {}).get("ms", float("nan"))
-    out["hybrid"] = {"workload": lat.name, "horizon_steps": 14000, "plain_s": t_plain,
-                     "hybrid_s": t_h, "eps_T": H.runtime_reduction(t_plain, t_h),
-                     "eps_N": H.step_reduction(5, 100, 200), "fno_calls": log.fno_calls,
-                     "lbm_steps": log.lbm_steps, "fallbacks": len(log.fallbacks),
-                     "lbm_step_ms": step_ms, "fno_call_in_lbm_steps": fno_ms / step_ms,
-                     "note": "random FNO weights: timing only"}
+def bench_hybrid(out, ellipse_seeds=4, shear_seeds=10):
+    """The trained hybrids on this GPU, wall time against the plain lattice on the
+    same GPU (eps_T) next to the step reduction (eps_N) and the field errors:
+    (a) flows past ellipses at 256x128 with the flagship FNO: 20 cycles of 5 FNO
+        calls of dt = 100, re-initialisation and 200 lattice steps;
+    (b) the double shear layer at 128x128 with the small surrogate pair (a density
+        and a velocity model), 1:k hybrids with Delta T = 223 lattice steps over 30
+        outputs; error reductions against the pure surrogate rollout."""
+    import os
+    from paper_2604_27158_amd import unsteady as U, shear as S
+    if os.path.exists(U.DEFAULT_WEIGHTS):
+        r = U.hybrid_study(U.TrainedFno(), list(U.TEST_SEEDS)[:ellipse_seeds])
+        r.pop("per_seed", None)
+        r["workload"] = "ellipses256x128 (1-5 ellipses, Re 100-200), trained flagship FNO"
+        out["hybrid"] = r
+    else:
+        out["hybrid"] = {"skipped": "trained ellipse surrogate weights not present"}
+    if os.path.exists(S.weights_path("small")):
+        r = S.study("small", list(S.TEST_SEEDS)[:shear_seeds])
+        r.pop("curves", None)
+        r["workload"] = "double-shear128x128, small surrogate pair (dT = 223 steps)"
+        r["paper_eps_T_pct_context"] = {"1:1": 11.8, "1:2": 7.7, "1:3": 5.7,
+                                        "hardware": "RTX A4000, 2.6M-parameter pair"}
+        out["shear_hybrid"] = r
+    else:
+        out["shear_hybrid"] = {"skipped": "trained shear surrogate weights not present"}
 
 
 def bench_batch(out, steps=20000):
@@ -409,8 +395,8 @@ def main():
         del GB
         torch.cuda.empty_cache()
     if not args.no_extras:
-        model = bench_fno(out)
-        bench_hybrid(out, model)
+        bench_fno(out)
+        bench_hybrid(out)
         bench_batch(out)
         bench_steady(out, lat, args.steady_max)
         bench_time_to_steady(out, args.steady_seeds)
