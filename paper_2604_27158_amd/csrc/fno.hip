@@ -80,11 +80,22 @@ __device__ __forceinline__ int acc_row(int r) {
 }
 __device__ __forceinline__ int acc_col() { return threadIdx.x & 31; }
 
+template <int KIND>
+__device__ __forceinline__ float act_t(float x) {
+    if constexpr (KIND == FNO_ACT_GELU) return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f));
+    else if constexpr (KIND == FNO_ACT_RELU) return x > 0.0f ? x : 0.0f;
+    else if constexpr (KIND == FNO_ACT_SILU) return x / (1.0f + expf(-x));
+    else return x;
+}
+
+// Run-time activation choice for the cold paths.  The forward kernels take the
+// activation as a template argument instead: with a run-time switch inside an
+// unrolled epilogue the compiler evaluates every branch and selects.
 __device__ __forceinline__ float act_f(int kind, float x) {
     switch (kind) {
-        case FNO_ACT_GELU: return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f));
-        case FNO_ACT_RELU: return x > 0.0f ? x : 0.0f;
-        case FNO_ACT_SILU: return x / (1.0f + expf(-x));
+        case FNO_ACT_GELU: return act_t<FNO_ACT_GELU>(x);
+        case FNO_ACT_RELU: return act_t<FNO_ACT_RELU>(x);
+        case FNO_ACT_SILU: return act_t<FNO_ACT_SILU>(x);
         default: return x;
     }
 }
@@ -121,35 +132,40 @@ struct FnoDev {
 
 // Lift: x (cin channels, float32) + coordinates -> width/2 (act) -> width, rounded
 // to bf16, written channels-last; the zero-padded region and w >= W' hold zeros.
+// NO = CP (32 or 64): the register tile of output channels; ACT = d.act.
+template <int NO, int ACT>
 __global__ __launch_bounds__(256) void k_fno_lift(FnoDev d, const float* __restrict__ x) {
     // weights staged in LDS once per workgroup, zero-padded to the register tile
-    // (8 inputs, 64 outputs) so that the point loop has no channel-count branches
+    // (8 inputs, NO outputs) so that the point loop has no channel-count branches
     // and reads each weight row with 16-byte broadcasts
     __shared__ __align__(16) float w1s[32][8];
-    __shared__ __align__(16) float w2t[32][64];  // w2t[k][c] = W2[c][k]
-    __shared__ __align__(16) float b2s[64];
+    __shared__ __align__(16) float w2t[32][NO];  // w2t[k][c] = W2[c][k]
+    __shared__ __align__(16) float b2s[NO];
     __shared__ float b1s[32];
     for (int t = threadIdx.x; t < 32 * 8; t += blockDim.x) {
         const int k = t / 8, c = t % 8;
         w1s[k][c] = (k < d.half && c < d.cl) ? d.lift1w[k * d.cl + c] : 0.0f;
     }
-    for (int t = threadIdx.x; t < 32 * 64; t += blockDim.x) {
-        const int k = t / 64, c = t % 64;
+    for (int t = threadIdx.x; t < 32 * NO; t += blockDim.x) {
+        const int k = t / NO, c = t % NO;
         w2t[k][c] = (k < d.half && c < d.width) ? d.lift2w[c * d.half + k] : 0.0f;
     }
-    for (int t = threadIdx.x; t < 64; t += blockDim.x) b2s[t] = t < d.width ? d.lift2b[t] : 0.0f;
+    for (int t = threadIdx.x; t < NO; t += blockDim.x) b2s[t] = t < d.width ? d.lift2b[t] : 0.0f;
     for (int t = threadIdx.x; t < 32; t += blockDim.x) b1s[t] = t < d.half ? d.lift1b[t] : 0.0f;
     __syncthreads();
-    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const size_t total = (size_t)d.B * d.Hp * d.Wpad;
+    // point indices fit 32 bits (B Hp Wpad CP < 2^31 is checked on the host), so
+    // the index arithmetic avoids 64-bit division
+    const unsigned idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned total = (unsigned)d.B * d.Hp * d.Wpad;
     if (idx >= total) return;
-    const int w = (int)(idx % d.Wpad);
-    const int h = (int)((idx / d.Wpad) % d.Hp);
-    const int b = (int)(idx / ((size_t)d.Wpad * d.Hp));
-    __bf16* out = d.v0 + idx * d.CP;
-    float o[64];
+    const unsigned rw = idx / (unsigned)d.Wpad;
+    const int w = (int)(idx - rw * d.Wpad);
+    const int b = (int)(rw / (unsigned)d.Hp);
+    const int h = (int)(rw - (unsigned)b * d.Hp);
+    __bf16* out = d.v0 + (size_t)idx * d.CP;
+    float o[NO];
 #pragma unroll
-    for (int c = 0; c < 64; ++c) o[c] = 0.0f;
+    for (int c = 0; c < NO; ++c) o[c] = 0.0f;
     if (h < d.H && w < d.W) {
         float z[8];
 #pragma unroll
@@ -168,25 +184,25 @@ __global__ __launch_bounds__(256) void k_fno_lift(FnoDev d, const float* __restr
         }
         const size_t pt = ((size_t)b * d.H + h) * d.W + w;
 #pragma unroll
-        for (int c = 0; c < 64; ++c) o[c] = b2s[c];
+        for (int c = 0; c < NO; ++c) o[c] = b2s[c];
         for (int k = 0; k < d.half; ++k) {
             // padded inputs carry zero weights and zero values: exact no-ops
             float s = b1s[k];
 #pragma unroll
             for (int c = 0; c < 8; ++c) s = fmaf(w1s[k][c], z[c], s);
             if (d.sv_a1) d.sv_a1[pt * 32 + k] = s;
-            const float hk = act_f(d.act, s);
+            const float hk = act_t<ACT>(s);
             // o[c] += W2[c][k] * hid[k], accumulated over k in order
 #pragma unroll
-            for (int c = 0; c < 64; ++c) o[c] = fmaf(w2t[k][c], hk, o[c]);
+            for (int c = 0; c < NO; ++c) o[c] = fmaf(w2t[k][c], hk, o[c]);
         }
 #pragma unroll
-        for (int c = 0; c < 64; ++c)
+        for (int c = 0; c < NO; ++c)
             if (c >= d.width) o[c] = 0.0f;  // padded channels stay zero
     }
 #pragma unroll
-    for (int c0 = 0; c0 < 64; c0 += 8) {
-        if (c0 < d.CP) {
+    for (int c0 = 0; c0 < NO; c0 += 8) {
+        {
             bf16x8 t;
 #pragma unroll
             for (int e = 0; e < 8; ++e) t[e] = to_bf16(o[c0 + e]);
@@ -332,8 +348,10 @@ __device__ __forceinline__ void stage_z(const FnoDev& d, int b, int h, __bf16* z
 }
 
 // Row inverse DFT + 1x1 convolution + bias (+ activation) for one (b, h).
+// ACT: d.act, or the identity for the last layer.
+template <int ACT>
 __global__ __launch_bounds__(256) void k_fno_rowinv(FnoDev d, const __bf16* __restrict__ v,
-                                                    __bf16* __restrict__ vout, int layer, int last) {
+                                                    __bf16* __restrict__ vout, int layer) {
     const int b = blockIdx.x / d.Hp, h = blockIdx.x % d.Hp;
     const int tid = threadIdx.x, wave = tid >> 6, nw = blockDim.x >> 6;
     const size_t rowoff = ((size_t)b * d.Hp + h) * d.Wpad * d.CP;
@@ -359,7 +377,7 @@ __global__ __launch_bounds__(256) void k_fno_rowinv(FnoDev d, const __bf16* __re
             const int w = mi * 32 + acc_row(r);
             float val = acc[r] + bo;
             if (d.sv_pre) d.sv_pre[rowoff + (size_t)w * d.CP + o] = w < d.Wp ? val : 0.0f;
-            if (!last) val = act_f(d.act, val);
+            val = act_t<ACT>(val);
             if (w >= d.Wp) val = 0.0f;
             vout[rowoff + (size_t)w * d.CP + o] = to_bf16(val);
         }
@@ -374,14 +392,16 @@ __global__ __launch_bounds__(256) void k_fno_rowinv(FnoDev d, const __bf16* __re
 // per-point dot product over the last LDS row (float32 out).
 constexpr int DEC_PTS = 32;
 
+// (point indices fit 32 bits: B Hp Wpad CP < 2^31 is checked on the host)
 __device__ __forceinline__ size_t dec_point_offset(const FnoDev& d, size_t pt) {
-    const size_t w = pt % d.W, h = (pt / d.W) % d.H, b = pt / ((size_t)d.W * d.H);
-    return (b * d.Hp + h) * d.Wpad + w;
+    const unsigned p = (unsigned)pt, r = p / (unsigned)d.W, w = p - r * d.W;
+    const unsigned b = r / (unsigned)d.H, h = r - b * d.H;
+    return ((size_t)b * d.Hp + h) * d.Wpad + w;
 }
 
 __device__ __forceinline__ size_t dec_out_offset(const FnoDev& d, size_t pt, int o) {
-    const size_t hw = (size_t)d.H * d.W, b = pt / hw;
-    return (b * d.cout + o) * hw + pt % hw;
+    const unsigned p = (unsigned)pt, hw = (unsigned)d.H * d.W, b = p / hw;
+    return ((size_t)b * d.cout + o) * hw + (p - b * hw);
 }
 
 __device__ __forceinline__ void dec_stage_input(const FnoDev& d, const __bf16* __restrict__ v,
@@ -401,6 +421,8 @@ __device__ __forceinline__ void dec_stage_input(const FnoDev& d, const __bf16* _
     }
 }
 
+// ACT = d.dec_act.
+template <int ACT>
 __global__ __launch_bounds__(256) void k_fno_dec(FnoDev d, const __bf16* __restrict__ v,
                                                  float* __restrict__ out) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -410,6 +432,21 @@ __global__ __launch_bounds__(256) void k_fno_dec(FnoDev d, const __bf16* __restr
     __bf16* bufB = bufA + DEC_PTS * KP;
     const size_t total = (size_t)d.B * d.H * d.W;
     const size_t pt0 = ((size_t)blockIdx.x * 4 + wave) * DEC_PTS;
+    // output layer's weights (cout <= 8 rows of din <= 64) and bias staged in LDS
+    __shared__ __align__(16) __bf16 wo[8 * 64];
+    __shared__ float bo[8];
+    {
+        const __bf16* wg = d.decw;
+        const float* bg = d.decb;
+        int dn = d.CP;
+        for (int l = 0; l < d.dec_layers; ++l) {
+            wg += (size_t)d.DSP * dn;
+            bg += d.DSP;
+            dn = d.DSP;
+        }
+        for (int t = threadIdx.x; t < d.cout * dn; t += blockDim.x) wo[t] = wg[t];
+        for (int t = threadIdx.x; t < d.cout; t += blockDim.x) bo[t] = bg[t];
+    }
     dec_stage_input(d, v, pt0, total, bufA, lane);
     __syncthreads();
     int din = d.CP;
@@ -427,7 +464,7 @@ __global__ __launch_bounds__(256) void k_fno_dec(FnoDev d, const __bf16* __restr
                 const size_t pt = pt0 + pp;
                 const float val = acc[r] + bs;
                 if (d.sv_dec && pt < total) d.sv_dec[((size_t)l * total + pt) * d.DSP + su] = val;
-                const float a = su < d.dec_size ? act_f(d.dec_act, val) : 0.0f;
+                const float a = su < d.dec_size ? act_t<ACT>(val) : 0.0f;
                 bufB[pp * KP + su] = to_bf16(a);
             }
         }
@@ -441,9 +478,13 @@ __global__ __launch_bounds__(256) void k_fno_dec(FnoDev d, const __bf16* __restr
     const size_t pt = pt0 + pp;
     if (pt < total) {
         for (int o = lane >> 5; o < d.cout; o += 2) {
-            float acc = bp[o];
-            for (int i = 0; i < din; ++i)
-                acc = fmaf(from_bf16(wp[o * din + i]), from_bf16(bufA[pp * KP + i]), acc);
+            float acc = bo[o];
+            for (int i = 0; i < din; i += 8) {   // din is a multiple of 32
+                const bf16x8 a = *reinterpret_cast<const bf16x8*>(bufA + pp * KP + i);
+                const bf16x8 w = *reinterpret_cast<const bf16x8*>(wo + o * din + i);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) acc = fmaf(from_bf16(w[e]), from_bf16(a[e]), acc);
+            }
             out[dec_out_offset(d, pt, o)] = acc;
         }
     }
@@ -481,6 +522,42 @@ static int rup(int x, int m) { return (x + m - 1) / m * m; }
 // (one bf16 + one float row of 32 points)
 static size_t dec_lds(const FnoDev& d) { return (size_t)4 * 2 * DEC_PTS * d.DKP * 2; }
 static size_t dec_bwd_lds(const FnoDev& d) { return (size_t)4 * DEC_PTS * d.DKP * (2 + 4); }
+// Host dispatch of a run-time activation kind to the template argument A.
+#define FNO_WITH_ACT(kind, ...)                                                  \
+    switch (kind) {                                                              \
+        case FNO_ACT_GELU: { constexpr int A = FNO_ACT_GELU; __VA_ARGS__; break; } \
+        case FNO_ACT_RELU: { constexpr int A = FNO_ACT_RELU; __VA_ARGS__; break; } \
+        case FNO_ACT_SILU: { constexpr int A = FNO_ACT_SILU; __VA_ARGS__; break; } \
+        default: { constexpr int A = FNO_ACT_IDENTITY; __VA_ARGS__; break; }        \
+    }
+
+// lift over npts padded points, with the register tile matching CP (32 or 64)
+static void launch_lift(const FnoDev& d, size_t npts, const float* d_in, hipStream_t st) {
+    const unsigned grid = (unsigned)((npts + 255) / 256);
+    if (d.CP <= 32) {
+        FNO_WITH_ACT(d.act, (k_fno_lift<32, A><<<grid, 256, 0, st>>>(d, d_in)))
+    } else {
+        FNO_WITH_ACT(d.act, (k_fno_lift<64, A><<<grid, 256, 0, st>>>(d, d_in)))
+    }
+}
+
+static size_t zs_lds(const FnoDev& d);
+
+// row inverse of layer l over all (b, h) rows; the last layer has no activation
+static void launch_rowinv(const FnoDev& d, const __bf16* v, __bf16* vout, int l, hipStream_t st) {
+    const unsigned grid = (unsigned)(d.B * d.Hp);
+    FNO_WITH_ACT(l == d.L - 1 ? FNO_ACT_IDENTITY : d.act,
+                 (k_fno_rowinv<A><<<grid, 256, zs_lds(d), st>>>(d, v, vout, l)))
+}
+
+static size_t dec_lds(const FnoDev& d);
+
+static void launch_dec(const FnoDev& d, const __bf16* v, float* out, hipStream_t st) {
+    const size_t nout = (size_t)d.B * d.H * d.W;
+    const unsigned grid = (unsigned)((nout + 4 * DEC_PTS - 1) / (4 * DEC_PTS));
+    FNO_WITH_ACT(d.dec_act, (k_fno_dec<A><<<grid, 256, dec_lds(d), st>>>(d, v, out)))
+}
+
 // dynamic LDS of the row-inverse kernels: the row's Z transposed, [CP][KKp + 8] bf16
 static size_t zs_lds(const FnoDev& d) { return (size_t)d.CP * (d.KKp + 8) * 2; }
 
@@ -869,7 +946,7 @@ static void launch_forward(const fno_model* m, const float* d_in, float* d_out, 
     d.T = reinterpret_cast<__bf16*>(ws + 2 * L.v);
     d.Z = reinterpret_cast<__bf16*>(ws + 2 * L.v + L.T);
     const size_t npts = (size_t)B * d.Hp * d.Wpad;
-    k_fno_lift<<<(unsigned)((npts + 255) / 256), 256, 0, st>>>(d, d_in);
+    launch_lift(d, npts, d_in, st);
     const size_t lds_row = (size_t)d.CP * d.Wpad * 2;
     const size_t lds_col = (size_t)d.R2 * d.CP * 4 + (size_t)d.CP * d.R2 * 2;
     __bf16* cur = d.v0;
@@ -877,11 +954,10 @@ static void launch_forward(const fno_model* m, const float* d_in, float* d_out, 
     for (int l = 0; l < d.L; ++l) {
         k_fno_rowfwd<<<B * d.Hpad, 256, lds_row, st>>>(d, cur);
         k_fno_col<<<B * d.m2, 256, lds_col, st>>>(d, l);
-        k_fno_rowinv<<<B * d.Hp, 256, zs_lds(d), st>>>(d, cur, nxt, l, l == d.L - 1);
+        launch_rowinv(d, cur, nxt, l, st);
         __bf16* t = cur; cur = nxt; nxt = t;
     }
-    const size_t nout = (size_t)B * d.H * d.W;
-    k_fno_dec<<<(unsigned)((nout + 4 * DEC_PTS - 1) / (4 * DEC_PTS)), 256, dec_lds(d), st>>>(d, cur, d_out);
+    launch_dec(d, cur, d_out, st);
 }
 
 extern "C" int fno_forward(const fno_model* m, const float* d_in, float* d_out, int32_t B,
@@ -1203,7 +1279,7 @@ __global__ __launch_bounds__(256) void k_fno_act_bwd(FnoDev d, FnoBwd g, const f
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t total = (size_t)d.B * d.Hp * d.Wpad * d.CP;
     if (i >= total) return;
-    const int w = (int)((i / d.CP) % d.Wpad);
+    const int w = (int)(((unsigned)i / (unsigned)d.CP) % (unsigned)d.Wpad);
     float v = w < d.Wp ? g.dv[i] : 0.0f;
     if (!last) v *= act_grad(d.act, pre[i]);
     g.dpre[i] = v;
@@ -1329,9 +1405,10 @@ __global__ __launch_bounds__(256) void k_fno_lift_bwd(FnoDev d, FnoBwd g, const 
     const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t total = (size_t)d.B * d.H * d.W;
     if (idx >= total) return;
-    const int w = (int)(idx % d.W);
-    const int h = (int)((idx / d.W) % d.H);
-    const int b = (int)(idx / ((size_t)d.W * d.H));
+    const unsigned rw = (unsigned)idx / (unsigned)d.W;
+    const int w = (int)((unsigned)idx - rw * d.W);
+    const int b = (int)(rw / (unsigned)d.H);
+    const int h = (int)(rw - (unsigned)b * d.H);
     const size_t vpt = ((size_t)b * d.Hp + h) * d.Wpad + w;
     float s[32];
 #pragma unroll
@@ -1496,7 +1573,7 @@ extern "C" int fno_forward_train(const fno_model* m, const float* d_in, float* d
     d.Z = P.Z;
     d.v0 = P.v[0];
     d.sv_a1 = P.a1;
-    k_fno_lift<<<(unsigned)((t.Pl + 255) / 256), 256, 0, st>>>(d, d_in);
+    launch_lift(d, t.Pl, d_in, st);
     d.sv_a1 = nullptr;
     const size_t lds_row = (size_t)d.CP * d.Wpad * 2;
     const size_t lds_col = (size_t)d.R2 * d.CP * 4 + (size_t)d.CP * d.R2 * 2;
@@ -1506,12 +1583,11 @@ extern "C" int fno_forward_train(const fno_model* m, const float* d_in, float* d
         k_fno_col<<<B * d.m2, 256, lds_col, st>>>(d, l);
         d.sv_X = nullptr;
         d.sv_pre = P.pre[l];
-        k_fno_rowinv<<<B * d.Hp, 256, zs_lds(d), st>>>(d, P.v[l], P.v[l + 1], l, l == d.L - 1);
+        launch_rowinv(d, P.v[l], P.v[l + 1], l, st);
         d.sv_pre = nullptr;
     }
     d.sv_dec = P.dec;
-    const size_t nout = t.P0;
-    k_fno_dec<<<(unsigned)((nout + 4 * DEC_PTS - 1) / (4 * DEC_PTS)), 256, dec_lds(d), st>>>(d, P.v[d.L], d_out);
+    launch_dec(d, P.v[d.L], d_out, st);
     LBM_HIP(hipGetLastError());
     return LBM_OK;
 }
