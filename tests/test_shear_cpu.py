@@ -67,3 +67,13 @@ def test_errors():
     bad = ref.copy()
     bad[0, 0, 0] = np.nan
     assert S.errors(bad, ref) == (float("inf"), float("inf"))
+
+
+@pytest.mark.parametrize("group,want", [("small", (151_811, 2_409_771)), ("large", (5_621_835, 5_621_875))])
+def test_surrogate_groups_have_the_paper_parameter_counts(group, want):
+    """The two model groups of the paper's shear table (density, velocity)."""
+    from oracle import fno as ofno
+    got = tuple(ofno.param_count(ofno.Spec(cin=s.cin, width=s.width, layers=s.layers, m1=s.m1, m2=s.m2,
+                                           dec_layers=s.dec_layers, dec_size=s.dec_size, cout=s.cout,
+                                           padding=s.padding)) for s in S.GROUPS[group])
+    assert got == want
