@@ -46,7 +46,7 @@ __device__ __forceinline__ f32x16 mma_tile(const __bf16* A, int lda, const __bf1
     // current group's products, so that at most one memory latency per group is
     // exposed (these tiles are latency-bound at batch 1: few waves per CU)
     constexpr int U = 4;
-    bf16x8 av[U], bv[U];
+    bf16x8 av[U] = {}, bv[U] = {};   // slots past K stay defined (zero) and unused
 #pragma unroll
     for (int j = 0; j < U; ++j)
         if (16 * j < K) {
@@ -54,7 +54,7 @@ __device__ __forceinline__ f32x16 mma_tile(const __bf16* A, int lda, const __bf1
             bv[j] = *reinterpret_cast<const bf16x8*>(b + 16 * j);
         }
     for (int k0 = 0; k0 < K; k0 += 16 * U) {
-        bf16x8 an[U], bn[U];
+        bf16x8 an[U] = {}, bn[U] = {};
         const int k1 = k0 + 16 * U;
 #pragma unroll
         for (int j = 0; j < U; ++j)
@@ -257,7 +257,11 @@ __global__ __launch_bounds__(256) void k_fno_rowfwd(FnoDev d, const __bf16* __re
 
 // Column forward DFT, per-mode complex mixing and column inverse DFT for one
 // (sample, k2).
-__global__ __launch_bounds__(256) void k_fno_col(FnoDev d, int layer) {
+// Launched with COL_THREADS threads: at batch 1 there is one workgroup per mode
+// column and the kernel is a chain of memory latencies, so more waves shorten it.
+constexpr int COL_THREADS = 512;
+
+__global__ __launch_bounds__(COL_THREADS) void k_fno_col(FnoDev d, int layer) {
     extern __shared__ __align__(16) unsigned char smem[];
     float* xs = reinterpret_cast<float*>(smem);                                  // [R2][CP]
     __bf16* ys = reinterpret_cast<__bf16*>(smem + sizeof(float) * d.R2 * d.CP);  // [CP][R2]
@@ -266,19 +270,49 @@ __global__ __launch_bounds__(256) void k_fno_col(FnoDev d, int layer) {
     const int H2 = 2 * d.Hpad;
     const int Nt = d.CP / 32;
     const __bf16* Ts = d.T + ((size_t)b * d.m2 + k2) * d.CP * H2;  // [CP][2 Hpad]
+    float* svX = d.sv_X ? d.sv_X + ((size_t)b * d.m2 + k2) * d.R2 * d.CP : nullptr;
     // X[r][c] = sum_{ri,h} EcolA[r][ri,h] T[c][ri,h]
-    const int Mt1 = d.R2 / 32;
-    for (int t = wave; t < Mt1 * Nt; t += nw) {
-        const int mi = t / Nt, ni = t % Nt;
-        f32x16 acc = {};
-        acc = mma_tile(d.EcolA + (size_t)mi * 32 * H2, H2, Ts + (size_t)ni * 32 * H2, H2, H2, acc);
-        const int c = ni * 32 + acc_col();
+    const int Mt1 = d.R2 / 32, T1 = Mt1 * Nt;
+    if (T1 >= nw) {
+        for (int t = wave; t < T1; t += nw) {
+            const int mi = t / Nt, ni = t % Nt;
+            f32x16 acc = {};
+            acc = mma_tile(d.EcolA + (size_t)mi * 32 * H2, H2, Ts + (size_t)ni * 32 * H2, H2, H2, acc);
+            const int c = ni * 32 + acc_col();
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const float xv = from_bf16(to_bf16(acc[r]));
-            xs[(mi * 32 + acc_row(r)) * d.CP + c] = xv;
-            if (d.sv_X)
-                d.sv_X[(((size_t)b * d.m2 + k2) * d.R2 + mi * 32 + acc_row(r)) * d.CP + c] = xv;
+            for (int r = 0; r < 16; ++r) {
+                const float xv = from_bf16(to_bf16(acc[r]));
+                xs[(mi * 32 + acc_row(r)) * d.CP + c] = xv;
+                if (svX) svX[(mi * 32 + acc_row(r)) * d.CP + c] = xv;
+            }
+        }
+    } else {
+        // fewer tiles than waves: the K range (2 Hpad, in 16-wide steps) is split
+        // into S parts, wave w taking tile w mod T1 and part w / T1.  Part 0 writes
+        // xs, part s > 0 its own [R2][CP] partial after ys; the parts are then added
+        // in part order (deterministic) and rounded.
+        const int S = nw / T1, KS = H2 / 16;
+        const int tile = wave % T1, part = wave / T1;
+        const int mi = tile / Nt, ni = tile % Nt;
+        const int k0 = 16 * (part * KS / S), k1 = 16 * ((part + 1) * KS / S);
+        float* parts = reinterpret_cast<float*>(smem + (size_t)d.R2 * d.CP * 6);  // [S-1][R2][CP]
+        if (part < S) {
+            f32x16 acc = {};
+            if (k1 > k0)
+                acc = mma_tile(d.EcolA + (size_t)mi * 32 * H2 + k0, H2, Ts + (size_t)ni * 32 * H2 + k0, H2,
+                               k1 - k0, acc);
+            float* dst = part == 0 ? xs : parts + (size_t)(part - 1) * d.R2 * d.CP;
+            const int c = ni * 32 + acc_col();
+#pragma unroll
+            for (int r = 0; r < 16; ++r) dst[(mi * 32 + acc_row(r)) * d.CP + c] = acc[r];
+        }
+        __syncthreads();
+        for (int i = tid; i < d.R2 * d.CP; i += blockDim.x) {
+            float v = xs[i];
+            for (int q = 1; q < S; ++q) v += parts[(size_t)(q - 1) * d.R2 * d.CP + i];
+            const float xv = from_bf16(to_bf16(v));
+            xs[i] = xv;
+            if (svX) svX[i] = xv;
         }
     }
     for (int i = tid; i < d.CP * d.R2; i += blockDim.x) ys[i] = to_bf16(0.0f);
@@ -558,6 +592,14 @@ static void launch_dec(const FnoDev& d, const __bf16* v, float* out, hipStream_t
     FNO_WITH_ACT(d.dec_act, (k_fno_dec<A><<<grid, 256, dec_lds(d), st>>>(d, v, out)))
 }
 
+// dynamic LDS of the column kernel: xs [R2][CP] float, ys [CP][R2] bf16 and, when
+// its K range is split over spare waves, S - 1 float partials of xs
+static size_t col_lds(const FnoDev& d) {
+    const int T1 = (d.R2 / 32) * (d.CP / 32), nw = COL_THREADS / 64;
+    const int S = T1 >= nw ? 1 : nw / T1;
+    return (size_t)d.R2 * d.CP * (4 + 2) + (size_t)(S - 1) * d.R2 * d.CP * 4;
+}
+
 // dynamic LDS of the row-inverse kernels: the row's Z transposed, [CP][KKp + 8] bf16
 static size_t zs_lds(const FnoDev& d) { return (size_t)d.CP * (d.KKp + 8) * 2; }
 
@@ -749,8 +791,7 @@ extern "C" int fno_model_create(fno_model** out, const fno_spec* spec, const flo
     d.cout = s.cout;
     d.act = s.act; d.dec_act = s.dec_act;
     if ((size_t)d.CP * d.Wpad * 2 > 64 * 1024) return fail(LBM_EUNSUPPORTED, "row of %d x %d too large for LDS", d.Wpad, d.CP);
-    if (((size_t)d.R2 * d.CP * 4 + (size_t)d.CP * d.R2 * 2) > 64 * 1024)
-        return fail(LBM_EUNSUPPORTED, "mode block too large for LDS");
+    if (col_lds(d) > 64 * 1024) return fail(LBM_EUNSUPPORTED, "mode block too large for LDS");
     if (zs_lds(d) > 64 * 1024) return fail(LBM_EUNSUPPORTED, "row coefficients too large for LDS");
     fno_model* m = new (std::nothrow) fno_model();
     if (!m) return fail(LBM_ENOMEM, "model allocation");
@@ -948,12 +989,11 @@ static void launch_forward(const fno_model* m, const float* d_in, float* d_out, 
     const size_t npts = (size_t)B * d.Hp * d.Wpad;
     launch_lift(d, npts, d_in, st);
     const size_t lds_row = (size_t)d.CP * d.Wpad * 2;
-    const size_t lds_col = (size_t)d.R2 * d.CP * 4 + (size_t)d.CP * d.R2 * 2;
     __bf16* cur = d.v0;
     __bf16* nxt = d.v1;
     for (int l = 0; l < d.L; ++l) {
         k_fno_rowfwd<<<B * d.Hpad, 256, lds_row, st>>>(d, cur);
-        k_fno_col<<<B * d.m2, 256, lds_col, st>>>(d, l);
+        k_fno_col<<<B * d.m2, COL_THREADS, col_lds(d), st>>>(d, l);
         launch_rowinv(d, cur, nxt, l, st);
         __bf16* t = cur; cur = nxt; nxt = t;
     }
@@ -1576,11 +1616,10 @@ extern "C" int fno_forward_train(const fno_model* m, const float* d_in, float* d
     launch_lift(d, t.Pl, d_in, st);
     d.sv_a1 = nullptr;
     const size_t lds_row = (size_t)d.CP * d.Wpad * 2;
-    const size_t lds_col = (size_t)d.R2 * d.CP * 4 + (size_t)d.CP * d.R2 * 2;
     for (int l = 0; l < d.L; ++l) {
         k_fno_rowfwd<<<B * d.Hpad, 256, lds_row, st>>>(d, P.v[l]);
         d.sv_X = P.X[l];
-        k_fno_col<<<B * d.m2, 256, lds_col, st>>>(d, l);
+        k_fno_col<<<B * d.m2, COL_THREADS, col_lds(d), st>>>(d, l);
         d.sv_X = nullptr;
         d.sv_pre = P.pre[l];
         launch_rowinv(d, P.v[l], P.v[l + 1], l, st);
