@@ -213,6 +213,30 @@ __global__ __launch_bounds__(256) void k_fno_lift(FnoDev d, const float* __restr
 
 // Row forward DFT: one workgroup per (b, h), h < Hpad (rows h >= H' write zeros so
 // the column transform's padded K range is exactly zero).
+// Row DFT of row (b, h < Hp) from its transposed copy vt[c][w] in LDS:
+// T[k2][c][ri][h] = sum_w EwT[2 k2 + ri][w] vt[c][w].
+__device__ __forceinline__ void row_dft_from_lds(const FnoDev& d, const __bf16* vt, int b, int h) {
+    const size_t tstride = (size_t)2 * d.Hpad;
+    __bf16* Tb = d.T + (size_t)b * d.m2 * d.CP * tstride;
+    const int wave = threadIdx.x >> 6;
+    const int Mt = d.KKp / 32, Nt = d.CP / 32;
+    for (int t = wave; t < Mt * Nt; t += blockDim.x >> 6) {
+        const int mi = t / Nt, ni = t % Nt;
+        f32x16 acc = {};
+        acc = mma_tile(d.EwT + (size_t)mi * 32 * d.Wpad, d.Wpad, vt + ni * 32 * d.Wpad, d.Wpad,
+                       d.Wpad, acc);
+        const int c = ni * 32 + acc_col();
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int kk = mi * 32 + acc_row(r);
+            if (kk < 2 * d.m2) {
+                const int k2 = kk >> 1, ri = kk & 1;
+                Tb[((size_t)k2 * d.CP + c) * tstride + ri * d.Hpad + h] = to_bf16(acc[r]);
+            }
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_fno_rowfwd(FnoDev d, const __bf16* __restrict__ v) {
     extern __shared__ __align__(16) unsigned char smem[];
     __bf16* vt = reinterpret_cast<__bf16*>(smem);  // [CP][Wpad]
@@ -236,23 +260,7 @@ __global__ __launch_bounds__(256) void k_fno_rowfwd(FnoDev d, const __bf16* __re
         for (int e = 0; e < 8; ++e) vt[(c0 + e) * d.Wpad + w] = t[e];
     }
     __syncthreads();
-    const int wave = tid >> 6;
-    const int Mt = d.KKp / 32, Nt = d.CP / 32;
-    for (int t = wave; t < Mt * Nt; t += blockDim.x >> 6) {
-        const int mi = t / Nt, ni = t % Nt;
-        f32x16 acc = {};
-        acc = mma_tile(d.EwT + (size_t)mi * 32 * d.Wpad, d.Wpad, vt + ni * 32 * d.Wpad, d.Wpad,
-                       d.Wpad, acc);
-        const int c = ni * 32 + acc_col();
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int kk = mi * 32 + acc_row(r);
-            if (kk < 2 * d.m2) {
-                const int k2 = kk >> 1, ri = kk & 1;
-                Tb[((size_t)k2 * d.CP + c) * tstride + ri * d.Hpad + h] = to_bf16(acc[r]);
-            }
-        }
-    }
+    row_dft_from_lds(d, vt, b, h);
 }
 
 // Column forward DFT, per-mode complex mixing and column inverse DFT for one
@@ -382,8 +390,10 @@ __device__ __forceinline__ void stage_z(const FnoDev& d, int b, int h, __bf16* z
 }
 
 // Row inverse DFT + 1x1 convolution + bias (+ activation) for one (b, h).
-// ACT: d.act, or the identity for the last layer.
-template <int ACT>
+// ACT: d.act, or the identity for the last layer.  DFT: also take the next layer's
+// row DFT of the output row (kept in LDS, transposed), so the next layer needs no
+// row-forward launch; rows h >= Hp of T stay the zeros the first row DFT wrote.
+template <int ACT, bool DFT>
 __global__ __launch_bounds__(256) void k_fno_rowinv(FnoDev d, const __bf16* __restrict__ v,
                                                     __bf16* __restrict__ vout, int layer) {
     const int b = blockIdx.x / d.Hp, h = blockIdx.x % d.Hp;
@@ -392,6 +402,7 @@ __global__ __launch_bounds__(256) void k_fno_rowinv(FnoDev d, const __bf16* __re
     const __bf16* vrow = v + rowoff;
     extern __shared__ __align__(16) unsigned char smem[];
     __bf16* zs = reinterpret_cast<__bf16*>(smem);  // [CP][KKp + 8]
+    __bf16* vt = zs + (size_t)d.CP * (d.KKp + 8);  // [CP][Wpad] (DFT)
     stage_z(d, b, h, zs);
     const int KKs = d.KKp + 8;
     const __bf16* Wc = d.Wc + (size_t)layer * d.CP * d.CP;
@@ -413,8 +424,14 @@ __global__ __launch_bounds__(256) void k_fno_rowinv(FnoDev d, const __bf16* __re
             if (d.sv_pre) d.sv_pre[rowoff + (size_t)w * d.CP + o] = w < d.Wp ? val : 0.0f;
             val = act_t<ACT>(val);
             if (w >= d.Wp) val = 0.0f;
-            vout[rowoff + (size_t)w * d.CP + o] = to_bf16(val);
+            const __bf16 vb = to_bf16(val);
+            vout[rowoff + (size_t)w * d.CP + o] = vb;
+            if constexpr (DFT) vt[o * d.Wpad + w] = vb;
         }
+    }
+    if constexpr (DFT) {
+        __syncthreads();
+        row_dft_from_lds(d, vt, b, h);
     }
 }
 
@@ -577,11 +594,22 @@ static void launch_lift(const FnoDev& d, size_t npts, const float* d_in, hipStre
 
 static size_t zs_lds(const FnoDev& d);
 
-// row inverse of layer l over all (b, h) rows; the last layer has no activation
+// whether the row inverse can also hold the output row for the next row DFT in LDS
+static bool fuse_row_dft(const FnoDev& d) {
+    return zs_lds(d) + (size_t)d.CP * d.Wpad * 2 <= 64 * 1024;
+}
+
+// row inverse of layer l over all (b, h) rows; the last layer has no activation,
+// the others also take the next layer's row DFT when it fits (fuse_row_dft)
 static void launch_rowinv(const FnoDev& d, const __bf16* v, __bf16* vout, int l, hipStream_t st) {
     const unsigned grid = (unsigned)(d.B * d.Hp);
-    FNO_WITH_ACT(l == d.L - 1 ? FNO_ACT_IDENTITY : d.act,
-                 (k_fno_rowinv<A><<<grid, 256, zs_lds(d), st>>>(d, v, vout, l)))
+    if (l < d.L - 1 && fuse_row_dft(d)) {
+        const size_t lds = zs_lds(d) + (size_t)d.CP * d.Wpad * 2;
+        FNO_WITH_ACT(d.act, (k_fno_rowinv<A, true><<<grid, 256, lds, st>>>(d, v, vout, l)))
+    } else {
+        FNO_WITH_ACT(l == d.L - 1 ? FNO_ACT_IDENTITY : d.act,
+                     (k_fno_rowinv<A, false><<<grid, 256, zs_lds(d), st>>>(d, v, vout, l)))
+    }
 }
 
 static size_t dec_lds(const FnoDev& d);
@@ -991,8 +1019,11 @@ static void launch_forward(const fno_model* m, const float* d_in, float* d_out, 
     const size_t lds_row = (size_t)d.CP * d.Wpad * 2;
     __bf16* cur = d.v0;
     __bf16* nxt = d.v1;
+    // the first layer's row DFT (it also writes T's zero rows h >= Hp); with
+    // fuse_row_dft the row inverse of each layer produces the next layer's row DFT
+    const bool fused = fuse_row_dft(d);
     for (int l = 0; l < d.L; ++l) {
-        k_fno_rowfwd<<<B * d.Hpad, 256, lds_row, st>>>(d, cur);
+        if (l == 0 || !fused) k_fno_rowfwd<<<B * d.Hpad, 256, lds_row, st>>>(d, cur);
         k_fno_col<<<B * d.m2, COL_THREADS, col_lds(d), st>>>(d, l);
         launch_rowinv(d, cur, nxt, l, st);
         __bf16* t = cur; cur = nxt; nxt = t;
@@ -1616,8 +1647,9 @@ extern "C" int fno_forward_train(const fno_model* m, const float* d_in, float* d
     launch_lift(d, t.Pl, d_in, st);
     d.sv_a1 = nullptr;
     const size_t lds_row = (size_t)d.CP * d.Wpad * 2;
+    const bool fused = fuse_row_dft(d);  // later layers' row DFT in the row inverse
     for (int l = 0; l < d.L; ++l) {
-        k_fno_rowfwd<<<B * d.Hpad, 256, lds_row, st>>>(d, P.v[l]);
+        if (l == 0 || !fused) k_fno_rowfwd<<<B * d.Hpad, 256, lds_row, st>>>(d, P.v[l]);
         d.sv_X = P.X[l];
         k_fno_col<<<B * d.m2, COL_THREADS, col_lds(d), st>>>(d, l);
         d.sv_X = nullptr;
