@@ -38,8 +38,10 @@ def lib():
         L.oracle_run.restype = _i
         L.oracle_macros.argtypes = [_i, _i, _d, _d, _p, _p, _p, _p, _p]
         L.oracle_sums.argtypes = [_i, _i, _p, _p, _p, _p, _p, _p]
-        L.oracle_adjoint_step.argtypes = [_i, _i, _d, _d, _d, _i, _i, _p, _p, _p, _p]
+        L.oracle_adjoint_step.argtypes = [_i, _i, _d, _d, _d, _i, _i, _d, _d, _p, _p, _p, _p]
         L.oracle_adjoint_step.restype = _i
+        L.oracle_bc_vjp.argtypes = [_i, _i, _i, _d, _d, _p, _p]
+        L.oracle_bc_vjp.restype = None
         L.oracle_feq_vjp.argtypes = [_i, _i, _p, _p, _p, _p, _p, _p, _p, _p]
         L.oracle_lattice.argtypes = [_p, _p, _p, _p]
         L.oracle_threads.restype = _i
@@ -153,11 +155,20 @@ def sums(mask, rho, rho_prev, ux, uy):
 
 
 def adjoint_step(lat, mask, f_n, lam_np1):
+    """lam_n = C'(f(n))^T P^T Z'^T lam_{n+1} (Z: Zou-He closures, identity otherwise)."""
     f_n = _f64(f_n); lam_np1 = _f64(lam_np1); out = np.zeros_like(f_n)
     rc = lib().oracle_adjoint_step(lat.nx, lat.ny, lat.tau, lat.gx, lat.gy, lat.bc_x, lat.bc_y,
-                                   _ptr(mask), _ptr(f_n), _ptr(lam_np1), _ptr(out))
+                                   lat.u_in, lat.rho_out, _ptr(mask), _ptr(f_n), _ptr(lam_np1),
+                                   _ptr(out))
     if rc != 0:
-        raise ValueError("adjoint not defined for Zou-He boundaries")
+        raise ValueError("adjoint not defined for this boundary configuration")
+    return out
+
+
+def bc_vjp(lat, mask, lam):
+    """Z'^T lam: the transposed Jacobian of the boundary closures (Zou-He columns)."""
+    out = _f64(lam).copy()
+    lib().oracle_bc_vjp(lat.nx, lat.ny, lat.bc_x, lat.u_in, lat.rho_out, _ptr(mask), _ptr(out))
     return out
 
 
@@ -212,4 +223,5 @@ def rollout_grad(lat, mask, rho0, ux0, uy0, nsteps, target):
     lam = macro_mse_grad_f(lat, mask, states[-1], target)
     for n in range(nsteps - 1, -1, -1):
         lam = adjoint_step(lat, mask, states[n], lam)
-    return feq_vjp(mask, rho0, ux0, uy0, lam)
+    # f(0) = Z(f_eq(rho0, u0)): through the closures, then the equilibrium
+    return feq_vjp(mask, rho0, ux0, uy0, bc_vjp(lat, mask, lam))

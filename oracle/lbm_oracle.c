@@ -15,7 +15,7 @@
  *     velocity u = (sum c f + rho g / 2) / rho when a body force g is present,
  *   - Guo forcing term S_q = (1 - 1/(2 tau)) w_q [3 (c_q - u) + 9 (c_q.u) c_q] . rho g,
  *   - obstacle raster (Sec. 3.1.1, Eq. 8), FP64 residual and mass sums,
- *   - the exact vector-Jacobian product of one step (adjoint).
+ *   - the exact vector-Jacobian product of one step (adjoint), Zou-He closures included.
  *
  * State convention: f(n) is the pre-collision population at integer time n, i.e.
  * after streaming and boundary conditions.  One step maps f(n) -> f(n+1) =
@@ -319,14 +319,78 @@ void oracle_sums(int nx, int ny, const uint8_t* mask, const double* rho, const d
 
 /* ---------------------------------------------------------------- adjoint */
 
-/* Vector-Jacobian product of one step (periodic and wall boundaries; Zou-He columns
- * are not covered): given the pre-collision state f(n) and lam_np1 = dL/df(n+1),
- * returns lam_n = dL/df(n) = C'(f(n))^T P^T lam_np1, where P is the streaming /
- * bounce-back permutation and C' the per-node collision Jacobian. */
+/* Jacobians of the Zou-He closures (zouhe_inlet / zouhe_outlet above) with respect
+ * to the node's populations after streaming: identity rows for the known
+ * populations, the closure's derivative for the three unknown ones. */
+static void zouhe_inlet_jacobian(double u_in, double J[Q][Q]) {
+    double drho[Q] = {1.0, 0.0, 1.0, 2.0, 1.0, 0.0, 2.0, 2.0, 0.0};  /* d rho / d f_q */
+    for (int q = 0; q < Q; ++q) drho[q] /= 1.0 - u_in;
+    for (int a = 0; a < Q; ++a)
+        for (int b = 0; b < Q; ++b) J[a][b] = a == b ? 1.0 : 0.0;
+    for (int b = 0; b < Q; ++b) {
+        J[1][b] = (2.0 / 3.0) * u_in * drho[b];
+        J[5][b] = (1.0 / 6.0) * u_in * drho[b];
+        J[8][b] = (1.0 / 6.0) * u_in * drho[b];
+    }
+    J[1][3] += 1.0;                                   /* f1 = f3 + 2/3 rho u_in */
+    J[5][7] += 1.0; J[5][2] -= 0.5; J[5][4] += 0.5;   /* f5 = f7 - (f2 - f4)/2 + rho u_in/6 */
+    J[8][6] += 1.0; J[8][2] += 0.5; J[8][4] -= 0.5;   /* f8 = f6 + (f2 - f4)/2 + rho u_in/6 */
+}
+
+static void zouhe_outlet_jacobian(double rho_out, double J[Q][Q]) {
+    double dux[Q] = {1.0, 2.0, 1.0, 0.0, 1.0, 2.0, 0.0, 0.0, 2.0};  /* d u_x / d f_q */
+    for (int q = 0; q < Q; ++q) dux[q] /= rho_out;
+    for (int a = 0; a < Q; ++a)
+        for (int b = 0; b < Q; ++b) J[a][b] = a == b ? 1.0 : 0.0;
+    for (int b = 0; b < Q; ++b) {
+        J[3][b] = -(2.0 / 3.0) * rho_out * dux[b];
+        J[6][b] = -(1.0 / 6.0) * rho_out * dux[b];
+        J[7][b] = -(1.0 / 6.0) * rho_out * dux[b];
+    }
+    J[3][1] += 1.0;                                   /* f3 = f1 - 2/3 rho_out u_x */
+    J[6][8] += 1.0; J[6][2] -= 0.5; J[6][4] += 0.5;   /* f6 = f8 - (f2 - f4)/2 - rho_out u_x/6 */
+    J[7][5] += 1.0; J[7][2] += 0.5; J[7][4] -= 0.5;   /* f7 = f5 + (f2 - f4)/2 - rho_out u_x/6 */
+}
+
+/* lam <- Z'^T lam in place: the transpose of the boundary closures' Jacobian at the
+ * fluid nodes of the Zou-He columns (identity elsewhere and for other boundaries). */
+void oracle_bc_vjp(int nx, int ny, int bc_x, double u_in, double rho_out, const uint8_t* mask,
+                   double* lam) {
+    if (bc_x != BC_ZOUHE) return;
+    cfg_t c = make_cfg(nx, ny, 1.0, 0.0, 0.0, bc_x, 0, u_in, rho_out);
+    double Jin[Q][Q], Jout[Q][Q];
+    zouhe_inlet_jacobian(u_in, Jin);
+    zouhe_outlet_jacobian(rho_out, Jout);
+    for (int j = 0; j < ny; ++j)
+        for (int side = 0; side < 2; ++side) {
+            const int i = side == 0 ? 0 : nx - 1;
+            if (mask[(size_t)j * nx + i]) continue;
+            double (*J)[Q] = side == 0 ? Jin : Jout;
+            double l[Q], nu[Q];
+            for (int q = 0; q < Q; ++q) l[q] = lam[at(&c, q, j, i)];
+            for (int b = 0; b < Q; ++b) {
+                nu[b] = 0.0;
+                for (int a = 0; a < Q; ++a) nu[b] += J[a][b] * l[a];
+            }
+            for (int q = 0; q < Q; ++q) lam[at(&c, q, j, i)] = nu[q];
+        }
+}
+
+/* Vector-Jacobian product of one step f(n+1) = Z(P C(f(n))): given the pre-collision
+ * state f(n) and lam_np1 = dL/df(n+1), returns lam_n = dL/df(n) =
+ * C'(f(n))^T P^T Z'^T lam_np1, where Z is the Zou-He closure of the boundary columns
+ * (identity for periodic and wall boundaries), P the streaming / bounce-back
+ * permutation and C' the per-node collision Jacobian. */
 int oracle_adjoint_step(int nx, int ny, double tau, double gx, double gy, int bc_x, int bc_y,
-                        const uint8_t* mask, const double* f, const double* lam_np1, double* lam_n) {
-    if (bc_x == BC_ZOUHE || bc_y == BC_ZOUHE) return -1;
-    cfg_t c = make_cfg(nx, ny, tau, gx, gy, bc_x, bc_y, 0.0, 1.0);
+                        double u_in, double rho_out, const uint8_t* mask, const double* f,
+                        const double* lam_in, double* lam_n) {
+    if (bc_y == BC_ZOUHE) return -1;
+    cfg_t c = make_cfg(nx, ny, tau, gx, gy, bc_x, bc_y, u_in, rho_out);
+    const size_t total = (size_t)Q * nx * ny;
+    double* lam_np1 = (double*)malloc(total * sizeof(double));
+    if (!lam_np1) return -2;
+    memcpy(lam_np1, lam_in, total * sizeof(double));
+    oracle_bc_vjp(nx, ny, bc_x, u_in, rho_out, mask, lam_np1);
     const double om = 1.0 / tau;
     const double pref = 1.0 - 0.5 * om;
 #pragma omp parallel for schedule(static)
@@ -374,6 +438,7 @@ int oracle_adjoint_step(int nx, int ny, double tau, double gx, double gy, int bc
                 lam_n[at(&c, q, j, i)] = (1.0 - om) * mu[q] + a + bx * dux + by * duy;
             }
         }
+    free(lam_np1);
     return 0;
 }
 
