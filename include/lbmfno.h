@@ -217,17 +217,20 @@ int lbm_info(const lbm_ctx* ctx, int64_t* fluid_nodes, int64_t* steps_done);
 /* ================================================================ adjoint
  *
  * Reverse-mode derivatives of the lattice (the paper's solver is differentiable,
- * Sec. 2.1): a rollout f(0) = f_eq(rho0, u0), f(n+1) = P C(f(n)), loss L(macros(f(N)))
- * is differentiated by
+ * Sec. 2.1): a rollout f(0) = Z(f_eq(rho0, u0)), f(n+1) = Z(P C(f(n))), loss
+ * L(macros(f(N))), where Z is the Zou-He closure of the boundary columns (identity
+ * for periodic and wall boundaries), is differentiated by
  *   lam_N = lbm_macro_vjp(f(N), dL/d macros),
  *   lam_n = lbm_adjoint_step(f(n), lam_{n+1})  for n = N-1 .. 0,
  *   dL/d(rho0, u0) = lbm_feq_vjp(rho0, u0, lam_0),
  * with f(n) recomputed from checkpoints.  All arrays float32 device, populations
  * [9][ny][nx] absolute (as from lbm_get_populations), fields [ny][nx]; solid
- * nodes get zeros.  Periodic and wall boundaries only (Zou-He: LBM_EUNSUPPORTED). */
+ * nodes get zeros.  Every boundary kind of lbm_init is covered. */
 
-/* lam_n = C'(f(n))^T P^T lam_{n+1}: P^T is the inverse of the streaming /
- * bounce-back permutation, C' the per-node collision Jacobian (with the Guo term).
+/* lam_n = C'(f(n))^T P^T Z'^T lam_{n+1}: Z'^T is the transposed Jacobian of the
+ * Zou-He closures (the unknown populations' adjoints move onto the known populations
+ * they are formed from), P^T the inverse of the streaming / bounce-back permutation,
+ * C' the per-node collision Jacobian (with the Guo term).
  * d_lam_np1 and d_lam_n must differ.  Asynchronous on ctx's stream. */
 int lbm_adjoint_step(lbm_ctx* ctx, const float* d_f_n, const float* d_lam_np1, float* d_lam_n);
 
@@ -236,7 +239,8 @@ int lbm_adjoint_step(lbm_ctx* ctx, const float* d_f_n, const float* d_lam_np1, f
 int lbm_macro_vjp(lbm_ctx* ctx, const float* d_f_n, const float* d_g_rho, const float* d_g_ux,
                   const float* d_g_uy, float* d_lam);
 
-/* Gradient of the initial fields through f(0) = f_eq(rho, u) (Eq. 1). */
+/* Gradient of the initial fields through f(0) = Z(f_eq(rho, u)) (Eq. 1 and the
+ * boundary closures that lbm_init / lbm_reinit_from_macro apply). */
 int lbm_feq_vjp(lbm_ctx* ctx, const float* d_rho, const float* d_ux, const float* d_uy,
                 const float* d_lam, float* d_g_rho, float* d_g_ux, float* d_g_uy);
 

@@ -1784,12 +1784,15 @@ namespace lbmfno {
 
 // ================================================================= adjoint
 //
-// Vector-Jacobian product of one step f(n+1) = P C(f(n)) (periodic and wall
-// boundaries): lam_n = C'(f(n))^T P^T lam_{n+1}.  P^T is the inverse of the pull
-// permutation: slot (q, y) was pulled by y + c_q when that node is fluid and inside
-// the domain (link bit opp(q)-1 of y clear), otherwise it bounced back into y as
-// opp(q).  C' is the per-node collision Jacobian with d rho / d f_j = 1 and
-// d u / d f_j = (c_j - u + g/2) / rho.  FP64 registers, float32 in and out.
+// Vector-Jacobian product of one step f(n+1) = Z(P C(f(n))):
+// lam_n = C'(f(n))^T P^T Z'^T lam_{n+1}.  Z is the Zou-He closure of the boundary
+// columns (identity for periodic and wall boundaries); Z'^T, the transpose of its
+// Jacobian, is applied on the fly where lam_{n+1} is read at a Zou-He column node
+// (zh_nu).  P^T is the inverse of the pull permutation: slot (q, y) was pulled by
+// y + c_q when that node is fluid and inside the domain (link bit opp(q)-1 of y
+// clear), otherwise it bounced back into y as opp(q).  C' is the per-node collision
+// Jacobian with d rho / d f_j = 1 and d u / d f_j = (c_j - u + g/2) / rho.  FP64
+// registers, float32 in and out.
 struct AdjArgs {
     const float* __restrict__ f;      // pre-collision populations f(n), absolute
     const float* __restrict__ lam1;   // lam_{n+1}
@@ -1797,10 +1800,44 @@ struct AdjArgs {
     const uint8_t* __restrict__ link;
     const uint8_t* __restrict__ mask;
     LatticeGeom g;
-    double omega, guo, gx, gy;
+    double omega, guo, gx, gy, u_in, rho_out;
 };
 
-template <bool FORCE>
+// (Z'^T lam)_q at a fluid node t of a Zou-He column.  The closures (zouhe()) set the
+// three unknown populations from the known ones after streaming; in the transpose
+// the unknowns' adjoints move onto the known populations they were formed from, and
+// the unknown slots themselves get zero.  Inlet (x = 0, velocity u_in): unknowns
+// 1, 5, 8, rho = (f0 + f2 + f4 + 2 (f3 + f6 + f7)) / (1 - u_in); outlet
+// (x = nx - 1, density rho_out): unknowns 3, 6, 7, u_x = -1 + (f0 + f2 + f4 +
+// 2 (f1 + f5 + f8)) / rho_out.
+__device__ __forceinline__ double zh_nu(const float* __restrict__ lam, size_t N, int t, int q,
+                                        bool inlet, double u_in) {
+    if (inlet) {
+        if (q == 1 || q == 5 || q == 8) return 0.0;
+        const double l1 = lam[1 * N + t], l5 = lam[5 * N + t], l8 = lam[8 * N + t];
+        const double drho = (q == 3 || q == 6 || q == 7) ? 2.0 : 1.0;   // q in {0, 2, 4}: 1
+        double v = (double)lam[q * N + t] +
+                   u_in / (1.0 - u_in) * drho * ((2.0 / 3.0) * l1 + (1.0 / 6.0) * (l5 + l8));
+        if (q == 3) v += l1;
+        if (q == 7) v += l5;
+        if (q == 6) v += l8;
+        if (q == 2) v += 0.5 * (l8 - l5);
+        if (q == 4) v += 0.5 * (l5 - l8);
+        return v;
+    }
+    if (q == 3 || q == 6 || q == 7) return 0.0;
+    const double l3 = lam[3 * N + t], l6 = lam[6 * N + t], l7 = lam[7 * N + t];
+    const double dux = (q == 1 || q == 5 || q == 8) ? 2.0 : 1.0;         // q in {0, 2, 4}: 1
+    double v = (double)lam[q * N + t] - dux * ((2.0 / 3.0) * l3 + (1.0 / 6.0) * (l6 + l7));
+    if (q == 1) v += l3;
+    if (q == 8) v += l6;
+    if (q == 5) v += l7;
+    if (q == 2) v += 0.5 * (l7 - l6);
+    if (q == 4) v += 0.5 * (l6 - l7);
+    return v;
+}
+
+template <bool FORCE, bool ZH>
 __global__ __launch_bounds__(256) void k_adjoint_step(AdjArgs a) {
     const int b = blockIdx.x;
     const int by = b / a.g.gridx, bx = b - by * a.g.gridx;
@@ -1817,20 +1854,24 @@ __global__ __launch_bounds__(256) void k_adjoint_step(AdjArgs a) {
     const int im = i == 0 ? a.g.nx - 1 : i - 1, ip = i == a.g.nx - 1 ? 0 : i + 1;
     const int jm = j == 0 ? a.g.ny - 1 : j - 1, jp = j == a.g.ny - 1 ? 0 : j + 1;
     const int r0 = j * a.g.nx, rm = jm * a.g.nx, rp = jp * a.g.nx;
-    // push target y + c_q for q = 1..8
+    // push target y + c_q for q = 1..8; (Z'^T lam_{n+1}) read at node t of column col
+    const int nx = a.g.nx;
+    auto nu = [&](int q, int t, int col) -> double {
+        if (ZH && (col == 0 || col == nx - 1)) return zh_nu(a.lam1, N, t, q, col == 0, a.u_in);
+        return (double)a.lam1[q * N + t];
+    };
     double mu[9];
-    mu[0] = a.lam1[n];
-#define LBM_PUSH(Q, TGT)                                                                  \
-    mu[Q] = ((lk >> (opp_of(Q) - 1)) & 1u) ? (double)a.lam1[opp_of(Q) * N + n]           \
-                                           : (double)a.lam1[Q * N + (TGT)];
-    LBM_PUSH(1, r0 + ip)
-    LBM_PUSH(2, rp + i)
-    LBM_PUSH(3, r0 + im)
-    LBM_PUSH(4, rm + i)
-    LBM_PUSH(5, rp + ip)
-    LBM_PUSH(6, rp + im)
-    LBM_PUSH(7, rm + im)
-    LBM_PUSH(8, rm + ip)
+    mu[0] = nu(0, n, i);
+#define LBM_PUSH(Q, TGT, COL)                                                             \
+    mu[Q] = ((lk >> (opp_of(Q) - 1)) & 1u) ? nu(opp_of(Q), n, i) : nu(Q, (TGT), (COL));
+    LBM_PUSH(1, r0 + ip, ip)
+    LBM_PUSH(2, rp + i, i)
+    LBM_PUSH(3, r0 + im, im)
+    LBM_PUSH(4, rm + i, i)
+    LBM_PUSH(5, rp + ip, ip)
+    LBM_PUSH(6, rp + im, im)
+    LBM_PUSH(7, rm + im, im)
+    LBM_PUSH(8, rm + ip, ip)
 #undef LBM_PUSH
     double f[9];
 #pragma unroll
@@ -1901,9 +1942,11 @@ __global__ __launch_bounds__(256) void k_macro_vjp(const float* __restrict__ fpo
         lam[q * NN + n] = (float)(ar + (ax * (cx_of(q) - vx) + ay * (cy_of(q) - vy)) / rho);
 }
 
-// Pull-back through f(0) = f_eq(rho, u): g_rho = sum_q lam_q d f_eq_q / d rho,
-// g_u = sum_q lam_q d f_eq_q / d u (solids: 0).
-__global__ __launch_bounds__(256) void k_feq_vjp(const uint8_t* __restrict__ mask, int N,
+// Pull-back through f(0) = Z(f_eq(rho, u)): g_rho = sum_q nu_q d f_eq_q / d rho,
+// g_u = sum_q nu_q d f_eq_q / d u with nu = Z'^T lam (the Zou-He closures, zh != 0,
+// at the boundary columns; lam itself elsewhere).  Solids: 0.
+__global__ __launch_bounds__(256) void k_feq_vjp(const uint8_t* __restrict__ mask, int N, int nx,
+                                                 int zh, double u_in,
                                                  const float* __restrict__ rho,
                                                  const float* __restrict__ ux,
                                                  const float* __restrict__ uy,
@@ -1914,11 +1957,13 @@ __global__ __launch_bounds__(256) void k_feq_vjp(const uint8_t* __restrict__ mas
     if (n >= N) return;
     if (mask[n]) { grho[n] = 0.0f; gux[n] = 0.0f; guy[n] = 0.0f; return; }
     const size_t NN = (size_t)N;
+    const int col = n % nx;
+    const bool closed = zh && (col == 0 || col == nx - 1);
     const double r = rho[n], u = ux[n], v = uy[n];
     const double usq = fma(u, u, v * v);
     double a = 0.0, bx = 0.0, by = 0.0;
     for (int q = 0; q < 9; ++q) {
-        const double l = lam[q * NN + n];
+        const double l = closed ? zh_nu(lam, NN, n, q, col == 0, u_in) : (double)lam[q * NN + n];
         const double cu = cx_of(q) * u + cy_of(q) * v;
         const double wq = w_of_d(q);
         a = fma(l, wq * (1.0 + fma(cu, fma(4.5, cu, 3.0), -1.5 * usq)), a);
@@ -1940,8 +1985,6 @@ extern "C" int lbm_adjoint_step(lbm_ctx* c, const float* d_f_n, const float* d_l
     if (!c) return fail(LBM_EINVAL, "ctx is NULL");
     if (!d_f_n || !d_lam_np1 || !d_lam_n) return fail(LBM_EINVAL, "NULL buffer");
     if (d_lam_np1 == d_lam_n) return fail(LBM_EINVAL, "lam_{n+1} and lam_n must differ");
-    if (c->cfg.bc_x == LBM_BC_ZOUHE)
-        return fail(LBM_EUNSUPPORTED, "adjoint of Zou-He columns is not implemented");
     AdjArgs a;
     a.f = d_f_n;
     a.lam1 = d_lam_np1;
@@ -1953,9 +1996,17 @@ extern "C" int lbm_adjoint_step(lbm_ctx* c, const float* d_f_n, const float* d_l
     a.guo = 1.0 - 0.5 / c->cfg.tau;
     a.gx = c->cfg.gx;
     a.gy = c->cfg.gy;
+    a.u_in = c->cfg.u_in;
+    a.rho_out = c->cfg.rho_out;
     dim3 blk(TX, TY), grd(c->nblocks);
-    if (a.gx != 0.0 || a.gy != 0.0) k_adjoint_step<true><<<grd, blk, 0, c->stream>>>(a);
-    else k_adjoint_step<false><<<grd, blk, 0, c->stream>>>(a);
+    const bool force = a.gx != 0.0 || a.gy != 0.0, zh = c->cfg.bc_x == LBM_BC_ZOUHE;
+    if (zh) {
+        if (force) k_adjoint_step<true, true><<<grd, blk, 0, c->stream>>>(a);
+        else k_adjoint_step<false, true><<<grd, blk, 0, c->stream>>>(a);
+    } else {
+        if (force) k_adjoint_step<true, false><<<grd, blk, 0, c->stream>>>(a);
+        else k_adjoint_step<false, false><<<grd, blk, 0, c->stream>>>(a);
+    }
     LBM_HIP(hipGetLastError());
     return LBM_OK;
 }
@@ -1977,8 +2028,9 @@ extern "C" int lbm_feq_vjp(lbm_ctx* c, const float* d_rho, const float* d_ux, co
     if (!d_rho || !d_ux || !d_uy || !d_lam || !d_g_rho || !d_g_ux || !d_g_uy)
         return fail(LBM_EINVAL, "NULL buffer");
     const int N = c->g.N;
-    k_feq_vjp<<<(N + 255) / 256, 256, 0, c->stream>>>(c->d_mask, N, d_rho, d_ux, d_uy, d_lam,
-                                                      d_g_rho, d_g_ux, d_g_uy);
+    k_feq_vjp<<<(N + 255) / 256, 256, 0, c->stream>>>(c->d_mask, N, c->g.nx,
+                                                      c->cfg.bc_x == LBM_BC_ZOUHE, c->cfg.u_in,
+                                                      d_rho, d_ux, d_uy, d_lam, d_g_rho, d_g_ux, d_g_uy);
     LBM_HIP(hipGetLastError());
     return LBM_OK;
 }

@@ -86,3 +86,46 @@ def test_full_size_rollout_directional_derivative(gpu):
     an = sum(float(np.sum(a * b)) for a, b in zip(g, d))
     print(f"directional derivative: GPU adjoint {an:.8e}, FP64 central difference {fd:.8e}")
     assert abs(an - fd) <= 1e-4 * abs(fd)
+
+
+def zouhe_lattice(nx=48, ny=24):
+    return W.Lattice(nx=nx, ny=ny, tau=0.7, bc_x=W.BC_ZOUHE, bc_y=W.BC_PERIODIC, u_in=0.03,
+                     rho_out=1.01, shapes=[W.circle(nx // 2, ny // 2, 4), W.circle(nx // 5, ny // 4, 2)],
+                     wrap_x=False, wrap_y=True)
+
+
+def test_adjoint_step_through_zouhe_columns_matches_oracle(gpu):
+    """One step's adjoint on a lattice with Zou-He inlet and outlet columns (the
+    closures' transposed Jacobian applied where lam_{n+1} is read), vs the FP64 oracle."""
+    import torch
+    lat = zouhe_lattice()
+    O = olbm.Sim(lat).init(*W.random_macro_fields(5, lat.nx, lat.ny, amp_u=0.03)).run(15)
+    f = O.f.astype(np.float32)
+    lam = W.random_array(6, f.shape).astype(np.float32) * (O.mask == 0)
+    ref = olbm.adjoint_step(lat, O.mask, f.astype(np.float64), lam.astype(np.float64))
+    G = gpu.Lattice.from_workload(lat)
+    out = G.adjoint_step(torch.from_numpy(f).cuda(), torch.from_numpy(lam).cuda()).cpu().numpy()
+    fl = np.repeat((O.mask == 0)[None], 9, 0)
+    e = rel_l2(out[fl], ref[fl])
+    edge = np.zeros_like(fl)
+    edge[:, :, :2] = edge[:, :, -2:] = True
+    e_edge = rel_l2(out[fl & edge], ref[fl & edge])
+    print(f"Zou-He adjoint step rel-L2 vs FP64 oracle: {e:.2e} (boundary columns {e_edge:.2e})")
+    assert e < 1e-6 and e_edge < 1e-6
+    assert np.all(out[~fl] == 0)
+
+
+def test_rollout_gradient_through_zouhe_columns_matches_oracle(gpu):
+    """Checkpointed rollout (80 steps, checkpoints every 30) on a Zou-He lattice:
+    gradient w.r.t. the initial fields, through the closures of every step and of
+    the initial equilibrium, vs the FP64 oracle."""
+    lat = zouhe_lattice(40, 20)
+    init, tgt, mask, loss, g = rollout_case(gpu, lat, 80, 30, seed=9)
+    ref = olbm.rollout_grad(lat, mask, *init, 80, tgt)
+    lref = olbm.rollout_loss(lat, mask, *init, 80, tgt)
+    fl = mask == 0
+    errs = [rel_l2(a[fl], b[fl]) for a, b in zip(g, ref)]
+    print(f"Zou-He rollout: loss gpu {loss:.8e} oracle {lref:.8e}; grad rel-L2 " +
+          " ".join(f"{x:.2e}" for x in errs))
+    assert abs(loss - lref) <= 1e-5 * lref
+    assert max(errs) < 1e-5
