@@ -32,6 +32,7 @@ def lib():
         L.oracle_raster.argtypes = [_i, _i, _i, _i, _p, _i, _p]
         L.oracle_feq.argtypes = [_d, _d, _d, _p]
         L.oracle_init.argtypes = [_i, _i, _d, _d, _d, _i, _i, _d, _d, _p, _p, _p, _p, _p]
+        L.oracle_init_neq.argtypes = [_i, _i, _d, _d, _d, _i, _i, _d, _d, _p, _p, _p, _p, _p]
         L.oracle_collide.argtypes = [_i, _i, _d, _d, _d, _p, _p, _p]
         L.oracle_stream.argtypes = [_i, _i, _i, _i, _d, _d, _p, _p, _p]
         L.oracle_run.argtypes = [_i, _i, _d, _d, _d, _i, _i, _d, _d, _p, _p, _i]
@@ -99,13 +100,16 @@ class Sim:
         L = self.lat
         return (self.nx, self.ny, L.tau, L.gx, L.gy, L.bc_x, L.bc_y, L.u_in, L.rho_out)
 
-    def init(self, rho=None, ux=None, uy=None):
+    def init(self, rho=None, ux=None, uy=None, neq: bool = False):
+        """f(0) = f_eq(rho, u) (+ the first-order non-equilibrium part with neq), then
+        the boundary closures."""
         shp = (self.ny, self.nx)
         rho = _f64(np.ones(shp) if rho is None else rho)
         ux = _f64(np.zeros(shp) if ux is None else ux)
         uy = _f64(np.zeros(shp) if uy is None else uy)
         self.f = np.zeros((9, self.ny, self.nx))
-        lib().oracle_init(*self._args(), _ptr(self.mask), _ptr(rho), _ptr(ux), _ptr(uy), _ptr(self.f))
+        fn = lib().oracle_init_neq if neq else lib().oracle_init
+        fn(*self._args(), _ptr(self.mask), _ptr(rho), _ptr(ux), _ptr(uy), _ptr(self.f))
         self.steps = 0
         return self
 

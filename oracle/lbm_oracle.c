@@ -221,6 +221,65 @@ void oracle_init(int nx, int ny, double tau, double gx, double gy, int bc_x, int
     apply_bc(&c, mask, f);
 }
 
+/* Velocity derivative along one axis at fluid node (i, j): central difference when
+ * both neighbours are fluid nodes inside the domain (periodic axes wrap), one-sided
+ * when only one is, zero when neither is. */
+static double velocity_derivative(const cfg_t* c, const uint8_t* mask, const double* u, int i, int j,
+                                  int axis) {
+    int ok[2], nb[2];
+    for (int s = 0; s < 2; ++s) {
+        const int d = s == 0 ? 1 : -1;
+        int a = i + (axis == 0 ? d : 0), b = j + (axis == 1 ? d : 0);
+        int inside = 1;
+        if (a < 0 || a >= c->nx) {
+            if (c->bc_x == BC_PERIODIC) a = (a + c->nx) % c->nx; else inside = 0;
+        }
+        if (b < 0 || b >= c->ny) {
+            if (c->bc_y == BC_PERIODIC) b = (b + c->ny) % c->ny; else inside = 0;
+        }
+        ok[s] = inside && !mask[(size_t)b * c->nx + a];
+        nb[s] = inside ? b * c->nx + a : 0;
+    }
+    const double u0 = u[(size_t)j * c->nx + i];
+    if (ok[0] && ok[1]) return 0.5 * (u[nb[0]] - u[nb[1]]);
+    if (ok[0]) return u[nb[0]] - u0;
+    if (ok[1]) return u0 - u[nb[1]];
+    return 0.0;
+}
+
+/* f(0) = f_eq(rho0, u0) + f_neq on fluid nodes, then the boundary closures, where
+ * f_neq is the first-order (Chapman-Enskog) non-equilibrium part of the
+ * pre-collision populations, f_neq_q = -tau w_q rho / c_s^2 (c_q c_q - c_s^2 I) : grad u,
+ * with the velocity gradient from velocity_derivative.  Its zeroth and first moments
+ * vanish and its second moment is the viscous stress -rho c_s^2 tau (grad u + grad u^T).
+ * Body-force contributions to f_neq are not included. */
+void oracle_init_neq(int nx, int ny, double tau, double gx, double gy, int bc_x, int bc_y,
+                     double u_in, double rho_out, const uint8_t* mask, const double* rho0,
+                     const double* ux0, const double* uy0, double* f) {
+    cfg_t c = make_cfg(nx, ny, tau, gx, gy, bc_x, bc_y, u_in, rho_out);
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            const size_t n = (size_t)j * nx + i;
+            double feq[Q];
+            if (mask[n]) {
+                for (int q = 0; q < Q; ++q) f[at(&c, q, j, i)] = WQ[q];
+                continue;
+            }
+            equilibrium(rho0[n], ux0[n], uy0[n], feq);
+            const double dxux = velocity_derivative(&c, mask, ux0, i, j, 0);
+            const double dyux = velocity_derivative(&c, mask, ux0, i, j, 1);
+            const double dxuy = velocity_derivative(&c, mask, uy0, i, j, 0);
+            const double dyuy = velocity_derivative(&c, mask, uy0, i, j, 1);
+            const double cs2 = 1.0 / 3.0;
+            for (int q = 0; q < Q; ++q) {
+                const double qxx = CX[q] * CX[q] - cs2, qyy = CY[q] * CY[q] - cs2, qxy = CX[q] * CY[q];
+                const double contr = qxx * dxux + qxy * (dyux + dxuy) + qyy * dyuy;
+                f[at(&c, q, j, i)] = feq[q] - tau * WQ[q] * rho0[n] / cs2 * contr;
+            }
+        }
+    apply_bc(&c, mask, f);
+}
+
 /* Collision on every fluid node: fstar = C(f). */
 void oracle_collide(int nx, int ny, double tau, double gx, double gy, const uint8_t* mask,
                     const double* f, double* fstar) {

@@ -359,3 +359,49 @@ def test_zouhe_closure_adjoint_transpose_identity():
     Pv = (lbm.stream(periodic, mask, fs + h * v) - lbm.stream(periodic, mask, fs - h * v)) / (2 * h)
     a2, b2 = float(np.sum(Zv * w * fl)), float(np.sum(Pv * wz * fl))
     assert abs(a2 - b2) <= 1e-8 * abs(b2)
+
+
+# ------------------------------------------------- non-equilibrium initialisation
+
+def test_neq_init_moments_are_the_viscous_stress():
+    """f(0) - f_eq has zero mass and momentum at every node, and its second moment is
+    the Chapman-Enskog viscous stress -rho c_s^2 tau (grad u + grad u^T), with the
+    gradient taken here by numpy central differences on a periodic box."""
+    nx, ny, tau = 20, 16, 0.9
+    lat = W.Lattice(nx=nx, ny=ny, tau=tau, bc_x=W.BC_PERIODIC, bc_y=W.BC_PERIODIC, shapes=[],
+                    wrap_x=True, wrap_y=True)
+    mask = np.zeros((ny, nx), np.uint8)
+    rho, ux, uy = W.random_macro_fields(31, nx, ny, amp_u=0.05)
+    f_eq = lbm.Sim(lat, mask).init(rho, ux, uy).f
+    f = lbm.Sim(lat, mask).init(rho, ux, uy, neq=True).f
+    d = f - f_eq
+    cx, cy, _, _ = lbm.lattice()
+    assert np.abs(d.sum(axis=0)).max() < 1e-15
+    assert np.abs(np.tensordot(cx, d, 1)).max() < 1e-15 and np.abs(np.tensordot(cy, d, 1)).max() < 1e-15
+    ddx = lambda a: 0.5 * (np.roll(a, -1, 1) - np.roll(a, 1, 1))
+    ddy = lambda a: 0.5 * (np.roll(a, -1, 0) - np.roll(a, 1, 0))
+    k = -rho * tau / 3.0
+    pxx = np.tensordot(cx * cx, d, 1)
+    pxy = np.tensordot(cx * cy, d, 1)
+    pyy = np.tensordot(cy * cy, d, 1)
+    assert np.allclose(pxx, k * 2 * ddx(ux), rtol=0, atol=1e-15)
+    assert np.allclose(pyy, k * 2 * ddy(uy), rtol=0, atol=1e-15)
+    assert np.allclose(pxy, k * (ddy(ux) + ddx(uy)), rtol=0, atol=1e-15)
+
+
+def test_neq_init_removes_the_shear_wave_start_transient():
+    """A decaying shear wave u_x = A sin(k y) started from f_eq alone carries a start
+    transient (the missing viscous stress) that leaves a lasting amplitude error; with
+    the non-equilibrium part the lattice follows A exp(-nu k^2 t) sin(k y) far closer."""
+    nx, ny, tau, A = 8, 64, 0.8, 1e-3
+    nu, kk = (tau - 0.5) / 3.0, 2 * np.pi / ny
+    lat = W.Lattice(nx=nx, ny=ny, tau=tau, bc_x=W.BC_PERIODIC, bc_y=W.BC_PERIODIC, shapes=[],
+                    wrap_x=True, wrap_y=True)
+    mask = np.zeros((ny, nx), np.uint8)
+    y = np.arange(ny)[:, None] * np.ones((1, nx))
+    exact = lambda t: A * np.exp(-nu * kk * kk * t) * np.sin(kk * y)
+    err = {}
+    for neq in (False, True):
+        s = lbm.Sim(lat, mask).init(np.ones((ny, nx)), exact(0), np.zeros((ny, nx)), neq=neq).run(5)
+        err[neq] = np.abs(s.macros()[1] - exact(5)).max() / A
+    assert err[False] > 3e-4 and err[True] < 1e-5, err
