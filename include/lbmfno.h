@@ -137,6 +137,17 @@ void lbm_destroy(lbm_ctx* ctx);
  * d_rho, d_ux, d_uy: float32 [ny][nx]; values on solid nodes are ignored. */
 int lbm_reinit_from_macro(lbm_ctx* ctx, const float* d_rho, const float* d_ux, const float* d_uy);
 
+/* lbm_reinit_from_macro plus the first-order (Chapman-Enskog) non-equilibrium part
+ * of the pre-collision populations, f_q = f_eq_q - tau w_q rho / c_s^2
+ * (c_q c_q - c_s^2 I) : grad u, so that the hand-off also carries the viscous stress
+ * -rho c_s^2 tau (grad u + grad u^T) that f_eq alone drops (Sec. 2.3 hand-off; the
+ * stress-free start otherwise relaxes through a transient of a few tau).  grad u by
+ * central differences between fluid nodes (one-sided next to solids and open
+ * boundaries, zero with no fluid neighbour on an axis); body-force terms are not
+ * included.  Same arguments and errors as lbm_reinit_from_macro. */
+int lbm_reinit_from_macro_neq(lbm_ctx* ctx, const float* d_rho, const float* d_ux,
+                              const float* d_uy);
+
 /* Advance n >= 0 steps: each gathers f(t) (streaming Eq. 3 with bounce-back and
  * Zou-He), takes moments (Eqs. 4-5, u = (sum c f + rho g/2)/rho), collides (Eq. 2
  * with the Guo term) and stores the result for the next pull.  With rep == NULL

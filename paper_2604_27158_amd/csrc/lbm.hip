@@ -168,31 +168,61 @@ __device__ __forceinline__ R feq_dev(R drho, R rho, R ux, R uy) {
     return feq_dev<P, R>(drho, rho, ux, uy, R(1.5) * fma(ux, ux, uy * uy));
 }
 
-__device__ __forceinline__ float feq_dev_rt(int p, double drho, double rho, double ux, double uy) {
+__device__ __forceinline__ double feq_dev_rt(int p, double drho, double rho, double ux, double uy) {
     switch (p) {
-        case 0: return (float)feq_dev<0>(drho, rho, ux, uy);
-        case 1: return (float)feq_dev<1>(drho, rho, ux, uy);
-        case 2: return (float)feq_dev<2>(drho, rho, ux, uy);
-        case 3: return (float)feq_dev<3>(drho, rho, ux, uy);
-        case 4: return (float)feq_dev<4>(drho, rho, ux, uy);
-        case 5: return (float)feq_dev<5>(drho, rho, ux, uy);
-        case 6: return (float)feq_dev<6>(drho, rho, ux, uy);
-        case 7: return (float)feq_dev<7>(drho, rho, ux, uy);
-        default: return (float)feq_dev<8>(drho, rho, ux, uy);
+        case 0: return feq_dev<0>(drho, rho, ux, uy);
+        case 1: return feq_dev<1>(drho, rho, ux, uy);
+        case 2: return feq_dev<2>(drho, rho, ux, uy);
+        case 3: return feq_dev<3>(drho, rho, ux, uy);
+        case 4: return feq_dev<4>(drho, rho, ux, uy);
+        case 5: return feq_dev<5>(drho, rho, ux, uy);
+        case 6: return feq_dev<6>(drho, rho, ux, uy);
+        case 7: return feq_dev<7>(drho, rho, ux, uy);
+        default: return feq_dev<8>(drho, rho, ux, uy);
     }
+}
+
+// Derivative of the field u along x (axis 0) or y (axis 1) at fluid node (i, j):
+// central difference when both neighbours are fluid nodes inside the domain
+// (periodic axes wrap), one-sided when one is, zero when neither is.
+__device__ __forceinline__ double vel_deriv(const LatticeGeom& g, const uint8_t* __restrict__ mask,
+                                            const float* __restrict__ u, int i, int j, int axis) {
+    bool ok[2];
+    int nb[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const int d = s == 0 ? 1 : -1;
+        int a = i + (axis == 0 ? d : 0), b = j + (axis == 1 ? d : 0);
+        bool inside = true;
+        if (a < 0 || a >= g.nx) {
+            if (g.bc_x == LBM_BC_PERIODIC) a = (a + g.nx) % g.nx; else inside = false;
+        }
+        if (b < 0 || b >= g.ny) {
+            if (g.bc_y == LBM_BC_PERIODIC) b = (b + g.ny) % g.ny; else inside = false;
+        }
+        nb[s] = inside ? b * g.nx + a : 0;
+        ok[s] = inside && mask[nb[s]] == 0;
+    }
+    const double u0 = u[j * g.nx + i];
+    if (ok[0] && ok[1]) return 0.5 * ((double)u[nb[0]] - (double)u[nb[1]]);
+    if (ok[0]) return (double)u[nb[0]] - u0;
+    if (ok[1]) return u0 - (double)u[nb[1]];
+    return 0.0;
 }
 
 // Scatter f(0) into a store: slot (p, y) receives what y + c_p pulls, or, when that
 // node is solid/outside, what bounces back into y as opp(p).
 //   FROM_FIELDS: f_q(x) = f_eq_q(rho(x), u(x))        (re-initialisation)
 //   else:        f_q(x) = given populations (absolute) (state restore)
-template <bool FROM_FIELDS>
+// NEQ (with FROM_FIELDS): add the first-order non-equilibrium part of the
+// pre-collision populations, -tau w_q rho / c_s^2 (c_q c_q - c_s^2 I) : grad u.
+template <bool FROM_FIELDS, bool NEQ>
 __global__ __launch_bounds__(256) void k_scatter(LatticeGeom g, const uint8_t* __restrict__ mask,
                                                  const float* __restrict__ rho,
                                                  const float* __restrict__ ux,
                                                  const float* __restrict__ uy,
                                                  const float* __restrict__ fin,
-                                                 float* __restrict__ dst) {
+                                                 float* __restrict__ dst, double tau) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y;
     if (i >= g.nx) return;
@@ -211,7 +241,19 @@ __global__ __launch_bounds__(256) void k_scatter(LatticeGeom g, const uint8_t* _
         float v;
         if (FROM_FIELDS) {
             const double r = rho[src];
-            v = feq_dev_rt(dir, r - 1.0, r, ux[src], uy[src]);
+            double e = feq_dev_rt(dir, r - 1.0, r, ux[src], uy[src]);
+            if (NEQ) {
+                const int si = src % g.nx, sj = src / g.nx;
+                const double dxux = vel_deriv(g, mask, ux, si, sj, 0);
+                const double dyux = vel_deriv(g, mask, ux, si, sj, 1);
+                const double dxuy = vel_deriv(g, mask, uy, si, sj, 0);
+                const double dyuy = vel_deriv(g, mask, uy, si, sj, 1);
+                const double cx = cx_of(dir), cy = cy_of(dir);
+                const double contr = (cx * cx - 1.0 / 3.0) * dxux + cx * cy * (dyux + dxuy) +
+                                     (cy * cy - 1.0 / 3.0) * dyuy;
+                e -= 3.0 * tau * w_of_d(dir) * r * contr;
+            }
+            v = (float)e;
         } else {
             v = (float)((double)fin[dir * N + src] - w_of_d(dir));
         }
@@ -1300,24 +1342,37 @@ extern "C" int lbm_init(lbm_ctx** out, const lbm_config* cfg, const uint8_t* d_m
     return LBM_OK;
 }
 
-extern "C" int lbm_reinit_from_macro(lbm_ctx* c, const float* d_rho, const float* d_ux,
-                                     const float* d_uy) {
+static int reinit(lbm_ctx* c, const float* d_rho, const float* d_ux, const float* d_uy, bool neq) {
     if (!c) return fail(LBM_EINVAL, "ctx is NULL");
     if (!d_rho || !d_ux || !d_uy) return fail(LBM_EINVAL, "NULL field");
     dim3 blk(256), grd((c->g.nx + 255) / 256, c->g.ny);
-    k_scatter<true><<<grd, blk, 0, c->stream>>>(c->g, c->d_mask, d_rho, d_ux, d_uy, nullptr,
-                                                c->f[c->cur]);
+    if (neq)
+        k_scatter<true, true><<<grd, blk, 0, c->stream>>>(c->g, c->d_mask, d_rho, d_ux, d_uy, nullptr,
+                                                          c->f[c->cur], c->cfg.tau);
+    else
+        k_scatter<true, false><<<grd, blk, 0, c->stream>>>(c->g, c->d_mask, d_rho, d_ux, d_uy, nullptr,
+                                                           c->f[c->cur], c->cfg.tau);
     LBM_HIP(hipGetLastError());
     c->steps = 0;
     return LBM_OK;
+}
+
+extern "C" int lbm_reinit_from_macro(lbm_ctx* c, const float* d_rho, const float* d_ux,
+                                     const float* d_uy) {
+    return reinit(c, d_rho, d_ux, d_uy, false);
+}
+
+extern "C" int lbm_reinit_from_macro_neq(lbm_ctx* c, const float* d_rho, const float* d_ux,
+                                         const float* d_uy) {
+    return reinit(c, d_rho, d_ux, d_uy, true);
 }
 
 extern "C" int lbm_set_populations(lbm_ctx* c, const float* d_f) {
     if (!c) return fail(LBM_EINVAL, "ctx is NULL");
     if (!d_f) return fail(LBM_EINVAL, "d_f is NULL");
     dim3 blk(256), grd((c->g.nx + 255) / 256, c->g.ny);
-    k_scatter<false><<<grd, blk, 0, c->stream>>>(c->g, c->d_mask, nullptr, nullptr, nullptr, d_f,
-                                                 c->f[c->cur]);
+    k_scatter<false, false><<<grd, blk, 0, c->stream>>>(c->g, c->d_mask, nullptr, nullptr, nullptr,
+                                                        d_f, c->f[c->cur], c->cfg.tau);
     LBM_HIP(hipGetLastError());
     return LBM_OK;
 }

@@ -87,6 +87,7 @@ SIGNATURES = [
     ("lbm_init", ctypes.c_int, [ctypes.POINTER(_p), ctypes.POINTER(LbmConfig), _p, _p, _p, _p]),
     ("lbm_destroy", None, [_p]),
     ("lbm_reinit_from_macro", ctypes.c_int, [_p, _p, _p, _p]),
+    ("lbm_reinit_from_macro_neq", ctypes.c_int, [_p, _p, _p, _p]),
     ("lbm_step", ctypes.c_int, [_p, _i32, ctypes.POINTER(LbmReport)]),
     ("lbm_get_macro", ctypes.c_int, [_p, _p, _p, _p, _i32]),
     ("lbm_get_populations", ctypes.c_int, [_p, _p]),
@@ -279,15 +280,17 @@ class Lattice:
         for t in ins:
             t.record_stream(self.stream)
 
-    def reinit(self, rho, ux, uy):
+    def reinit(self, rho, ux, uy, neq: bool = False):
+        """f = f_eq(rho, u) (with neq, plus the first-order non-equilibrium part from the
+        velocity gradient), then the boundary closures; the step count restarts."""
         import torch
         self._after_caller()
         with torch.cuda.stream(self.stream):
             rho, ux, uy = (t.to(device="cuda", dtype=torch.float32).contiguous() for t in (rho, ux, uy))
         self._take_inputs(rho, ux, uy)
         self._keep = (rho, ux, uy)
-        check(self.lib.lbm_reinit_from_macro(self.ctx, rho.data_ptr(), ux.data_ptr(), uy.data_ptr()),
-              "lbm_reinit_from_macro")
+        fn = self.lib.lbm_reinit_from_macro_neq if neq else self.lib.lbm_reinit_from_macro
+        check(fn(self.ctx, rho.data_ptr(), ux.data_ptr(), uy.data_ptr()), "lbm_reinit_from_macro")
 
     def macros(self, rho_minus_one: bool = False, out=None):
         """(rho, ux, uy) [3][ny][nx] float32; written into `out` (a contiguous device

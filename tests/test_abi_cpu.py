@@ -73,6 +73,7 @@ def test_null_arguments(lib):
     assert lib.lbm_step(None, 1, None) == -1
     assert lib.lbm_get_macro(None, 1, 2, 3, 0) == -1
     assert lib.lbm_reinit_from_macro(None, 1, 2, 3) == -1
+    assert lib.lbm_reinit_from_macro_neq(None, 1, 2, 3) == -1
 
 
 def test_raster_validation(lib):
