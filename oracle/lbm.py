@@ -37,6 +37,9 @@ def lib():
         L.oracle_stream.argtypes = [_i, _i, _i, _i, _d, _d, _p, _p, _p]
         L.oracle_run.argtypes = [_i, _i, _d, _d, _d, _i, _i, _d, _d, _p, _p, _i]
         L.oracle_run.restype = _i
+        L.oracle_collide_trt.argtypes = [_i, _i, _d, _d, _d, _d, _p, _p, _p]
+        L.oracle_run_trt.argtypes = [_i, _i, _d, _d, _d, _d, _i, _i, _d, _d, _p, _p, _i]
+        L.oracle_run_trt.restype = _i
         L.oracle_macros.argtypes = [_i, _i, _d, _d, _p, _p, _p, _p, _p]
         L.oracle_sums.argtypes = [_i, _i, _p, _p, _p, _p, _p, _p]
         L.oracle_adjoint_step.argtypes = [_i, _i, _d, _d, _d, _i, _i, _d, _d, _p, _p, _p, _p]
@@ -114,7 +117,13 @@ class Sim:
         return self
 
     def run(self, n: int):
-        rc = lib().oracle_run(*self._args(), _ptr(self.mask), _ptr(self.f), int(n))
+        lam = getattr(self.lat, "trt_lambda", 0.0)
+        if lam > 0.0:
+            L = self.lat
+            rc = lib().oracle_run_trt(self.nx, self.ny, L.tau, lam, L.gx, L.gy, L.bc_x, L.bc_y, L.u_in,
+                                      L.rho_out, _ptr(self.mask), _ptr(self.f), int(n))
+        else:
+            rc = lib().oracle_run(*self._args(), _ptr(self.mask), _ptr(self.f), int(n))
         if rc != 0:
             raise MemoryError("oracle_run")
         self.steps += n
@@ -128,8 +137,14 @@ class Sim:
 
 
 def collide(lat, mask, f):
+    """BGK collision, or TRT when lat.trt_lambda > 0."""
     f = _f64(f); out = np.zeros_like(f)
-    lib().oracle_collide(lat.nx, lat.ny, lat.tau, lat.gx, lat.gy, _ptr(mask), _ptr(f), _ptr(out))
+    lam = getattr(lat, "trt_lambda", 0.0)
+    if lam > 0.0:
+        lib().oracle_collide_trt(lat.nx, lat.ny, lat.tau, lam, lat.gx, lat.gy, _ptr(mask), _ptr(f),
+                                 _ptr(out))
+    else:
+        lib().oracle_collide(lat.nx, lat.ny, lat.tau, lat.gx, lat.gy, _ptr(mask), _ptr(f), _ptr(out))
     return out
 
 

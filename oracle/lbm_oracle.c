@@ -45,6 +45,7 @@ typedef struct {
     double tau, gx, gy;
     int bc_x, bc_y;
     double u_in, rho_out;
+    double lambda;  /* > 0: two-relaxation-time collision with this magic parameter */
 } cfg_t;
 
 static size_t at(const cfg_t* c, int q, int j, int i) {
@@ -115,18 +116,35 @@ static void moments(const double* f, double gx, double gy, double* rho, double* 
     *uy = (jy + 0.5 * r * gy) / r;
 }
 
-/* BGK collision (Eq. 2, sign-corrected) plus the Guo forcing term. */
+/* BGK collision (Eq. 2, sign-corrected) plus the Guo forcing term.  With
+ * c->lambda > 0 the two-relaxation-time (TRT) collision instead (Ginzburg 2005; an
+ * extension, the paper uses BGK): the parts of f, f_eq and the Guo source that are
+ * even and odd under c -> -c relax with tau+ = tau and with tau- from the magic
+ * parameter lambda = (tau+ - 1/2)(tau- - 1/2); the source's parts get the factors
+ * (1 - 1/(2 tau+)) and (1 - 1/(2 tau-)).  tau- = tau+ gives back BGK. */
 static void collide_node(const double* f, const cfg_t* c, double* fstar) {
-    double rho, ux, uy, feq[Q];
+    double rho, ux, uy, feq[Q], src[Q];
     moments(f, c->gx, c->gy, &rho, &ux, &uy);
     equilibrium(rho, ux, uy, feq);
-    const double pref = 1.0 - 1.0 / (2.0 * c->tau);
-    for (int q = 0; q < Q; ++q) {
+    for (int q = 0; q < Q; ++q) {   /* Guo source without its relaxation factor */
         const double cu = CX[q] * ux + CY[q] * uy;
         const double sx = 3.0 * (CX[q] - ux) + 9.0 * cu * CX[q];
         const double sy = 3.0 * (CY[q] - uy) + 9.0 * cu * CY[q];
-        const double S = pref * WQ[q] * (sx * rho * c->gx + sy * rho * c->gy);
-        fstar[q] = f[q] - (f[q] - feq[q]) / c->tau + S;
+        src[q] = WQ[q] * (sx * rho * c->gx + sy * rho * c->gy);
+    }
+    if (c->lambda <= 0.0) {
+        const double pref = 1.0 - 1.0 / (2.0 * c->tau);
+        for (int q = 0; q < Q; ++q) fstar[q] = f[q] - (f[q] - feq[q]) / c->tau + pref * src[q];
+        return;
+    }
+    const double tau_p = c->tau, tau_m = 0.5 + c->lambda / (c->tau - 0.5);
+    for (int q = 0; q < Q; ++q) {
+        const int b = OPP[q];
+        const double fp = 0.5 * (f[q] + f[b]), fm = 0.5 * (f[q] - f[b]);
+        const double ep = 0.5 * (feq[q] + feq[b]), em = 0.5 * (feq[q] - feq[b]);
+        const double sp = 0.5 * (src[q] + src[b]), sm = 0.5 * (src[q] - src[b]);
+        fstar[q] = f[q] - (fp - ep) / tau_p - (fm - em) / tau_m + (1.0 - 0.5 / tau_p) * sp +
+                   (1.0 - 0.5 / tau_m) * sm;
     }
 }
 
@@ -195,7 +213,7 @@ static void apply_bc(const cfg_t* c, const uint8_t* mask, double* f) {
 
 static cfg_t make_cfg(int nx, int ny, double tau, double gx, double gy, int bc_x, int bc_y,
                       double u_in, double rho_out) {
-    cfg_t c = {nx, ny, tau, gx, gy, bc_x, bc_y, u_in, rho_out};
+    cfg_t c = {nx, ny, tau, gx, gy, bc_x, bc_y, u_in, rho_out, 0.0};
     return c;
 }
 
@@ -281,9 +299,9 @@ void oracle_init_neq(int nx, int ny, double tau, double gx, double gy, int bc_x,
 }
 
 /* Collision on every fluid node: fstar = C(f). */
-void oracle_collide(int nx, int ny, double tau, double gx, double gy, const uint8_t* mask,
-                    const double* f, double* fstar) {
-    cfg_t c = make_cfg(nx, ny, tau, gx, gy, 0, 0, 0.0, 1.0);
+static void collide_all(const cfg_t* cp, const uint8_t* mask, const double* f, double* fstar) {
+    const cfg_t c = *cp;
+    const int nx = c.nx, ny = c.ny;
 #pragma omp parallel for schedule(static)
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
@@ -296,6 +314,20 @@ void oracle_collide(int nx, int ny, double tau, double gx, double gy, const uint
             collide_node(g, &c, h);
             for (int q = 0; q < Q; ++q) fstar[at(&c, q, j, i)] = h[q];
         }
+}
+
+void oracle_collide(int nx, int ny, double tau, double gx, double gy, const uint8_t* mask,
+                    const double* f, double* fstar) {
+    cfg_t c = make_cfg(nx, ny, tau, gx, gy, 0, 0, 0.0, 1.0);
+    collide_all(&c, mask, f, fstar);
+}
+
+/* TRT collision (collide_node with lambda > 0). */
+void oracle_collide_trt(int nx, int ny, double tau, double lambda, double gx, double gy,
+                        const uint8_t* mask, const double* f, double* fstar) {
+    cfg_t c = make_cfg(nx, ny, tau, gx, gy, 0, 0, 0.0, 1.0);
+    c.lambda = lambda;
+    collide_all(&c, mask, f, fstar);
 }
 
 /* Streaming (Eq. 3) with halfway bounce-back, then the boundary closures. */
@@ -328,6 +360,20 @@ int oracle_run(int nx, int ny, double tau, double gx, double gy, int bc_x, int b
     if (!tmp) return -1;
     for (int s = 0; s < nsteps; ++s) {
         oracle_collide(nx, ny, tau, gx, gy, mask, f, tmp);
+        oracle_stream(nx, ny, bc_x, bc_y, u_in, rho_out, mask, tmp, f);
+    }
+    free(tmp);
+    return 0;
+}
+
+/* oracle_run with the TRT collision (magic parameter lambda > 0). */
+int oracle_run_trt(int nx, int ny, double tau, double lambda, double gx, double gy, int bc_x,
+                   int bc_y, double u_in, double rho_out, const uint8_t* mask, double* f, int nsteps) {
+    const size_t n = (size_t)Q * nx * ny;
+    double* tmp = (double*)malloc(n * sizeof(double));
+    if (!tmp) return -1;
+    for (int s = 0; s < nsteps; ++s) {
+        oracle_collide_trt(nx, ny, tau, lambda, gx, gy, mask, f, tmp);
         oracle_stream(nx, ny, bc_x, bc_y, u_in, rho_out, mask, tmp, f);
     }
     free(tmp);

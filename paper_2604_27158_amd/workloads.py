@@ -104,6 +104,7 @@ class Lattice:
     wrap_y: bool = True
     seed: int = 0
     name: str = ""
+    trt_lambda: float = 0.0   # > 0: two-relaxation-time collision with this magic parameter
 
     def shapes_array(self) -> np.ndarray:
         if not self.shapes:

@@ -405,3 +405,64 @@ def test_neq_init_removes_the_shear_wave_start_transient():
         s = lbm.Sim(lat, mask).init(np.ones((ny, nx)), exact(0), np.zeros((ny, nx)), neq=neq).run(5)
         err[neq] = np.abs(s.macros()[1] - exact(5)).max() / A
     assert err[False] > 3e-4 and err[True] < 1e-5, err
+
+
+# ------------------------------------------------------------ TRT collision
+
+@pytest.mark.parametrize("tau", [0.56, 0.8, 1.3])
+def test_trt_magic_three_sixteenths_gives_exact_parabolic_poiseuille(tau):
+    """With the magic parameter 3/16 the TRT scheme with halfway bounce-back carries
+    the parabolic Poiseuille profile u(y) = g/(2 nu) (y + 1/2)(N - 1/2 - y), walls
+    exactly halfway, at every tau (Ginzburg & d'Humieres); BGK does so only at one tau."""
+    N, g = 16, 1e-6
+    lat = W.Lattice(nx=2, ny=N, tau=tau, gx=g, bc_x=W.BC_PERIODIC, bc_y=W.BC_WALL, trt_lambda=3.0 / 16)
+    mask = np.zeros((N, 2), np.uint8)
+    nu = (tau - 0.5) / 3
+    y = np.arange(N)
+    ue = g / (2 * nu) * (y + 0.5) * (N - 0.5 - y)
+    s = lbm.Sim(lat, mask).init(ux=np.repeat(ue[:, None], 2, 1))
+    s.run(int(40.0 * N * N / (math.pi ** 2 * nu)) + 2000)
+    rho, ux, uy = s.macros()
+    assert np.max(np.abs(ux[:, 0] - ue)) / ue.max() < 1e-9
+    assert np.max(np.abs(uy)) < 1e-10 * ue.max()
+
+
+def test_trt_with_equal_relaxation_times_is_bgk():
+    """lambda = (tau - 1/2)^2 makes tau- = tau+: the TRT step is the BGK step."""
+    lat = W.Lattice(nx=30, ny=22, tau=0.83, gx=2e-5, gy=-1e-5, bc_x=W.BC_PERIODIC, bc_y=W.BC_WALL,
+                    shapes=[W.circle(12, 10, 4)], wrap_x=True, wrap_y=False)
+    mask = lbm.raster(lat.nx, lat.ny, lat.shapes_array(), True, False)
+    f0 = lbm.Sim(lat, mask).init(*W.random_macro_fields(41, lat.nx, lat.ny, amp_u=0.05)).f
+    trt = W.Lattice(**{**lat.__dict__, "trt_lambda": (lat.tau - 0.5) ** 2})
+    a = lbm.collide(lat, mask, f0)
+    b = lbm.collide(trt, mask, f0)
+    assert np.max(np.abs(a - b)) < 1e-15
+
+
+@pytest.mark.parametrize("tau,lam", [(0.52, 0.25), (0.8, 3.0 / 16), (1.2, 0.1)])
+def test_trt_shear_wave_decay_is_linear_operator_eigenvalue(tau, lam):
+    """A small shear wave decays by the shear eigenvalue of the linearised TRT step
+    diag(exp(-i k.c_q)) [I - (P+/tau+ + P-/tau-)(I - E)], with P+- the projectors onto
+    the parts even and odd under c -> -c (numpy.linalg.eigvals)."""
+    ny, U = 32, 1e-6
+    k = 2 * math.pi / ny
+    lat = W.Lattice(nx=2, ny=ny, tau=tau, trt_lambda=lam)
+    y = np.arange(ny)
+    s = lbm.Sim(lat, np.zeros((ny, 2), np.uint8)).init(ux=np.repeat((U * np.sin(k * y))[:, None], 2, 1))
+    s.run(400)
+
+    def amp():
+        return 2.0 / ny * np.sum(s.macros()[1][:, 0] * np.sin(k * y))
+    a0 = amp(); s.run(1); a1 = amp()
+    c = np.stack([CX, CY], 1).astype(float)
+    opp = np.array([np.where((c == -c[q]).all(1))[0][0] for q in range(9)])
+    Pp = 0.5 * (np.eye(9) + np.eye(9)[opp])
+    Pm = 0.5 * (np.eye(9) - np.eye(9)[opp])
+    tau_m = 0.5 + lam / (tau - 0.5)
+    E = WQ[:, None] * (1.0 + 3.0 * c @ c.T)
+    L = np.diag(np.exp(-1j * k * CY)) @ (np.eye(9) - (Pp / tau + Pm / tau_m) @ (np.eye(9) - E))
+    ev = np.linalg.eigvals(L)
+    nu = (tau - 0.5) / 3
+    mu = ev[np.argmin(np.abs(ev - (1 - nu * k * k)))]
+    assert abs(mu.imag) < 1e-12
+    assert abs(a1 / a0 - mu.real) < 1e-9
