@@ -213,13 +213,15 @@ def bench_hybrid(out, ellipse_seeds=4, shear_seeds=10):
         out["shear_hybrid"] = {"skipped": "trained shear surrogate weights not present"}
 
 
-def bench_batch(out, steps=20000):
+def bench_batch(out, steps=20000, trt_lambda=0.0, key="batch"):
     """100 trajectories of flows past 1-5 ellipses, sizes from {256x128, 384x192,
-    512x256}, one launch per step (graph-replayed), autotuned kernel."""
+    512x256}, one launch per step (graph-replayed), autotuned kernel; with
+    trt_lambda > 0 the same flows with the TRT collision."""
+    import dataclasses
     import torch
     from paper_2604_27158_amd import lbmfno
     from paper_2604_27158_amd import workloads as W
-    lats = [W.ellipse_flow(s) for s in range(100)]
+    lats = [dataclasses.replace(W.ellipse_flow(s), trt_lambda=trt_lambda) for s in range(100)]
     B = lbmfno.Batch(lats)
     for i, lat in enumerate(lats):
         B.trajectory(i).reinit(*(torch.from_numpy(a) for a in W.plug_flow(lat)))
@@ -243,7 +245,8 @@ def bench_batch(out, steps=20000):
     per_launch = 2 if " pair" in B.choice else 1
     ach = bytes_step * steps / per_launch / (ms * 1e-3) / 1e9
     eq = bytes_step * steps / (ms * 1e-3) / 1e9
-    out["batch"] = {"trajectories": len(lats), "nodes": B.nodes, "steps": steps,
+    out[key] = {"collision": f"TRT lambda {trt_lambda:g}" if trt_lambda > 0 else "BGK",
+                "trajectories": len(lats), "nodes": B.nodes, "steps": steps,
                     "glups": B.nodes * steps / (ms * 1e6), "seconds": ms / 1e3,
                     "kernel": B.choice, "steps_per_launch": per_launch, "achieved_GBs": ach,
                     "frac": ach / HBM_PEAK_GBS, "one_step_equivalent_GBs": eq,
@@ -398,6 +401,7 @@ def main():
         bench_fno(out)
         bench_hybrid(out)
         bench_batch(out)
+        bench_batch(out, trt_lambda=0.25, key="batch_trt")
         bench_steady(out, lat, args.steady_max)
         bench_time_to_steady(out, args.steady_seeds)
     if not args.no_cpu_baseline:

@@ -90,6 +90,13 @@ typedef struct lbm_config {
     double u_in, rho_out;
     int32_t arith;
     int32_t kernel;
+    double trt_lambda;  /* 0: BGK (Eq. 2).  > 0: two-relaxation-time collision (an
+                           extension for stability at low tau): the parts of f, f_eq and
+                           the Guo source even under c -> -c relax with tau, the odd parts
+                           with tau- from lambda = (tau - 1/2)(tau- - 1/2) (1/4: the
+                           stability-optimal choice, 3/16: walls exactly halfway for
+                           Poiseuille flow).  LBM_ARITH_LEAN only; a batch is all BGK or
+                           all TRT; lbm_adjoint_step covers BGK only. */
 } lbm_config;
 
 /* Diagnostics of the state at time n (FP64 accumulation over fluid nodes). */

@@ -269,6 +269,7 @@ struct StepArgs {
     float* __restrict__ drho_out;
     LatticeGeom g;
     double omega, guo, gx, gy, u_in, rho_out;
+    double omega_m, guo_m;  // TRT: odd-part relaxation rate and Guo factor
 };
 
 // Pull gather of f(t) at node (i, j) from the deviation store: direction q reads
@@ -415,13 +416,47 @@ __device__ __forceinline__ float collide_q_lean(float fq, double dr64, double rh
     return out;
 }
 
+// Two-relaxation-time collision in the lean arithmetic (an extension; the paper
+// uses BGK).  The pair (q, opp q) splits into the parts even and odd under
+// c -> -c: f_e = (f_q + f_qb)/2 relaxes to w (drho + rho (4.5 (c.u)^2 - 1.5 u^2))
+// at rate omega+ = 1/tau, f_o = (f_q - f_qb)/2 to 3 w rho c.u at rate omega-; the
+// Guo source's even part w rho (9 (c.u)(c.g) - 3 u.g) gets 1 - omega+/2, its odd
+// part 3 w rho c.g gets 1 - omega-/2.  The linear equilibrium terms are formed in
+// FP64 as in Lean.
+struct LeanTRT {};
+
+template <int Q, int QB, bool FORCE>
+__device__ __forceinline__ void collide_pair_trt(float v[9], double dr64, double rho3, double ux,
+                                                 double uy, float rho, float ux32, float uy32,
+                                                 float usq15, float omp, float omm, float guop,
+                                                 float guom, float gx, float gy) {
+    const float even_lin = (float)(w_of_d(Q) * dr64);
+    const float odd_lin = (float)(w_of_d(Q) * rho3 * cdot<Q, double>(ux, uy));
+    const float cu = cdot<Q, float>(ux32, uy32);
+    const float quad = w_of(Q) * rho * fmaf(4.5f * cu, cu, -usq15);
+    const float ne = 0.5f * (v[Q] + v[QB]) - (even_lin + quad);
+    const float no = 0.5f * (v[Q] - v[QB]) - odd_lin;
+    float a = fmaf(-omp, ne, fmaf(-omm, no, v[Q]));
+    float b = fmaf(-omp, ne, fmaf(omm, no, v[QB]));
+    if (FORCE) {
+        const float cg = cdot<Q, float>(gx, gy);
+        const float ug = fmaf(ux32, gx, uy32 * gy);
+        const float se = w_of(Q) * rho * fmaf(9.0f * cu, cg, -3.0f * ug);
+        const float so = 3.0f * w_of(Q) * rho * cg;
+        a = fmaf(guop, se, fmaf(guom, so, a));
+        b = fmaf(guop, se, fmaf(-guom, so, b));
+    }
+    v[Q] = a;
+    v[QB] = b;
+}
+
 // Boundary closure, moments and collision of one fluid node in arithmetic R
-// (float, double or Lean) on its gathered float populations v (replaced by the
-// post-collision deviations); returns drho.  Every step kernel calls this, so all
-// of them evaluate one operation sequence.
+// (float, double, Lean or LeanTRT) on its gathered float populations v (replaced
+// by the post-collision deviations); returns drho.  Every step kernel calls this,
+// so all of them evaluate one operation sequence.
 template <bool ZH, bool FORCE, typename R>
 __device__ __forceinline__ float collide_node(float v[9], int x, int nx, const StepArgs& a) {
-    if constexpr (std::is_same<R, Lean>::value) {
+    if constexpr (std::is_same<R, Lean>::value || std::is_same<R, LeanTRT>::value) {
         if (ZH) zouhe<float>(v, x, nx, (float)a.u_in, (float)a.rho_out);
         const float dr = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7])) + v[8];
         const float jx = (v[1] - v[3]) + (v[5] - v[6]) + (v[8] - v[7]);
@@ -441,10 +476,19 @@ __device__ __forceinline__ float collide_node(float v[9], int x, int nx, const S
         const float rho = (float)rho64, ux32 = (float)ux, uy32 = (float)uy;
         const float usq15 = 1.5f * fmaf(ux32, ux32, uy32 * uy32);
         const float om = (float)a.omega, guo = (float)a.guo, gx = (float)a.gx, gy = (float)a.gy;
+        if constexpr (std::is_same<R, LeanTRT>::value) {
+            const float omm = (float)a.omega_m, guom = (float)a.guo_m;
+            v[0] = collide_q_lean<0, FORCE>(v[0], dr64, rho3, ux, uy, rho, ux32, uy32, usq15, om, guo, gx, gy);
+#define LBM_TRT(Q, QB) \
+    collide_pair_trt<Q, QB, FORCE>(v, dr64, rho3, ux, uy, rho, ux32, uy32, usq15, om, omm, guo, guom, gx, gy);
+            LBM_TRT(1, 3) LBM_TRT(2, 4) LBM_TRT(5, 7) LBM_TRT(6, 8)
+#undef LBM_TRT
+        } else {
 #define LBM_LEAN(Q) v[Q] = collide_q_lean<Q, FORCE>(v[Q], dr64, rho3, ux, uy, rho, ux32, uy32, usq15, om, guo, gx, gy);
-        LBM_LEAN(0) LBM_LEAN(1) LBM_LEAN(2) LBM_LEAN(3) LBM_LEAN(4)
-        LBM_LEAN(5) LBM_LEAN(6) LBM_LEAN(7) LBM_LEAN(8)
+            LBM_LEAN(0) LBM_LEAN(1) LBM_LEAN(2) LBM_LEAN(3) LBM_LEAN(4)
+            LBM_LEAN(5) LBM_LEAN(6) LBM_LEAN(7) LBM_LEAN(8)
 #undef LBM_LEAN
+        }
         return dr;
     } else {
         R f[9];
@@ -708,7 +752,7 @@ struct BatchTile {
     int traj, bx, by, pad;
 };
 
-template <bool QUAD, bool NT>
+template <bool QUAD, bool NT, typename R>
 __global__ __launch_bounds__(256) void k_bgk_batch(const StepArgs* __restrict__ args,
                                                    const BatchTile* __restrict__ tiles) {
     const int b = xcd_remap(blockIdx.x, gridDim.x);
@@ -718,26 +762,26 @@ __global__ __launch_bounds__(256) void k_bgk_batch(const StepArgs* __restrict__ 
     const bool force = a.gx != 0.0 || a.gy != 0.0;
     if (QUAD) {
         if (zh) {
-            if (force) step_quad<true, true, false, NT, Lean>(a, t.bx, t.by);
-            else step_quad<true, false, false, NT, Lean>(a, t.bx, t.by);
+            if (force) step_quad<true, true, false, NT, R>(a, t.bx, t.by);
+            else step_quad<true, false, false, NT, R>(a, t.bx, t.by);
         } else {
-            if (force) step_quad<false, true, false, NT, Lean>(a, t.bx, t.by);
-            else step_quad<false, false, false, NT, Lean>(a, t.bx, t.by);
+            if (force) step_quad<false, true, false, NT, R>(a, t.bx, t.by);
+            else step_quad<false, false, false, NT, R>(a, t.bx, t.by);
         }
     } else {
         if (zh) {
-            if (force) step_node<true, true, false, NT, Lean>(a, t.bx, t.by);
-            else step_node<true, false, false, NT, Lean>(a, t.bx, t.by);
+            if (force) step_node<true, true, false, NT, R>(a, t.bx, t.by);
+            else step_node<true, false, false, NT, R>(a, t.bx, t.by);
         } else {
-            if (force) step_node<false, true, false, NT, Lean>(a, t.bx, t.by);
-            else step_node<false, false, false, NT, Lean>(a, t.bx, t.by);
+            if (force) step_node<false, true, false, NT, R>(a, t.bx, t.by);
+            else step_node<false, false, false, NT, R>(a, t.bx, t.by);
         }
     }
 }
 
 // Batched two-step launch: k_bgk_step2's tile step over the trajectory-major tile
 // table (its 64 x 4 tiles are the one-node kernel's).
-template <bool NT>
+template <bool NT, typename R>
 __global__ __launch_bounds__(256) void k_bgk_batch2(const StepArgs* __restrict__ args,
                                                     const BatchTile* __restrict__ tiles) {
     __shared__ float P[9 * PAIR_LN];
@@ -747,11 +791,11 @@ __global__ __launch_bounds__(256) void k_bgk_batch2(const StepArgs* __restrict__
     const bool zh = a.g.bc_x == LBM_BC_ZOUHE;
     const bool force = a.gx != 0.0 || a.gy != 0.0;
     if (zh) {
-        if (force) step_pair<true, true, NT, Lean>(a, t.bx, t.by, P);
-        else step_pair<true, false, NT, Lean>(a, t.bx, t.by, P);
+        if (force) step_pair<true, true, NT, R>(a, t.bx, t.by, P);
+        else step_pair<true, false, NT, R>(a, t.bx, t.by, P);
     } else {
-        if (force) step_pair<false, true, NT, Lean>(a, t.bx, t.by, P);
-        else step_pair<false, false, NT, Lean>(a, t.bx, t.by, P);
+        if (force) step_pair<false, true, NT, R>(a, t.bx, t.by, P);
+        else step_pair<false, false, NT, R>(a, t.bx, t.by, P);
     }
 }
 
@@ -1020,6 +1064,10 @@ static int validate_config(const lbm_config* c) {
     if (!finite_d(c->gx) || !finite_d(c->gy)) return fail(LBM_EINVAL, "non-finite body force");
     if (c->arith != LBM_ARITH_MIXED && c->arith != LBM_ARITH_FP32 && c->arith != LBM_ARITH_LEAN)
         return fail(LBM_EINVAL, "arith = %d", c->arith);
+    if (!(c->trt_lambda >= 0.0) || !std::isfinite(c->trt_lambda))
+        return fail(LBM_EINVAL, "trt_lambda = %g (0 for BGK, > 0 for TRT)", c->trt_lambda);
+    if (c->trt_lambda > 0.0 && c->arith != LBM_ARITH_LEAN)
+        return fail(LBM_EUNSUPPORTED, "the TRT collision runs in LBM_ARITH_LEAN");
     if (c->kernel < LBM_KERNEL_AUTO || c->kernel > LBM_KERNEL_PAIR)
         return fail(LBM_EINVAL, "kernel = %d", c->kernel);
     if (c->bc_x < 0 || c->bc_x > 2 || c->bc_y < 0 || c->bc_y > 1)
@@ -1107,6 +1155,16 @@ static void release(lbm_ctx* c) {
 
 extern "C" void lbm_destroy(lbm_ctx* ctx) { release(ctx); }
 
+// BGK rate and Guo factor from tau; with TRT (trt_lambda > 0) also the odd-part
+// rate from the magic parameter lambda = (tau+ - 1/2)(tau- - 1/2).
+static void set_relaxation(StepArgs& a, const lbm_config& cfg) {
+    a.omega = 1.0 / cfg.tau;
+    a.guo = 1.0 - 0.5 / cfg.tau;
+    const double tau_m = cfg.trt_lambda > 0.0 ? 0.5 + cfg.trt_lambda / (cfg.tau - 0.5) : cfg.tau;
+    a.omega_m = 1.0 / tau_m;
+    a.guo_m = 1.0 - 0.5 / tau_m;
+}
+
 static int launch_step(lbm_ctx* c, bool write_drho) {
     StepArgs a;
     a.src = c->f[c->cur];
@@ -1115,8 +1173,7 @@ static int launch_step(lbm_ctx* c, bool write_drho) {
     a.mask = c->d_mask;
     a.drho_out = c->d_drho;
     a.g = c->g;
-    a.omega = 1.0 / c->cfg.tau;
-    a.guo = 1.0 - 0.5 / c->cfg.tau;
+    set_relaxation(a, c->cfg);
     a.gx = c->cfg.gx;
     a.gy = c->cfg.gy;
     a.u_in = c->cfg.u_in;
@@ -1124,6 +1181,7 @@ static int launch_step(lbm_ctx* c, bool write_drho) {
     const bool zh = c->cfg.bc_x == LBM_BC_ZOUHE;
     const bool force = c->cfg.gx != 0.0 || c->cfg.gy != 0.0;
     const int ar = c->cfg.arith;
+    const bool trt = c->cfg.trt_lambda > 0.0;
     const bool nt = c->nontemporal;
     hipStream_t s = c->stream;
     if (c->vec4) {
@@ -1139,6 +1197,7 @@ static int launch_step(lbm_ctx* c, bool write_drho) {
         constexpr bool Z = Z_, F = F_, W = W_;                                        \
         if (ar == LBM_ARITH_FP32) LBM_STEP_ARITH(float)                               \
         else if (ar == LBM_ARITH_MIXED) LBM_STEP_ARITH(double)                        \
+        else if (trt) LBM_STEP_ARITH(LeanTRT)                                         \
         else LBM_STEP_ARITH(Lean)                                                     \
     }
         LBM_STEP_CASE(false, false, false)
@@ -1166,6 +1225,7 @@ static int launch_step(lbm_ctx* c, bool write_drho) {
         constexpr bool Z = Z_, F = F_, W = W_;                                        \
         if (ar == LBM_ARITH_FP32) LBM_STEP_ARITH(float)                               \
         else if (ar == LBM_ARITH_MIXED) LBM_STEP_ARITH(double)                        \
+        else if (trt) LBM_STEP_ARITH(LeanTRT)                                         \
         else LBM_STEP_ARITH(Lean)                                                     \
     }
     LBM_STEP_CASE(false, false, false)
@@ -1192,8 +1252,7 @@ static int launch_step2(lbm_ctx* c) {
     a.mask = c->d_mask;
     a.drho_out = c->d_drho;
     a.g = c->g;
-    a.omega = 1.0 / c->cfg.tau;
-    a.guo = 1.0 - 0.5 / c->cfg.tau;
+    set_relaxation(a, c->cfg);
     a.gx = c->cfg.gx;
     a.gy = c->cfg.gy;
     a.u_in = c->cfg.u_in;
@@ -1201,6 +1260,7 @@ static int launch_step2(lbm_ctx* c) {
     const bool zh = c->cfg.bc_x == LBM_BC_ZOUHE;
     const bool force = c->cfg.gx != 0.0 || c->cfg.gy != 0.0;
     const int ar = c->cfg.arith;
+    const bool trt = c->cfg.trt_lambda > 0.0;
     const bool nt = c->nontemporal;
     hipStream_t s = c->stream;
     dim3 blk(TX, TY), grd(c->g.gridx * ((c->g.ny + PAIR_RY - 1) / PAIR_RY));
@@ -1214,6 +1274,7 @@ static int launch_step2(lbm_ctx* c) {
         constexpr bool Z = Z_, F = F_;                                                \
         if (ar == LBM_ARITH_FP32) LBM_STEP2_ARITH(float)                              \
         else if (ar == LBM_ARITH_MIXED) LBM_STEP2_ARITH(double)                       \
+        else if (trt) LBM_STEP2_ARITH(LeanTRT)                                        \
         else LBM_STEP2_ARITH(Lean)                                                    \
     }
     LBM_STEP2_CASE(false, false)
@@ -1531,6 +1592,7 @@ struct lbm_batch {
     int ntiles = 0;
     bool quad = false, nt = false;
     bool pair = false;      // two steps per launch (k_bgk_batch2 on the one-node tiles)
+    bool trt = false;       // every trajectory uses the TRT collision
     int parity = 0;
     int64_t steps = 0;
     int chunk = 32;
@@ -1559,8 +1621,7 @@ static StepArgs step_args_for(const lbm_ctx* c, int parity) {
     a.mask = c->d_mask;
     a.drho_out = c->d_drho;
     a.g = c->g;
-    a.omega = 1.0 / c->cfg.tau;
-    a.guo = 1.0 - 0.5 / c->cfg.tau;
+    set_relaxation(a, c->cfg);
     a.gx = c->cfg.gx;
     a.gy = c->cfg.gy;
     a.u_in = c->cfg.u_in;
@@ -1588,21 +1649,33 @@ static int build_tiles(lbm_batch* b, bool quad) {
     return LBM_OK;
 }
 
-static void launch_batch2(lbm_batch* b, int parity) {
+template <typename R>
+static void launch_batch2_r(lbm_batch* b, int parity) {
     dim3 blk(TX, TY), grd(b->ntiles);
-    if (b->nt) k_bgk_batch2<true><<<grd, blk, 0, b->stream>>>(b->d_args[parity], b->d_tiles);
-    else k_bgk_batch2<false><<<grd, blk, 0, b->stream>>>(b->d_args[parity], b->d_tiles);
+    if (b->nt) k_bgk_batch2<true, R><<<grd, blk, 0, b->stream>>>(b->d_args[parity], b->d_tiles);
+    else k_bgk_batch2<false, R><<<grd, blk, 0, b->stream>>>(b->d_args[parity], b->d_tiles);
+}
+
+static void launch_batch2(lbm_batch* b, int parity) {
+    if (b->trt) launch_batch2_r<LeanTRT>(b, parity);
+    else launch_batch2_r<Lean>(b, parity);
+}
+
+template <typename R>
+static void launch_batch_r(lbm_batch* b, int parity) {
+    dim3 blk(TX, TY), grd(b->ntiles);
+    if (b->quad) {
+        if (b->nt) k_bgk_batch<true, true, R><<<grd, blk, 0, b->stream>>>(b->d_args[parity], b->d_tiles);
+        else k_bgk_batch<true, false, R><<<grd, blk, 0, b->stream>>>(b->d_args[parity], b->d_tiles);
+    } else {
+        if (b->nt) k_bgk_batch<false, true, R><<<grd, blk, 0, b->stream>>>(b->d_args[parity], b->d_tiles);
+        else k_bgk_batch<false, false, R><<<grd, blk, 0, b->stream>>>(b->d_args[parity], b->d_tiles);
+    }
 }
 
 static void launch_batch(lbm_batch* b, int parity) {
-    dim3 blk(TX, TY), grd(b->ntiles);
-    if (b->quad) {
-        if (b->nt) k_bgk_batch<true, true><<<grd, blk, 0, b->stream>>>(b->d_args[parity], b->d_tiles);
-        else k_bgk_batch<true, false><<<grd, blk, 0, b->stream>>>(b->d_args[parity], b->d_tiles);
-    } else {
-        if (b->nt) k_bgk_batch<false, true><<<grd, blk, 0, b->stream>>>(b->d_args[parity], b->d_tiles);
-        else k_bgk_batch<false, false><<<grd, blk, 0, b->stream>>>(b->d_args[parity], b->d_tiles);
-    }
+    if (b->trt) launch_batch_r<LeanTRT>(b, parity);
+    else launch_batch_r<Lean>(b, parity);
 }
 
 static int reset_rest(lbm_batch* b) {
@@ -1731,12 +1804,15 @@ extern "C" int lbm_batch_create(lbm_batch** out, const lbm_traj_desc* h_desc, in
         if (rc) return fail(rc, "trajectory %d: %s", i, lbm_last_error());
         if (h_desc[i].cfg.arith != LBM_ARITH_LEAN)
             return fail(LBM_EUNSUPPORTED, "trajectory %d: batches run the LBM_ARITH_LEAN step", i);
+        if ((h_desc[i].cfg.trt_lambda > 0.0) != (h_desc[0].cfg.trt_lambda > 0.0))
+            return fail(LBM_EINVAL, "trajectory %d: a batch is all BGK or all TRT", i);
         if (!h_desc[i].d_mask || !h_desc[i].d_fA || !h_desc[i].d_fB)
             return fail(LBM_EINVAL, "trajectory %d: NULL device buffer", i);
     }
     lbm_batch* b = new (std::nothrow) lbm_batch();
     if (!b) return fail(LBM_ENOMEM, "batch allocation");
     b->n = ntraj;
+    b->trt = h_desc[0].cfg.trt_lambda > 0.0;
     b->stream = (hipStream_t)stream;
     bool quad_ok = true;
     for (int i = 0; i < ntraj; ++i) {
@@ -2040,6 +2116,8 @@ extern "C" int lbm_adjoint_step(lbm_ctx* c, const float* d_f_n, const float* d_l
     if (!c) return fail(LBM_EINVAL, "ctx is NULL");
     if (!d_f_n || !d_lam_np1 || !d_lam_n) return fail(LBM_EINVAL, "NULL buffer");
     if (d_lam_np1 == d_lam_n) return fail(LBM_EINVAL, "lam_{n+1} and lam_n must differ");
+    if (c->cfg.trt_lambda > 0.0)
+        return fail(LBM_EUNSUPPORTED, "the adjoint is of the BGK step (trt_lambda = 0)");
     AdjArgs a;
     a.f = d_f_n;
     a.lam1 = d_lam_np1;

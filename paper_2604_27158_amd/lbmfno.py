@@ -28,7 +28,8 @@ class LbmConfig(ctypes.Structure):
                 ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32),
                 ("tau", ctypes.c_double), ("gx", ctypes.c_double), ("gy", ctypes.c_double),
                 ("u_in", ctypes.c_double), ("rho_out", ctypes.c_double),
-                ("arith", ctypes.c_int32), ("kernel", ctypes.c_int32)]
+                ("arith", ctypes.c_int32), ("kernel", ctypes.c_int32),
+                ("trt_lambda", ctypes.c_double)]
 
 
 ARITH_MIXED, ARITH_FP32, ARITH_LEAN = 0, 1, 2
@@ -195,12 +196,12 @@ class Lattice:
 
     def __init__(self, nx, ny, tau, gx=0.0, gy=0.0, bc_x=BC_PERIODIC, bc_y=BC_PERIODIC,
                  u_in=0.0, rho_out=1.0, mask=None, stream=None, arith=ARITH_LEAN,
-                 kernel=KERNEL_AUTO):
+                 kernel=KERNEL_AUTO, trt_lambda=0.0):
         import torch
         self.lib = load()
         self.nx, self.ny = int(nx), int(ny)
         self.cfg = LbmConfig(self.nx, self.ny, bc_x, bc_y, float(tau), float(gx), float(gy),
-                             float(u_in), float(rho_out), int(arith), int(kernel))
+                             float(u_in), float(rho_out), int(arith), int(kernel), float(trt_lambda))
         self.stream = stream if stream is not None else torch.cuda.Stream()
         with torch.cuda.stream(self.stream):
             self.fA = torch.empty((9, ny, nx), dtype=torch.float32, device="cuda")
@@ -221,7 +222,8 @@ class Lattice:
         with torch.cuda.stream(stream):
             mask = mask_raster(lat.nx, lat.ny, lat.shapes_array(), lat.wrap_x, lat.wrap_y, stream)
         return cls(lat.nx, lat.ny, lat.tau, lat.gx, lat.gy, lat.bc_x, lat.bc_y, lat.u_in,
-                   lat.rho_out, mask=mask, stream=stream, arith=arith, kernel=kernel)
+                   lat.rho_out, mask=mask, stream=stream, arith=arith, kernel=kernel,
+                   trt_lambda=getattr(lat, "trt_lambda", 0.0))
 
     @classmethod
     def _view(cls, lib, ctx, nx, ny, mask, stream, owner):
@@ -429,7 +431,8 @@ class Batch:
                 self._bufs.append((mask, fA, fB))
                 descs[k].cfg = LbmConfig(lat.nx, lat.ny, lat.bc_x, lat.bc_y, float(lat.tau),
                                          float(lat.gx), float(lat.gy), float(lat.u_in),
-                                         float(lat.rho_out), ARITH_LEAN, KERNEL_AUTO)
+                                         float(lat.rho_out), ARITH_LEAN, KERNEL_AUTO,
+                                         float(getattr(lat, "trt_lambda", 0.0)))
                 descs[k].d_mask, descs[k].d_fA, descs[k].d_fB = mask.data_ptr(), fA.data_ptr(), fB.data_ptr()
         self.handle = _p()
         cache = tune_cache.encode() if tune_cache else None

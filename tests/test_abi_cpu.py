@@ -42,7 +42,8 @@ def test_every_declared_symbol_is_exported_and_bound(lib):
 
 
 def _cfg(**kw):
-    c = dict(nx=16, ny=8, bc_x=0, bc_y=0, tau=0.8, gx=0.0, gy=0.0, u_in=0.0, rho_out=1.0, arith=0, kernel=0)
+    c = dict(nx=16, ny=8, bc_x=0, bc_y=0, tau=0.8, gx=0.0, gy=0.0, u_in=0.0, rho_out=1.0, arith=0, kernel=0,
+             trt_lambda=0.0)
     c.update(kw)
     return lbmfno.LbmConfig(**c)
 
@@ -50,7 +51,8 @@ def _cfg(**kw):
 @pytest.mark.parametrize("kw", [dict(tau=0.5), dict(tau=float("nan")), dict(nx=0), dict(ny=-3),
                                 dict(bc_x=7), dict(bc_y=2), dict(nx=30000, ny=30000),
                                 dict(bc_x=2, u_in=1.5), dict(bc_x=2, rho_out=0.0),
-                                dict(gx=float("inf")), dict(arith=5), dict(kernel=4)])
+                                dict(gx=float("inf")), dict(arith=5), dict(kernel=4),
+                                dict(trt_lambda=-0.25), dict(trt_lambda=float("nan"))])
 def test_lbm_init_rejects_invalid_config(lib, kw):
     ctx = ctypes.c_void_p()
     rc = lib.lbm_init(ctypes.byref(ctx), ctypes.byref(_cfg(**kw)), 1, 2, 3, None)
@@ -62,6 +64,8 @@ def test_unsupported_combinations(lib):
     ctx = ctypes.c_void_p()
     assert lib.lbm_init(ctypes.byref(ctx), ctypes.byref(_cfg(bc_x=2, gx=1e-6)), 1, 2, 3, None) == -4
     assert lib.lbm_init(ctypes.byref(ctx), ctypes.byref(_cfg(bc_x=2, bc_y=1)), 1, 2, 3, None) == -4
+    # the TRT collision runs in the lean arithmetic only
+    assert lib.lbm_init(ctypes.byref(ctx), ctypes.byref(_cfg(trt_lambda=0.25, arith=0)), 1, 2, 3, None) == -4
 
 
 def test_null_arguments(lib):

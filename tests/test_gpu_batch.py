@@ -121,3 +121,27 @@ def test_batch_detects_trajectory_stepped_alone(gpu):
     t.step(1)
     with pytest.raises(gpu.LbmError):
         B.step(1)
+
+
+def test_trt_batch_equals_single_lattices(gpu, tmp_path):
+    """A batch of TRT trajectories (ellipse flows, one Zou-He porous lattice) gives the
+    bits of the same TRT lattices stepped alone; mixing BGK and TRT is rejected."""
+    import dataclasses
+    from paper_2604_27158_amd import lbmfno
+    lats = [dataclasses.replace(W.ellipse_flow(s), trt_lambda=0.25) for s in range(4)]
+    lats.append(dataclasses.replace(W.porous_circles(5, nx=300, ny=100, rmin=4, rmax=8, keepout=10),
+                                    trt_lambda=3.0 / 16))
+    B = gpu.Batch(lats, tune_cache=str(tmp_path / "tune.txt"))
+    for i, lat in enumerate(lats):
+        if lat.name.startswith("ellipses"):
+            plug(B.trajectory(i), lat)
+    B.step(201)
+    for i, lat in enumerate(lats):
+        G = gpu.Lattice.from_workload(lat)
+        if lat.name.startswith("ellipses"):
+            plug(G, lat)
+        G.step(201)
+        assert np.array_equal(B.trajectory(i).populations().cpu().numpy(),
+                              G.populations().cpu().numpy()), lat.name
+    with pytest.raises(lbmfno.LbmError):
+        gpu.Batch([lats[0], W.ellipse_flow(9)])

@@ -314,3 +314,55 @@ def test_all_fp32_arithmetic_variant_reports_its_error(gpu):
         e = field_errors(np_(G.macros()), O.macros(), mask)
         print(f"all-FP32 step {O.steps}: " + " ".join(f"{k}={v:.2e}" for k, v in e.items()))
         assert max(e["rho"], e["ux"], e["uy"]) < 1e-4
+
+
+# ------------------------------------------------------------------ TRT collision
+
+def with_trt(lat, lam):
+    import dataclasses
+    return dataclasses.replace(lat, trt_lambda=lam, name=lat.name + f"-trt{lam:g}")
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("seed,lam", [(0, 0.25), (3, 3.0 / 16)])
+def test_trt_channel_parity_2000(gpu, seed, lam, kernel):
+    """TRT collision (lean arithmetic) on the forced walled channel with obstacles,
+    against the FP64 oracle's TRT after 1000 and 2000 steps."""
+    lat = with_trt(W.channel_walls_circles(seed), lam)
+    for step, g, r, mask, _, _ in run_pair(gpu, lat, [1000, 2000], kernel=kernel):
+        e = field_errors(g, r, mask)
+        print(f"{lat.name} step {step}: " + " ".join(f"{k}={v:.2e}" for k, v in e.items()))
+        assert e["rho"] < TOL and e["ux"] < TOL and e["uy"] < TOL, e
+
+
+def test_trt_zouhe_parity_and_kernels_agree_bitwise(gpu):
+    """TRT on a Zou-He porous flow: oracle parity after 1000 steps; the three step
+    kernels give identical bits; TRT with tau- = tau+ stays within rounding of BGK."""
+    base = W.porous_circles(4, nx=400, ny=200, rmin=6, rmax=12, keepout=20)
+    lat = with_trt(base, 0.25)
+    for step, g, r, mask, _, _ in run_pair(gpu, lat, [1000]):
+        e = field_errors(g, r, mask)
+        print(f"{lat.name} step {step}: " + " ".join(f"{k}={v:.2e}" for k, v in e.items()))
+        assert e["rho"] < TOL and e["ux"] < TOL and e["uy"] < TOL, e
+    runs = [gpu_lattice(gpu, lat, k) for k in (1, 2, 3)]
+    for G in runs:
+        G.step(301)
+    ref = np_(runs[0].populations())
+    for G in runs[1:]:
+        assert np.array_equal(np_(G.populations()), ref)
+    eq = gpu_lattice(gpu, with_trt(base, (base.tau - 0.5) ** 2))
+    bgk = gpu_lattice(gpu, base)
+    eq.step(300)
+    bgk.step(300)
+    a, b = (np_(G.macros()).astype(np.float64) for G in (eq, bgk))
+    fl = olbm.raster(base.nx, base.ny, base.shapes_array(), base.wrap_x, base.wrap_y) == 0
+    assert max(rel_l2(a[k][fl], b[k][fl]) for k in range(3)) < 1e-6
+
+
+def test_trt_rejected_by_the_adjoint(gpu):
+    import torch
+    from paper_2604_27158_amd import lbmfno
+    G = gpu_lattice(gpu, with_trt(W.channel_walls_circles(1), 0.25))
+    f = G.populations()
+    with pytest.raises(lbmfno.LbmError):
+        G.adjoint_step(f, torch.zeros_like(f))
