@@ -84,7 +84,9 @@ template <int KIND>
 __device__ __forceinline__ float act_t(float x) {
     if constexpr (KIND == FNO_ACT_GELU) return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f));
     else if constexpr (KIND == FNO_ACT_RELU) return x > 0.0f ? x : 0.0f;
-    else if constexpr (KIND == FNO_ACT_SILU) return x / (1.0f + expf(-x));
+    // SiLU x sigmoid(x) with the hardware exponential and reciprocal (a few ulp in
+    // FP32, far below the bf16 rounding that follows every activation)
+    else if constexpr (KIND == FNO_ACT_SILU) return x * __builtin_amdgcn_rcpf(1.0f + __expf(-x));
     else return x;
 }
 

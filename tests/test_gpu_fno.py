@@ -134,3 +134,21 @@ def test_fno_graph_forward_matches_eager(gpu, name):
     outb = torch.empty((2, spec.cout, H, Wd), device="cuda")
     m.forward(x, out=outb, graph=True)
     assert torch.equal(outb, m(x))
+
+
+def test_flagship_batch_100_matches_single_samples(gpu):
+    """The benchmark's launch configuration (flagship model, 128 x 256, batch 100):
+    sampled outputs of the batched forward are bit-identical to batch-1 forwards of
+    the same samples, and sample 0 meets the oracle bar."""
+    import torch
+    from paper_2604_27158_amd import fno as gfno
+    spec = W.FnoSpec()
+    params = W.fno_random_params(17, gfno.param_layout(spec), spec.width)
+    m = gfno.Fno(spec, params, 128, 256)
+    x = torch.from_numpy(W.random_array(23, (100, 4, 128, 256)).astype(np.float32)).cuda()
+    yb = m(x)
+    for b in (0, 41, 99):
+        assert torch.equal(m(x[b:b + 1].clone())[0], yb[b]), b
+    y0 = yb[0:1].cpu().numpy().astype(np.float64)
+    ref = ofno.forward(ospec(spec), params, x[0:1].cpu().numpy().astype(np.float64), "bf16")
+    assert rel(y0, ref) < TOL_BF16
