@@ -213,6 +213,47 @@ def bench_hybrid(out, ellipse_seeds=4, shear_seeds=10):
         out["shear_hybrid"] = {"skipped": "trained shear surrogate weights not present"}
 
 
+def bench_adjoint(out, reps=3):
+    """The differentiable coupling at the configured size: a flagship-shaped FNO
+    (4 -> 3, width 32, 4 layers, 12 x 12 modes; seeded small random weights) hands
+    (rho - 1, u, v) to a 512x256 walled channel with 40 obstacles, 200 lattice steps
+    checkpointed every 50, MSE against the plain lattice's own state; gradient
+    through the lattice adjoint and the FNO backward kernels, then AdamW.  Reports
+    milliseconds per training step (all of it on the GPU)."""
+    import numpy as np
+    import torch
+    from paper_2604_27158_amd import lbmfno, fno as gfno
+    from paper_2604_27158_amd import workloads as W
+    from paper_2604_27158_amd.adjoint import fno_through_lattice
+    lat = W.channel_walls_circles(4, nx=512, ny=256, n_circles=40, rmin=6, rmax=14, tau=0.8, g=0.0)
+    G = lbmfno.Lattice.from_workload(lat)
+    spec = W.FnoSpec()
+    params = 0.05 * W.fno_random_params(3, gfno.param_layout(spec), spec.width)
+    tr = gfno.Trainer(gfno.Fno(spec, params, lat.ny, lat.nx), params, lr=1e-3)
+    r0, u0, v0 = W.random_macro_fields(7, lat.nx, lat.ny, amp_u=0.02)
+    mask = G.mask.to(torch.float32)
+    G.reinit(*(torch.from_numpy(a).float() for a in (r0, u0, v0)))
+    G.step(200)
+    tgt = G.macros().clone()
+    x = torch.stack([torch.from_numpy(a).float().cuda() for a in (r0 - 1.0, u0, v0)] + [mask])[None].contiguous()
+    fluid = G.mask == 0
+
+    def one():
+        loss, _ = fno_through_lattice(tr, x, G, 200, tgt, fluid, ckpt_every=50)
+        tr.adamw()
+        return loss
+    one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = [one() for _ in range(reps)]
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / reps * 1e3
+    out["adjoint_fno_training"] = {"workload": f"{lat.name}, 200 steps, checkpoints every 50",
+                                   "fno": "4->3 width 32, 4 layers, 12x12 modes", "ms_per_training_step": ms,
+                                   "per_training_step": "200 lattice steps, 200 recomputed from checkpoints, 200 adjoint steps, FNO forward + backward + AdamW",
+                                   "losses": losses}
+
+
 def bench_batch(out, steps=20000, trt_lambda=0.0, key="batch"):
     """100 trajectories of flows past 1-5 ellipses, sizes from {256x128, 384x192,
     512x256}, one launch per step (graph-replayed), autotuned kernel; with
@@ -402,6 +443,7 @@ def main():
         bench_hybrid(out)
         bench_batch(out)
         bench_batch(out, trt_lambda=0.25, key="batch_trt")
+        bench_adjoint(out)
         bench_steady(out, lat, args.steady_max)
         bench_time_to_steady(out, args.steady_seeds)
     if not args.no_cpu_baseline:

@@ -143,6 +143,17 @@ def loss_and_grad(spec: ofno.Spec, flat_params, x, target, precision: str = "fp6
     return float(loss.detach()), flat.grad.numpy().copy(), out.detach().numpy()
 
 
+def vjp(spec: ofno.Spec, flat_params, x, g_out, precision: str = "fp64"):
+    """(output, sum over outputs of g_out * d output / d params): the parameter
+    gradient of any loss whose gradient with respect to the FNO output is g_out
+    (float64 numpy)."""
+    flat = torch.tensor(np.asarray(flat_params, dtype=np.float64).ravel(), requires_grad=True)
+    xt = torch.from_numpy(np.asarray(x, dtype=np.float64))
+    out = forward(spec, flat, xt, precision)
+    (g,) = torch.autograd.grad(out, flat, grad_outputs=torch.from_numpy(np.asarray(g_out, np.float64)))
+    return out.detach().numpy(), g.numpy().copy()
+
+
 def group_slices(spec: ofno.Spec):
     """name -> slice of every parameter tensor in the packed vector."""
     out, off = {}, 0

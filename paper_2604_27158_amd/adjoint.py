@@ -63,3 +63,44 @@ class LatticeRollout(torch.autograd.Function):
 def rollout(lattice, rho0, ux0, uy0, nsteps: int, ckpt_every: int = 50):
     """Differentiable macros(f(nsteps)) of the lattice started at f_eq(rho0, u0)."""
     return LatticeRollout.apply(rho0, ux0, uy0, lattice, nsteps, ckpt_every)
+
+
+def fno_through_lattice(trainer, x, lattice, nsteps: int, target, fluid, rho_offset: float = 1.0,
+                        ckpt_every: int = 50):
+    """Loss and FNO parameter gradient of a hybrid hand-off trained through the
+    lattice (the benchmark spec's differentiable coupling): the FNO maps x [1][cin][H][W]
+    to fields (rho - rho_offset, ux, uy); the lattice starts from f_eq of those
+    fields and runs nsteps (checkpointed adjoint, LatticeRollout); the loss is the
+    mean squared error of its macroscopic fields against target [3][H][W] (for
+    instance the plain lattice's own state, which judges the surrogate) over the
+    fluid nodes (bool [H][W]).  The lattice adjoint gives dL/d fields, and the FNO
+    backward kernels take it on to the parameters (into trainer.g).  Returns
+    (loss, trainer.g)."""
+    import torch
+    y = trainer.forward(x)
+    fields = y[0].detach().clone().requires_grad_(True)
+    rho, ux, uy = rollout(lattice, fields[0] + rho_offset, fields[1], fields[2], nsteps, ckpt_every)
+    fl = fluid.to(torch.float32)
+    n = 3.0 * fl.sum()
+    loss = (((rho - target[0]) ** 2 + (ux - target[1]) ** 2 + (uy - target[2]) ** 2) * fl).sum() / n
+    loss.backward()
+    g = trainer.backward(x, fields.grad.unsqueeze(0).contiguous())
+    return float(loss.detach()), g
+
+
+def train_through_lattice(trainer, samples, lattice, nsteps: int, fluid, epochs: int = 1,
+                          rho_offset: float = 1.0, ckpt_every: int = 50, log=None):
+    """AdamW on the FNO through the lattice: for each (x, target) sample (device
+    tensors [1][cin][H][W] and [3][H][W]) one fno_through_lattice gradient and one
+    AdamW step.  Returns the per-epoch mean losses."""
+    hist = []
+    for ep in range(epochs):
+        tot = 0.0
+        for x, tgt in samples:
+            loss, _ = fno_through_lattice(trainer, x, lattice, nsteps, tgt, fluid, rho_offset, ckpt_every)
+            trainer.adamw()
+            tot += loss
+        hist.append(tot / max(len(samples), 1))
+        if log:
+            log(f"through-lattice epoch {ep + 1}/{epochs}: loss {hist[-1]:.4e}")
+    return hist

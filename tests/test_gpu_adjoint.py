@@ -129,3 +129,69 @@ def test_rollout_gradient_through_zouhe_columns_matches_oracle(gpu):
           " ".join(f"{x:.2e}" for x in errs))
     assert abs(loss - lref) <= 1e-5 * lref
     assert max(errs) < 1e-5
+
+
+def test_fno_gradient_through_the_lattice_matches_oracle_chain(gpu):
+    """FNO -> equilibrium hand-off -> 60 lattice steps (checkpoints every 25) -> MSE
+    against a lattice target: the FNO parameter gradient from the GPU chain (lattice
+    adjoint, then the FNO backward kernels) against the FP64 oracle chain (oracle
+    rollout adjoint, then the straight-through bf16 oracle's vector-Jacobian product)."""
+    import torch
+    from oracle import fno as ofno, fno_grad
+    from paper_2604_27158_amd import fno as gfno
+    from paper_2604_27158_amd.adjoint import fno_through_lattice
+    H = Wd = 32
+    lat = W.Lattice(nx=Wd, ny=H, tau=0.8, bc_x=W.BC_PERIODIC, bc_y=W.BC_WALL,
+                    shapes=[W.circle(12, 14, 4)], wrap_x=True, wrap_y=False)
+    spec = W.FnoSpec(cin=4, width=8, layers=1, m1=4, m2=4, dec_layers=1, dec_size=8, cout=3, padding=2)
+    ospec = ofno.Spec(cin=4, width=8, layers=1, m1=4, m2=4, dec_layers=1, dec_size=8, cout=3, padding=2)
+    params = 0.2 * W.fno_random_params(5, gfno.param_layout(spec), spec.width)
+    mask = olbm.raster(lat.nx, lat.ny, lat.shapes_array(), lat.wrap_x, lat.wrap_y)
+    r0, u0, v0 = W.random_macro_fields(6, Wd, H)
+    x = np.stack([r0 - 1.0, u0, v0, mask.astype(np.float64)])[None]
+    tgt = np.stack(olbm.Sim(lat, mask).init(r0, u0, v0).run(60).macros())
+    n = 60
+    # GPU chain
+    model = gfno.Fno(spec, params, H, Wd)
+    tr = gfno.Trainer(model, params)
+    G = gpu.Lattice.from_workload(lat)
+    loss, g = fno_through_lattice(tr, torch.from_numpy(x).float().cuda(), G, n,
+                                  torch.from_numpy(tgt).float().cuda(), torch.from_numpy(mask == 0).cuda(),
+                                  ckpt_every=25)
+    g = g.cpu().numpy().astype(np.float64)
+    # oracle chain
+    y = ofno.forward(ospec, params, x, "bf16")[0]
+    g_fields = olbm.rollout_grad(lat, mask, 1.0 + y[0], y[1], y[2], n, tgt)
+    lref = olbm.rollout_loss(lat, mask, 1.0 + y[0], y[1], y[2], n, tgt)
+    _, gref = fno_grad.vjp(ospec, params, x, np.stack(g_fields)[None], "bf16")
+    e = np.linalg.norm(g - gref) / np.linalg.norm(gref)
+    print(f"loss gpu {loss:.6e} oracle {lref:.6e}; parameter-gradient rel-L2 {e:.2e}")
+    assert abs(loss - lref) <= 1e-2 * lref
+    assert e < 2e-2
+
+
+def test_training_through_the_lattice_reduces_the_loss(gpu):
+    """AdamW on an FNO whose fields hand off to 40 lattice steps, against the plain
+    lattice's own states from the true initial fields (4 LBM-generated samples)."""
+    import torch
+    from paper_2604_27158_amd import fno as gfno
+    from paper_2604_27158_amd.adjoint import train_through_lattice
+    H = Wd = 32
+    lat = W.Lattice(nx=Wd, ny=H, tau=0.8, bc_x=W.BC_PERIODIC, bc_y=W.BC_WALL,
+                    shapes=[W.circle(12, 14, 4)], wrap_x=True, wrap_y=False)
+    spec = W.FnoSpec(cin=4, width=8, layers=1, m1=4, m2=4, dec_layers=1, dec_size=8, cout=3, padding=2)
+    params = 0.2 * W.fno_random_params(9, gfno.param_layout(spec), spec.width)
+    tr = gfno.Trainer(gfno.Fno(spec, params, H, Wd), params, lr=3e-3, weight_decay=0.0)
+    G = gpu.Lattice.from_workload(lat)
+    mask = olbm.raster(lat.nx, lat.ny, lat.shapes_array(), lat.wrap_x, lat.wrap_y)
+    samples = []
+    for s in range(4):
+        r0, u0, v0 = W.random_macro_fields(60 + s, Wd, H)
+        G.reinit(*(torch.from_numpy(a).float() for a in (r0, u0, v0)))
+        G.step(40)
+        tgt = G.macros().clone()
+        x = torch.from_numpy(np.stack([r0 - 1.0, u0, v0, mask.astype(np.float64)])[None]).float().cuda()
+        samples.append((x, tgt))
+    hist = train_through_lattice(tr, samples, G, 40, torch.from_numpy(mask == 0).cuda(), epochs=30)
+    print("through-lattice losses:", " ".join(f"{h:.3e}" for h in hist[::5]), f"{hist[-1]:.3e}")
+    assert np.isfinite(hist).all() and hist[-1] < 0.25 * hist[0]

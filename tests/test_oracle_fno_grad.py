@@ -89,3 +89,21 @@ def test_straight_through_gradient_close_to_fp64():
     _, g64, _ = fno_grad.loss_and_grad(spec, params, x, tgt, "fp64")
     _, gbf, _ = fno_grad.loss_and_grad(spec, params, x, tgt, "bf16")
     assert np.linalg.norm(gbf - g64) <= 3e-2 * np.linalg.norm(g64)
+
+
+@pytest.mark.parametrize("name,spec,H,Wd", SPECS[:2])
+def test_vjp_with_an_arbitrary_output_gradient_matches_central_differences(name, spec, H, Wd):
+    """vjp(g_out) is the gradient of <g_out, FNO(x)>: central differences of the numpy
+    oracle's forward along random parameter directions."""
+    params, x, _ = problem(spec, H, Wd, 31)
+    g_out = W.random_array(32, (2, spec.cout, H, Wd))
+    _, g = fno_grad.vjp(spec, params, x, g_out)
+    rng = np.random.default_rng(8)
+    for _ in range(3):
+        d = rng.standard_normal(params.size)
+        d /= np.linalg.norm(d)
+        h = 1e-5
+        fp = float(np.sum(g_out * ofno.forward(spec, params + h * d, x, "fp64")))
+        fm = float(np.sum(g_out * ofno.forward(spec, params - h * d, x, "fp64")))
+        fd = (fp - fm) / (2 * h)
+        assert abs(fd - g @ d) <= 1e-6 * (abs(fd) + 1e-3 * np.linalg.norm(g))
