@@ -152,3 +152,27 @@ def test_flagship_batch_100_matches_single_samples(gpu):
     y0 = yb[0:1].cpu().numpy().astype(np.float64)
     ref = ofno.forward(ospec(spec), params, x[0:1].cpu().numpy().astype(np.float64), "bf16")
     assert rel(y0, ref) < TOL_BF16
+
+
+def test_fno_graph_sees_weight_refresh(gpu):
+    """The captured forward reads the weights through their device arrays: after an
+    AdamW step (which refreshes them in place) a replay equals the eager forward with
+    the new weights, and differs from the replay before the update."""
+    import torch
+    from paper_2604_27158_amd import fno as gfno
+    _, spec, H, Wd, _ = next(c for c in CASES if c[0] == "shear-rho-small")
+    params = W.fno_random_params(77, gfno.param_layout(spec), spec.width)
+    m = gfno.Fno(spec, params, H, Wd)
+    tr = gfno.Trainer(m, params, lr=1e-2)
+    x = torch.from_numpy(fields_input(12, 1, spec.cin, H, Wd)).float().cuda()
+    out = torch.empty((1, spec.cout, H, Wd), device="cuda")
+    m.forward(x, out=out, graph=True)
+    before = out.clone()
+    y = tr.forward(x)
+    _, dout = tr.mse(y, torch.zeros_like(y))
+    tr.backward(x, dout)
+    tr.adamw()
+    m.forward(x, out=out, graph=True)
+    torch.cuda.synchronize()
+    assert torch.equal(out, m(x.clone()))
+    assert not torch.equal(out, before)
