@@ -328,21 +328,23 @@ __global__ __launch_bounds__(COL_THREADS) void k_fno_col(FnoDev d, int layer) {
     for (int i = tid; i < d.CP * d.R2; i += blockDim.x) ys[i] = to_bf16(0.0f);
     __syncthreads();
     // Y[k][o] = sum_i X[k][i] R[i][o][k][k2] (complex), k over the 2 m1 kept rows
-    // Only the width real channels take part: the padded channels of X are zero and
-    // so are R's padded rows and columns, and ys was cleared above.  Weights are read
-    // two complex values (8 bytes) at a time; width is even.
+    // Only output channels o < width are formed (ys was cleared above), over input
+    // channels rounded up to a multiple of 4: the padded channels of X are zero and
+    // so are R's padded rows and columns.  Weights are read four complex values
+    // (16 bytes) at a time.
     const __bf16* R = d.Rmix + ((size_t)layer * d.m2 + k2) * d.K1 * d.CP * d.CP * 2;
+    const int wi = (d.width + 3) & ~3;
     for (int idx = tid; idx < d.K1 * d.width; idx += blockDim.x) {
         const int k = idx / d.width, o = idx % d.width;
         const float* xr = xs + k * d.CP;
         const float* xi = xs + (d.K1 + k) * d.CP;
-        const bf16x4* Rk = reinterpret_cast<const bf16x4*>(R + ((size_t)k * d.CP + o) * d.CP * 2);
+        const bf16x8* Rk = reinterpret_cast<const bf16x8*>(R + ((size_t)k * d.CP + o) * d.CP * 2);
         float sr = 0.0f, si = 0.0f;
-        for (int i = 0; i < d.width; i += 2) {
-            const bf16x4 r4 = Rk[i >> 1];
+        for (int i = 0; i < wi; i += 4) {
+            const bf16x8 r8 = Rk[i >> 2];
 #pragma unroll
-            for (int e = 0; e < 2; ++e) {
-                const float rr = from_bf16(r4[2 * e]), rim = from_bf16(r4[2 * e + 1]);
+            for (int e = 0; e < 4; ++e) {
+                const float rr = from_bf16(r8[2 * e]), rim = from_bf16(r8[2 * e + 1]);
                 const float a = xr[i + e], c = xi[i + e];
                 sr = fmaf(a, rr, sr);
                 sr = fmaf(-c, rim, sr);
