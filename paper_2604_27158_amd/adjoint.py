@@ -40,23 +40,33 @@ class LatticeRollout(torch.autograd.Function):
     def backward(ctx, g_rho, g_ux, g_uy):
         lat = ctx.lat
         rho0, ux0, uy0, f_N = ctx.saved_tensors
-        zeros = torch.zeros_like(rho0)
-        g = [t if t is not None else zeros for t in (g_rho, g_ux, g_uy)]
-        lam = lat.macro_vjp(f_N, *g)
-        spare = torch.empty_like(lam)
-        nseg = len(ctx.ckpts)
-        for s in range(nseg - 1, -1, -1):
-            start = s * ctx.every
-            k = min(ctx.every, ctx.nsteps - start)
-            lat.load_state(ctx.ckpts[s])
-            states = [lat.populations()]
-            for _ in range(k - 1):
-                lat.step(1)
-                states.append(lat.populations())
-            for n in range(k - 1, -1, -1):
-                lat.adjoint_step(states[n], lam, out=spare)
-                lam, spare = spare, lam
-        gr = lat.feq_vjp(rho0, ux0, uy0, lam)
+        cur = torch.cuda.current_stream()
+        # everything below is issued on the lattice's stream (no cross-stream waits per
+        # step), into one preallocated buffer of a segment's states
+        with torch.cuda.stream(lat.stream):
+            lat.stream.wait_stream(cur)
+            zeros = torch.zeros_like(rho0)
+            g = [t if t is not None else zeros for t in (g_rho, g_ux, g_uy)]
+            lam = lat.macro_vjp(f_N, *g)
+            spare = torch.empty_like(lam)
+            states = torch.empty((min(ctx.every, ctx.nsteps),) + tuple(lam.shape), dtype=lam.dtype,
+                                 device=lam.device)
+            nseg = len(ctx.ckpts)
+            for s in range(nseg - 1, -1, -1):
+                start = s * ctx.every
+                k = min(ctx.every, ctx.nsteps - start)
+                lat.load_state(ctx.ckpts[s])
+                lat.populations(out=states[0])
+                for i in range(1, k):
+                    lat.step(1)
+                    lat.populations(out=states[i])
+                for n in range(k - 1, -1, -1):
+                    lat.adjoint_step(states[n], lam, out=spare)
+                    lam, spare = spare, lam
+            gr = lat.feq_vjp(rho0, ux0, uy0, lam)
+        cur.wait_stream(lat.stream)
+        for t in gr:
+            t.record_stream(cur)
         return gr[0], gr[1], gr[2], None, None, None
 
 

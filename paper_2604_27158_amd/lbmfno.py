@@ -312,10 +312,19 @@ class Lattice:
         self._hand_over(out)
         return out
 
-    def populations(self):
+    def populations(self, out=None):
+        """Pre-collision populations f(n), absolute, [9][ny][nx] float32; written into
+        `out` (a contiguous device tensor of that shape) when given."""
         import torch
-        with torch.cuda.stream(self.stream):
-            out = torch.empty((9, self.ny, self.nx), dtype=torch.float32, device="cuda")
+        if out is None:
+            with torch.cuda.stream(self.stream):
+                out = torch.empty((9, self.ny, self.nx), dtype=torch.float32, device="cuda")
+        else:
+            if (tuple(out.shape) != (9, self.ny, self.nx) or out.dtype != torch.float32
+                    or not out.is_cuda or not out.is_contiguous()):
+                raise ValueError("out must be a contiguous float32 device tensor [9][ny][nx]")
+            self._after_caller()
+            out.record_stream(self.stream)
         check(self.lib.lbm_get_populations(self.ctx, out.data_ptr()), "lbm_get_populations")
         self._hand_over(out)
         return out
