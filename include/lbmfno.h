@@ -101,7 +101,7 @@ typedef struct lbm_config {
 
 /* Diagnostics of the state at time n (FP64 accumulation over fluid nodes). */
 typedef struct lbm_report {
-    double residual;     /* sum |rho(n) - rho(n-1)| / sum rho(n) */
+    double residual;     /* sum |rho(n) - rho(n-1)| / sum rho(n) (0 without fluid nodes) */
     double mass;         /* sum rho(n) */
     double mom_x, mom_y; /* sum rho(n) u(n) */
     int64_t steps_done;  /* n: steps since the last (re)initialisation */

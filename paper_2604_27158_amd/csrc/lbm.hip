@@ -1493,7 +1493,7 @@ extern "C" int lbm_step(lbm_ctx* c, int32_t n, lbm_report* rep) {
     LBM_HIP(hipMemcpyAsync(c->h_out, c->d_out, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     LBM_HIP(hipStreamSynchronize(c->stream));
     rep->mass = c->h_out[1];
-    rep->residual = c->h_out[0] / c->h_out[1];
+    rep->residual = c->h_out[1] > 0.0 ? c->h_out[0] / c->h_out[1] : 0.0;  // no fluid: nothing changes
     rep->mom_x = c->h_out[2];
     rep->mom_y = c->h_out[3];
     rep->steps_done = c->steps;

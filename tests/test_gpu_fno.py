@@ -57,6 +57,9 @@ CASES = [
                                 cout=2, padding=9), 64, 64, 1),
     ("ragged-50x70-w64", W.FnoSpec(cin=3, width=64, layers=2, m1=5, m2=7, dec_layers=2, dec_size=48,
                                    cout=3, padding=3, act="relu", dec_act="gelu"), 50, 70, 3),
+    # every mode kept (m1 = H'/2, m2 = W'/2), no padding, odd-sized ragged grid
+    ("all-modes-18x22", W.FnoSpec(cin=2, width=10, layers=2, m1=9, m2=11, dec_layers=1, dec_size=12,
+                                  cout=2, padding=0), 18, 22, 2),
 ]
 
 
@@ -107,6 +110,7 @@ def test_fno_rejects_bad_arguments(gpu):
     ws = m.workspace(1)
     rc = m.lib.fno_forward(m.model, x.data_ptr(), out.data_ptr(), 1, ws.data_ptr(), 16, None)
     assert rc == -1
+    assert m.lib.fno_forward(m.model, x.data_ptr(), out.data_ptr(), 0, ws.data_ptr(), ws.numel(), None) == -1
 
 
 @pytest.mark.parametrize("name", ["shear-u-small", "ragged-50x70-w64"])

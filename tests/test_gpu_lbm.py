@@ -366,3 +366,21 @@ def test_trt_rejected_by_the_adjoint(gpu):
     f = G.populations()
     with pytest.raises(lbmfno.LbmError):
         G.adjoint_step(f, torch.zeros_like(f))
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_all_solid_lattice_is_a_no_op(gpu, kernel):
+    """Degenerate case: a lattice without fluid nodes steps without touching anything;
+    its report has zero mass and momentum and a zero residual, its macros are the
+    solid values (1, 0, 0)."""
+    import torch
+    lat = W.Lattice(nx=40, ny=24, tau=0.7, bc_x=W.BC_PERIODIC, bc_y=W.BC_WALL,
+                    shapes=[W.circle(20, 12, 40)], wrap_x=True, wrap_y=False)
+    mask = olbm.raster(lat.nx, lat.ny, lat.shapes_array(), True, False)
+    assert mask.all()
+    G = gpu_lattice(gpu, lat, kernel)
+    rep = G.step(33, report=True)
+    assert rep["mass"] == 0.0 and rep["residual"] == 0.0 and rep["fluid_nodes"] == 0
+    assert rep["mom_x"] == 0.0 and rep["mom_y"] == 0.0
+    m = np_(G.macros())
+    assert np.all(m[0] == 1.0) and np.all(m[1:] == 0.0)
