@@ -74,10 +74,12 @@ extern "C" {
 #define LBM_KERNEL_NODE 1  /* one node per lane, 4-byte accesses (any nx) */
 #define LBM_KERNEL_QUAD 2  /* four x nodes per lane, 16-byte accesses (nx % 4 == 0,
                               16-byte aligned stores) */
-#define LBM_KERNEL_PAIR 3  /* two steps per launch: a 64 x 4 tile and its one-node
-                              ring advance one step into LDS, then the tile advances
+#define LBM_KERNEL_PAIR 3  /* two steps per launch: a tile and its one-node ring
+                              advance one step into LDS, then the tile advances
                               again from LDS (temporal blocking; half the store
-                              traffic per step).  Any nx. */
+                              traffic per step).  64 x 8 tiles when both population
+                              copies fit 128 MiB, else 64 x 4 tiles with streaming
+                              stores.  Any nx. */
 
 /* Lattice description.  tau > 1/2 is the BGK relaxation time (nu = (tau-1/2)/3 in
  * lattice units), (gx, gy) a uniform body force per unit mass (Guo forcing; use 0

@@ -541,26 +541,33 @@ __global__ __launch_bounds__(256) void k_bgk_step(StepArgs a) {
     step_node<ZH, FORCE, WDRHO, NT, R>(a, b - by * a.g.gridx, by);
 }
 
-// Two fused steps per launch (temporal blocking).  A workgroup owns a TX x PAIR_RY
-// tile (64 x 4 nodes: measured fastest against 64 x 8 and 64 x 16 on cache-resident
-// and HBM-resident lattices alike, the many small workgroups hiding more latency
-// than the larger tiles save in ring recomputation).  Step n -> n+1 runs on the tile and a one-node ring around it (the nodes
-// the tile pulls from), gathering from the store in global memory as the one-step
-// kernel does and keeping the post-collision values in LDS; step n+1 -> n+2 then
-// runs on the tile, pulling from LDS, and only its result is stored.  Both steps
-// call collide_node on the same float inputs, so the result is bit-identical to
-// two one-step launches, while the store traffic and the launch count per step
-// halve.  Ring nodes outside a non-periodic axis, and solid ring nodes, are never
-// pulled (their links bounce) and are skipped; on a periodic axis the ring wraps.
-constexpr int PAIR_RY = 4;
-constexpr int PAIR_LW = TX + 2, PAIR_LN = PAIR_LW * (PAIR_RY + 2);
+// Two fused steps per launch (temporal blocking).  A workgroup of TX x RY lanes
+// owns a TX x RY tile.  Step n -> n+1 runs on the tile and a one-node ring around
+// it (the nodes the tile pulls from), gathering from the store in global memory
+// as the one-step kernel does and keeping the post-collision values in LDS; step
+// n+1 -> n+2 then runs on the tile, pulling from LDS, and only its result is
+// stored.  Both steps call collide_node on the same float inputs, so the result
+// is bit-identical to two one-step launches, while the store traffic and the
+// launch count per step halve.  Ring nodes outside a non-periodic axis, and solid
+// ring nodes, are never pulled (their links bounce) and are skipped; on a
+// periodic axis the ring wraps.
+//
+// Tile height: a lattice whose two population copies fit the last-level cache
+// runs 64 x 8 tiles (fewer ring recomputations, measured 6-7% faster there), a
+// lattice streamed from HBM runs 64 x 4 tiles (more, smaller workgroups hide more
+// of the HBM latency; 64 x 8 and 64 x 16 measured 3% and 12% slower there).  The
+// batched launch reuses the one-step kernel's 64 x 4 tile table.
+constexpr int pair_lw() { return TX + 2; }
+constexpr int pair_ln(int ry) { return pair_lw() * (ry + 2); }
+constexpr int pair_ry(bool nt) { return nt ? 4 : 8; }
 
-template <bool ZH, bool FORCE, bool NT, typename R>
+template <int RY, bool ZH, bool FORCE, bool NT, typename R>
 __device__ __forceinline__ void step_pair(const StepArgs& a, int bx, int by, float* __restrict__ P) {
-    const int x0 = bx * TX, y0 = by * PAIR_RY;
+    constexpr int PAIR_LW = pair_lw(), PAIR_LN = pair_ln(RY);
+    const int x0 = bx * TX, y0 = by * RY;
     const int nx = a.g.nx, ny = a.g.ny;
     const int tid = threadIdx.y * TX + threadIdx.x;
-    for (int e = tid; e < PAIR_LN; e += TX * TY) {
+    for (int e = tid; e < PAIR_LN; e += TX * RY) {
         const int ly = e / PAIR_LW, lx = e - ly * PAIR_LW;
         int i = x0 - 1 + lx, j = y0 - 1 + ly;
         if (i < 0 || i >= nx) {
@@ -583,7 +590,7 @@ __device__ __forceinline__ void step_pair(const StepArgs& a, int bx, int by, flo
     }
     __syncthreads();
     const size_t N = (size_t)a.g.N;
-    for (int r = threadIdx.y; r < PAIR_RY; r += TY) {
+    for (int r = threadIdx.y; r < RY; r += RY) {
         const int i = x0 + threadIdx.x, j = y0 + r;
         if (i >= nx || j >= ny) continue;
         const int n = j * nx + i;
@@ -615,11 +622,11 @@ __device__ __forceinline__ void step_pair(const StepArgs& a, int bx, int by, flo
 }
 
 template <bool ZH, bool FORCE, bool NT, typename R>
-__global__ __launch_bounds__(256) void k_bgk_step2(StepArgs a) {
-    __shared__ float P[9 * PAIR_LN];
+__global__ __launch_bounds__(TX * pair_ry(NT)) void k_bgk_step2(StepArgs a) {
+    __shared__ float P[9 * pair_ln(pair_ry(NT))];
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int by = b / a.g.gridx;
-    step_pair<ZH, FORCE, NT, R>(a, b - by * a.g.gridx, by, P);
+    step_pair<pair_ry(NT), ZH, FORCE, NT, R>(a, b - by * a.g.gridx, by, P);
 }
 
 // Four-wide step (nx % 4 == 0): each lane owns four consecutive x nodes of one
@@ -780,22 +787,22 @@ __global__ __launch_bounds__(256) void k_bgk_batch(const StepArgs* __restrict__ 
 }
 
 // Batched two-step launch: k_bgk_step2's tile step over the trajectory-major tile
-// table (its 64 x 4 tiles are the one-node kernel's).
+// table (its 64 x TY tiles are the one-node kernel's).
 template <bool NT, typename R>
 __global__ __launch_bounds__(256) void k_bgk_batch2(const StepArgs* __restrict__ args,
                                                     const BatchTile* __restrict__ tiles) {
-    __shared__ float P[9 * PAIR_LN];
+    __shared__ float P[9 * pair_ln(TY)];
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const BatchTile t = tiles[b];
     const StepArgs a = args[t.traj];
     const bool zh = a.g.bc_x == LBM_BC_ZOUHE;
     const bool force = a.gx != 0.0 || a.gy != 0.0;
     if (zh) {
-        if (force) step_pair<true, true, NT, R>(a, t.bx, t.by, P);
-        else step_pair<true, false, NT, R>(a, t.bx, t.by, P);
+        if (force) step_pair<TY, true, true, NT, R>(a, t.bx, t.by, P);
+        else step_pair<TY, true, false, NT, R>(a, t.bx, t.by, P);
     } else {
-        if (force) step_pair<false, true, NT, R>(a, t.bx, t.by, P);
-        else step_pair<false, false, NT, R>(a, t.bx, t.by, P);
+        if (force) step_pair<TY, false, true, NT, R>(a, t.bx, t.by, P);
+        else step_pair<TY, false, false, NT, R>(a, t.bx, t.by, P);
     }
 }
 
@@ -1263,7 +1270,8 @@ static int launch_step2(lbm_ctx* c) {
     const bool trt = c->cfg.trt_lambda > 0.0;
     const bool nt = c->nontemporal;
     hipStream_t s = c->stream;
-    dim3 blk(TX, TY), grd(c->g.gridx * ((c->g.ny + PAIR_RY - 1) / PAIR_RY));
+    const int ry = pair_ry(nt);
+    dim3 blk(TX, ry), grd(c->g.gridx * ((c->g.ny + ry - 1) / ry));
 #define LBM_STEP2_ARITH(R)                                                             \
     {                                                                                 \
         if (nt) k_bgk_step2<Z, F, true, R><<<grd, blk, 0, s>>>(a);                    \

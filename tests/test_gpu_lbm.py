@@ -259,6 +259,20 @@ def test_step_kernels_agree_bitwise(gpu):
             assert rp["residual"] == reps[0]["residual"] and rp["mass"] == reps[0]["mass"]
 
 
+def test_two_step_tile_heights_agree_bitwise(gpu):
+    """The two-step kernel runs 64 x 8 tiles on a lattice whose two population
+    copies fit 128 MiB and 64 x 4 tiles with streaming stores above that; both
+    give the one-step kernel's bits (2048 x 1024 porous Zou-He flow, 151 MB of
+    populations, and a 1024 x 512 one, 38 MB), after 101 steps."""
+    for lat in (W.porous_circles(5, nx=2048, ny=1024, keepout=60, rmin=12, rmax=30),
+                W.porous_circles(6, nx=1024, ny=512, keepout=30, rmin=8, rmax=20)):
+        one, two = gpu_lattice(gpu, lat, 1), gpu_lattice(gpu, lat, 3)
+        assert two.step_kernel().startswith("pair")
+        one.step(101)
+        two.step(101)
+        assert np.array_equal(np_(one.populations()), np_(two.populations())), lat.name
+
+
 def test_large_lattice_quad_kernel_sampled_parity(gpu):
     """Four-wide launch on a 2048x1024 porous lattice (the kernel the benchmark's
     large lattice runs), 200 steps, against the FP64 oracle on every fluid node."""
