@@ -80,9 +80,23 @@ __device__ __forceinline__ int acc_row(int r) {
 }
 __device__ __forceinline__ int acc_col() { return threadIdx.x & 31; }
 
+// GELU x Phi(x) = x (1 + erf(x / sqrt 2)) / 2 for the forward kernels, with erf from
+// Abramowitz & Stegun, Handbook of Mathematical Functions, 7.1.26: for z >= 0,
+// erf z = 1 - t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-z^2), t = 1 / (1 + p z),
+// absolute error below 1.5e-7.  With z = |x| / sqrt 2 and
+// g = x t (a1 + ...) exp(-x^2 / 2) / 2, GELU is x - g for x >= 0 and g for x < 0.
+// The error (a few 1e-7 of |x|) is far below the bf16 rounding that follows.
+__device__ __forceinline__ float gelu_fast(float x) {
+    const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * 0.70710678118654752f * fabsf(x));
+    const float p = t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f +
+                    t * (-1.453152027f + t * 1.061405429f))));
+    const float g = 0.5f * x * p * __expf(-0.5f * x * x);
+    return x >= 0.0f ? x - g : g;
+}
+
 template <int KIND>
 __device__ __forceinline__ float act_t(float x) {
-    if constexpr (KIND == FNO_ACT_GELU) return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f));
+    if constexpr (KIND == FNO_ACT_GELU) return gelu_fast(x);
     else if constexpr (KIND == FNO_ACT_RELU) return x > 0.0f ? x : 0.0f;
     // SiLU x sigmoid(x) with the hardware exponential and reciprocal (a few ulp in
     // FP32, far below the bf16 rounding that follows every activation)
@@ -328,23 +342,21 @@ __global__ __launch_bounds__(COL_THREADS) void k_fno_col(FnoDev d, int layer) {
     for (int i = tid; i < d.CP * d.R2; i += blockDim.x) ys[i] = to_bf16(0.0f);
     __syncthreads();
     // Y[k][o] = sum_i X[k][i] R[i][o][k][k2] (complex), k over the 2 m1 kept rows
-    // Only output channels o < width are formed (ys was cleared above), over input
-    // channels rounded up to a multiple of 4: the padded channels of X are zero and
-    // so are R's padded rows and columns.  Weights are read four complex values
-    // (16 bytes) at a time.
+    // Only the width real channels take part: the padded channels of X are zero and
+    // so are R's padded rows and columns, and ys was cleared above.  Weights are read
+    // two complex values (8 bytes) at a time; width is even.
     const __bf16* R = d.Rmix + ((size_t)layer * d.m2 + k2) * d.K1 * d.CP * d.CP * 2;
-    const int wi = (d.width + 3) & ~3;
     for (int idx = tid; idx < d.K1 * d.width; idx += blockDim.x) {
         const int k = idx / d.width, o = idx % d.width;
         const float* xr = xs + k * d.CP;
         const float* xi = xs + (d.K1 + k) * d.CP;
-        const bf16x8* Rk = reinterpret_cast<const bf16x8*>(R + ((size_t)k * d.CP + o) * d.CP * 2);
+        const bf16x4* Rk = reinterpret_cast<const bf16x4*>(R + ((size_t)k * d.CP + o) * d.CP * 2);
         float sr = 0.0f, si = 0.0f;
-        for (int i = 0; i < wi; i += 4) {
-            const bf16x8 r8 = Rk[i >> 2];
+        for (int i = 0; i < d.width; i += 2) {
+            const bf16x4 r4 = Rk[i >> 1];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const float rr = from_bf16(r8[2 * e]), rim = from_bf16(r8[2 * e + 1]);
+            for (int e = 0; e < 2; ++e) {
+                const float rr = from_bf16(r4[2 * e]), rim = from_bf16(r4[2 * e + 1]);
                 const float a = xr[i + e], c = xi[i + e];
                 sr = fmaf(a, rr, sr);
                 sr = fmaf(-c, rim, sr);
