@@ -65,9 +65,20 @@ def profiled_traffic(name: str):
 def algorithmic_bytes(fluid: int, total: int) -> int:
     """Per launch of a step kernel: a fluid node loads 9 and stores 9 float32
     populations and reads its link byte (73 B); a solid node reads its link byte and
-    mask byte.  A one-step kernel moves this once per step; the two-step kernel once
-    per two steps (the intermediate state stays in LDS)."""
+    mask byte.  A one-step kernel moves this once per step; a fused S-step kernel
+    once per S steps (the intermediate states stay in LDS)."""
     return 73 * fluid + 2 * (total - fluid)
+
+
+def steps_per_launch(kname: str) -> int:
+    """Lattice steps per launch of the kernel named by lbm_step_kernel
+    ("pair-64x8/lean": 2, "deep3-64x16/lean": 3, "node/lean": 1)."""
+    shape = kname.split("/")[0]
+    if shape.startswith("pair"):
+        return 2
+    if shape.startswith("deep"):
+        return int(shape[4:].split("-")[0])
+    return 1
 
 
 def roofline(G, fluid, N, kern_ms, traffic_name):
@@ -76,14 +87,14 @@ def roofline(G, fluid, N, kern_ms, traffic_name):
     the one-step equivalent (the bandwidth a one-step-per-launch kernel would need
     for the same lattice updates per second)."""
     kname = G.step_kernel()
-    per_launch = 2 if kname.startswith("pair") else 1
+    per_launch = steps_per_launch(kname)
     launch_ms = kern_ms * per_launch
     b = algorithmic_bytes(fluid, N)
     ach = b / (launch_ms * 1e-3) / 1e9
     eq = b / (kern_ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": ach / HBM_PEAK_GBS, "traffic": profiled_traffic(traffic_name),
-            "kernel": ("k_bgk_step2 " if per_launch == 2 else "k_bgk_step ") + kname,
+            "kernel": ("k_bgk_multi " if per_launch > 1 else "k_bgk_step ") + kname,
             "steps_per_launch": per_launch, "bytes_per_launch": b, "launch_ms": launch_ms,
             "one_step_equivalent": {"achieved": eq, "frac": eq / HBM_PEAK_GBS}}
 
@@ -429,11 +440,12 @@ def main():
         big = porous_large(args.seed)
         GB = lbmfno.Lattice.from_workload(big)
         fl_b, _ = GB.info()
-        msb, kb, _, _ = time_lattice(GB, 100, 5, 1)
+        inner_b = 101                 # 100 fused steps per bench step: whole launches of 2 or 4
+        msb, kb, _, _ = time_lattice(GB, inner_b, 5, 1)
         rb = roofline(GB, fl_b, big.nx * big.ny, kb, "porous8192x4096")
         rb.update({"frac_of_copy": rb["achieved"] / copy_gbs,
                    "one_step_equivalent_frac_of_copy": rb["one_step_equivalent"]["achieved"] / copy_gbs,
-                   "workload": big.name, "glups": 100 * big.nx * big.ny / (msb * 1e6)})
+                   "workload": big.name, "glups": inner_b * big.nx * big.ny / (msb * 1e6)})
         out["roofline_hbm_resident"] = rb
         GB.close()
         del GB

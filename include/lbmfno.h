@@ -70,7 +70,7 @@ extern "C" {
                               force in slowly varying flow */
 
 /* Step-kernel choice; every choice computes the same values. */
-#define LBM_KERNEL_AUTO 0  /* LBM_KERNEL_PAIR (batches: the autotuner's cached pick) */
+#define LBM_KERNEL_AUTO 0  /* LBM_KERNEL_DEEP (batches: the autotuner's cached pick) */
 #define LBM_KERNEL_NODE 1  /* one node per lane, 4-byte accesses (any nx) */
 #define LBM_KERNEL_QUAD 2  /* four x nodes per lane, 16-byte accesses (nx % 4 == 0,
                               16-byte aligned stores) */
@@ -80,6 +80,12 @@ extern "C" {
                               traffic per step).  64 x 8 tiles when both population
                               copies fit 128 MiB, else 64 x 4 tiles with streaming
                               stores.  Any nx. */
+#define LBM_KERNEL_DEEP 4  /* deeper temporal blocking: three steps per launch (a
+                              two-node ring) when both population copies fit
+                              128 MiB, on 64 x 16 tiles when the lattice has at
+                              least 512 of them, else 64 x 8; four steps per launch
+                              (a three-node ring, 64 x 8 tiles, streaming stores)
+                              above 128 MiB.  Any nx. */
 
 /* Lattice description.  tau > 1/2 is the BGK relaxation time (nu = (tau-1/2)/3 in
  * lattice units), (gx, gy) a uniform body force per unit mass (Guo forcing; use 0
@@ -227,8 +233,9 @@ int lbm_save_state(lbm_ctx* ctx, float* d_out);
 int lbm_load_state(lbm_ctx* ctx, const float* d_in);
 
 /* The step kernel and arithmetic this context runs: "<shape>/<arith>" with shape
- * node (one node per lane), quad (four nodes per lane) or pair (two steps per
- * launch) and arith lean, mixed or fp32.  Static string; "" for a NULL ctx. */
+ * node (one node per lane), quad (four nodes per lane), pair-64xR (two steps per
+ * launch on 64 x R tiles) or deepS-64xR (S steps per launch on 64 x R tiles) and
+ * arith lean, mixed or fp32.  Static string; "" for a NULL ctx. */
 const char* lbm_step_kernel(const lbm_ctx* ctx);
 
 /* Number of fluid nodes and the current step counter (host values). */

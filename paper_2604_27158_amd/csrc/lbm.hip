@@ -541,43 +541,123 @@ __global__ __launch_bounds__(256) void k_bgk_step(StepArgs a) {
     step_node<ZH, FORCE, WDRHO, NT, R>(a, b - by * a.g.gridx, by);
 }
 
-// Two fused steps per launch (temporal blocking).  A workgroup of TX x RY lanes
-// owns a TX x RY tile.  Step n -> n+1 runs on the tile and a one-node ring around
-// it (the nodes the tile pulls from), gathering from the store in global memory
-// as the one-step kernel does and keeping the post-collision values in LDS; step
-// n+1 -> n+2 then runs on the tile, pulling from LDS, and only its result is
-// stored.  Both steps call collide_node on the same float inputs, so the result
-// is bit-identical to two one-step launches, while the store traffic and the
-// launch count per step halve.  Ring nodes outside a non-periodic axis, and solid
-// ring nodes, are never pulled (their links bounce) and are skipped; on a
+// S fused steps per launch (temporal blocking).  A workgroup of TX x RY lanes
+// owns a TX x RY tile.  Level 0 advances the tile and the (S-1)-node ring around
+// it by one step, gathering from the store in global memory as the one-step
+// kernel does, and keeps the post-collision values in LDS.  Each further level
+// advances a ring one node narrower, pulling from the level before in LDS (the
+// new values wait in registers across a barrier, then overwrite the LDS copy);
+// the last level advances the tile alone and only its result is stored.  Every
+// level calls collide_node on the same float inputs as a one-step launch, so the
+// result is bit-identical to S one-step launches, while one load and one store of
+// the populations serve S steps.  Ring nodes outside a non-periodic axis, and
+// solid ring nodes, are never pulled (their links bounce) and are skipped; on a
 // periodic axis the ring wraps.
 //
-// Tile height: a lattice whose two population copies fit the last-level cache
-// runs 64 x 8 tiles (fewer ring recomputations, measured 6-7% faster there), a
-// lattice streamed from HBM runs 64 x 4 tiles (more, smaller workgroups hide more
-// of the HBM latency; 64 x 8 and 64 x 16 measured 3% and 12% slower there).  The
-// batched launch reuses the one-step kernel's 64 x 4 tile table.
-constexpr int pair_lw() { return TX + 2; }
-constexpr int pair_ln(int ry) { return pair_lw() * (ry + 2); }
-constexpr int pair_ry(bool nt) { return nt ? 4 : 8; }
+// Shapes in use (lattice update rates measured on 1024x512, 512x256, 128x128 and
+// 8192x4096 porous flows):
+//   S = 2, 64 x 8   cache-resident lattices, LBM_KERNEL_PAIR
+//   S = 2, 64 x 4   lattices streamed from HBM, LBM_KERNEL_PAIR, and the batch
+//   S = 3, 64 x 16  cache-resident lattices whose grid gives every CU two
+//                   workgroups (1024x512: 106 against 92 GLUPS for S = 2)
+//   S = 3, 64 x 8   smaller cache-resident lattices (512x256: 47 against 44)
+//   S = 4, 64 x 8   lattices streamed from HBM (8192x4096: 127 against 97; S = 3
+//                   reaches 119, 64 x 16 tiles 113)
+// Deeper blocking trades redundant ring collisions (29 % at S = 2, 64 x 8; 45 %
+// at S = 4, 64 x 8) for fewer global-memory round trips; the kernel is bound by
+// memory latency, not by the vector ALUs (34 % busy at S = 2).
+template <int S, int RY>
+struct Ring {
+    static constexpr int W(int lvl) { return TX + 2 * (S - 1 - lvl); }
+    static constexpr int H(int lvl) { return RY + 2 * (S - 1 - lvl); }
+    static constexpr int LN(int lvl) { return W(lvl) * H(lvl); }
+};
 
-template <int RY, bool ZH, bool FORCE, bool NT, typename R>
-__device__ __forceinline__ void step_pair(const StepArgs& a, int bx, int by, float* __restrict__ P) {
-    constexpr int PAIR_LW = pair_lw(), PAIR_LN = pair_ln(RY);
+// Pull f at LDS position c of a level with row width W and plane stride LN: the
+// streaming neighbours, or the node's own opposite population on a bounced link.
+__device__ __forceinline__ void pull_lds(const float* __restrict__ P, int W, int LN, int c, unsigned lk,
+                                         float f[9]) {
+    f[0] = P[0 * LN + c];
+    f[1] = P[1 * LN + c - 1];
+    f[2] = P[2 * LN + c - W];
+    f[3] = P[3 * LN + c + 1];
+    f[4] = P[4 * LN + c + W];
+    f[5] = P[5 * LN + c - W - 1];
+    f[6] = P[6 * LN + c - W + 1];
+    f[7] = P[7 * LN + c + W + 1];
+    f[8] = P[8 * LN + c + W - 1];
+    if (lk != 0u) {
+#define LBM_BBL(Q) if ((lk >> (Q - 1)) & 1u) f[Q] = P[opp_of(Q) * LN + c];
+        LBM_BBL(1) LBM_BBL(2) LBM_BBL(3) LBM_BBL(4) LBM_BBL(5) LBM_BBL(6) LBM_BBL(7) LBM_BBL(8)
+#undef LBM_BBL
+    }
+}
+
+// Lattice node of ring position (i, j), wrapped on a periodic axis; false when the
+// position lies outside a non-periodic axis.
+__device__ __forceinline__ bool ring_node(const LatticeGeom& g, int& i, int& j) {
+    if (i < 0 || i >= g.nx) {
+        if (g.bc_x != LBM_BC_PERIODIC) return false;
+        i = ((i % g.nx) + g.nx) % g.nx;
+    }
+    if (j < 0 || j >= g.ny) {
+        if (g.bc_y != LBM_BC_PERIODIC) return false;
+        j = ((j % g.ny) + g.ny) % g.ny;
+    }
+    return true;
+}
+
+// Levels 1 .. S-2: the ring S-1-LVL nodes wide, from level LVL-1 in LDS.
+template <int S, int RY, int LVL, bool ZH, bool FORCE, typename R>
+__device__ __forceinline__ void ring_levels(const StepArgs& a, int x0, int y0, int tid, float* __restrict__ P) {
+    if constexpr (LVL < S - 1) {
+        using G = Ring<S, RY>;
+        constexpr int W = G::W(LVL), LN = G::LN(LVL), WP = G::W(LVL - 1), LNP = G::LN(LVL - 1);
+        constexpr int IT = (LN + TX * RY - 1) / (TX * RY);
+        constexpr int RING = S - 1 - LVL;
+        float v[IT][9];
+        bool ok[IT];
+#pragma unroll
+        for (int t = 0; t < IT; ++t) {
+            ok[t] = false;
+            const int e = tid + t * TX * RY;
+            if (e >= LN) continue;
+            const int ly = e / W, lx = e - ly * W;
+            int i = x0 - RING + lx, j = y0 - RING + ly;
+            if (!ring_node(a.g, i, j)) continue;
+            const int n = j * a.g.nx + i;
+            const unsigned lk = a.link[n];
+            if (is_solid(lk, a.mask, n)) continue;
+            float f[9];
+            pull_lds(P, WP, LNP, (ly + 1) * WP + lx + 1, lk, f);
+            (void)collide_node<ZH, FORCE, R>(f, i, a.g.nx, a);
+#pragma unroll
+            for (int q = 0; q < 9; ++q) v[t][q] = f[q];
+            ok[t] = true;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < IT; ++t) {
+            if (!ok[t]) continue;
+#pragma unroll
+            for (int q = 0; q < 9; ++q) P[q * LN + tid + t * TX * RY] = v[t][q];
+        }
+        __syncthreads();
+        ring_levels<S, RY, LVL + 1, ZH, FORCE, R>(a, x0, y0, tid, P);
+    }
+}
+
+template <int S, int RY, bool ZH, bool FORCE, bool NT, typename R>
+__device__ __forceinline__ void step_multi(const StepArgs& a, int bx, int by, float* __restrict__ P) {
+    using G = Ring<S, RY>;
+    constexpr int W0 = G::W(0), LN0 = G::LN(0);
     const int x0 = bx * TX, y0 = by * RY;
     const int nx = a.g.nx, ny = a.g.ny;
     const int tid = threadIdx.y * TX + threadIdx.x;
-    for (int e = tid; e < PAIR_LN; e += TX * RY) {
-        const int ly = e / PAIR_LW, lx = e - ly * PAIR_LW;
-        int i = x0 - 1 + lx, j = y0 - 1 + ly;
-        if (i < 0 || i >= nx) {
-            if (a.g.bc_x != LBM_BC_PERIODIC) continue;
-            i = ((i % nx) + nx) % nx;
-        }
-        if (j < 0 || j >= ny) {
-            if (a.g.bc_y != LBM_BC_PERIODIC) continue;
-            j = ((j % ny) + ny) % ny;
-        }
+    for (int e = tid; e < LN0; e += TX * RY) {
+        const int ly = e / W0, lx = e - ly * W0;
+        int i = x0 - (S - 1) + lx, j = y0 - (S - 1) + ly;
+        if (!ring_node(a.g, i, j)) continue;
         const int n = j * nx + i;
         const unsigned lk = a.link[n];
         if (is_solid(lk, a.mask, n)) continue;
@@ -586,47 +666,33 @@ __device__ __forceinline__ void step_pair(const StepArgs& a, int bx, int by, flo
         gather_bounce<float>(a.src, a.g, lk, n, f);
         (void)collide_node<ZH, FORCE, R>(f, i, nx, a);
 #pragma unroll
-        for (int q = 0; q < 9; ++q) P[q * PAIR_LN + e] = f[q];
+        for (int q = 0; q < 9; ++q) P[q * LN0 + e] = f[q];
     }
     __syncthreads();
+    ring_levels<S, RY, 1, ZH, FORCE, R>(a, x0, y0, tid, P);
+    constexpr int WL = G::W(S - 2), LNL = G::LN(S - 2);
+    const int i = x0 + threadIdx.x, j = y0 + threadIdx.y;
+    if (i >= nx || j >= ny) return;
+    const int n = j * nx + i;
+    const unsigned lk = a.link[n];
+    if (is_solid(lk, a.mask, n)) return;
+    float f[9];
+    pull_lds(P, WL, LNL, (threadIdx.y + 1) * WL + threadIdx.x + 1, lk, f);
+    (void)collide_node<ZH, FORCE, R>(f, i, nx, a);
     const size_t N = (size_t)a.g.N;
-    for (int r = threadIdx.y; r < RY; r += RY) {
-        const int i = x0 + threadIdx.x, j = y0 + r;
-        if (i >= nx || j >= ny) continue;
-        const int n = j * nx + i;
-        const unsigned lk = a.link[n];
-        if (is_solid(lk, a.mask, n)) continue;
-        const int c = (r + 1) * PAIR_LW + threadIdx.x + 1;
-        float f[9];
-        f[0] = P[0 * PAIR_LN + c];
-        f[1] = P[1 * PAIR_LN + c - 1];
-        f[2] = P[2 * PAIR_LN + c - PAIR_LW];
-        f[3] = P[3 * PAIR_LN + c + 1];
-        f[4] = P[4 * PAIR_LN + c + PAIR_LW];
-        f[5] = P[5 * PAIR_LN + c - PAIR_LW - 1];
-        f[6] = P[6 * PAIR_LN + c - PAIR_LW + 1];
-        f[7] = P[7 * PAIR_LN + c + PAIR_LW + 1];
-        f[8] = P[8 * PAIR_LN + c + PAIR_LW - 1];
-        if (lk != 0u) {
-#define LBM_BB2(Q) if ((lk >> (Q - 1)) & 1u) f[Q] = P[opp_of(Q) * PAIR_LN + c];
-            LBM_BB2(1) LBM_BB2(2) LBM_BB2(3) LBM_BB2(4) LBM_BB2(5) LBM_BB2(6) LBM_BB2(7) LBM_BB2(8)
-#undef LBM_BB2
-        }
-        (void)collide_node<ZH, FORCE, R>(f, i, nx, a);
-        float* __restrict__ d = a.dst + n;
+    float* __restrict__ d = a.dst + n;
 #pragma unroll
-        for (int q = 0; q < 9; ++q) {
-            if (NT) __builtin_nontemporal_store(f[q], d + q * N); else d[q * N] = f[q];
-        }
+    for (int q = 0; q < 9; ++q) {
+        if (NT) __builtin_nontemporal_store(f[q], d + q * N); else d[q * N] = f[q];
     }
 }
 
-template <bool ZH, bool FORCE, bool NT, typename R>
-__global__ __launch_bounds__(TX * pair_ry(NT)) void k_bgk_step2(StepArgs a) {
-    __shared__ float P[9 * pair_ln(pair_ry(NT))];
+template <int S, int RY, bool ZH, bool FORCE, bool NT, typename R>
+__global__ __launch_bounds__(TX * RY) void k_bgk_multi(StepArgs a) {
+    __shared__ float P[9 * Ring<S, RY>::LN(0)];
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int by = b / a.g.gridx;
-    step_pair<pair_ry(NT), ZH, FORCE, NT, R>(a, b - by * a.g.gridx, by, P);
+    step_multi<S, RY, ZH, FORCE, NT, R>(a, b - by * a.g.gridx, by, P);
 }
 
 // Four-wide step (nx % 4 == 0): each lane owns four consecutive x nodes of one
@@ -786,23 +852,23 @@ __global__ __launch_bounds__(256) void k_bgk_batch(const StepArgs* __restrict__ 
     }
 }
 
-// Batched two-step launch: k_bgk_step2's tile step over the trajectory-major tile
-// table (its 64 x TY tiles are the one-node kernel's).
+// Batched two-step launch: the two-step tile routine over the trajectory-major
+// tile table (its 64 x TY tiles are the one-node kernel's).
 template <bool NT, typename R>
 __global__ __launch_bounds__(256) void k_bgk_batch2(const StepArgs* __restrict__ args,
                                                     const BatchTile* __restrict__ tiles) {
-    __shared__ float P[9 * pair_ln(TY)];
+    __shared__ float P[9 * Ring<2, TY>::LN(0)];
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const BatchTile t = tiles[b];
     const StepArgs a = args[t.traj];
     const bool zh = a.g.bc_x == LBM_BC_ZOUHE;
     const bool force = a.gx != 0.0 || a.gy != 0.0;
     if (zh) {
-        if (force) step_pair<TY, true, true, NT, R>(a, t.bx, t.by, P);
-        else step_pair<TY, true, false, NT, R>(a, t.bx, t.by, P);
+        if (force) step_multi<2, TY, true, true, NT, R>(a, t.bx, t.by, P);
+        else step_multi<2, TY, true, false, NT, R>(a, t.bx, t.by, P);
     } else {
-        if (force) step_pair<TY, false, true, NT, R>(a, t.bx, t.by, P);
-        else step_pair<TY, false, false, NT, R>(a, t.bx, t.by, P);
+        if (force) step_multi<2, TY, false, true, NT, R>(a, t.bx, t.by, P);
+        else step_multi<2, TY, false, false, NT, R>(a, t.bx, t.by, P);
     }
 }
 
@@ -1033,6 +1099,9 @@ __global__ __launch_bounds__(64) void k_compare_final(const double* __restrict__
 
 using namespace lbmfno;
 
+// Fused multi-step kernel shapes: steps per launch, tile height, store kind.
+enum FusedShape { SHAPE_NONE, SHAPE_PAIR8, SHAPE_PAIR4_NT, SHAPE_DEEP3_8, SHAPE_DEEP3_16, SHAPE_DEEP4_8_NT };
+
 struct lbm_ctx {
     lbm_config cfg;
     LatticeGeom g;
@@ -1054,7 +1123,8 @@ struct lbm_ctx {
     int device;
     bool nontemporal;
     bool vec4;       // four-wide step kernel (nx % 4 == 0)
-    bool pair;       // two steps per launch (k_bgk_step2)
+    int spl;         // steps per launch of the fused kernel (1: a one-step kernel)
+    int shape;       // FusedShape of the fused kernel
     int gridx4;      // workgroups along x for the four-wide kernel
     int nblocks4;
 };
@@ -1075,7 +1145,7 @@ static int validate_config(const lbm_config* c) {
         return fail(LBM_EINVAL, "trt_lambda = %g (0 for BGK, > 0 for TRT)", c->trt_lambda);
     if (c->trt_lambda > 0.0 && c->arith != LBM_ARITH_LEAN)
         return fail(LBM_EUNSUPPORTED, "the TRT collision runs in LBM_ARITH_LEAN");
-    if (c->kernel < LBM_KERNEL_AUTO || c->kernel > LBM_KERNEL_PAIR)
+    if (c->kernel < LBM_KERNEL_AUTO || c->kernel > LBM_KERNEL_DEEP)
         return fail(LBM_EINVAL, "kernel = %d", c->kernel);
     if (c->bc_x < 0 || c->bc_x > 2 || c->bc_y < 0 || c->bc_y > 1)
         return fail(LBM_EINVAL, "boundary codes bc_x=%d bc_y=%d", c->bc_x, c->bc_y);
@@ -1250,8 +1320,33 @@ static int launch_step(lbm_ctx* c, bool write_drho) {
     return LBM_OK;
 }
 
-// Two steps in one launch (k_bgk_step2): store parity flips once.
-static int launch_step2(lbm_ctx* c) {
+// One shape of the fused multi-step kernel, dispatched over the boundary,
+// forcing and arithmetic variants.
+template <int S, int RY, bool NT>
+static void launch_multi_shape(const lbm_ctx* c, const StepArgs& a) {
+    const bool zh = c->cfg.bc_x == LBM_BC_ZOUHE;
+    const bool force = c->cfg.gx != 0.0 || c->cfg.gy != 0.0;
+    const int ar = c->cfg.arith;
+    const bool trt = c->cfg.trt_lambda > 0.0;
+    hipStream_t s = c->stream;
+    dim3 blk(TX, RY), grd(c->g.gridx * ((c->g.ny + RY - 1) / RY));
+#define LBM_MULTI_ARITH(Z, F)                                                           \
+    {                                                                                 \
+        if (ar == LBM_ARITH_FP32) k_bgk_multi<S, RY, Z, F, NT, float><<<grd, blk, 0, s>>>(a); \
+        else if (ar == LBM_ARITH_MIXED) k_bgk_multi<S, RY, Z, F, NT, double><<<grd, blk, 0, s>>>(a); \
+        else if (trt) k_bgk_multi<S, RY, Z, F, NT, LeanTRT><<<grd, blk, 0, s>>>(a);  \
+        else k_bgk_multi<S, RY, Z, F, NT, Lean><<<grd, blk, 0, s>>>(a);              \
+    }
+    if (zh) {
+        if (force) LBM_MULTI_ARITH(true, true) else LBM_MULTI_ARITH(true, false)
+    } else {
+        if (force) LBM_MULTI_ARITH(false, true) else LBM_MULTI_ARITH(false, false)
+    }
+#undef LBM_MULTI_ARITH
+}
+
+// c->spl steps in one launch (k_bgk_multi): the store parity flips once.
+static int launch_multi(lbm_ctx* c) {
     StepArgs a;
     a.src = c->f[c->cur];
     a.dst = c->f[c->cur ^ 1];
@@ -1264,35 +1359,16 @@ static int launch_step2(lbm_ctx* c) {
     a.gy = c->cfg.gy;
     a.u_in = c->cfg.u_in;
     a.rho_out = c->cfg.rho_out;
-    const bool zh = c->cfg.bc_x == LBM_BC_ZOUHE;
-    const bool force = c->cfg.gx != 0.0 || c->cfg.gy != 0.0;
-    const int ar = c->cfg.arith;
-    const bool trt = c->cfg.trt_lambda > 0.0;
-    const bool nt = c->nontemporal;
-    hipStream_t s = c->stream;
-    const int ry = pair_ry(nt);
-    dim3 blk(TX, ry), grd(c->g.gridx * ((c->g.ny + ry - 1) / ry));
-#define LBM_STEP2_ARITH(R)                                                             \
-    {                                                                                 \
-        if (nt) k_bgk_step2<Z, F, true, R><<<grd, blk, 0, s>>>(a);                    \
-        else k_bgk_step2<Z, F, false, R><<<grd, blk, 0, s>>>(a);                      \
+    switch (c->shape) {
+        case SHAPE_PAIR8: launch_multi_shape<2, 8, false>(c, a); break;
+        case SHAPE_PAIR4_NT: launch_multi_shape<2, 4, true>(c, a); break;
+        case SHAPE_DEEP3_8: launch_multi_shape<3, 8, false>(c, a); break;
+        case SHAPE_DEEP3_16: launch_multi_shape<3, 16, false>(c, a); break;
+        case SHAPE_DEEP4_8_NT: launch_multi_shape<4, 8, true>(c, a); break;
+        default: return fail(LBM_EINVAL, "no fused shape selected");
     }
-#define LBM_STEP2_CASE(Z_, F_)                                                         \
-    if (zh == Z_ && force == F_) {                                                    \
-        constexpr bool Z = Z_, F = F_;                                                \
-        if (ar == LBM_ARITH_FP32) LBM_STEP2_ARITH(float)                              \
-        else if (ar == LBM_ARITH_MIXED) LBM_STEP2_ARITH(double)                       \
-        else if (trt) LBM_STEP2_ARITH(LeanTRT)                                        \
-        else LBM_STEP2_ARITH(Lean)                                                    \
-    }
-    LBM_STEP2_CASE(false, false)
-    LBM_STEP2_CASE(false, true)
-    LBM_STEP2_CASE(true, false)
-    LBM_STEP2_CASE(true, true)
-#undef LBM_STEP2_CASE
-#undef LBM_STEP2_ARITH
     c->cur ^= 1;
-    c->steps += 2;
+    c->steps += c->spl;
     return LBM_OK;
 }
 
@@ -1359,10 +1435,25 @@ extern "C" int lbm_init(lbm_ctx** out, const lbm_config* cfg, const uint8_t* d_m
         delete c;
         return fail(LBM_EUNSUPPORTED, "four-wide kernel needs nx %% 4 == 0 and 16-byte aligned stores");
     }
-    // Two steps per launch beat every one-step kernel at every size measured
-    // (128x128, 512x256, 1024x512, 8192x4096): on large lattices by halving the
-    // store traffic, on small, latency-bound ones by halving the launches.
-    c->pair = cfg->kernel == LBM_KERNEL_PAIR || cfg->kernel == LBM_KERNEL_AUTO;
+    const size_t N = (size_t)c->g.N;
+    // two stores above 128 MB cannot stay in the 256 MB last-level cache across a step
+    c->nontemporal = 2 * 9 * N * sizeof(float) > ((size_t)128 << 20);
+    // Fused multi-step launches beat every one-step kernel at every size measured
+    // (128x128 to 8192x4096): on large lattices by cutting the population traffic
+    // per step, on small, latency-bound ones by cutting the launches.  The deep
+    // kernel (the default) runs three steps per launch on cache-resident lattices,
+    // on 64 x 16 tiles when that grid still gives every CU two workgroups, and four
+    // steps per launch with streaming stores on lattices streamed from HBM.
+    const int64_t tiles16 = (int64_t)c->g.gridx * ((cfg->ny + 15) / 16);
+    c->shape = SHAPE_NONE;
+    c->spl = 1;
+    if (cfg->kernel == LBM_KERNEL_PAIR) {
+        c->shape = c->nontemporal ? SHAPE_PAIR4_NT : SHAPE_PAIR8;
+        c->spl = 2;
+    } else if (cfg->kernel == LBM_KERNEL_DEEP || cfg->kernel == LBM_KERNEL_AUTO) {
+        c->shape = c->nontemporal ? SHAPE_DEEP4_8_NT : tiles16 >= 512 ? SHAPE_DEEP3_16 : SHAPE_DEEP3_8;
+        c->spl = c->nontemporal ? 4 : 3;
+    }
     c->vec4 = cfg->kernel == LBM_KERNEL_QUAD;
     c->gridx4 = (cfg->nx + 4 * TX - 1) / (4 * TX);
     c->nblocks4 = c->gridx4 * ((cfg->ny + TY - 1) / TY);
@@ -1370,10 +1461,8 @@ extern "C" int lbm_init(lbm_ctx** out, const lbm_config* cfg, const uint8_t* d_m
     c->f[1] = d_fB;
     c->cur = 0;
     c->stream = (hipStream_t)stream;
-    c->graph_chunk = 32;
-    const size_t N = (size_t)c->g.N;
-    // two stores above 128 MB cannot stay in the 256 MB last-level cache across a step
-    c->nontemporal = 2 * 9 * N * sizeof(float) > ((size_t)128 << 20);
+    // a graph chunk is an even number of launches (the store parity returns)
+    c->graph_chunk = c->spl == 3 ? 30 : 32;
 #define LBM_TRY(call)                                                                   \
     do {                                                                                \
         hipError_t e_ = (call);                                                         \
@@ -1451,8 +1540,8 @@ static int build_graph(lbm_ctx* c) {
     const int64_t steps0 = c->steps;
     hipGraph_t graph = nullptr;
     LBM_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-    if (c->pair) {
-        for (int k = 0; k < c->graph_chunk; k += 2) launch_step2(c);
+    if (c->spl > 1) {
+        for (int k = 0; k < c->graph_chunk; k += c->spl) launch_multi(c);
     } else {
         for (int k = 0; k < c->graph_chunk; ++k) launch_step(c, false);
     }
@@ -1487,8 +1576,8 @@ extern "C" int lbm_step(lbm_ctx* c, int32_t n, lbm_report* rep) {
             plain -= c->graph_chunk;
         }
     }
-    if (c->pair)
-        for (; plain >= 2; plain -= 2) launch_step2(c);
+    if (c->spl > 1)
+        for (; plain >= c->spl; plain -= c->spl) launch_multi(c);
     for (int k = 0; k < plain; ++k) launch_step(c, false);
     LBM_HIP(hipGetLastError());
     if (!rep) return LBM_OK;
@@ -1577,7 +1666,14 @@ extern "C" int lbm_compare_fields(lbm_ctx* c, const float* d_drho, const float* 
 extern "C" const char* lbm_step_kernel(const lbm_ctx* c) {
     if (!c) return "";
     const bool lean = c->cfg.arith == LBM_ARITH_LEAN, f32 = c->cfg.arith == LBM_ARITH_FP32;
-    if (c->pair) return lean ? "pair/lean" : f32 ? "pair/fp32" : "pair/mixed";
+    static const char* const fused[6][3] = {
+        {"", "", ""},
+        {"pair-64x8/lean", "pair-64x8/fp32", "pair-64x8/mixed"},
+        {"pair-64x4/lean", "pair-64x4/fp32", "pair-64x4/mixed"},
+        {"deep3-64x8/lean", "deep3-64x8/fp32", "deep3-64x8/mixed"},
+        {"deep3-64x16/lean", "deep3-64x16/fp32", "deep3-64x16/mixed"},
+        {"deep4-64x8/lean", "deep4-64x8/fp32", "deep4-64x8/mixed"}};
+    if (c->spl > 1) return fused[c->shape][lean ? 0 : f32 ? 1 : 2];
     if (c->vec4) return lean ? "quad/lean" : f32 ? "quad/fp32" : "quad/mixed";
     return lean ? "node/lean" : f32 ? "node/fp32" : "node/mixed";
 }

@@ -33,7 +33,7 @@ class LbmConfig(ctypes.Structure):
 
 
 ARITH_MIXED, ARITH_FP32, ARITH_LEAN = 0, 1, 2
-KERNEL_AUTO, KERNEL_NODE, KERNEL_QUAD, KERNEL_PAIR = 0, 1, 2, 3
+KERNEL_AUTO, KERNEL_NODE, KERNEL_QUAD, KERNEL_PAIR, KERNEL_DEEP = 0, 1, 2, 3, 4
 
 
 class LbmReport(ctypes.Structure):

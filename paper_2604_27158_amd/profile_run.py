@@ -1,9 +1,10 @@
 """Fixed kernel sequences for hardware-counter runs (rocprofv3 --pmc).
 
 Launches the step kernel of a workload directly (no graph replay, so every
-dispatch is visible to the counter collector; two steps per call, i.e. one launch
-of the two-step kernel the workload runs by default) and the library's copy
-kernel on a buffer of known size, which calibrates the byte counters:
+dispatch is visible to the counter collector; each call advances the lattice by
+the steps of one launch of the fused kernel the workload runs by default) and the
+library's copy kernel on a buffer of known size, which calibrates the byte
+counters:
 
     python -m paper_2604_27158_amd.profile_run --workload porous1024 --steps 50
 
@@ -36,14 +37,12 @@ def main():
     if args.workload == "fno":
         run_fno(args.steps)
         return
-    if args.workload == "porous1024":
-        lat = W.porous_circles(0)
-    else:
-        import bench
-        lat = bench.porous_large(0)
+    import bench
+    lat = W.porous_circles(0) if args.workload == "porous1024" else bench.porous_large(0)
     G = lbmfno.Lattice.from_workload(lat)
-    for _ in range(args.steps // 2):
-        G.step(2)
+    spl = bench.steps_per_launch(G.step_kernel())
+    for _ in range(args.steps // spl):
+        G.step(spl)
     G.synchronize()
     fluid, _ = G.info()
     a = torch.ones(COPY_FLOATS, dtype=torch.float32, device="cuda")

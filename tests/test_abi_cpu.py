@@ -51,7 +51,7 @@ def _cfg(**kw):
 @pytest.mark.parametrize("kw", [dict(tau=0.5), dict(tau=float("nan")), dict(nx=0), dict(ny=-3),
                                 dict(bc_x=7), dict(bc_y=2), dict(nx=30000, ny=30000),
                                 dict(bc_x=2, u_in=1.5), dict(bc_x=2, rho_out=0.0),
-                                dict(gx=float("inf")), dict(arith=5), dict(kernel=4),
+                                dict(gx=float("inf")), dict(arith=5), dict(kernel=5),
                                 dict(trt_lambda=-0.25), dict(trt_lambda=float("nan"))])
 def test_lbm_init_rejects_invalid_config(lib, kw):
     ctx = ctypes.c_void_p()

@@ -60,7 +60,7 @@ def test_mask_bit_exact(gpu, maker, args, seed):
     print(f"{lat.name}: {int(m_ref.sum())} solid cells, porosity {1 - m_ref.mean():.4f}")
 
 
-KERNELS = [1, 2, 3]   # one node per lane, four nodes per lane, two steps per launch
+KERNELS = [1, 2, 3, 4]   # one node per lane, four nodes per lane, two steps per launch, 3 or 4 steps per launch
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
@@ -239,38 +239,54 @@ def test_report_sums_and_residual(gpu):
 
 
 def test_step_kernels_agree_bitwise(gpu):
-    """All step kernels (one node, four nodes per lane, two steps per launch) evaluate
-    the same expressions in the same order: identical bits after 301 steps (graph
-    chunks, paired launches and a single one) and after a report step, on a forced
-    walled channel, a Zou-He porous flow and a periodic box with obstacles."""
+    """All step kernels (one node, four nodes per lane, two and three steps per
+    launch) evaluate the same expressions in the same order: identical bits after
+    301 steps (graph chunks, fused launches and single ones) and after a report
+    step, on a forced walled channel, a Zou-He porous flow and a periodic box with
+    obstacles."""
     lats = (W.channel_walls_circles(2), W.porous_circles(3, nx=512, ny=256, rmin=6, rmax=12, keepout=20),
             W.periodic_box(96, 40, 0.7, gx=1e-6, shapes=[W.circle(20, 10, 5), W.circle(90, 38, 4)]))
     for lat in lats:
-        runs = [gpu_lattice(gpu, lat, k) for k in (1, 2, 3)]
+        runs = [gpu_lattice(gpu, lat, k) for k in (1, 2, 3, 4)]
         for G in runs:
             G.step(301)
         ref = np_(runs[0].populations())
-        for k, G in zip((2, 3), runs[1:]):
+        for k, G in zip((2, 3, 4), runs[1:]):
             assert np.array_equal(np_(G.populations()), ref), (lat.name, k)
         reps = [G.step(7, report=True) for G in runs]
         ref = np_(runs[0].populations())
-        for k, G, rp in zip((2, 3), runs[1:], reps[1:]):
+        for k, G, rp in zip((2, 3, 4), runs[1:], reps[1:]):
             assert np.array_equal(np_(G.populations()), ref), (lat.name, k)
             assert rp["residual"] == reps[0]["residual"] and rp["mass"] == reps[0]["mass"]
 
 
-def test_two_step_tile_heights_agree_bitwise(gpu):
-    """The two-step kernel runs 64 x 8 tiles on a lattice whose two population
-    copies fit 128 MiB and 64 x 4 tiles with streaming stores above that; both
-    give the one-step kernel's bits (2048 x 1024 porous Zou-He flow, 151 MB of
-    populations, and a 1024 x 512 one, 38 MB), after 101 steps."""
-    for lat in (W.porous_circles(5, nx=2048, ny=1024, keepout=60, rmin=12, rmax=30),
-                W.porous_circles(6, nx=1024, ny=512, keepout=30, rmin=8, rmax=20)):
-        one, two = gpu_lattice(gpu, lat, 1), gpu_lattice(gpu, lat, 3)
-        assert two.step_kernel().startswith("pair")
-        one.step(101)
-        two.step(101)
-        assert np.array_equal(np_(one.populations()), np_(two.populations())), lat.name
+@pytest.mark.parametrize("lat,shapes", [
+    (W.porous_circles(5, nx=2048, ny=1024, keepout=60, rmin=12, rmax=30), ("pair-64x4", "deep4-64x8")),
+    (W.porous_circles(6, nx=1024, ny=512, keepout=30, rmin=8, rmax=20), ("pair-64x8", "deep3-64x16")),
+    (W.porous_circles(7, nx=520, ny=200, keepout=20, rmin=6, rmax=14), ("pair-64x8", "deep3-64x8")),
+    (W.periodic_box(70, 5, 0.7, gx=2e-6, shapes=[W.circle(30, 2, 1.5)]), ("pair-64x8", "deep3-64x8"))],
+    ids=["2048x1024", "1024x512", "520x200", "70x5-periodic"])
+def test_fused_shapes_agree_bitwise(gpu, lat, shapes):
+    """Every fused multi-step shape gives the one-step kernel's bits after 101
+    steps and after a report step: two-step 64 x 4 tiles with streaming stores and
+    four-step 64 x 8 tiles on a 2048 x 1024 Zou-He lattice (151 MB of populations,
+    above the 128 MiB cache-residency threshold); two-step 64 x 8 and three-step
+    64 x 16 tiles on 1024 x 512; three-step 64 x 8 tiles on a 520 x 200 lattice
+    (ragged tiles in x and y) and on a forced periodic 70 x 5 box, whose
+    two-node ring wraps around the 5 rows more than once."""
+    one = gpu_lattice(gpu, lat, 1)
+    fused = [gpu_lattice(gpu, lat, k) for k in (3, 4)]
+    assert tuple(G.step_kernel().split("/")[0] for G in fused) == shapes
+    for G in [one] + fused:
+        G.step(101)
+    ref = np_(one.populations())
+    for G in fused:
+        assert np.array_equal(np_(G.populations()), ref), (lat.name, G.step_kernel())
+    reps = [G.step(5, report=True) for G in [one] + fused]
+    ref = np_(one.populations())
+    for G, rp in zip(fused, reps[1:]):
+        assert np.array_equal(np_(G.populations()), ref), (lat.name, G.step_kernel())
+        assert rp["residual"] == reps[0]["residual"] and rp["mass"] == reps[0]["mass"]
 
 
 def test_large_lattice_quad_kernel_sampled_parity(gpu):
