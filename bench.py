@@ -294,7 +294,7 @@ def bench_batch(out, steps=20000, trt_lambda=0.0, key="batch"):
         t = B.trajectory(i)
         m = t.macros()
         nonfinite += int(t.check_fields(m[0], m[1], m[2])["nonfinite"] > 0)
-    per_launch = 2 if " pair" in B.choice else 1
+    per_launch = steps_per_launch(B.choice.split()[1].split("+")[0])   # "tuned deep4+nt ..."
     ach = bytes_step * steps / per_launch / (ms * 1e-3) / 1e9
     eq = bytes_step * steps / (ms * 1e-3) / 1e9
     out[key] = {"collision": f"TRT lambda {trt_lambda:g}" if trt_lambda > 0 else "BGK",

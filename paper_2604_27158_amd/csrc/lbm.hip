@@ -852,23 +852,23 @@ __global__ __launch_bounds__(256) void k_bgk_batch(const StepArgs* __restrict__ 
     }
 }
 
-// Batched two-step launch: the two-step tile routine over the trajectory-major
-// tile table (its 64 x TY tiles are the one-node kernel's).
-template <bool NT, typename R>
-__global__ __launch_bounds__(256) void k_bgk_batch2(const StepArgs* __restrict__ args,
-                                                    const BatchTile* __restrict__ tiles) {
-    __shared__ float P[9 * Ring<2, TY>::LN(0)];
+// Batched fused launch: the S-step tile routine over a trajectory-major table of
+// 64 x RY tiles (for S = 2 the one-node kernel's 64 x TY table).
+template <int S, int RY, bool NT, typename R>
+__global__ __launch_bounds__(TX * RY) void k_bgk_batchm(const StepArgs* __restrict__ args,
+                                                        const BatchTile* __restrict__ tiles) {
+    __shared__ float P[9 * Ring<S, RY>::LN(0)];
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const BatchTile t = tiles[b];
     const StepArgs a = args[t.traj];
     const bool zh = a.g.bc_x == LBM_BC_ZOUHE;
     const bool force = a.gx != 0.0 || a.gy != 0.0;
     if (zh) {
-        if (force) step_multi<2, TY, true, true, NT, R>(a, t.bx, t.by, P);
-        else step_multi<2, TY, true, false, NT, R>(a, t.bx, t.by, P);
+        if (force) step_multi<S, RY, true, true, NT, R>(a, t.bx, t.by, P);
+        else step_multi<S, RY, true, false, NT, R>(a, t.bx, t.by, P);
     } else {
-        if (force) step_multi<2, TY, false, true, NT, R>(a, t.bx, t.by, P);
-        else step_multi<2, TY, false, false, NT, R>(a, t.bx, t.by, P);
+        if (force) step_multi<S, RY, false, true, NT, R>(a, t.bx, t.by, P);
+        else step_multi<S, RY, false, false, NT, R>(a, t.bx, t.by, P);
     }
 }
 
@@ -1695,11 +1695,13 @@ struct lbm_batch {
     BatchTile* d_tiles = nullptr;
     int ntiles = 0;
     bool quad = false, nt = false;
-    bool pair = false;      // two steps per launch (k_bgk_batch2 on the one-node tiles)
+    int spl = 1;            // steps per launch: 2 pair (one-node tiles), 3 or 4 deep (64 x 8 tiles)
+    BatchTile* d_mtiles = nullptr;   // 64 x 8 tile table of the deep shapes
+    int nmtiles = 0;
     bool trt = false;       // every trajectory uses the TRT collision
     int parity = 0;
     int64_t steps = 0;
-    int chunk = 32;
+    int chunk = 32;         // graph chunk: an even number of launches
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     std::string choice;
 };
@@ -1711,6 +1713,7 @@ static void batch_release(lbm_batch* b) {
         if (b->d_args[k]) (void)hipFree(b->d_args[k]);
     }
     if (b->d_tiles) (void)hipFree(b->d_tiles);
+    if (b->d_mtiles) (void)hipFree(b->d_mtiles);
     for (lbm_ctx* c : b->ctx) release(c);
     delete b;
 }
@@ -1735,31 +1738,44 @@ static StepArgs step_args_for(const lbm_ctx* c, int parity) {
 
 // Tile table for one kernel shape: trajectory-major, rows of tiles in order, so
 // that the XCD remap keeps each trajectory's tiles (which share halo rows) together.
-static int build_tiles(lbm_batch* b, bool quad) {
+// Trajectory-major tile table of 64 x rows tiles (four-wide: 256 x rows).
+static int make_tiles(lbm_batch* b, bool quad, int rows, BatchTile** d, int* count) {
     std::vector<BatchTile> t;
     for (int i = 0; i < b->n; ++i) {
         const lbm_ctx* c = b->ctx[i];
         const int gx = quad ? c->gridx4 : c->g.gridx;
-        const int gy = (c->g.ny + TY - 1) / TY;
+        const int gy = (c->g.ny + rows - 1) / rows;
         for (int y = 0; y < gy; ++y)
             for (int x = 0; x < gx; ++x) t.push_back(BatchTile{i, x, y, 0});
     }
-    if (b->d_tiles) (void)hipFree(b->d_tiles);
-    b->d_tiles = nullptr;
-    LBM_HIP(hipMalloc(&b->d_tiles, t.size() * sizeof(BatchTile)));
-    LBM_HIP(hipMemcpy(b->d_tiles, t.data(), t.size() * sizeof(BatchTile), hipMemcpyHostToDevice));
-    b->ntiles = (int)t.size();
-    b->quad = quad;
+    if (*d) (void)hipFree(*d);
+    *d = nullptr;
+    LBM_HIP(hipMalloc(d, t.size() * sizeof(BatchTile)));
+    LBM_HIP(hipMemcpy(*d, t.data(), t.size() * sizeof(BatchTile), hipMemcpyHostToDevice));
+    *count = (int)t.size();
     return LBM_OK;
 }
 
-template <typename R>
-static void launch_batch2_r(lbm_batch* b, int parity) {
-    dim3 blk(TX, TY), grd(b->ntiles);
-    if (b->nt) k_bgk_batch2<true, R><<<grd, blk, 0, b->stream>>>(b->d_args[parity], b->d_tiles);
-    else k_bgk_batch2<false, R><<<grd, blk, 0, b->stream>>>(b->d_args[parity], b->d_tiles);
+static int build_tiles(lbm_batch* b, bool quad) {
+    b->quad = quad;
+    int rc = make_tiles(b, quad, TY, &b->d_tiles, &b->ntiles);
+    if (rc || b->spl < 3) return rc;
+    return make_tiles(b, false, 8, &b->d_mtiles, &b->nmtiles);
 }
 
+template <int S, int RY, typename R>
+static void launch_batchm_s(lbm_batch* b, int parity, const BatchTile* tiles, int ntiles) {
+    dim3 blk(TX, RY), grd(ntiles);
+    if (b->nt) k_bgk_batchm<S, RY, true, R><<<grd, blk, 0, b->stream>>>(b->d_args[parity], tiles);
+    else k_bgk_batchm<S, RY, false, R><<<grd, blk, 0, b->stream>>>(b->d_args[parity], tiles);
+}
+template <typename R>
+static void launch_batch2_r(lbm_batch* b, int parity) {
+    if (b->spl == 2) launch_batchm_s<2, TY, R>(b, parity, b->d_tiles, b->ntiles);
+    else if (b->spl == 3) launch_batchm_s<3, 8, R>(b, parity, b->d_mtiles, b->nmtiles);
+    else launch_batchm_s<4, 8, R>(b, parity, b->d_mtiles, b->nmtiles);
+}
+// One fused launch of b->spl steps.
 static void launch_batch2(lbm_batch* b, int parity) {
     if (b->trt) launch_batch2_r<LeanTRT>(b, parity);
     else launch_batch2_r<Lean>(b, parity);
@@ -1839,11 +1855,17 @@ static void cache_store(const char* path, const std::string& key, int shape, boo
 }
 
 // Kernel shapes of a batch: 0 one node per lane, 1 four nodes per lane, 2 two steps
-// per launch (on the one-node tiles).
-static const char* shape_name(int shape) { return shape == 1 ? "quad" : shape == 2 ? "pair" : "node"; }
+// per launch (on the one-node tiles), 3 and 4 three and four steps per launch (on
+// 64 x 8 tiles).
+static const int kBatchShapes = 5;
+static const char* shape_name(int shape) {
+    static const char* const names[kBatchShapes] = {"node", "quad", "pair", "deep3", "deep4"};
+    return names[shape];
+}
 
 static int set_shape(lbm_batch* b, int shape) {
-    b->pair = shape == 2;
+    b->spl = shape >= 2 ? shape : 1;
+    b->chunk = b->spl == 3 ? 30 : 32;
     return build_tiles(b, shape == 1);
 }
 
@@ -1851,7 +1873,7 @@ static int autotune(lbm_batch* b, bool quad_ok, const char* cache) {
     const std::string key = batch_key(b);
     int q = 0;
     bool t = false;
-    if (cache_lookup(cache, key, &q, &t) && q >= 0 && q <= 2 && (quad_ok || q != 1)) {
+    if (cache_lookup(cache, key, &q, &t) && q >= 0 && q < kBatchShapes && (quad_ok || q != 1)) {
         b->nt = t;
         int rc = set_shape(b, q);
         if (rc) return rc;
@@ -1864,25 +1886,25 @@ static int autotune(lbm_batch* b, bool quad_ok, const char* cache) {
     hipEvent_t e0, e1;
     LBM_HIP(hipEventCreate(&e0));
     LBM_HIP(hipEventCreate(&e1));
-    for (int qi = 2; qi >= 0; --qi) {
+    for (int qi = kBatchShapes - 1; qi >= 0; --qi) {
         if (qi == 1 && !quad_ok) continue;
         int rc = set_shape(b, qi);
         if (rc) return rc;
         for (int ti = 0; ti < 2; ++ti) {
             b->nt = ti != 0;
-            // 16 timed launches (32 steps for the two-step shape), after an even warm-up
+            // 16 timed launches (16 x spl steps), after an even warm-up
             for (int k = 0; k < 4; ++k) {
-                if (b->pair) launch_batch2(b, k & 1); else launch_batch(b, k & 1);
+                if (b->spl > 1) launch_batch2(b, k & 1); else launch_batch(b, k & 1);
             }
             LBM_HIP(hipEventRecord(e0, b->stream));
             for (int k = 0; k < 16; ++k) {
-                if (b->pair) launch_batch2(b, k & 1); else launch_batch(b, k & 1);
+                if (b->spl > 1) launch_batch2(b, k & 1); else launch_batch(b, k & 1);
             }
             LBM_HIP(hipEventRecord(e1, b->stream));
             LBM_HIP(hipEventSynchronize(e1));
             float ms = 0.0f;
             LBM_HIP(hipEventElapsedTime(&ms, e0, e1));
-            ms /= b->pair ? 32.0f : 16.0f;   // per lattice step
+            ms /= 16.0f * b->spl;   // per lattice step
             if (ms < best) { best = ms; bq = qi; bt = b->nt; }
         }
     }
@@ -1954,8 +1976,8 @@ static int batch_build_graph(lbm_batch* b) {
     const int start = b->parity;
     hipGraph_t g = nullptr;
     LBM_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-    if (b->pair) {
-        for (int k = 0; k < b->chunk / 2; ++k) launch_batch2(b, start ^ (k & 1));
+    if (b->spl > 1) {
+        for (int k = 0; k < b->chunk / b->spl; ++k) launch_batch2(b, start ^ (k & 1));
     } else {
         for (int k = 0; k < b->chunk; ++k) launch_batch(b, start ^ (k & 1));
     }
@@ -1987,8 +2009,8 @@ extern "C" int lbm_batch_step(lbm_batch* b, int32_t n) {
             left -= b->chunk;  // an even number of parity flips
         }
     }
-    if (b->pair) {
-        for (; left >= 2; left -= 2) {
+    if (b->spl > 1) {
+        for (; left >= b->spl; left -= b->spl) {
             launch_batch2(b, b->parity);
             b->parity ^= 1;
         }

@@ -113,6 +113,40 @@ def test_tuner_cache_roundtrip(gpu, tmp_path):
     assert a.choice.split()[1] == b.choice.split()[1]
 
 
+@pytest.mark.parametrize("shape", ["node", "pair", "deep3", "deep4"])
+@pytest.mark.parametrize("nt", [0, 1])
+def test_every_batch_shape_equals_single_lattices(gpu, tmp_path, shape, nt):
+    """Each kernel shape the tuner can pick (forced through its cache file: one node
+    per lane, two steps per launch on the one-node tiles, three and four steps per
+    launch on 64 x 8 tiles), with and without streaming stores, gives the bits of
+    the lattices stepped alone: uneven ellipse flows, a forced walled channel and a
+    ragged 300 x 100 Zou-He porous lattice, 133 steps (graph chunks, fused launches
+    and single-step tails)."""
+    names = ["node", "quad", "pair", "deep3", "deep4"]
+    cache = tmp_path / "tune.txt"
+    lats = [W.ellipse_flow(s) for s in range(3)] + [W.channel_walls_circles(1),
+                                                   W.porous_circles(2, nx=300, ny=100, rmin=4, rmax=8, keepout=10)]
+    first = gpu.Batch(lats, tune_cache=str(cache))
+    key = cache.read_text().split()[0]
+    first.close()
+    cache.write_text(f"{key} {names.index(shape)} {nt}\n")
+    B = gpu.Batch(lats, tune_cache=str(cache))
+    assert B.choice == f"cached {shape}" + ("+nt" if nt else ""), B.choice
+    for i, lat in enumerate(lats):
+        if lat.name.startswith("ellipses"):
+            plug(B.trajectory(i), lat)
+    B.step(133)
+    for i, lat in enumerate(lats):
+        G = gpu.Lattice.from_workload(lat)
+        if lat.name.startswith("ellipses"):
+            plug(G, lat)
+        G.step(133)
+        assert np.array_equal(B.trajectory(i).populations().cpu().numpy(), G.populations().cpu().numpy()), \
+            (shape, nt, lat.name)
+        G.close()
+    B.close()
+
+
 def test_batch_detects_trajectory_stepped_alone(gpu):
     lats = [W.ellipse_flow(s) for s in range(2)]
     B = gpu.Batch(lats)
