@@ -199,6 +199,14 @@ typedef struct lbm_field_stats {
 int lbm_check_fields(lbm_ctx* ctx, const float* d_rho, const float* d_ux, const float* d_uy,
                      lbm_field_stats* out);
 
+/* lbm_check_fields without the wait, for a guard resolved later (the hybrid's
+ * speculative cycle, Sec. 2.3): writes mass (sum rho), max |u| and the non-finite
+ * node count, as doubles, then 0, to d_stats[0..3] (device memory owned by the
+ * caller, 4 doubles), asynchronously on ctx's stream.  Calls on one ctx share its
+ * reduction scratch and are ordered by the stream. */
+int lbm_check_fields_async(lbm_ctx* ctx, const float* d_rho, const float* d_ux, const float* d_uy,
+                           double* d_stats);
+
 /* Distance of macroscopic fields from a reference over the fluid nodes of ctx's
  * mask (the convergence measures of the porous steady-state study, Sec. 3.1):
  * relative L1 norms sum|a - ref| / sum|ref| of rho, ux and uy, and the pressure

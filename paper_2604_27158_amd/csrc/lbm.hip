@@ -1614,10 +1614,10 @@ extern "C" int lbm_get_populations(lbm_ctx* c, float* d_f) {
     return launch_macro(c, nullptr, nullptr, nullptr, 0, d_f, false);
 }
 
-extern "C" int lbm_check_fields(lbm_ctx* c, const float* d_rho, const float* d_ux,
-                                const float* d_uy, lbm_field_stats* out) {
-    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
-    if (!d_rho || !d_ux || !d_uy || !out) return fail(LBM_EINVAL, "NULL argument");
+// Field statistics [mass, max |u|, non-finite count, 0] into d_out (device, 4
+// doubles), asynchronously on ctx's stream.
+static int launch_field_stats(lbm_ctx* c, const float* d_rho, const float* d_ux, const float* d_uy,
+                              double* d_out) {
     const int N = c->g.N;
     const int nb = (N + 255) / 256;
     if (nb > c->nblocks) {
@@ -1625,8 +1625,24 @@ extern "C" int lbm_check_fields(lbm_ctx* c, const float* d_rho, const float* d_u
         return fail(LBM_EINVAL, "internal: partial buffer too small");
     }
     k_field_stats<<<nb, 256, 0, c->stream>>>(c->d_mask, N, d_rho, d_ux, d_uy, c->d_partials);
-    k_field_stats_final<<<1, 256, 0, c->stream>>>(c->d_partials, nb, c->d_out);
+    k_field_stats_final<<<1, 256, 0, c->stream>>>(c->d_partials, nb, d_out);
     LBM_HIP(hipGetLastError());
+    return LBM_OK;
+}
+
+extern "C" int lbm_check_fields_async(lbm_ctx* c, const float* d_rho, const float* d_ux,
+                                      const float* d_uy, double* d_stats) {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (!d_rho || !d_ux || !d_uy || !d_stats) return fail(LBM_EINVAL, "NULL argument");
+    return launch_field_stats(c, d_rho, d_ux, d_uy, d_stats);
+}
+
+extern "C" int lbm_check_fields(lbm_ctx* c, const float* d_rho, const float* d_ux,
+                                const float* d_uy, lbm_field_stats* out) {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (!d_rho || !d_ux || !d_uy || !out) return fail(LBM_EINVAL, "NULL argument");
+    int rc = launch_field_stats(c, d_rho, d_ux, d_uy, c->d_out);
+    if (rc) return rc;
     LBM_HIP(hipMemcpyAsync(c->h_out, c->d_out, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     LBM_HIP(hipStreamSynchronize(c->stream));
     out->mass = c->h_out[0];

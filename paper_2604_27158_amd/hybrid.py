@@ -70,10 +70,18 @@ class HybridRunner:
     """Unsteady super-time-stepping on one lattice with one FNO bound to its grid.
 
     lattice: lbmfno.Lattice (nx = W, ny = H of the FNO); fno: fno.Fno with cin = 4
-    inputs (rho, ux, uy, mask) and cout = 3 outputs (rho, ux, uy)."""
+    inputs (rho, ux, uy, mask) and cout = 3 outputs (rho, ux, uy).
+
+    speculative=True takes the guard off the host's critical path: a cycle hands the
+    prediction to the lattice at once, after saving the lattice state and queueing
+    the guard's statistics into pinned host memory behind the FNO calls; the guard is
+    resolved at the start of the next cycle (or by finish()), when those statistics
+    have long been ready, and a rejected cycle is undone (state restored) and redone
+    with lattice steps.  The states and the log equal those of the synchronous guard;
+    the host no longer waits for the GPU twice per cycle."""
 
     def __init__(self, lattice, fno, dt_fno: int = 100, k_fno: int = 5, n_lbm: int = 200,
-                 guard: Optional[Guard] = None):
+                 guard: Optional[Guard] = None, speculative: bool = False):
         import torch
         if fno.spec.cin != 4 or fno.spec.cout != 3:
             raise ValueError("the hybrid FNO maps (rho, ux, uy, mask) -> (rho, ux, uy)")
@@ -88,6 +96,15 @@ class HybridRunner:
             self.maskf = lattice.mask.to(torch.float32)
         self.model_time = 0          # lattice-step units advanced so far
         self.log = CycleLog()
+        self.speculative = bool(speculative)
+        self._pending = None         # model time of a cycle whose guard is unresolved
+        if self.speculative:
+            with torch.cuda.stream(lattice.stream):
+                self._saved = torch.empty(int(lattice.lib.lbm_state_elems(lattice.ctx)),
+                                          dtype=torch.float32, device="cuda")
+                self._dstats = torch.empty(8, dtype=torch.float64, device="cuda")
+            self._hstats = torch.empty(8, dtype=torch.float64, pin_memory=True)
+            self._ready = torch.cuda.Event()
 
     def _fno_rollout(self, macros):
         """K chained FNO calls from the lattice's current macroscopic fields."""
@@ -109,6 +126,9 @@ class HybridRunner:
             self._cycle()
 
     def _cycle(self):
+        if self.speculative:
+            self._cycle_speculative()
+            return
         macros = self.lat.macros()
         ref = self.lat.check_fields(macros[0], macros[1], macros[2])
         pred = self._fno_rollout(macros)
@@ -125,12 +145,56 @@ class HybridRunner:
         self.log.lbm_steps += self.n_lbm
         self.model_time += self.k_fno * self.dt_fno + self.n_lbm
 
+    def _cycle_speculative(self):
+        import torch
+        self._resolve()
+        lat = self.lat
+        lat.save_state(out=self._saved)
+        macros = lat.macros()
+        lat.check_fields_async(macros[0], macros[1], macros[2], self._dstats[0:4])
+        pred = self._fno_rollout(macros)
+        lat.check_fields_async(pred[0], pred[1], pred[2], self._dstats[4:8])
+        with torch.cuda.stream(lat.stream):
+            self._hstats.copy_(self._dstats, non_blocking=True)
+            self._ready.record(lat.stream)
+        lat.reinit(pred[0], pred[1], pred[2])
+        lat.step(self.n_lbm)
+        self._pending = self.model_time
+        self.log.fno_calls += self.k_fno
+        self.log.lbm_steps += self.n_lbm
+        self.model_time += self.k_fno * self.dt_fno + self.n_lbm
+
+    def _resolve(self):
+        """Apply the guard to the last speculative cycle; undo and redo it with
+        lattice steps when the prediction is rejected."""
+        if self._pending is None:
+            return
+        self._ready.synchronize()
+        h = self._hstats.tolist()
+        stats = {"mass": h[4], "max_speed": h[5], "nonfinite": int(h[6])}
+        ok, why = self.guard.accept(stats, h[0])
+        if not ok:
+            self.lat.load_state(self._saved)
+            self.lat.step(self.k_fno * self.dt_fno + self.n_lbm)
+            self.log.fno_calls -= self.k_fno
+            self.log.lbm_steps += self.k_fno * self.dt_fno
+            self.log.fallbacks.append(f"t={self._pending}: {why}")
+        self._pending = None
+
+    def finish(self):
+        """Resolve the last speculative cycle (a no-op for the synchronous guard)."""
+        import torch
+        with torch.cuda.stream(self.lat.stream):
+            self._resolve()
+        return self.log
+
     def run(self, cycles: int, on_cycle=None):
         for c in range(cycles):
             self.cycle()
             if on_cycle is not None:
+                self.finish()     # the callback sees the guarded state
                 on_cycle(c, self)
-        return self.log
+        return self.finish()
 
 
 def time_call(fn, stream, reps: int = 1):

@@ -97,6 +97,7 @@ SIGNATURES = [
     ("lbm_stream_copy", ctypes.c_int, [_p, _p, ctypes.c_size_t, _p]),
     ("lbm_step_kernel", ctypes.c_char_p, [_p]),
     ("lbm_check_fields", ctypes.c_int, [_p, _p, _p, _p, ctypes.POINTER(FieldStats)]),
+    ("lbm_check_fields_async", ctypes.c_int, [_p, _p, _p, _p, _p]),
     ("lbm_compare_fields", ctypes.c_int, [_p, _p, _p, _p, _p, _p, _p, ctypes.POINTER(FieldError)]),
     ("lbm_adjoint_step", ctypes.c_int, [_p, _p, _p, _p]),
     ("lbm_state_elems", ctypes.c_size_t, [_p]),
@@ -346,6 +347,16 @@ class Lattice:
                                         ctypes.byref(st)), "lbm_check_fields")
         return st.as_dict()
 
+    def check_fields_async(self, rho, ux, uy, out):
+        """lbm_check_fields without the wait: [mass, max |u|, non-finite count, 0] as
+        float64 into the device tensor `out` (4 elements), on the lattice stream."""
+        import torch
+        if out.dtype != torch.float64 or out.numel() < 4 or not out.is_cuda or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float64 device tensor of 4 elements")
+        self._take_inputs(rho, ux, uy, out)
+        check(self.lib.lbm_check_fields_async(self.ctx, rho.data_ptr(), ux.data_ptr(), uy.data_ptr(),
+                                              out.data_ptr()), "lbm_check_fields_async")
+
     def compare(self, fields, ref):
         """lbm_compare_fields of [3][ny][nx] (rho - 1, ux, uy) device tensors."""
         fields, ref = fields.contiguous(), ref.contiguous()
@@ -356,11 +367,17 @@ class Lattice:
                                           ref[2].data_ptr(), ctypes.byref(e)), "lbm_compare_fields")
         return e.as_dict()
 
-    def save_state(self):
-        """Exact copy of the current store (a device tensor)."""
+    def save_state(self, out=None):
+        """Exact copy of the current store (a device tensor; into `out` when given)."""
         import torch
-        with torch.cuda.stream(self.stream):
-            out = torch.empty(int(self.lib.lbm_state_elems(self.ctx)), dtype=torch.float32, device="cuda")
+        n = int(self.lib.lbm_state_elems(self.ctx))
+        if out is None:
+            with torch.cuda.stream(self.stream):
+                out = torch.empty(n, dtype=torch.float32, device="cuda")
+        elif out.dtype != torch.float32 or out.numel() != n or not out.is_cuda or not out.is_contiguous():
+            raise ValueError(f"out must be a contiguous float32 device tensor of {n} elements")
+        else:
+            self._take_inputs(out)
         check(self.lib.lbm_save_state(self.ctx, out.data_ptr()), "lbm_save_state")
         self._hand_over(out)
         return out

@@ -78,6 +78,7 @@ def test_null_arguments(lib):
     assert lib.lbm_get_macro(None, 1, 2, 3, 0) == -1
     assert lib.lbm_reinit_from_macro(None, 1, 2, 3) == -1
     assert lib.lbm_reinit_from_macro_neq(None, 1, 2, 3) == -1
+    assert lib.lbm_check_fields_async(None, 1, 2, 3, 4) == -1
 
 
 def test_raster_validation(lib):

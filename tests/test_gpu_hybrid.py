@@ -68,3 +68,35 @@ def test_guard_falls_back_to_plain_lattice(gpu):
     P.reinit(*(torch.from_numpy(a) for a in W.plug_flow(lat)))
     P.step(250)
     assert np.array_equal(G.populations().cpu().numpy(), P.populations().cpu().numpy())
+
+
+@pytest.mark.parametrize("scale,fallbacks", [(0.05, 0), (1e30, 3)])
+def test_speculative_guard_equals_synchronous(gpu, scale, fallbacks):
+    """The speculative runner (guard resolved one cycle later from pinned memory,
+    rejected cycles undone and redone with lattice steps) leaves the same lattice
+    bits and the same log as the synchronous guard: predictions accepted (a damped
+    random model) and every one rejected (outputs overflow), 3 cycles each."""
+    from paper_2604_27158_amd import hybrid as H
+    lat, A, f = make(gpu, scale=scale)
+    _, B, _ = make(gpu, scale=scale)
+    guard = H.Guard(max_speed=0.35, mass_rel_tol=0.05)
+    ra = H.HybridRunner(A, f, dt_fno=100, k_fno=2, n_lbm=60, guard=guard)
+    rb = H.HybridRunner(B, f, dt_fno=100, k_fno=2, n_lbm=60, guard=guard, speculative=True)
+    la, lb = ra.run(3), rb.run(3)
+    assert len(la.fallbacks) == fallbacks
+    assert (la.fno_calls, la.lbm_steps, la.fallbacks) == (lb.fno_calls, lb.lbm_steps, lb.fallbacks)
+    assert ra.model_time == rb.model_time
+    assert np.array_equal(A.populations().cpu().numpy(), B.populations().cpu().numpy())
+
+
+def test_check_fields_async_matches_synchronous(gpu):
+    import torch
+    lat, G, _ = make(gpu)
+    G.step(30)
+    m = G.macros()
+    st = G.check_fields(m[0], m[1], m[2])
+    out = torch.full((4,), -1.0, dtype=torch.float64, device="cuda")
+    G.check_fields_async(m[0], m[1], m[2], out)
+    G.synchronize()
+    h = out.cpu().tolist()
+    assert h[0] == st["mass"] and h[1] == st["max_speed"] and int(h[2]) == st["nonfinite"] and h[3] == 0.0
