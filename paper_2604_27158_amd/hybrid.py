@@ -94,6 +94,7 @@ class HybridRunner:
             self.x = torch.empty((1, 4, lattice.ny, lattice.nx), dtype=torch.float32, device="cuda")
             self.y = torch.empty((1, 3, lattice.ny, lattice.nx), dtype=torch.float32, device="cuda")
             self.maskf = lattice.mask.to(torch.float32)
+            self.x[0, 3].copy_(self.maskf)   # the mask channel never changes
         self.model_time = 0          # lattice-step units advanced so far
         self.log = CycleLog()
         self.speculative = bool(speculative)
@@ -110,8 +111,8 @@ class HybridRunner:
         """K chained FNO calls from the lattice's current macroscopic fields."""
         import torch
         with torch.cuda.stream(self.lat.stream):
-            self.x[0, :3].copy_(macros)
-            self.x[0, 3].copy_(self.maskf)
+            if macros.data_ptr() != self.x.data_ptr():
+                self.x[0, :3].copy_(macros)
             for k in range(self.k_fno):
                 self.fno.forward(self.x, out=self.y, stream=self.lat.stream, graph=True)
                 if k + 1 < self.k_fno:
@@ -150,7 +151,7 @@ class HybridRunner:
         self._resolve()
         lat = self.lat
         lat.save_state(out=self._saved)
-        macros = lat.macros()
+        macros = lat.macros(out=self.x[0, :3])   # straight into the FNO input
         lat.check_fields_async(macros[0], macros[1], macros[2], self._dstats[0:4])
         pred = self._fno_rollout(macros)
         lat.check_fields_async(pred[0], pred[1], pred[2], self._dstats[4:8])
