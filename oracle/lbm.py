@@ -44,6 +44,8 @@ def lib():
         L.oracle_sums.argtypes = [_i, _i, _p, _p, _p, _p, _p, _p]
         L.oracle_adjoint_step.argtypes = [_i, _i, _d, _d, _d, _i, _i, _d, _d, _p, _p, _p, _p]
         L.oracle_adjoint_step.restype = _i
+        L.oracle_adjoint_step_trt.argtypes = [_i, _i, _d, _d, _d, _d, _i, _i, _d, _d, _p, _p, _p, _p]
+        L.oracle_adjoint_step_trt.restype = _i
         L.oracle_bc_vjp.argtypes = [_i, _i, _i, _d, _d, _p, _p]
         L.oracle_bc_vjp.restype = None
         L.oracle_feq_vjp.argtypes = [_i, _i, _p, _p, _p, _p, _p, _p, _p, _p]
@@ -174,11 +176,18 @@ def sums(mask, rho, rho_prev, ux, uy):
 
 
 def adjoint_step(lat, mask, f_n, lam_np1):
-    """lam_n = C'(f(n))^T P^T Z'^T lam_{n+1} (Z: Zou-He closures, identity otherwise)."""
+    """lam_n = C'(f(n))^T P^T Z'^T lam_{n+1} (Z: Zou-He closures, identity otherwise);
+    C is the TRT collision when lat.trt_lambda > 0, else BGK."""
     f_n = _f64(f_n); lam_np1 = _f64(lam_np1); out = np.zeros_like(f_n)
-    rc = lib().oracle_adjoint_step(lat.nx, lat.ny, lat.tau, lat.gx, lat.gy, lat.bc_x, lat.bc_y,
-                                   lat.u_in, lat.rho_out, _ptr(mask), _ptr(f_n), _ptr(lam_np1),
-                                   _ptr(out))
+    lam = float(getattr(lat, "trt_lambda", 0.0))
+    if lam > 0.0:
+        rc = lib().oracle_adjoint_step_trt(lat.nx, lat.ny, lat.tau, lam, lat.gx, lat.gy, lat.bc_x,
+                                           lat.bc_y, lat.u_in, lat.rho_out, _ptr(mask), _ptr(f_n),
+                                           _ptr(lam_np1), _ptr(out))
+    else:
+        rc = lib().oracle_adjoint_step(lat.nx, lat.ny, lat.tau, lat.gx, lat.gy, lat.bc_x, lat.bc_y,
+                                       lat.u_in, lat.rho_out, _ptr(mask), _ptr(f_n), _ptr(lam_np1),
+                                       _ptr(out))
     if rc != 0:
         raise ValueError("adjoint not defined for this boundary configuration")
     return out

@@ -486,8 +486,8 @@ void oracle_bc_vjp(int nx, int ny, int bc_x, double u_in, double rho_out, const 
  * C'(f(n))^T P^T Z'^T lam_np1, where Z is the Zou-He closure of the boundary columns
  * (identity for periodic and wall boundaries), P the streaming / bounce-back
  * permutation and C' the per-node collision Jacobian. */
-int oracle_adjoint_step(int nx, int ny, double tau, double gx, double gy, int bc_x, int bc_y,
-                        double u_in, double rho_out, const uint8_t* mask, const double* f,
+static int adjoint_step(int nx, int ny, double tau, double lambda, double gx, double gy, int bc_x,
+                        int bc_y, double u_in, double rho_out, const uint8_t* mask, const double* f,
                         const double* lam_in, double* lam_n) {
     if (bc_y == BC_ZOUHE) return -1;
     cfg_t c = make_cfg(nx, ny, tau, gx, gy, bc_x, bc_y, u_in, rho_out);
@@ -536,15 +536,57 @@ int oracle_adjoint_step(int nx, int ny, double tau, double gx, double gy, int bc
                 bx += mu[q] * (om * dfe_dux + dS_dux);
                 by += mu[q] * (om * dfe_duy + dS_duy);
             }
+            double diag[Q];
+            for (int q = 0; q < Q; ++q) diag[q] = (1.0 - om) * mu[q];
+            if (lambda > 0.0) {
+                /* TRT: C = I - (w+ P+ + w- P-)(I - J) + (p+ P+ + p- P-) S', with P+- the
+                 * projections on the parts of a population pair even and odd under
+                 * c -> -c (symmetric), J = d f_eq / d f, S' = d S / d f without the
+                 * relaxation prefactor and p+- = 1 - w+-/2.  So C^T mu = mu - nu +
+                 * J^T nu + S'^T sg with nu = w+ mu+ + w- mu- and sg = p+ mu+ + p- mu-. */
+                const double tau_m = 0.5 + lambda / (tau - 0.5);
+                const double om_m = 1.0 / tau_m, pref_m = 1.0 - 0.5 * om_m;
+                a = bx = by = 0.0;
+                for (int q = 0; q < Q; ++q) {
+                    const double even = 0.5 * (mu[q] + mu[OPP[q]]), odd = 0.5 * (mu[q] - mu[OPP[q]]);
+                    const double nu = om * even + om_m * odd, sg = pref * even + pref_m * odd;
+                    const double cu = CX[q] * ux + CY[q] * uy;
+                    const double cg = CX[q] * gx + CY[q] * gy;
+                    const double dfe_dr = WQ[q] * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+                    const double dfe_dux = WQ[q] * rho * (3.0 * CX[q] + 9.0 * cu * CX[q] - 3.0 * ux);
+                    const double dfe_duy = WQ[q] * rho * (3.0 * CY[q] + 9.0 * cu * CY[q] - 3.0 * uy);
+                    const double ds_dr = WQ[q] * (3.0 * (cg - gdotu) + 9.0 * cu * cg);
+                    const double ds_dux = WQ[q] * rho * (-3.0 * gx + 9.0 * CX[q] * cg);
+                    const double ds_duy = WQ[q] * rho * (-3.0 * gy + 9.0 * CY[q] * cg);
+                    a += nu * dfe_dr + sg * ds_dr;
+                    bx += nu * dfe_dux + sg * ds_dux;
+                    by += nu * dfe_duy + sg * ds_duy;
+                    diag[q] = mu[q] - nu;
+                }
+            }
             /* u = (sum c f)/rho + g/2, so du/df_j = (c_j - u + g/2)/rho. */
             for (int q = 0; q < Q; ++q) {
                 const double dux = (CX[q] - ux + 0.5 * gx) / rho;
                 const double duy = (CY[q] - uy + 0.5 * gy) / rho;
-                lam_n[at(&c, q, j, i)] = (1.0 - om) * mu[q] + a + bx * dux + by * duy;
+                lam_n[at(&c, q, j, i)] = diag[q] + a + bx * dux + by * duy;
             }
         }
     free(lam_np1);
     return 0;
+}
+
+int oracle_adjoint_step(int nx, int ny, double tau, double gx, double gy, int bc_x, int bc_y,
+                        double u_in, double rho_out, const uint8_t* mask, const double* f,
+                        const double* lam_in, double* lam_n) {
+    return adjoint_step(nx, ny, tau, 0.0, gx, gy, bc_x, bc_y, u_in, rho_out, mask, f, lam_in, lam_n);
+}
+
+/* oracle_adjoint_step of the TRT step (magic parameter lambda > 0). */
+int oracle_adjoint_step_trt(int nx, int ny, double tau, double lambda, double gx, double gy, int bc_x,
+                            int bc_y, double u_in, double rho_out, const uint8_t* mask, const double* f,
+                            const double* lam_in, double* lam_n) {
+    if (!(lambda > 0.0)) return -1;
+    return adjoint_step(nx, ny, tau, lambda, gx, gy, bc_x, bc_y, u_in, rho_out, mask, f, lam_in, lam_n);
 }
 
 /* Pull back dL/df(0) through f(0) = f_eq(rho0, u0): per node

@@ -466,3 +466,76 @@ def test_trt_shear_wave_decay_is_linear_operator_eigenvalue(tau, lam):
     mu = ev[np.argmin(np.abs(ev - (1 - nu * k * k)))]
     assert abs(mu.imag) < 1e-12
     assert abs(a1 / a0 - mu.real) < 1e-9
+
+
+# ------------------------------------------------------------- TRT adjoint
+
+def test_trt_adjoint_transpose_identity():
+    """<J v, w> = <v, J^T w> for one TRT step (lambda = 1/4, tau = 0.9, so tau- = 0.875
+    differs from tau) with a body force, walls and an obstacle: J v from central
+    differences of the oracle's forward TRT step."""
+    import dataclasses
+    nx, ny = 12, 10
+    lat = W.Lattice(nx=nx, ny=ny, tau=0.9, gx=1e-5, gy=2e-6, bc_x=W.BC_WALL, bc_y=W.BC_PERIODIC,
+                    shapes=[W.circle(6, 5, 2)], wrap_x=False, wrap_y=True)
+    lat = dataclasses.replace(lat, trt_lambda=0.25)
+    mask = lbm.raster(nx, ny, lat.shapes_array(), False, True)
+    rng = np.random.default_rng(7)
+    s = lbm.Sim(lat, mask).init(*W.random_macro_fields(4, nx, ny))
+    f = s.f.copy()
+    fl = np.repeat((mask == 0)[None], 9, 0)
+    v = rng.standard_normal(f.shape) * fl
+    w = rng.standard_normal(f.shape) * fl
+
+    def step(ff):
+        return lbm.stream(lat, mask, lbm.collide(lat, mask, ff))
+    h = 1e-6
+    Jv = (step(f + h * v) - step(f - h * v)) / (2 * h)
+    JTw = lbm.adjoint_step(lat, mask, f, w)
+    a, b = float(np.sum(Jv * w * fl)), float(np.sum(v * JTw))
+    assert abs(a - b) <= 1e-8 * abs(b)
+    # the BGK adjoint of the same state is a different map (the pin would catch a
+    # TRT adjoint that ignored lambda)
+    bgk = lbm.adjoint_step(dataclasses.replace(lat, trt_lambda=0.0), mask, f, w)
+    assert abs(float(np.sum(v * bgk)) - b) > 1e-6 * abs(b)
+
+
+@pytest.mark.parametrize("lam", [0.25, 3.0 / 16])
+def test_trt_adjoint_rollout_matches_central_finite_differences(lam):
+    """TRT rollout gradient through Zou-He columns (24x12 lattice with an obstacle, 25
+    steps) and on a forced walled channel (32x16, 20 steps) vs FP64 central
+    differences along random directions."""
+    import dataclasses
+    lats = [zouhe_lattice(),
+            W.Lattice(nx=32, ny=16, tau=0.75, gx=3e-6, bc_x=W.BC_PERIODIC, bc_y=W.BC_WALL,
+                      shapes=[W.circle(10, 8, 3)], wrap_x=True, wrap_y=False)]
+    for lat, n, seed in zip(lats, (25, 20), (31, 41)):
+        lat = dataclasses.replace(lat, trt_lambda=lam)
+        mask = lbm.raster(lat.nx, lat.ny, lat.shapes_array(), lat.wrap_x, lat.wrap_y)
+        rho0, ux0, uy0 = W.random_macro_fields(seed, lat.nx, lat.ny, amp_rho=0.02, amp_u=0.03)
+        tgt = W.random_macro_fields(seed + 1, lat.nx, lat.ny)
+        g = lbm.rollout_grad(lat, mask, rho0, ux0, uy0, n, tgt)
+        rng = np.random.default_rng(seed)
+        h = 1e-6
+        for _ in range(2):
+            d = [rng.standard_normal((lat.ny, lat.nx)) * (mask == 0) for _ in range(3)]
+            lp = lbm.rollout_loss(lat, mask, rho0 + h * d[0], ux0 + h * d[1], uy0 + h * d[2], n, tgt)
+            lm = lbm.rollout_loss(lat, mask, rho0 - h * d[0], ux0 - h * d[1], uy0 - h * d[2], n, tgt)
+            fd = (lp - lm) / (2 * h)
+            an = sum(float(np.sum(a * b)) for a, b in zip(g, d))
+            assert abs(fd - an) <= 1e-7 * abs(an), (lat.name, fd, an)
+
+
+def test_trt_adjoint_with_equal_times_is_the_bgk_adjoint():
+    """lambda = (tau - 1/2)^2 gives tau- = tau: the TRT adjoint is then the BGK adjoint
+    (to rounding)."""
+    import dataclasses
+    nx, ny = 16, 12
+    lat = W.Lattice(nx=nx, ny=ny, tau=0.8, gx=2e-6, bc_x=W.BC_PERIODIC, bc_y=W.BC_WALL,
+                    shapes=[W.circle(8, 6, 2)], wrap_x=True, wrap_y=False)
+    mask = lbm.raster(nx, ny, lat.shapes_array(), True, False)
+    s = lbm.Sim(lat, mask).init(*W.random_macro_fields(9, nx, ny))
+    w = np.random.default_rng(3).standard_normal(s.f.shape) * np.repeat((mask == 0)[None], 9, 0)
+    a = lbm.adjoint_step(lat, mask, s.f, w)
+    b = lbm.adjoint_step(dataclasses.replace(lat, trt_lambda=0.3 ** 2), mask, s.f, w)
+    assert np.max(np.abs(a - b)) <= 1e-14 * np.max(np.abs(a))
