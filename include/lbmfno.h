@@ -104,7 +104,7 @@ typedef struct lbm_config {
                            with tau- from lambda = (tau - 1/2)(tau- - 1/2) (1/4: the
                            stability-optimal choice, 3/16: walls exactly halfway for
                            Poiseuille flow).  LBM_ARITH_LEAN only; a batch is all BGK or
-                           all TRT; lbm_adjoint_step covers BGK only. */
+                           all TRT; lbm_adjoint_step differentiates either collision. */
 } lbm_config;
 
 /* Diagnostics of the state at time n (FP64 accumulation over fluid nodes). */
@@ -265,7 +265,11 @@ int lbm_info(const lbm_ctx* ctx, int64_t* fluid_nodes, int64_t* steps_done);
 /* lam_n = C'(f(n))^T P^T Z'^T lam_{n+1}: Z'^T is the transposed Jacobian of the
  * Zou-He closures (the unknown populations' adjoints move onto the known populations
  * they are formed from), P^T the inverse of the streaming / bounce-back permutation,
- * C' the per-node collision Jacobian (with the Guo term).
+ * C' the per-node collision Jacobian (with the Guo term): for BGK
+ * (1 - 1/tau) I + (1/tau) J + (1 - 1/(2 tau)) S', for TRT (trt_lambda > 0)
+ * I - (P+/tau + P-/tau-)(I - J) + ((1 - 1/(2 tau)) P+ + (1 - 1/(2 tau-)) P-) S', with
+ * J = d f_eq / d f, S' the Guo source's derivative without its prefactor and P+-
+ * the projections on the parts of a population pair even and odd under c -> -c.
  * d_lam_np1 and d_lam_n must differ.  Asynchronous on ctx's stream. */
 int lbm_adjoint_step(lbm_ctx* ctx, const float* d_f_n, const float* d_lam_np1, float* d_lam_n);
 

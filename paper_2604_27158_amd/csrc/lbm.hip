@@ -2074,6 +2074,7 @@ struct AdjArgs {
     const uint8_t* __restrict__ mask;
     LatticeGeom g;
     double omega, guo, gx, gy, u_in, rho_out;
+    double omega_m, guo_m;            // TRT: 1 / tau-, 1 - 1 / (2 tau-)
 };
 
 // (Z'^T lam)_q at a fluid node t of a Zou-He column.  The closures (zouhe()) set the
@@ -2110,7 +2111,12 @@ __device__ __forceinline__ double zh_nu(const float* __restrict__ lam, size_t N,
     return v;
 }
 
-template <bool FORCE, bool ZH>
+// TRT: the collision relaxes the pair-even part of f - f_eq at omega and the
+// pair-odd part at omega_m, with the Guo source split the same way, so
+// C^T mu = mu - nu + J^T nu + S'^T sg with nu = omega mu+ + omega_m mu- and
+// sg = guo mu+ + guo_m mu- (mu+- the even and odd parts of mu, J = d f_eq / d f,
+// S' the source's derivative without its prefactor).
+template <bool FORCE, bool ZH, bool TRT>
 __global__ __launch_bounds__(256) void k_adjoint_step(AdjArgs a) {
     const int b = blockIdx.x;
     const int by = b / a.g.gridx, bx = b - by * a.g.gridx;
@@ -2146,6 +2152,16 @@ __global__ __launch_bounds__(256) void k_adjoint_step(AdjArgs a) {
     LBM_PUSH(7, rm + im, im)
     LBM_PUSH(8, rm + ip, ip)
 #undef LBM_PUSH
+    double nu_[9], sg[9];
+    if (TRT) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            const int qb = opp_of(q);
+            const double even = 0.5 * (mu[q] + mu[qb]), odd = 0.5 * (mu[q] - mu[qb]);
+            nu_[q] = fma(a.omega, even, a.omega_m * odd);
+            sg[q] = fma(a.guo, even, a.guo_m * odd);
+        }
+    }
     double f[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) f[q] = (double)a.f[q * N + n] - w_of_d(q);
@@ -2162,16 +2178,29 @@ __global__ __launch_bounds__(256) void k_adjoint_step(AdjArgs a) {
         const double k = wq * m.rho * fma(9.0, cu, 3.0);                                      \
         double dfx = (double)cx_of(Q) * k - wq * m.rho * 3.0 * m.ux;                          \
         double dfy = (double)cy_of(Q) * k - wq * m.rho * 3.0 * m.uy;                          \
-        double t = a.omega * dfr, tx = a.omega * dfx, ty = a.omega * dfy;                    \
-        if (FORCE) {                                                                          \
-            const double cg = cdot<Q, double>(a.gx, a.gy);                                    \
-            t += a.guo * wq * (3.0 * (cg - gu) + 9.0 * cu * cg);                              \
-            tx += a.guo * wq * m.rho * (-3.0 * a.gx + 9.0 * (double)cx_of(Q) * cg);           \
-            ty += a.guo * wq * m.rho * (-3.0 * a.gy + 9.0 * (double)cy_of(Q) * cg);           \
+        if (TRT) {                                                                            \
+            double t = nu_[Q] * dfr, tx = nu_[Q] * dfx, ty = nu_[Q] * dfy;                    \
+            if (FORCE) {                                                                      \
+                const double cg = cdot<Q, double>(a.gx, a.gy);                                \
+                t = fma(sg[Q], wq * (3.0 * (cg - gu) + 9.0 * cu * cg), t);                    \
+                tx = fma(sg[Q], wq * m.rho * (-3.0 * a.gx + 9.0 * (double)cx_of(Q) * cg), tx); \
+                ty = fma(sg[Q], wq * m.rho * (-3.0 * a.gy + 9.0 * (double)cy_of(Q) * cg), ty); \
+            }                                                                                 \
+            A += t;                                                                           \
+            Bx += tx;                                                                         \
+            By += ty;                                                                         \
+        } else {                                                                              \
+            double t = a.omega * dfr, tx = a.omega * dfx, ty = a.omega * dfy;                \
+            if (FORCE) {                                                                      \
+                const double cg = cdot<Q, double>(a.gx, a.gy);                                \
+                t += a.guo * wq * (3.0 * (cg - gu) + 9.0 * cu * cg);                          \
+                tx += a.guo * wq * m.rho * (-3.0 * a.gx + 9.0 * (double)cx_of(Q) * cg);       \
+                ty += a.guo * wq * m.rho * (-3.0 * a.gy + 9.0 * (double)cy_of(Q) * cg);       \
+            }                                                                                 \
+            A = fma(mu[Q], t, A);                                                             \
+            Bx = fma(mu[Q], tx, Bx);                                                          \
+            By = fma(mu[Q], ty, By);                                                          \
         }                                                                                     \
-        A = fma(mu[Q], t, A);                                                                 \
-        Bx = fma(mu[Q], tx, Bx);                                                              \
-        By = fma(mu[Q], ty, By);                                                              \
     }
     LBM_ADJ_ACC(0) LBM_ADJ_ACC(1) LBM_ADJ_ACC(2) LBM_ADJ_ACC(3) LBM_ADJ_ACC(4)
     LBM_ADJ_ACC(5) LBM_ADJ_ACC(6) LBM_ADJ_ACC(7) LBM_ADJ_ACC(8)
@@ -2181,7 +2210,8 @@ __global__ __launch_bounds__(256) void k_adjoint_step(AdjArgs a) {
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
         const double dux = ((double)cx_of(q) - vx) * inv, duy = ((double)cy_of(q) - vy) * inv;
-        a.lam0[q * N + n] = (float)((1.0 - a.omega) * mu[q] + A + Bx * dux + By * duy);
+        const double diag = TRT ? mu[q] - nu_[q] : (1.0 - a.omega) * mu[q];
+        a.lam0[q * N + n] = (float)(diag + A + Bx * dux + By * duy);
     }
 }
 
@@ -2258,8 +2288,6 @@ extern "C" int lbm_adjoint_step(lbm_ctx* c, const float* d_f_n, const float* d_l
     if (!c) return fail(LBM_EINVAL, "ctx is NULL");
     if (!d_f_n || !d_lam_np1 || !d_lam_n) return fail(LBM_EINVAL, "NULL buffer");
     if (d_lam_np1 == d_lam_n) return fail(LBM_EINVAL, "lam_{n+1} and lam_n must differ");
-    if (c->cfg.trt_lambda > 0.0)
-        return fail(LBM_EUNSUPPORTED, "the adjoint is of the BGK step (trt_lambda = 0)");
     AdjArgs a;
     a.f = d_f_n;
     a.lam1 = d_lam_np1;
@@ -2269,19 +2297,26 @@ extern "C" int lbm_adjoint_step(lbm_ctx* c, const float* d_f_n, const float* d_l
     a.g = c->g;
     a.omega = 1.0 / c->cfg.tau;
     a.guo = 1.0 - 0.5 / c->cfg.tau;
+    const bool trt = c->cfg.trt_lambda > 0.0;
+    const double tau_m = trt ? 0.5 + c->cfg.trt_lambda / (c->cfg.tau - 0.5) : c->cfg.tau;
+    a.omega_m = 1.0 / tau_m;
+    a.guo_m = 1.0 - 0.5 / tau_m;
     a.gx = c->cfg.gx;
     a.gy = c->cfg.gy;
     a.u_in = c->cfg.u_in;
     a.rho_out = c->cfg.rho_out;
     dim3 blk(TX, TY), grd(c->nblocks);
     const bool force = a.gx != 0.0 || a.gy != 0.0, zh = c->cfg.bc_x == LBM_BC_ZOUHE;
-    if (zh) {
-        if (force) k_adjoint_step<true, true><<<grd, blk, 0, c->stream>>>(a);
-        else k_adjoint_step<false, true><<<grd, blk, 0, c->stream>>>(a);
-    } else {
-        if (force) k_adjoint_step<true, false><<<grd, blk, 0, c->stream>>>(a);
-        else k_adjoint_step<false, false><<<grd, blk, 0, c->stream>>>(a);
+#define LBM_ADJ_LAUNCH(T)                                                                \
+    if (zh) {                                                                            \
+        if (force) k_adjoint_step<true, true, T><<<grd, blk, 0, c->stream>>>(a);         \
+        else k_adjoint_step<false, true, T><<<grd, blk, 0, c->stream>>>(a);              \
+    } else {                                                                             \
+        if (force) k_adjoint_step<true, false, T><<<grd, blk, 0, c->stream>>>(a);        \
+        else k_adjoint_step<false, false, T><<<grd, blk, 0, c->stream>>>(a);             \
     }
+    if (trt) { LBM_ADJ_LAUNCH(true) } else { LBM_ADJ_LAUNCH(false) }
+#undef LBM_ADJ_LAUNCH
     LBM_HIP(hipGetLastError());
     return LBM_OK;
 }

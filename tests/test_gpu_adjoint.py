@@ -195,3 +195,42 @@ def test_training_through_the_lattice_reduces_the_loss(gpu):
     hist = train_through_lattice(tr, samples, G, 40, torch.from_numpy(mask == 0).cuda(), epochs=30)
     print("through-lattice losses:", " ".join(f"{h:.3e}" for h in hist[::5]), f"{hist[-1]:.3e}")
     assert np.isfinite(hist).all() and hist[-1] < 0.25 * hist[0]
+
+
+@pytest.mark.parametrize("lam", [0.25, 3.0 / 16])
+def test_trt_adjoint_step_matches_oracle(gpu, lam):
+    """The adjoint of the TRT step (forced walled lattice with obstacles, and a Zou-He
+    lattice) vs the FP64 oracle's TRT adjoint, which is pinned by central differences."""
+    import dataclasses
+    import torch
+    for lat, seed in ((small_lattice(), 11), (zouhe_lattice(), 13)):
+        lat = dataclasses.replace(lat, trt_lambda=lam)
+        O = olbm.Sim(lat).init(*W.random_macro_fields(seed, lat.nx, lat.ny, amp_u=0.03)).run(15)
+        f = O.f.astype(np.float32)
+        lamv = W.random_array(seed + 1, f.shape).astype(np.float32) * (O.mask == 0)
+        ref = olbm.adjoint_step(lat, O.mask, f.astype(np.float64), lamv.astype(np.float64))
+        bgk = olbm.adjoint_step(dataclasses.replace(lat, trt_lambda=0.0), O.mask, f.astype(np.float64),
+                                lamv.astype(np.float64))
+        G = gpu.Lattice.from_workload(lat)
+        out = G.adjoint_step(torch.from_numpy(f).cuda(), torch.from_numpy(lamv).cuda()).cpu().numpy()
+        fl = np.repeat((O.mask == 0)[None], 9, 0)
+        e = rel_l2(out[fl], ref[fl])
+        print(f"TRT {lam:g} {lat.name}: adjoint step rel-L2 vs FP64 oracle {e:.2e} "
+              f"(BGK adjoint differs by {rel_l2(bgk[fl], ref[fl]):.2e})")
+        assert e < 1e-6 and rel_l2(bgk[fl], ref[fl]) > 1e-4
+        assert np.all(out[~fl] == 0)
+
+
+def test_trt_rollout_gradient_matches_oracle(gpu):
+    """Checkpointed TRT rollout (lambda = 1/4; 80 steps, checkpoints every 30) on a
+    Zou-He lattice: gradient w.r.t. the initial fields vs the FP64 oracle."""
+    import dataclasses
+    lat = dataclasses.replace(zouhe_lattice(40, 20), trt_lambda=0.25)
+    init, tgt, mask, loss, g = rollout_case(gpu, lat, 80, 30, seed=17)
+    ref = olbm.rollout_grad(lat, mask, *init, 80, tgt)
+    lref = olbm.rollout_loss(lat, mask, *init, 80, tgt)
+    fl = mask == 0
+    errs = [rel_l2(a[fl], b[fl]) for a, b in zip(g, ref)]
+    print(f"TRT rollout: loss gpu {loss:.8e} oracle {lref:.8e}; grad rel-L2 " + " ".join(f"{x:.2e}" for x in errs))
+    assert abs(loss - lref) <= 1e-5 * lref
+    assert max(errs) < 1e-5

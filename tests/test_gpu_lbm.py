@@ -392,15 +392,6 @@ def test_trt_zouhe_parity_and_kernels_agree_bitwise(gpu):
     assert max(rel_l2(a[k][fl], b[k][fl]) for k in range(3)) < 1e-6
 
 
-def test_trt_rejected_by_the_adjoint(gpu):
-    import torch
-    from paper_2604_27158_amd import lbmfno
-    G = gpu_lattice(gpu, with_trt(W.channel_walls_circles(1), 0.25))
-    f = G.populations()
-    with pytest.raises(lbmfno.LbmError):
-        G.adjoint_step(f, torch.zeros_like(f))
-
-
 @pytest.mark.parametrize("kernel", KERNELS)
 def test_all_solid_lattice_is_a_no_op(gpu, kernel):
     """Degenerate case: a lattice without fluid nodes steps without touching anything;
