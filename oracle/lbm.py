@@ -11,6 +11,8 @@ from __future__ import annotations
 import ctypes
 import os
 
+import math
+
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -105,11 +107,18 @@ class Sim:
         L = self.lat
         return (self.nx, self.ny, L.tau, L.gx, L.gy, L.bc_x, L.bc_y, L.u_in, L.rho_out)
 
-    def init(self, rho=None, ux=None, uy=None, neq: bool = False):
+    def init(self, rho=None, ux=None, uy=None, neq: bool = False, mass=None):
         """f(0) = f_eq(rho, u) (+ the first-order non-equilibrium part with neq), then
-        the boundary closures."""
+        the boundary closures.  With `mass`, rho is first shifted by one constant over
+        the fluid nodes so that its fluid sum equals `mass` (a mass-conserving hand-off:
+        pass the current state's mass())."""
         shp = (self.ny, self.nx)
         rho = _f64(np.ones(shp) if rho is None else rho)
+        if mass is not None:
+            fl = self.mask == 0
+            nfl = int(fl.sum())
+            if nfl:
+                rho = rho + (float(mass) - math.fsum(rho[fl].tolist())) / nfl
         ux = _f64(np.zeros(shp) if ux is None else ux)
         uy = _f64(np.zeros(shp) if uy is None else uy)
         self.f = np.zeros((9, self.ny, self.nx))
@@ -117,6 +126,11 @@ class Sim:
         fn(*self._args(), _ptr(self.mask), _ptr(rho), _ptr(ux), _ptr(uy), _ptr(self.f))
         self.steps = 0
         return self
+
+    def mass(self) -> float:
+        """Sum of rho = sum_q f_q over the fluid nodes of the current state (fsum)."""
+        rho = self.f.sum(axis=0)
+        return math.fsum(rho[self.mask == 0].tolist())
 
     def run(self, n: int):
         lam = getattr(self.lat, "trt_lambda", 0.0)

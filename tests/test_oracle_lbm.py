@@ -539,3 +539,31 @@ def test_trt_adjoint_with_equal_times_is_the_bgk_adjoint():
     a = lbm.adjoint_step(lat, mask, s.f, w)
     b = lbm.adjoint_step(dataclasses.replace(lat, trt_lambda=0.3 ** 2), mask, s.f, w)
     assert np.max(np.abs(a - b)) <= 1e-14 * np.max(np.abs(a))
+
+
+# ------------------------------------------------ mass-conserving re-initialisation
+
+def test_mass_conserving_init_shifts_density_uniformly():
+    """init(..., mass=M) on walls and a periodic axis: the state's fluid mass is M
+    (f_eq sums to rho), the density differs from the handed-over one by a single
+    constant on every fluid node, the velocity is unchanged, and the lattice keeps M
+    over 50 forced steps (mass conservation of the BGK step with the Guo source)."""
+    nx, ny = 24, 14
+    lat = W.Lattice(nx=nx, ny=ny, tau=0.8, gx=2e-6, bc_x=W.BC_PERIODIC, bc_y=W.BC_WALL,
+                    shapes=[W.circle(8, 7, 3)], wrap_x=True, wrap_y=False)
+    mask = lbm.raster(nx, ny, lat.shapes_array(), True, False)
+    fl = mask == 0
+    rho, ux, uy = W.random_macro_fields(5, nx, ny, amp_rho=0.01, amp_u=0.02)
+    target = math.fsum(rho[fl].tolist()) * (1.0 + 3e-3)
+    s = lbm.Sim(lat, mask).init(rho, ux, uy, mass=target)
+    assert abs(s.mass() - target) <= 1e-13 * target
+    r, u, v = s.macros()
+    d = (r - rho)[fl]
+    assert abs(d.mean() - 3e-3 * math.fsum(rho[fl].tolist()) / fl.sum()) <= 1e-12
+    assert np.max(np.abs(d - d.mean())) <= 1e-13
+    # the velocity is unchanged (the moments add half the force, g/2, to the handed-over u)
+    assert np.max(np.abs(u - ux - 0.5 * lat.gx)[fl]) <= 1e-13 and np.max(np.abs(v - uy)[fl]) <= 1e-13
+    plain = lbm.Sim(lat, mask).init(rho, ux, uy)
+    assert abs(plain.mass() - math.fsum(rho[fl].tolist())) <= 1e-13 * target
+    s.run(50)
+    assert abs(s.mass() - target) <= 1e-12 * target
