@@ -163,6 +163,16 @@ int lbm_reinit_from_macro(lbm_ctx* ctx, const float* d_rho, const float* d_ux, c
 int lbm_reinit_from_macro_neq(lbm_ctx* ctx, const float* d_rho, const float* d_ux,
                               const float* d_uy);
 
+/* lbm_reinit_from_macro with a mass-conserving hand-off (an extension; the paper
+ * re-initialises from f_eq of the predicted fields, Sec. 2.3): rho is shifted by one
+ * constant over the fluid nodes so that the new state's fluid mass equals the
+ * current state's (the mass the lattice itself conserves with periodic and wall
+ * boundaries).  Both sums are FP64 reductions on the device (the current mass as
+ * lbm_step reports it), so the call stays asynchronous.  Same arguments and errors
+ * as lbm_reinit_from_macro. */
+int lbm_reinit_from_macro_mass(lbm_ctx* ctx, const float* d_rho, const float* d_ux,
+                               const float* d_uy);
+
 /* Advance n >= 0 steps: each gathers f(t) (streaming Eq. 3 with bounce-back and
  * Zou-He), takes moments (Eqs. 4-5, u = (sum c f + rho g/2)/rho), collides (Eq. 2
  * with the Guo term) and stores the result for the next pull.  With rep == NULL

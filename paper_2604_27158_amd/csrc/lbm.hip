@@ -216,13 +216,19 @@ __device__ __forceinline__ double vel_deriv(const LatticeGeom& g, const uint8_t*
 //   else:        f_q(x) = given populations (absolute) (state restore)
 // NEQ (with FROM_FIELDS): add the first-order non-equilibrium part of the
 // pre-collision populations, -tau w_q rho / c_s^2 (c_q c_q - c_s^2 I) : grad u.
-template <bool FROM_FIELDS, bool NEQ>
+// MASS: rho is shifted by (*m_cur - *m_in) * inv_fluid on every node (the current
+// state's fluid mass minus the handed-over fields' fluid sum, both reduced on the
+// device, over the fluid node count).
+template <bool FROM_FIELDS, bool NEQ, bool MASS = false>
 __global__ __launch_bounds__(256) void k_scatter(LatticeGeom g, const uint8_t* __restrict__ mask,
                                                  const float* __restrict__ rho,
                                                  const float* __restrict__ ux,
                                                  const float* __restrict__ uy,
                                                  const float* __restrict__ fin,
-                                                 float* __restrict__ dst, double tau) {
+                                                 float* __restrict__ dst, double tau,
+                                                 const double* __restrict__ m_cur = nullptr,
+                                                 const double* __restrict__ m_in = nullptr,
+                                                 double inv_fluid = 0.0) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y;
     if (i >= g.nx) return;
@@ -240,7 +246,7 @@ __global__ __launch_bounds__(256) void k_scatter(LatticeGeom g, const uint8_t* _
         const int dir = t >= 0 ? p : opp_of(p);
         float v;
         if (FROM_FIELDS) {
-            const double r = rho[src];
+            const double r = MASS ? (double)rho[src] + (*m_cur - *m_in) * inv_fluid : (double)rho[src];
             double e = feq_dev_rt(dir, r - 1.0, r, ux[src], uy[src]);
             if (NEQ) {
                 const int si = src % g.nx, sj = src / g.nx;
@@ -1523,6 +1529,30 @@ extern "C" int lbm_reinit_from_macro(lbm_ctx* c, const float* d_rho, const float
 extern "C" int lbm_reinit_from_macro_neq(lbm_ctx* c, const float* d_rho, const float* d_ux,
                                          const float* d_uy) {
     return reinit(c, d_rho, d_ux, d_uy, true);
+}
+
+static int launch_field_stats(lbm_ctx* c, const float* d_rho, const float* d_ux, const float* d_uy,
+                              double* d_out);
+
+extern "C" int lbm_reinit_from_macro_mass(lbm_ctx* c, const float* d_rho, const float* d_ux,
+                                          const float* d_uy) {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (!d_rho || !d_ux || !d_uy) return fail(LBM_EINVAL, "NULL field");
+    // current mass: the report's FP64 reduction of the state's moments -> d_out[4 + 1]
+    int rc = launch_macro(c, nullptr, nullptr, nullptr, 0, nullptr, true);
+    if (rc) return rc;
+    k_reduce_final<<<1, 256, 0, c->stream>>>(c->d_partials, c->nblocks, c->d_out + 4);
+    // fluid sum of the handed-over density -> d_out[8]
+    rc = launch_field_stats(c, d_rho, d_ux, d_uy, c->d_out + 8);
+    if (rc) return rc;
+    const double inv_fluid = c->fluid > 0 ? 1.0 / (double)c->fluid : 0.0;
+    dim3 blk(256), grd((c->g.nx + 255) / 256, c->g.ny);
+    k_scatter<true, false, true><<<grd, blk, 0, c->stream>>>(c->g, c->d_mask, d_rho, d_ux, d_uy, nullptr,
+                                                             c->f[c->cur], c->cfg.tau, c->d_out + 5,
+                                                             c->d_out + 8, inv_fluid);
+    LBM_HIP(hipGetLastError());
+    c->steps = 0;
+    return LBM_OK;
 }
 
 extern "C" int lbm_set_populations(lbm_ctx* c, const float* d_f) {

@@ -89,6 +89,7 @@ SIGNATURES = [
     ("lbm_destroy", None, [_p]),
     ("lbm_reinit_from_macro", ctypes.c_int, [_p, _p, _p, _p]),
     ("lbm_reinit_from_macro_neq", ctypes.c_int, [_p, _p, _p, _p]),
+    ("lbm_reinit_from_macro_mass", ctypes.c_int, [_p, _p, _p, _p]),
     ("lbm_step", ctypes.c_int, [_p, _i32, ctypes.POINTER(LbmReport)]),
     ("lbm_get_macro", ctypes.c_int, [_p, _p, _p, _p, _i32]),
     ("lbm_get_populations", ctypes.c_int, [_p, _p]),
@@ -283,16 +284,20 @@ class Lattice:
         for t in ins:
             t.record_stream(self.stream)
 
-    def reinit(self, rho, ux, uy, neq: bool = False):
+    def reinit(self, rho, ux, uy, neq: bool = False, mass: bool = False):
         """f = f_eq(rho, u) (with neq, plus the first-order non-equilibrium part from the
-        velocity gradient), then the boundary closures; the step count restarts."""
+        velocity gradient; with mass, rho shifted by a constant so that the fluid mass
+        stays the current state's), then the boundary closures; the step count restarts."""
         import torch
         self._after_caller()
         with torch.cuda.stream(self.stream):
             rho, ux, uy = (t.to(device="cuda", dtype=torch.float32).contiguous() for t in (rho, ux, uy))
         self._take_inputs(rho, ux, uy)
         self._keep = (rho, ux, uy)
-        fn = self.lib.lbm_reinit_from_macro_neq if neq else self.lib.lbm_reinit_from_macro
+        if neq and mass:
+            raise ValueError("choose one of neq and mass")
+        fn = (self.lib.lbm_reinit_from_macro_neq if neq else
+              self.lib.lbm_reinit_from_macro_mass if mass else self.lib.lbm_reinit_from_macro)
         check(fn(self.ctx, rho.data_ptr(), ux.data_ptr(), uy.data_ptr()), "lbm_reinit_from_macro")
 
     def macros(self, rho_minus_one: bool = False, out=None):

@@ -178,7 +178,7 @@ def is_fno_interval(t: int, k: int) -> bool:
     return t % (k + 1) == 0
 
 
-def rollouts(sur: Surrogate, seed: int, neq: bool = False):
+def rollouts(sur: Surrogate, seed: int, neq: bool = False, mass: bool = False):
     """Outputs 1..30 of the plain lattice, the pure FNO and the 1:k hybrids from one
     initial condition, as raw (rho, ux, uy) numpy fields, plus the hybrids' counts."""
     import torch
@@ -206,7 +206,7 @@ def rollouts(sur: Surrogate, seed: int, neq: bool = False):
                 if is_fno_interval(t, k):
                     H.macros(out=sur.x)
                     y = sur.step()
-                    H.reinit(y[0], y[1], y[2], neq=neq)
+                    H.reinit(y[0], y[1], y[2], neq=neq, mass=mass)
                     out.append(y.cpu().numpy().astype(np.float64))
                 else:
                     H.step(DT)
@@ -215,7 +215,7 @@ def rollouts(sur: Surrogate, seed: int, neq: bool = False):
     return ref, pure, hyb
 
 
-def timed_runs(sur: Surrogate, seed: int, reps: int = 3, neq: bool = False):
+def timed_runs(sur: Surrogate, seed: int, reps: int = 3, neq: bool = False, mass: bool = False):
     """Wall time of the 30 Delta T horizon on this GPU: plain lattice and each 1:k
     hybrid (FNO calls, re-initialisations and lattice steps; no measurements)."""
     import torch
@@ -239,7 +239,7 @@ def timed_runs(sur: Surrogate, seed: int, reps: int = 3, neq: bool = False):
                 if is_fno_interval(t, k):
                     G.macros(out=sur.x)
                     y = sur.step()
-                    G.reinit(y[0], y[1], y[2], neq=neq)
+                    G.reinit(y[0], y[1], y[2], neq=neq, mass=mass)
                     t += 1
                 else:
                     n = 1
@@ -267,15 +267,17 @@ def timed_runs(sur: Surrogate, seed: int, reps: int = 3, neq: bool = False):
     return res
 
 
-def study(group: str, seeds, log=None, path: str | None = None, neq: bool = False):
+def study(group: str, seeds, log=None, path: str | None = None, neq: bool = False, mass: bool = False):
     """neq: hand the surrogate's fields to the lattice with the first-order
-    non-equilibrium part (Lattice.reinit(..., neq=True)) instead of f_eq alone."""
+    non-equilibrium part (Lattice.reinit(..., neq=True)) instead of f_eq alone;
+    mass: shift the handed-over density so that the lattice keeps its mass
+    (Lattice.reinit(..., mass=True))."""
     sur = Surrogate(group, path)
     per = {"pure": [], **{k: [] for k in HYBRIDS}}
     curves = {"pure": np.zeros((OUTPUTS, 2)), **{k: np.zeros((OUTPUTS, 2)) for k in HYBRIDS}}
     t0 = time.perf_counter()
     for n, s in enumerate(seeds):
-        ref, pure, hyb = rollouts(sur, s, neq)
+        ref, pure, hyb = rollouts(sur, s, neq, mass)
         for name, run in (("pure", pure), *((k, hyb[k]) for k in HYBRIDS)):
             e = np.array([errors(p, r) for p, r in zip(run, ref)])
             per[name].append(e.mean(axis=0))
@@ -284,8 +286,8 @@ def study(group: str, seeds, log=None, path: str | None = None, neq: bool = Fals
             log(f"shear study: {n + 1}/{len(seeds)} trajectories ({time.perf_counter() - t0:.1f} s)")
     ns = len(seeds)
     glob = {name: np.mean(per[name], axis=0) for name in per}   # (MSE, vorticity) means
-    times = timed_runs(sur, list(seeds)[0], neq=neq)
-    out = {"group": group, "reinit": "f_eq + first-order f_neq" if neq else "f_eq", "trajectories": ns, "outputs": OUTPUTS, "dt": DT,
+    times = timed_runs(sur, list(seeds)[0], neq=neq, mass=mass)
+    out = {"group": group, "reinit": "f_eq + first-order f_neq" if neq else "f_eq, mass-conserving" if mass else "f_eq", "trajectories": ns, "outputs": OUTPUTS, "dt": DT,
            "global_mse": {str(k): float(glob[k][0]) for k in glob},
            "global_vorticity": {str(k): float(glob[k][1]) for k in glob},
            "error_reduction_pct": {}, "eps_T_pct": {}, "eps_N_pct": {},
@@ -323,12 +325,14 @@ def main():
     e.add_argument("--seeds", type=int, default=len(TEST_SEEDS))
     e.add_argument("--json", default=None)
     e.add_argument("--neq", action="store_true", help="re-initialise with the non-equilibrium part")
+    e.add_argument("--mass", action="store_true", help="mass-conserving re-initialisation")
     args = ap.parse_args()
     from paper_2604_27158_amd import lbmfno
     lbmfno.load()
     if args.cmd == "eval":
         import json
-        res = study(args.group, list(TEST_SEEDS)[:args.seeds], log_print, args.weights, neq=args.neq)
+        res = study(args.group, list(TEST_SEEDS)[:args.seeds], log_print, args.weights, neq=args.neq,
+                    mass=args.mass)
         log_print(json.dumps({k: v for k, v in res.items() if k != "curves"}))
         if args.json:
             with open(args.json, "w") as f:

@@ -79,6 +79,7 @@ def test_null_arguments(lib):
     assert lib.lbm_reinit_from_macro(None, 1, 2, 3) == -1
     assert lib.lbm_reinit_from_macro_neq(None, 1, 2, 3) == -1
     assert lib.lbm_check_fields_async(None, 1, 2, 3, 4) == -1
+    assert lib.lbm_reinit_from_macro_mass(None, 1, 2, 3) == -1
 
 
 def test_raster_validation(lib):

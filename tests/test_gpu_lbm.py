@@ -182,6 +182,58 @@ def test_reinit_neq_matches_oracle(gpu, case):
         assert rel_l2(a[fl], b[fl]) < 1e-5
 
 
+@pytest.mark.parametrize("case", ["walls-obstacles", "periodic", "zouhe-porous"])
+def test_reinit_mass_conserving_matches_oracle(gpu, case):
+    """lbm_reinit_from_macro_mass after 150 steps, with handed-over fields whose
+    density carries 0.3 % too much mass: the populations match the oracle's
+    mass-conserving init (its target the oracle state's own mass), the reported mass
+    right after is the pre-hand-off mass where the lattice conserves mass (walls,
+    periodic) while the plain hand-off keeps the surplus, and 200 steps on match."""
+    import math
+    import torch
+    if case == "walls-obstacles":
+        lat = W.channel_walls_circles(4)
+    elif case == "periodic":
+        lat = W.Lattice(nx=77, ny=50, tau=0.9, gx=1e-6, bc_x=W.BC_PERIODIC, bc_y=W.BC_PERIODIC,
+                        shapes=[W.circle(20, 20, 5)], wrap_x=True, wrap_y=True)
+    else:
+        lat = W.Lattice(nx=90, ny=44, tau=0.7, bc_x=W.BC_ZOUHE, bc_y=W.BC_PERIODIC, u_in=0.03,
+                        rho_out=1.0, shapes=[W.circle(40, 20, 6), W.circle(70, 35, 5)], wrap_x=False,
+                        wrap_y=True)
+    rho0, ux0, uy0 = W.random_macro_fields(23, lat.nx, lat.ny, amp_u=0.03)
+    G = gpu_lattice(gpu, lat)
+    G.reinit(torch.from_numpy(rho0), torch.from_numpy(ux0), torch.from_numpy(uy0))
+    O = olbm.Sim(lat).init(rho0, ux0, uy0)
+    G.step(150)
+    O.run(150)
+    before = G.step(1, report=True)["mass"]
+    O.run(1)
+    rho1, ux1, uy1 = W.random_macro_fields(29, lat.nx, lat.ny, amp_u=0.03)
+    rho1 = (rho1 * 1.003).astype(np.float32)
+    ux1, uy1 = ux1.astype(np.float32), uy1.astype(np.float32)
+    P = gpu_lattice(gpu, lat)
+    P.reinit(torch.from_numpy(rho1), torch.from_numpy(ux1), torch.from_numpy(uy1))
+    G.reinit(torch.from_numpy(rho1), torch.from_numpy(ux1), torch.from_numpy(uy1), mass=True)
+    f = np_(G.populations())
+    O.init(rho1.astype(np.float64), ux1.astype(np.float64), uy1.astype(np.float64), mass=O.mass())
+    fl = O.mask == 0
+    assert np.max(np.abs(f[:, fl] - O.f[:, fl])) < 3e-7
+    after = G.step(1, report=True)["mass"]
+    plain = P.step(1, report=True)["mass"]
+    print(f"{case}: mass before {before:.10e}, after mass-conserving hand-off {after:.10e}, "
+          f"after plain hand-off {plain:.10e}")
+    if lat.bc_x != W.BC_ZOUHE:
+        assert abs(after - before) <= 1e-6 * before
+        assert abs(plain - before) > 1e-3 * before
+    O.run(1)
+    G.step(199)
+    O.run(199)
+    r, u, v = (np_(t).astype(np.float64) for t in G.macros())
+    ro, uo, vo = O.macros()
+    for a, b in ((r, ro), (u, uo), (v, vo)):
+        assert rel_l2(a[fl], b[fl]) < 1e-5
+
+
 def test_set_get_populations_roundtrip_and_step(gpu):
     """set_populations(f) then get_populations() returns f; one step from it matches
     the oracle's step from the same f."""
