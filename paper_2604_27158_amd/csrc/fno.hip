@@ -557,6 +557,109 @@ __global__ __launch_bounds__(256) void k_fno_dec(FnoDev d, const __bf16* __restr
     }
 }
 
+// Inference: the last layer's row inverse (no activation, no next row DFT) fused
+// with the decoder, one workgroup per interior row (b, h < H).  The row's output,
+// rounded to bf16 exactly as the separate row inverse stores it, stays in LDS
+// ([Wpad][DKP]) as the decoder's input, so the last activation never goes to global
+// memory and the padded rows h >= H are not formed.  The waves take the row's
+// 32-point groups in turn; every wave runs the same number of rounds and layers, so
+// a wave without a group still meets every barrier.
+template <int DACT>
+__global__ __launch_bounds__(256) void k_fno_rowinv_dec(FnoDev d, const __bf16* __restrict__ v,
+                                                        float* __restrict__ out, int layer) {
+    const int b = blockIdx.x / d.H, h = blockIdx.x % d.H;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, nw = blockDim.x >> 6;
+    const int KP = d.DKP;
+    const size_t rowoff = ((size_t)b * d.Hp + h) * d.Wpad * d.CP;
+    const __bf16* vrow = v + rowoff;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __bf16* zs = reinterpret_cast<__bf16*>(smem);                     // [CP][KKp + 8]
+    __bf16* vr = zs + (size_t)d.CP * (d.KKp + 8);                     // [Wpad][DKP]
+    __bf16* own = vr + (size_t)d.Wpad * KP + (size_t)wave * DEC_PTS * KP;  // [32][DKP] per wave
+    __shared__ __align__(16) __bf16 wo[8 * 64];
+    __shared__ float bo[8];
+    {
+        const __bf16* wg = d.decw;
+        const float* bg = d.decb;
+        int dn = d.CP;
+        for (int l = 0; l < d.dec_layers; ++l) {
+            wg += (size_t)d.DSP * dn;
+            bg += d.DSP;
+            dn = d.DSP;
+        }
+        for (int t = tid; t < d.cout * dn; t += blockDim.x) wo[t] = wg[t];
+        for (int t = tid; t < d.cout; t += blockDim.x) bo[t] = bg[t];
+    }
+    stage_z(d, b, h, zs);  // ends with a barrier, which also covers wo and bo
+    const int KKs = d.KKp + 8;
+    const __bf16* Wc = d.Wc + (size_t)layer * d.CP * d.CP;
+    const float* bias = d.bc + (size_t)layer * d.CP;
+    const int Mt = d.Wpad / 32, Nt = d.CP / 32;
+    for (int t = wave; t < Mt * Nt; t += nw) {
+        const int mi = t / Nt, ni = t % Nt;
+        f32x16 acc = {};
+        acc = mma_tile(d.BinvT + (size_t)mi * 32 * d.KKp, d.KKp, zs + (size_t)ni * 32 * KKs, KKs,
+                       d.KKp, acc);
+        acc = mma_tile(vrow + (size_t)mi * 32 * d.CP, d.CP, Wc + (size_t)ni * 32 * d.CP, d.CP,
+                       d.CP, acc);
+        const int o = ni * 32 + acc_col();
+        const float bc = bias[o];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int w = mi * 32 + acc_row(r);
+            const float val = w < d.Wp ? acc[r] + bc : 0.0f;
+            vr[(size_t)w * KP + o] = to_bf16(val);
+        }
+    }
+    __syncthreads();
+    const int ng = (d.W + DEC_PTS - 1) / DEC_PTS, rounds = (ng + nw - 1) / nw;
+    for (int rd = 0; rd < rounds; ++rd) {
+        const int g = rd * nw + wave;
+        const bool live = g < ng;  // uniform over the wave
+        __bf16* bufA = vr + (size_t)(live ? g : 0) * DEC_PTS * KP;
+        __bf16* bufB = own;
+        int din = d.CP;
+        const __bf16* wp = d.decw;
+        const float* bp = d.decb;
+        for (int l = 0; l < d.dec_layers; ++l) {
+            if (live) {
+                for (int nt = 0; nt < d.DSP / 32; ++nt) {
+                    f32x16 acc = {};
+                    acc = mma_tile(bufA, KP, wp + (size_t)nt * 32 * din, din, din, acc);
+                    const int su = nt * 32 + acc_col();
+                    const float bs = bp[su];
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const float a = su < d.dec_size ? act_t<DACT>(acc[r] + bs) : 0.0f;
+                        bufB[acc_row(r) * KP + su] = to_bf16(a);
+                    }
+                }
+            }
+            __syncthreads();
+            __bf16* t = bufA; bufA = bufB; bufB = t;
+            wp += (size_t)d.DSP * din;
+            bp += d.DSP;
+            din = d.DSP;
+        }
+        if (live) {
+            const int pp = lane & 31, w = g * DEC_PTS + pp;
+            if (w < d.W) {
+                for (int o = lane >> 5; o < d.cout; o += 2) {
+                    float acc = bo[o];
+                    for (int i = 0; i < din; i += 8) {   // din is a multiple of 32
+                        const bf16x8 a = *reinterpret_cast<const bf16x8*>(bufA + pp * KP + i);
+                        const bf16x8 wv = *reinterpret_cast<const bf16x8*>(wo + o * din + i);
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) acc = fmaf(from_bf16(wv[e]), from_bf16(a[e]), acc);
+                    }
+                    out[(((size_t)b * d.cout + o) * d.H + h) * d.W + w] = acc;
+                }
+            }
+        }
+        __syncthreads();  // this round's reads of own / vr before the next round's writes
+    }
+}
+
 }  // namespace lbmfno
 
 // ------------------------------------------------------------ host side
@@ -634,6 +737,19 @@ static void launch_dec(const FnoDev& d, const __bf16* v, float* out, hipStream_t
     const size_t nout = (size_t)d.B * d.H * d.W;
     const unsigned grid = (unsigned)((nout + 4 * DEC_PTS - 1) / (4 * DEC_PTS));
     FNO_WITH_ACT(d.dec_act, (k_fno_dec<A><<<grid, 256, dec_lds(d), st>>>(d, v, out)))
+}
+
+// dynamic LDS of the fused last row inverse + decoder: the row's Z, its output row
+// [Wpad][DKP] and one [32][DKP] buffer per wave (static: the output layer, 1 KB)
+static size_t rowinv_dec_lds(const FnoDev& d) {
+    return zs_lds(d) + (size_t)d.Wpad * d.DKP * 2 + (size_t)4 * DEC_PTS * d.DKP * 2;
+}
+static bool fuse_dec(const FnoDev& d) {
+    return !d.sv_pre && !d.sv_dec && rowinv_dec_lds(d) + 2048 <= 64 * 1024;
+}
+static void launch_rowinv_dec(const FnoDev& d, const __bf16* v, float* out, int l, hipStream_t st) {
+    const unsigned grid = (unsigned)(d.B * d.H);
+    FNO_WITH_ACT(d.dec_act, (k_fno_rowinv_dec<A><<<grid, 256, rowinv_dec_lds(d), st>>>(d, v, out, l)))
 }
 
 // dynamic LDS of the column kernel: xs [R2][CP] float, ys [CP][R2] bf16 and, when
@@ -1038,9 +1154,15 @@ static void launch_forward(const fno_model* m, const float* d_in, float* d_out, 
     // the first layer's row DFT (it also writes T's zero rows h >= Hp); with
     // fuse_row_dft the row inverse of each layer produces the next layer's row DFT
     const bool fused = fuse_row_dft(d);
+    // the last layer's row inverse also runs the decoder when it fits (fuse_dec)
+    const bool fdec = fuse_dec(d);
     for (int l = 0; l < d.L; ++l) {
         if (l == 0 || !fused) k_fno_rowfwd<<<B * d.Hpad, 256, lds_row, st>>>(d, cur);
         k_fno_col<<<B * d.m2, COL_THREADS, col_lds(d), st>>>(d, l);
+        if (l == d.L - 1 && fdec) {
+            launch_rowinv_dec(d, cur, d_out, l, st);
+            return;
+        }
         launch_rowinv(d, cur, nxt, l, st);
         __bf16* t = cur; cur = nxt; nxt = t;
     }

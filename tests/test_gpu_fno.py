@@ -57,6 +57,9 @@ CASES = [
                                 cout=2, padding=9), 64, 64, 1),
     ("ragged-50x70-w64", W.FnoSpec(cin=3, width=64, layers=2, m1=5, m2=7, dec_layers=2, dec_size=48,
                                    cout=3, padding=3, act="relu", dec_act="gelu"), 50, 70, 3),
+    # no hidden decoder layer (the output layer reads the last Fourier layer directly)
+    ("no-hidden-decoder-40x72", W.FnoSpec(cin=2, width=32, layers=2, m1=4, m2=4, dec_layers=0, dec_size=32,
+                                          cout=3, padding=2), 40, 72, 1),
     # every mode kept (m1 = H'/2, m2 = W'/2), no padding, odd-sized ragged grid
     ("all-modes-18x22", W.FnoSpec(cin=2, width=10, layers=2, m1=9, m2=11, dec_layers=1, dec_size=12,
                                   cout=2, padding=0), 18, 22, 2),
@@ -180,3 +183,23 @@ def test_fno_graph_sees_weight_refresh(gpu):
     torch.cuda.synchronize()
     assert torch.equal(out, m(x.clone()))
     assert not torch.equal(out, before)
+
+
+@pytest.mark.parametrize("name,spec,H,Wd,B", CASES, ids=[c[0] for c in CASES])
+def test_fused_last_layer_and_decoder_equal_the_separate_kernels(gpu, name, spec, H, Wd, B):
+    """Inference runs the last row inverse and the decoder as one kernel (the row's
+    output kept in LDS); the training forward keeps them separate (it saves the
+    activations).  Same rounding points, so the outputs are bitwise equal: every
+    model shape above, including 0, 1, 2 and 3 hidden decoder layers, widths 32 and
+    64, and rows with fewer 32-point groups than waves."""
+    import torch
+    from paper_2604_27158_amd import fno as gfno
+    layout = gfno.param_layout(spec)
+    params = 0.2 * W.fno_random_params(zlib.crc32(name.encode()) % 1000, layout, spec.width)
+    m = gfno.Fno(spec, params, H, Wd)
+    x = torch.from_numpy(fields_input(5, B, spec.cin, H, Wd).astype(np.float32)).cuda()
+    y = m(x)
+    t = gfno.Trainer(m, params)
+    y_train = t.forward(x)
+    torch.cuda.synchronize()
+    assert torch.equal(y, y_train), float((y - y_train).abs().max())
