@@ -279,6 +279,91 @@ __global__ __launch_bounds__(256) void k_fno_rowfwd(FnoDev d, const __bf16* __re
     row_dft_from_lds(d, vt, b, h);
 }
 
+// Inference: the lift fused with the first layer's row DFT, one workgroup per row
+// (b, h < Hpad) with a lane per point of the row (blockDim.x >= Wpad).  Each lane
+// lifts its point as k_fno_lift does (same operations, same order), stores it to v
+// and into the row's transposed copy in LDS, from which the row DFT is taken as in
+// k_fno_rowfwd; rows h >= Hp only write T's zero rows.
+template <int NO, int ACT>
+__global__ __launch_bounds__(1024) void k_fno_lift_row(FnoDev d, const float* __restrict__ x) {
+    __shared__ __align__(16) float w1s[32][8];
+    __shared__ __align__(16) float w2t[32][NO];  // w2t[k][c] = W2[c][k]
+    __shared__ __align__(16) float b2s[NO];
+    __shared__ float b1s[32];
+    extern __shared__ __align__(16) unsigned char smem[];
+    __bf16* vt = reinterpret_cast<__bf16*>(smem);  // [CP][Wpad]
+    const int b = blockIdx.x / d.Hpad, h = blockIdx.x % d.Hpad;
+    const int tid = threadIdx.x;
+    if (h >= d.Hp) {
+        const size_t tstride = (size_t)2 * d.Hpad;
+        __bf16* Tb = d.T + (size_t)b * d.m2 * d.CP * tstride;
+        for (int i = tid; i < d.m2 * d.CP * 2; i += blockDim.x) {
+            const int ri = i & 1, kc = i >> 1;  // kc = k2 * CP + c
+            Tb[(size_t)kc * tstride + ri * d.Hpad + h] = to_bf16(0.0f);
+        }
+        return;
+    }
+    for (int t = tid; t < 32 * 8; t += blockDim.x) {
+        const int k = t / 8, c = t % 8;
+        w1s[k][c] = (k < d.half && c < d.cl) ? d.lift1w[k * d.cl + c] : 0.0f;
+    }
+    for (int t = tid; t < 32 * NO; t += blockDim.x) {
+        const int k = t / NO, c = t % NO;
+        w2t[k][c] = (k < d.half && c < d.width) ? d.lift2w[c * d.half + k] : 0.0f;
+    }
+    for (int t = tid; t < NO; t += blockDim.x) b2s[t] = t < d.width ? d.lift2b[t] : 0.0f;
+    for (int t = tid; t < 32; t += blockDim.x) b1s[t] = t < d.half ? d.lift1b[t] : 0.0f;
+    __syncthreads();
+    const int w = tid;
+    if (w < d.Wpad) {
+        __bf16* out = d.v0 + (((size_t)b * d.Hp + h) * d.Wpad + w) * d.CP;
+        float o[NO];
+#pragma unroll
+        for (int c = 0; c < NO; ++c) o[c] = 0.0f;
+        if (h < d.H && w < d.W) {
+            float z[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) z[c] = 0.0f;
+#pragma unroll
+            for (int c = 0; c < 6; ++c)
+                if (c < d.cin) z[c] = x[(((size_t)b * d.cin + c) * d.H + h) * d.W + w];
+            if (d.coords) {
+                const float xc = d.W > 1 ? (float)w / (float)(d.W - 1) : 0.0f;
+                const float yc = d.H > 1 ? (float)h / (float)(d.H - 1) : 0.0f;
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    if (c == d.cin) z[c] = xc;
+                    if (c == d.cin + 1) z[c] = yc;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < NO; ++c) o[c] = b2s[c];
+            for (int k = 0; k < d.half; ++k) {
+                float s = b1s[k];
+#pragma unroll
+                for (int c = 0; c < 8; ++c) s = fmaf(w1s[k][c], z[c], s);
+                const float hk = act_t<ACT>(s);
+#pragma unroll
+                for (int c = 0; c < NO; ++c) o[c] = fmaf(w2t[k][c], hk, o[c]);
+            }
+#pragma unroll
+            for (int c = 0; c < NO; ++c)
+                if (c >= d.width) o[c] = 0.0f;
+        }
+#pragma unroll
+        for (int c0 = 0; c0 < NO; c0 += 8) {
+            bf16x8 t;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) t[e] = to_bf16(o[c0 + e]);
+            *reinterpret_cast<bf16x8*>(out + c0) = t;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) vt[(size_t)(c0 + e) * d.Wpad + w] = t[e];
+        }
+    }
+    __syncthreads();
+    row_dft_from_lds(d, vt, b, h);
+}
+
 // Column forward DFT, per-mode complex mixing and column inverse DFT for one
 // (sample, k2).
 // Launched with COL_THREADS threads: at batch 1 there is one workgroup per mode
@@ -1147,8 +1232,20 @@ static void launch_forward(const fno_model* m, const float* d_in, float* d_out, 
     d.T = reinterpret_cast<__bf16*>(ws + 2 * L.v);
     d.Z = reinterpret_cast<__bf16*>(ws + 2 * L.v + L.T);
     const size_t npts = (size_t)B * d.Hp * d.Wpad;
-    launch_lift(d, npts, d_in, st);
     const size_t lds_row = (size_t)d.CP * d.Wpad * 2;
+    // the lift takes the first row DFT in the same kernel when a row fits one
+    // workgroup (a lane per point) and the row in LDS
+    const bool flift = !d.sv_a1 && d.Wpad <= 1024 && lds_row + 12 * 1024 <= 64 * 1024;
+    if (flift) {
+        const unsigned threads = (unsigned)rup(d.Wpad, 64), grid = (unsigned)(B * d.Hpad);
+        if (d.CP <= 32) {
+            FNO_WITH_ACT(d.act, (k_fno_lift_row<32, A><<<grid, threads, lds_row, st>>>(d, d_in)))
+        } else {
+            FNO_WITH_ACT(d.act, (k_fno_lift_row<64, A><<<grid, threads, lds_row, st>>>(d, d_in)))
+        }
+    } else {
+        launch_lift(d, npts, d_in, st);
+    }
     __bf16* cur = d.v0;
     __bf16* nxt = d.v1;
     // the first layer's row DFT (it also writes T's zero rows h >= Hp); with
@@ -1157,7 +1254,7 @@ static void launch_forward(const fno_model* m, const float* d_in, float* d_out, 
     // the last layer's row inverse also runs the decoder when it fits (fuse_dec)
     const bool fdec = fuse_dec(d);
     for (int l = 0; l < d.L; ++l) {
-        if (l == 0 || !fused) k_fno_rowfwd<<<B * d.Hpad, 256, lds_row, st>>>(d, cur);
+        if ((l == 0 && !flift) || (l > 0 && !fused)) k_fno_rowfwd<<<B * d.Hpad, 256, lds_row, st>>>(d, cur);
         k_fno_col<<<B * d.m2, COL_THREADS, col_lds(d), st>>>(d, l);
         if (l == d.L - 1 && fdec) {
             launch_rowinv_dec(d, cur, d_out, l, st);
