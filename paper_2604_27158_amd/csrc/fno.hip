@@ -144,6 +144,13 @@ struct FnoDev {
     float* sv_dec;    // decoder pre-activations, per layer [B][H][W][DSP]
 };
 
+// Row stride (bf16 elements) of a row's transposed copy vt[c][w] in LDS: Wpad plus
+// 8, so that the 32 channels a wavefront stores (or the 32 rows an MFMA operand
+// load reads) at one w fall on different banks (a stride of Wpad, a multiple of 32,
+// put them all on one bank); still a multiple of 8 for 16-byte loads.
+__host__ __device__ __forceinline__ int vt_stride(const FnoDev& d) { return d.Wpad + 8; }
+
+
 // ---------------------------------------------------------------- kernels
 
 // Lift: x (cin channels, float32) + coordinates -> width/2 (act) -> width, rounded
@@ -239,7 +246,7 @@ __device__ __forceinline__ void row_dft_from_lds(const FnoDev& d, const __bf16* 
     for (int t = wave; t < Mt * Nt; t += blockDim.x >> 6) {
         const int mi = t / Nt, ni = t % Nt;
         f32x16 acc = {};
-        acc = mma_tile(d.EwT + (size_t)mi * 32 * d.Wpad, d.Wpad, vt + ni * 32 * d.Wpad, d.Wpad,
+        acc = mma_tile(d.EwT + (size_t)mi * 32 * d.Wpad, d.Wpad, vt + ni * 32 * vt_stride(d), vt_stride(d),
                        d.Wpad, acc);
         const int c = ni * 32 + acc_col();
 #pragma unroll
@@ -255,7 +262,7 @@ __device__ __forceinline__ void row_dft_from_lds(const FnoDev& d, const __bf16* 
 
 __global__ __launch_bounds__(256) void k_fno_rowfwd(FnoDev d, const __bf16* __restrict__ v) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __bf16* vt = reinterpret_cast<__bf16*>(smem);  // [CP][Wpad]
+    __bf16* vt = reinterpret_cast<__bf16*>(smem);  // [CP][vt_stride]
     const int b = blockIdx.x / d.Hpad, h = blockIdx.x % d.Hpad;
     const int tid = threadIdx.x;
     const size_t tstride = (size_t)2 * d.Hpad;
@@ -273,7 +280,7 @@ __global__ __launch_bounds__(256) void k_fno_rowfwd(FnoDev d, const __bf16* __re
     for (int i = tid; i < nvec; i += blockDim.x) {
         const bf16x8 t = *reinterpret_cast<const bf16x8*>(row + 8 * i);
         const int w = (8 * i) / d.CP, c0 = (8 * i) % d.CP;
-        for (int e = 0; e < 8; ++e) vt[(c0 + e) * d.Wpad + w] = t[e];
+        for (int e = 0; e < 8; ++e) vt[(c0 + e) * vt_stride(d) + w] = t[e];
     }
     __syncthreads();
     row_dft_from_lds(d, vt, b, h);
@@ -291,7 +298,7 @@ __global__ __launch_bounds__(1024) void k_fno_lift_row(FnoDev d, const float* __
     __shared__ __align__(16) float b2s[NO];
     __shared__ float b1s[32];
     extern __shared__ __align__(16) unsigned char smem[];
-    __bf16* vt = reinterpret_cast<__bf16*>(smem);  // [CP][Wpad]
+    __bf16* vt = reinterpret_cast<__bf16*>(smem);  // [CP][vt_stride]
     const int b = blockIdx.x / d.Hpad, h = blockIdx.x % d.Hpad;
     const int tid = threadIdx.x;
     if (h >= d.Hp) {
@@ -357,7 +364,7 @@ __global__ __launch_bounds__(1024) void k_fno_lift_row(FnoDev d, const float* __
             for (int e = 0; e < 8; ++e) t[e] = to_bf16(o[c0 + e]);
             *reinterpret_cast<bf16x8*>(out + c0) = t;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) vt[(size_t)(c0 + e) * d.Wpad + w] = t[e];
+            for (int e = 0; e < 8; ++e) vt[(size_t)(c0 + e) * vt_stride(d) + w] = t[e];
         }
     }
     __syncthreads();
@@ -503,7 +510,7 @@ __global__ __launch_bounds__(256) void k_fno_rowinv(FnoDev d, const __bf16* __re
     const __bf16* vrow = v + rowoff;
     extern __shared__ __align__(16) unsigned char smem[];
     __bf16* zs = reinterpret_cast<__bf16*>(smem);  // [CP][KKp + 8]
-    __bf16* vt = zs + (size_t)d.CP * (d.KKp + 8);  // [CP][Wpad] (DFT)
+    __bf16* vt = zs + (size_t)d.CP * (d.KKp + 8);  // [CP][vt_stride] (DFT)
     stage_z(d, b, h, zs);
     const int KKs = d.KKp + 8;
     const __bf16* Wc = d.Wc + (size_t)layer * d.CP * d.CP;
@@ -527,7 +534,7 @@ __global__ __launch_bounds__(256) void k_fno_rowinv(FnoDev d, const __bf16* __re
             if (w >= d.Wp) val = 0.0f;
             const __bf16 vb = to_bf16(val);
             vout[rowoff + (size_t)w * d.CP + o] = vb;
-            if constexpr (DFT) vt[o * d.Wpad + w] = vb;
+            if constexpr (DFT) vt[o * vt_stride(d) + w] = vb;
         }
     }
     if constexpr (DFT) {
@@ -800,7 +807,7 @@ static size_t zs_lds(const FnoDev& d);
 
 // whether the row inverse can also hold the output row for the next row DFT in LDS
 static bool fuse_row_dft(const FnoDev& d) {
-    return zs_lds(d) + (size_t)d.CP * d.Wpad * 2 <= 64 * 1024;
+    return zs_lds(d) + (size_t)d.CP * vt_stride(d) * 2 <= 64 * 1024;
 }
 
 // row inverse of layer l over all (b, h) rows; the last layer has no activation,
@@ -808,7 +815,7 @@ static bool fuse_row_dft(const FnoDev& d) {
 static void launch_rowinv(const FnoDev& d, const __bf16* v, __bf16* vout, int l, hipStream_t st) {
     const unsigned grid = (unsigned)(d.B * d.Hp);
     if (l < d.L - 1 && fuse_row_dft(d)) {
-        const size_t lds = zs_lds(d) + (size_t)d.CP * d.Wpad * 2;
+        const size_t lds = zs_lds(d) + (size_t)d.CP * vt_stride(d) * 2;
         FNO_WITH_ACT(d.act, (k_fno_rowinv<A, true><<<grid, 256, lds, st>>>(d, v, vout, l)))
     } else {
         FNO_WITH_ACT(l == d.L - 1 ? FNO_ACT_IDENTITY : d.act,
@@ -1035,7 +1042,7 @@ extern "C" int fno_model_create(fno_model** out, const fno_spec* spec, const flo
     d.DKP = std::max(d.CP, d.DSP) + 8;
     d.cout = s.cout;
     d.act = s.act; d.dec_act = s.dec_act;
-    if ((size_t)d.CP * d.Wpad * 2 > 64 * 1024) return fail(LBM_EUNSUPPORTED, "row of %d x %d too large for LDS", d.Wpad, d.CP);
+    if ((size_t)d.CP * vt_stride(d) * 2 > 64 * 1024) return fail(LBM_EUNSUPPORTED, "row of %d x %d too large for LDS", d.Wpad, d.CP);
     if (col_lds(d) > 64 * 1024) return fail(LBM_EUNSUPPORTED, "mode block too large for LDS");
     if (zs_lds(d) > 64 * 1024) return fail(LBM_EUNSUPPORTED, "row coefficients too large for LDS");
     fno_model* m = new (std::nothrow) fno_model();
@@ -1232,7 +1239,7 @@ static void launch_forward(const fno_model* m, const float* d_in, float* d_out, 
     d.T = reinterpret_cast<__bf16*>(ws + 2 * L.v);
     d.Z = reinterpret_cast<__bf16*>(ws + 2 * L.v + L.T);
     const size_t npts = (size_t)B * d.Hp * d.Wpad;
-    const size_t lds_row = (size_t)d.CP * d.Wpad * 2;
+    const size_t lds_row = (size_t)d.CP * vt_stride(d) * 2;
     // the lift takes the first row DFT in the same kernel when a row fits one
     // workgroup (a lane per point) and the row in LDS
     const bool flift = !d.sv_a1 && d.Wpad <= 1024 && lds_row + 12 * 1024 <= 64 * 1024;
@@ -1881,7 +1888,7 @@ extern "C" int fno_forward_train(const fno_model* m, const float* d_in, float* d
     d.sv_a1 = P.a1;
     launch_lift(d, t.Pl, d_in, st);
     d.sv_a1 = nullptr;
-    const size_t lds_row = (size_t)d.CP * d.Wpad * 2;
+    const size_t lds_row = (size_t)d.CP * vt_stride(d) * 2;
     const bool fused = fuse_row_dft(d);  // later layers' row DFT in the row inverse
     for (int l = 0; l < d.L; ++l) {
         if (l == 0 || !fused) k_fno_rowfwd<<<B * d.Hpad, 256, lds_row, st>>>(d, P.v[l]);
@@ -1957,7 +1964,7 @@ extern "C" int fno_backward(const fno_model* m, const float* d_in, const float* 
                          d_grad + wofs[l], d_grad + bofs[l]);
     }
     // Fourier layers, last first
-    const size_t lds_row = (size_t)d.CP * d.Wpad * 2;
+    const size_t lds_row = (size_t)d.CP * vt_stride(d) * 2;
     const size_t lds_col = (size_t)d.R2 * d.CP * 4 + (size_t)d.CP * d.R2 * 2;
     for (int l = d.L - 1; l >= 0; --l) {
         const size_t lo = o_layers + (size_t)l * per_layer;
