@@ -80,12 +80,12 @@ extern "C" {
                               traffic per step).  64 x 8 tiles when both population
                               copies fit 128 MiB, else 64 x 4 tiles with streaming
                               stores.  Any nx. */
-#define LBM_KERNEL_DEEP 4  /* deeper temporal blocking: three steps per launch (a
-                              two-node ring) when both population copies fit
-                              128 MiB, on 64 x 16 tiles when the lattice has at
-                              least 512 of them, else 64 x 8; four steps per launch
-                              (a three-node ring, 64 x 8 tiles, streaming stores)
-                              above 128 MiB.  Any nx. */
+#define LBM_KERNEL_DEEP 4  /* deeper temporal blocking: four steps per launch (a
+                              three-node ring) on 64 x 16 tiles when both population
+                              copies fit 128 MiB and the lattice has at least 512
+                              such tiles, three steps (a two-node ring) on 64 x 8
+                              tiles on smaller ones, four steps on 64 x 8 tiles with
+                              streaming stores above 128 MiB.  Any nx. */
 
 /* Lattice description.  tau > 1/2 is the BGK relaxation time (nu = (tau-1/2)/3 in
  * lattice units), (gx, gy) a uniform body force per unit mass (Guo forcing; use 0

@@ -564,14 +564,15 @@ __global__ __launch_bounds__(256) void k_bgk_step(StepArgs a) {
 // 8192x4096 porous flows):
 //   S = 2, 64 x 8   cache-resident lattices, LBM_KERNEL_PAIR
 //   S = 2, 64 x 4   lattices streamed from HBM, LBM_KERNEL_PAIR, and the batch
-//   S = 3, 64 x 16  cache-resident lattices whose grid gives every CU two
-//                   workgroups (1024x512: 106 against 92 GLUPS for S = 2)
+//   S = 4, 64 x 16  cache-resident lattices whose grid gives every CU two
+//                   workgroups (1024x512: 107.5 against 105.0 GLUPS for S = 3 and
+//                   92 for S = 2)
 //   S = 3, 64 x 8   smaller cache-resident lattices (512x256: 47 against 44)
 //   S = 4, 64 x 8   lattices streamed from HBM (8192x4096: 127 against 97; S = 3
 //                   reaches 119, 64 x 16 tiles 113)
 // Deeper blocking trades redundant ring collisions (29 % at S = 2, 64 x 8; 45 %
-// at S = 4, 64 x 8) for fewer global-memory round trips; the kernel is bound by
-// memory latency, not by the vector ALUs (34 % busy at S = 2).
+// at S = 4, 64 x 8; 25 % at S = 4, 64 x 16) for fewer global-memory round trips;
+// the kernel is bound by memory latency, not by the vector ALUs (42 % busy).
 template <int S, int RY>
 struct Ring {
     static constexpr int W(int lvl) { return TX + 2 * (S - 1 - lvl); }
@@ -1106,7 +1107,7 @@ __global__ __launch_bounds__(64) void k_compare_final(const double* __restrict__
 using namespace lbmfno;
 
 // Fused multi-step kernel shapes: steps per launch, tile height, store kind.
-enum FusedShape { SHAPE_NONE, SHAPE_PAIR8, SHAPE_PAIR4_NT, SHAPE_DEEP3_8, SHAPE_DEEP3_16, SHAPE_DEEP4_8_NT };
+enum FusedShape { SHAPE_NONE, SHAPE_PAIR8, SHAPE_PAIR4_NT, SHAPE_DEEP3_8, SHAPE_DEEP4_16, SHAPE_DEEP4_8_NT };
 
 struct lbm_ctx {
     lbm_config cfg;
@@ -1369,7 +1370,7 @@ static int launch_multi(lbm_ctx* c) {
         case SHAPE_PAIR8: launch_multi_shape<2, 8, false>(c, a); break;
         case SHAPE_PAIR4_NT: launch_multi_shape<2, 4, true>(c, a); break;
         case SHAPE_DEEP3_8: launch_multi_shape<3, 8, false>(c, a); break;
-        case SHAPE_DEEP3_16: launch_multi_shape<3, 16, false>(c, a); break;
+        case SHAPE_DEEP4_16: launch_multi_shape<4, 16, false>(c, a); break;
         case SHAPE_DEEP4_8_NT: launch_multi_shape<4, 8, true>(c, a); break;
         default: return fail(LBM_EINVAL, "no fused shape selected");
     }
@@ -1447,9 +1448,10 @@ extern "C" int lbm_init(lbm_ctx** out, const lbm_config* cfg, const uint8_t* d_m
     // Fused multi-step launches beat every one-step kernel at every size measured
     // (128x128 to 8192x4096): on large lattices by cutting the population traffic
     // per step, on small, latency-bound ones by cutting the launches.  The deep
-    // kernel (the default) runs three steps per launch on cache-resident lattices,
-    // on 64 x 16 tiles when that grid still gives every CU two workgroups, and four
-    // steps per launch with streaming stores on lattices streamed from HBM.
+    // kernel (the default) runs four steps per launch on 64 x 16 tiles on
+    // cache-resident lattices whose grid still gives every CU two such workgroups,
+    // three steps on 64 x 8 tiles on smaller ones, and four steps on 64 x 8 tiles
+    // with streaming stores on lattices streamed from HBM.
     const int64_t tiles16 = (int64_t)c->g.gridx * ((cfg->ny + 15) / 16);
     c->shape = SHAPE_NONE;
     c->spl = 1;
@@ -1457,8 +1459,8 @@ extern "C" int lbm_init(lbm_ctx** out, const lbm_config* cfg, const uint8_t* d_m
         c->shape = c->nontemporal ? SHAPE_PAIR4_NT : SHAPE_PAIR8;
         c->spl = 2;
     } else if (cfg->kernel == LBM_KERNEL_DEEP || cfg->kernel == LBM_KERNEL_AUTO) {
-        c->shape = c->nontemporal ? SHAPE_DEEP4_8_NT : tiles16 >= 512 ? SHAPE_DEEP3_16 : SHAPE_DEEP3_8;
-        c->spl = c->nontemporal ? 4 : 3;
+        c->shape = c->nontemporal ? SHAPE_DEEP4_8_NT : tiles16 >= 512 ? SHAPE_DEEP4_16 : SHAPE_DEEP3_8;
+        c->spl = c->shape == SHAPE_DEEP3_8 ? 3 : 4;
     }
     c->vec4 = cfg->kernel == LBM_KERNEL_QUAD;
     c->gridx4 = (cfg->nx + 4 * TX - 1) / (4 * TX);
@@ -1717,7 +1719,7 @@ extern "C" const char* lbm_step_kernel(const lbm_ctx* c) {
         {"pair-64x8/lean", "pair-64x8/fp32", "pair-64x8/mixed"},
         {"pair-64x4/lean", "pair-64x4/fp32", "pair-64x4/mixed"},
         {"deep3-64x8/lean", "deep3-64x8/fp32", "deep3-64x8/mixed"},
-        {"deep3-64x16/lean", "deep3-64x16/fp32", "deep3-64x16/mixed"},
+        {"deep4-64x16/lean", "deep4-64x16/fp32", "deep4-64x16/mixed"},
         {"deep4-64x8/lean", "deep4-64x8/fp32", "deep4-64x8/mixed"}};
     if (c->spl > 1) return fused[c->shape][lean ? 0 : f32 ? 1 : 2];
     if (c->vec4) return lean ? "quad/lean" : f32 ? "quad/fp32" : "quad/mixed";
