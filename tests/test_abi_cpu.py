@@ -122,3 +122,30 @@ def test_fno_model_create_validates_on_host(lib):
                                 p.ctypes.data_as(ctypes.c_void_p), 10, 64, 64) == -1
     assert lib.fno_forward(None, 1, 2, 1, 3, 100, None) == -1
     assert lib.fno_forward_graph(None, 1, 2, 1, 3, 100, None) == -1
+
+
+@pytest.mark.parametrize("name,spl", [("node/lean", 1), ("quad/fp32", 1), ("pair-64x8/lean", 2),
+                                      ("pair-64x4/mixed", 2), ("deep3-64x8/lean", 3),
+                                      ("deep4-64x16/lean", 4), ("deep4-64x8/fp32", 4),
+                                      ("tuned deep3+nt 0.0616 ms/step".split()[1].split("+")[0], 3)])
+def test_bench_steps_per_launch_parses_every_kernel_name(name, spl):
+    """bench.py divides the algorithmic bytes of one launch by its duration; the
+    steps per launch come from the kernel name lbm_step_kernel (or the batch
+    tuner) reports, so every shape the library can name must parse."""
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    assert bench.steps_per_launch(name) == spl
+
+
+def test_every_fused_shape_name_is_reported_by_the_library(lib):
+    """The library's kernel-name table and the bench parser agree: every name in
+    the table parses to the steps its shape runs."""
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    src = open(os.path.join(ROOT, "paper_2604_27158_amd", "csrc", "lbm.hip")).read()
+    names = set(re.findall(r'"((?:pair|deep\d)-64x\d+)/(?:lean|fp32|mixed)"', src))
+    assert names == {"pair-64x8", "pair-64x4", "deep3-64x8", "deep4-64x16", "deep4-64x8"}
+    for n in names:
+        assert bench.steps_per_launch(n + "/lean") == (2 if n.startswith("pair") else int(n[4]))
