@@ -379,7 +379,7 @@ def cpu_baseline(lat, seconds):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(the lattice and FNO paths run on a single MI355X)", file=sys.stderr)
         sys.exit(2)
     import numpy as np

@@ -78,7 +78,7 @@ def rollout(lattice, rho0, ux0, uy0, nsteps: int, ckpt_every: int = 50):
 def fno_through_lattice(trainer, x, lattice, nsteps: int, target, fluid, rho_offset: float = 1.0,
                         ckpt_every: int = 50):
     """Loss and FNO parameter gradient of a hybrid hand-off trained through the
-    lattice (the benchmark spec's differentiable coupling): the FNO maps x [1][cin][H][W]
+    lattice (the differentiable FNO-lattice coupling): the FNO maps x [1][cin][H][W]
     to fields (rho - rho_offset, ux, uy); the lattice starts from f_eq of those
     fields and runs nsteps (checkpointed adjoint, LatticeRollout); the loss is the
     mean squared error of its macroscopic fields against target [3][H][W] (for
