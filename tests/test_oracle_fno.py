@@ -138,8 +138,10 @@ def test_bf16_mode_close_to_fp64():
 
 def _torch_fno(spec, flat, x):
     """The same network assembled from torch library routines in float64:
-    conv2d 1x1 for every pointwise map (weights [out][in]), torch.fft.rfft2/irfft2
-    for the spectral part, F.gelu (erf form) / F.silu for the activations."""
+    conv2d 1x1 for every pointwise map (weights [out][in]), F.pad for the zero
+    padding on the high side of H and W after the lift (cropped before the
+    decoder), torch.fft.rfft2/irfft2 for the spectral part, F.gelu (erf form) /
+    F.silu for the activations."""
     import torch.nn.functional as F
     P = {k: torch.from_numpy(np.ascontiguousarray(v)) for k, v in fno.unpack(spec, flat).items()}
     t = torch.from_numpy(x)
@@ -149,6 +151,9 @@ def _torch_fno(spec, flat, x):
     t = torch.cat([t, xs, ys], 1)
     conv = lambda w, b, a: F.conv2d(a, w[:, :, None, None], b)
     t = conv(P["lift2.w"], P["lift2.b"], F.gelu(conv(P["lift1.w"], P["lift1.b"], t)))
+    pad = spec.padding
+    t = F.pad(t, (0, pad, 0, pad))
+    H, Wd = H + pad, Wd + pad
     for n in range(spec.layers):
         X = torch.fft.rfft2(t)
         Y = torch.zeros_like(X)
@@ -160,13 +165,18 @@ def _torch_fno(spec, flat, x):
         t = torch.fft.irfft2(Y, s=(H, Wd)) + conv(P[f"conv{n}.w"], P[f"conv{n}.b"], t)
         if n < spec.layers - 1:
             t = F.gelu(t)
+    t = t[:, :, :H - pad, :Wd - pad]
     for n in range(spec.dec_layers):
         t = F.silu(conv(P[f"dec{n}.w"], P[f"dec{n}.b"], t))
     return conv(P["dec_out.w"], P["dec_out.b"], t).numpy()
 
 
-def test_forward_equals_torch_library_composition():
-    spec = fno.Spec(cin=4, width=8, layers=3, m1=3, m2=4, dec_layers=2, dec_size=6, cout=3)
+@pytest.mark.parametrize("padding", [0, 9, 4])
+def test_forward_equals_torch_library_composition(padding):
+    """Also pins the padding (9 in every model of the paper's tables): zeros on the
+    high side of both axes after the lift, cropped before the decoder."""
+    spec = fno.Spec(cin=4, width=8, layers=3, m1=3, m2=4, dec_layers=2, dec_size=6, cout=3,
+                    padding=padding)
     p = W.fno_random_params(21, fno.layout(spec), spec.width)
     x = _rand((2, 4, 12, 20), 22)
     a = fno.forward(spec, p, x)
