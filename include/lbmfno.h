@@ -402,6 +402,23 @@ int fno_forward(const fno_model* m, const float* d_in, float* d_out, int32_t B, 
 int fno_forward_graph(fno_model* m, const float* d_in, float* d_out, int32_t B, void* d_ws,
                       size_t ws_bytes, void* stream);
 
+/* fno_forward for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the workspace is
+ * a library-owned static device array of FNO_NOALLOC_SCRATCH_BYTES bytes, one per
+ * GPU, held until the process ends, so the call itself allocates nothing (no
+ * hipMalloc, hipFree or allocating library routine).  Its device address is looked
+ * up once per GPU by the first fno_model_create there.  The caller passes the
+ * input and output buffers as for fno_forward; results are bitwise equal to
+ * fno_forward's.  LBM_EINVAL when the batch needs more workspace than the array
+ * holds (fno_workspace_size(m, B) > FNO_NOALLOC_SCRATCH_BYTES), with the sizes in
+ * lbm_last_error().  Every call on one GPU shares that GPU's array and leaves its
+ * contents behind: calls that overlap on one GPU (on different streams, or from
+ * several threads) race and corrupt each other's results; serialise them, e.g. on
+ * one stream.  Asynchronous on `stream`. */
+#define FNO_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int fno_forward_noalloc(const fno_model* m, const float* d_in, float* d_out, int32_t B,
+                        void* stream);
+
 /* ---------------------------------------------------------------- FNO training
  * Training of the surrogate on lattice-generated samples (Sec. 2.2: FNO models
  * trained by minimising the mean squared error of the predicted fields, AdamW).

@@ -19,8 +19,10 @@
 // followed by bias and the activation, rounded to bf16 in the epilogue.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -1007,6 +1009,37 @@ static int build_param_maps(fno_model* m, const FnoDev& d) {
     return LBM_OK;
 }
 
+// ------------------------------------------- forward without any allocation
+//
+// fno_forward_noalloc runs fno_forward's kernels with their workspace in a
+// file-scope device array instead of a caller buffer.  Each GPU the library runs
+// on holds its own copy of the array until the process ends.  In host code the
+// array's name is only a host-side stand-in: kernels receive the device address
+// that hipGetSymbolAddress returned for that GPU, looked up once per device when
+// the first model is created there (with that device current).
+static __device__ __align__(256) unsigned char scratch[FNO_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+std::atomic<void*> g_scratch_ptr[kMaxDevices];
+}  // namespace
+
+// Device address of `scratch` on `device` (the current device), looked up once.
+static int scratch_setup(int device) {
+    if (device < 0 || device >= kMaxDevices)
+        return fail(LBM_EUNSUPPORTED, "device index %d beyond %d", device, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device].load()) return LBM_OK;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return fail(LBM_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", device,
+                    hipGetErrorString(e));
+    g_scratch_ptr[device].store(ptr);
+    return LBM_OK;
+}
+
 extern "C" int fno_model_create(fno_model** out, const fno_spec* spec, const float* h_params,
                                 int64_t nparams, int32_t H, int32_t W) {
     if (!out) return fail(LBM_EINVAL, "out is NULL");
@@ -1050,6 +1083,8 @@ extern "C" int fno_model_create(fno_model** out, const fno_spec* spec, const flo
     m->spec = s;
     (void)hipGetDevice(&m->device);
     auto bail = [&](int code) { fno_model_destroy(m); return code; };
+    // set-up of fno_forward_noalloc's workspace on this device (once per device)
+    if (int rc2 = scratch_setup(m->device)) return bail(rc2);
 
     // ---- unpack parameters (layout documented in lbmfno.h)
     const float* p = h_params;
@@ -1309,6 +1344,29 @@ extern "C" int fno_forward_graph(fno_model* m, const float* d_in, float* d_out, 
         m->g_B = B;
     }
     LBM_HIP(hipGraphLaunch(m->fwd_exec, (hipStream_t)stream));
+    return LBM_OK;
+}
+
+// fno_forward on the static scratch array (see the set-up above fno_model_create).
+extern "C" int fno_forward_noalloc(const fno_model* m, const float* d_in, float* d_out, int32_t B,
+                                   void* stream) {
+    if (!m) return fail(LBM_EINVAL, "model is NULL");
+    if (!d_in || !d_out) return fail(LBM_EINVAL, "NULL device buffer");
+    if (B < 1 || (int64_t)B * m->d.Hp * m->d.Wpad > ((int64_t)1 << 31) / 64)
+        return fail(LBM_EINVAL, "B = %d", B);
+    FnoDev d = m->d;
+    d.B = B;
+    const size_t need = ws_layout(d, B).total;
+    if (need > FNO_NOALLOC_SCRATCH_BYTES)
+        return fail(LBM_EINVAL,
+                    "batch %d needs %zu workspace bytes; the static scratch holds %zu "
+                    "(use fno_forward with a caller workspace)",
+                    B, need, (size_t)FNO_NOALLOC_SCRATCH_BYTES);
+    if (m->device < 0 || m->device >= kMaxDevices) return fail(LBM_EINVAL, "model device %d", m->device);
+    void* ws = g_scratch_ptr[m->device].load();
+    if (!ws) return fail(LBM_EHIP, "scratch not set up on device %d", m->device);
+    launch_forward(m, d_in, d_out, B, ws, (hipStream_t)stream);
+    LBM_HIP(hipGetLastError());
     return LBM_OK;
 }
 

@@ -119,6 +119,7 @@ SIGNATURES = [
     ("fno_workspace_size", ctypes.c_int, [_p, _i32, ctypes.POINTER(ctypes.c_size_t)]),
     ("fno_forward", ctypes.c_int, [_p, _p, _p, _i32, _p, ctypes.c_size_t, _p]),
     ("fno_forward_graph", ctypes.c_int, [_p, _p, _p, _i32, _p, ctypes.c_size_t, _p]),
+    ("fno_forward_noalloc", ctypes.c_int, [_p, _p, _p, _i32, _p]),
     ("fno_train_workspace_size", ctypes.c_int, [_p, _i32, ctypes.POINTER(ctypes.c_size_t)]),
     ("fno_forward_train", ctypes.c_int, [_p, _p, _p, _i32, _p, ctypes.c_size_t, _p]),
     ("fno_backward", ctypes.c_int, [_p, _p, _p, _i32, _p, ctypes.c_size_t, _p, _p]),
