@@ -1,9 +1,10 @@
 """GPU parity of the lattice hot path (masks, init/reinit, fused BGK step with
 bounce-back, Zou-He and Guo forcing, macros, FP64 sums) against the FP64 oracle.
 
-Bars: masks and permutations bit-exact; macroscopic fields within 1e-5 relative L2
-over fluid nodes after 1000 and 2000 FP32 steps; FP64 sums within the FP32 state's
-own rounding of the oracle.  Every case prints its error against FP64."""
+Bars: masks and permutations bit-exact; macroscopic fields (rho, ux, uy, and the
+density deviation rho - 1 read at full resolution) within 1e-5 relative L2 over
+fluid nodes after 1000 and 2000 FP32 steps; FP64 sums within the FP32 state's own
+rounding of the oracle.  Every case prints its error against FP64."""
 import math
 
 import numpy as np
@@ -11,7 +12,7 @@ import pytest
 
 from oracle import lbm as olbm
 from paper_2604_27158_amd import workloads as W
-from tests.helpers import field_errors, rel_l2
+from tests.helpers import field_errors, gpu_fields, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -33,7 +34,9 @@ def run_pair(gpu, lat, checkpoints, rho0=None, ux0=None, uy0=None, kernel=0):
     mask = olbm.raster(lat.nx, lat.ny, lat.shapes_array(), lat.wrap_x, lat.wrap_y)
     O = olbm.Sim(lat, mask)
     if rho0 is not None:
-        O.init(rho0, ux0, uy0)
+        # both sides start from the same float32 fields (the library takes float32)
+        rho0, ux0, uy0 = (np.asarray(a, np.float64).astype(np.float32) for a in (rho0, ux0, uy0))
+        O.init(*(a.astype(np.float64) for a in (rho0, ux0, uy0)))
         G.reinit(torch.from_numpy(rho0), torch.from_numpy(ux0), torch.from_numpy(uy0))
     else:
         O.init()
@@ -42,7 +45,7 @@ def run_pair(gpu, lat, checkpoints, rho0=None, ux0=None, uy0=None, kernel=0):
         G.step(c - done)
         O.run(c - done)
         done = c
-        yield c, np_(G.macros()), O.macros(), mask, G, O
+        yield c, gpu_fields(G), O.macros(), mask, G, O
 
 
 @pytest.mark.parametrize("maker,args", [
@@ -71,18 +74,19 @@ def test_channel_parity_1000_2000(gpu, seed, kernel):
     for step, g, r, mask, _, _ in run_pair(gpu, lat, [1000, 2000], kernel=kernel):
         e = field_errors(g, r, mask)
         print(f"seed {seed} step {step}: " + " ".join(f"{k}={v:.2e}" for k, v in e.items()))
-        assert e["rho"] < TOL and e["ux"] < TOL and e["uy"] < TOL, e
+        assert max(e["rho"], e["rho-1"], e["ux"], e["uy"]) < TOL, e
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("seed", [0, 1])
 def test_porous_zouhe_parity_full_size(gpu, seed, kernel):
-    """1024x512 porous medium, Zou-He inlet u = 0.02 / outlet rho = 1, tau = 0.6."""
+    """1024x512 porous medium, Zou-He inlet u = 0.02 / outlet rho = 1, tau = 0.6,
+    1000 and 2000 steps."""
     lat = W.porous_circles(seed)
-    for step, g, r, mask, _, _ in run_pair(gpu, lat, [1000], kernel=kernel):
+    for step, g, r, mask, _, _ in run_pair(gpu, lat, [1000, 2000], kernel=kernel):
         e = field_errors(g, r, mask)
         print(f"{lat.name} step {step}: " + " ".join(f"{k}={v:.2e}" for k, v in e.items()))
-        assert e["rho"] < TOL and e["ux"] < TOL and e["uy"] < TOL, e
+        assert max(e["rho"], e["rho-1"], e["ux"], e["uy"]) < TOL, e
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
@@ -93,7 +97,7 @@ def test_ellipse_zouhe_parity(gpu, seed, size, kernel):
     for step, g, r, mask, _, _ in run_pair(gpu, lat, [1000], *W.plug_flow(lat), kernel=kernel):
         e = field_errors(g, r, mask)
         print(f"{lat.name} step {step}: " + " ".join(f"{k}={v:.2e}" for k, v in e.items()))
-        assert e["rho"] < TOL and e["ux"] < TOL and e["uy"] < TOL, e
+        assert max(e["rho"], e["rho-1"], e["ux"], e["uy"]) < TOL, e
 
 
 def test_ellipse_high_mach_jet_case(gpu):
@@ -104,7 +108,7 @@ def test_ellipse_high_mach_jet_case(gpu):
     for step, g, r, mask, G, _ in run_pair(gpu, lat, [300], *W.plug_flow(lat)):
         e = field_errors(g, r, mask)
         print(f"{lat.name} step {step}: " + " ".join(f"{k}={v:.2e}" for k, v in e.items()))
-        assert e["rho"] < TOL and e["ux"] < TOL and e["uy"] < TOL, e
+        assert max(e["rho"], e["rho-1"], e["ux"], e["uy"]) < TOL, e
     G.step(700)
     assert np.isfinite(np_(G.macros())).all()
 
@@ -130,8 +134,13 @@ def test_ragged_and_tiny_lattices(gpu, nx, ny, bcx, bcy, kernel):
         du = np.sqrt((g[1] - r[1]) ** 2 + (g[2] - r[2]) ** 2)[fl]
         uu = np.sqrt(r[1] ** 2 + r[2] ** 2)[fl]
         e["u"] = float(np.linalg.norm(du) / np.linalg.norm(uu))
+        # the density deviation decays towards its (conserved) mean, which on these
+        # tiny periodic boxes can be ~1e-12: its error is taken relative to the
+        # deviation the run started from
+        e["rho-1 vs start"] = rel_l2(g[0] - 1.0, r[0] - 1.0, fl) * np.linalg.norm((r[0] - 1.0)[fl]) \
+            / np.linalg.norm((rho0 - 1.0)[fl])
         print(f"{nx}x{ny} bc=({bcx},{bcy}) step {step}: " + " ".join(f"{k}={v:.2e}" for k, v in e.items()))
-        assert e["rho"] < TOL and e["u"] < TOL, e
+        assert e["rho"] < TOL and e["rho-1 vs start"] < TOL and e["u"] < TOL, e
 
 
 def test_reinit_gives_equilibrium_populations(gpu):
@@ -351,7 +360,7 @@ def test_large_lattice_parity(gpu, kernel):
     for step, g, r, mask, _, _ in run_pair(gpu, lat, [200], kernel=kernel):
         e = field_errors(g, r, mask)
         print(f"{lat.name} step {step}: " + " ".join(f"{k}={v:.2e}" for k, v in e.items()))
-        assert e["rho"] < TOL and e["ux"] < TOL and e["uy"] < TOL, e
+        assert max(e["rho"], e["rho-1"], e["ux"], e["uy"]) < TOL, e
 
 
 def test_graph_replay_equals_direct_launches(gpu):
@@ -381,9 +390,9 @@ def test_arithmetic_modes_meet_the_bar(gpu, arith, bound):
         for n in (1000, 1000):
             G.step(n)
             O.run(n)
-            e = field_errors(np_(G.macros()), O.macros(), mask)
+            e = field_errors(gpu_fields(G), O.macros(), mask)
             print(f"{arith} {lat.name} step {O.steps}: " + " ".join(f"{k}={v:.2e}" for k, v in e.items()))
-            assert max(e["rho"], e["ux"], e["uy"]) < min(bound, 1e-5)
+            assert max(e["rho"], e["ux"], e["uy"]) < min(bound, 1e-5) and e["rho-1"] < 1e-5, e
 
 
 def test_all_fp32_arithmetic_variant_reports_its_error(gpu):
@@ -396,7 +405,7 @@ def test_all_fp32_arithmetic_variant_reports_its_error(gpu):
     for n in (1000, 1000):
         G.step(n)
         O.run(n)
-        e = field_errors(np_(G.macros()), O.macros(), mask)
+        e = field_errors(gpu_fields(G), O.macros(), mask)
         print(f"all-FP32 step {O.steps}: " + " ".join(f"{k}={v:.2e}" for k, v in e.items()))
         assert max(e["rho"], e["ux"], e["uy"]) < 1e-4
 
@@ -417,7 +426,7 @@ def test_trt_channel_parity_2000(gpu, seed, lam, kernel):
     for step, g, r, mask, _, _ in run_pair(gpu, lat, [1000, 2000], kernel=kernel):
         e = field_errors(g, r, mask)
         print(f"{lat.name} step {step}: " + " ".join(f"{k}={v:.2e}" for k, v in e.items()))
-        assert e["rho"] < TOL and e["ux"] < TOL and e["uy"] < TOL, e
+        assert max(e["rho"], e["rho-1"], e["ux"], e["uy"]) < TOL, e
 
 
 def test_trt_zouhe_parity_and_kernels_agree_bitwise(gpu):
@@ -428,7 +437,7 @@ def test_trt_zouhe_parity_and_kernels_agree_bitwise(gpu):
     for step, g, r, mask, _, _ in run_pair(gpu, lat, [1000]):
         e = field_errors(g, r, mask)
         print(f"{lat.name} step {step}: " + " ".join(f"{k}={v:.2e}" for k, v in e.items()))
-        assert e["rho"] < TOL and e["ux"] < TOL and e["uy"] < TOL, e
+        assert max(e["rho"], e["rho-1"], e["ux"], e["uy"]) < TOL, e
     runs = [gpu_lattice(gpu, lat, k) for k in (1, 2, 3)]
     for G in runs:
         G.step(301)
