@@ -439,6 +439,16 @@ int fno_train_workspace_size(const fno_model* m, int32_t B, size_t* bytes);
 int fno_forward_train(const fno_model* m, const float* d_in, float* d_out, int32_t B,
                       void* d_ws, size_t ws_bytes, void* stream);
 
+/* The latent state v_l that the last fno_forward_train saved in d_ws (same B):
+ * layer 0 is the lift's output (after the zero padding), layer l = 1..L the output
+ * of Fourier layer l - 1 (after its activation; none after the last), each as the
+ * bfloat16 values the forward carried, converted to float32 into d_out
+ * [B][width][H'][W'] (H' = H + padding, W' = W + padding).  For inspecting the
+ * forward stage by stage (Sec. 2.2, Eq. 6: lift, Fourier layers, decoder).
+ * Asynchronous on `stream`. */
+int fno_train_latent(const fno_model* m, const void* d_ws, size_t ws_bytes, int32_t B,
+                     int32_t layer, float* d_out, void* stream);
+
 /* Gradient of a scalar loss w.r.t. the packed parameters (layout above):
  * d_dout[B][cout][H][W] = dLoss/d out (float32, device); writes every element of
  * d_grad[fno_param_count] (float32, device; overwritten, not accumulated).

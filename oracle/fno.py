@@ -186,39 +186,64 @@ def coords(B, H, W):
     return xs, ys
 
 
-def forward(spec: Spec, flat_params, x, precision: str = "fp64", return_latent: bool = False):
-    """FNO forward on x [B][Cin][H][W] -> [B][Cout][H][W] (float64)."""
+def _policy(precision: str):
+    """(bf16 rounding, float32 rounding) of the precision mode."""
     if precision not in ("fp64", "bf16"):
         raise ValueError(precision)
-    bf = precision == "bf16"
-    rb = round_bf16 if bf else (lambda a: a)
-    r32 = round_f32 if bf else (lambda a: a)
-    P = unpack(spec, flat_params)
+    if precision == "bf16":
+        return round_bf16, round_f32
+    return (lambda a: a), (lambda a: a)
+
+
+def lift(spec: Spec, P: dict, x, precision: str = "fp64"):
+    """Stage 1: coordinates appended, P2(act(P1(.))) pointwise, zero padding on the
+    high side of H and W; returns the first latent v_0 [B][width][H'][W']."""
+    rb, r32 = _policy(precision)
     x = np.asarray(x, dtype=np.float64)
-    if bf:
+    if precision == "bf16":
         x = round_f32(x)
     B, _, H, W = x.shape
-    act, dact = ACTS[spec.act], ACTS[spec.dec_act]
     if spec.coords:
         xs, ys = coords(B, H, W)
         x = np.concatenate([x, xs, ys], axis=1)
     # lift (float32 weights in the bf16 policy, no bf16 rounding of its operands)
-    h = act(pointwise(r32(P["lift1.w"]), r32(P["lift1.b"]), x))
+    h = ACTS[spec.act](pointwise(r32(P["lift1.w"]), r32(P["lift1.b"]), x))
     v = pointwise(r32(P["lift2.w"]), r32(P["lift2.b"]), h)
     p = spec.padding
     if p:
         v = np.pad(v, ((0, 0), (0, 0), (0, p), (0, p)))
-    v = rb(v)
+    return rb(v)
+
+
+def fourier_layer(spec: Spec, P: dict, v, n: int, precision: str = "fp64"):
+    """Fourier layer n on the latent v [B][width][H'][W']: act(W v + b + F^-1(R F v)),
+    no activation after the last layer (Eq. 6)."""
+    rb, r32 = _policy(precision)
+    s = spectral_conv(v, P[f"spec{n}.r_top"], P[f"spec{n}.r_bot"], spec.m1, spec.m2, rb)
+    s = s + pointwise(P[f"conv{n}.w"], r32(P[f"conv{n}.b"]), v, rb)
+    v = ACTS[spec.act](s) if n < spec.layers - 1 else s
+    return rb(v)
+
+
+def decode(spec: Spec, P: dict, v, H: int, W: int, precision: str = "fp64"):
+    """Stage 3: crop the padding, then the pointwise decoder Q -> [B][Cout][H][W]."""
+    rb, r32 = _policy(precision)
+    v = v[:, :, :H, :W]
+    for n in range(spec.dec_layers):
+        v = rb(ACTS[spec.dec_act](pointwise(P[f"dec{n}.w"], r32(P[f"dec{n}.b"]), v, rb)))
+    return pointwise(P["dec_out.w"], r32(P["dec_out.b"]), v, rb)
+
+
+def forward(spec: Spec, flat_params, x, precision: str = "fp64", return_latent: bool = False):
+    """FNO forward on x [B][Cin][H][W] -> [B][Cout][H][W] (float64): lift, the
+    Fourier layers, decoder."""
+    _policy(precision)
+    P = unpack(spec, flat_params)
+    H, W = np.shape(x)[2], np.shape(x)[3]
+    v = lift(spec, P, x, precision)
     latents = [v]
     for n in range(spec.layers):
-        s = spectral_conv(v, P[f"spec{n}.r_top"], P[f"spec{n}.r_bot"], spec.m1, spec.m2, rb)
-        s = s + pointwise(P[f"conv{n}.w"], r32(P[f"conv{n}.b"]), v, rb)
-        v = act(s) if n < spec.layers - 1 else s
-        v = rb(v)
+        v = fourier_layer(spec, P, v, n, precision)
         latents.append(v)
-    if p:
-        v = v[:, :, :H, :W]
-    for n in range(spec.dec_layers):
-        v = rb(dact(pointwise(P[f"dec{n}.w"], r32(P[f"dec{n}.b"]), v, rb)))
-    out = pointwise(P["dec_out.w"], r32(P["dec_out.b"]), v, rb)
+    out = decode(spec, P, v, H, W, precision)
     return (out, latents) if return_latent else out

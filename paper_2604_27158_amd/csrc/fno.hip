@@ -1963,6 +1963,37 @@ extern "C" int fno_forward_train(const fno_model* m, const float* d_in, float* d
     return LBM_OK;
 }
 
+// Latent v[l] (bf16 [B][Hp][Wpad][CP], channels last) -> float32 [B][width][Hp][Wp].
+__global__ __launch_bounds__(256) void k_fno_export_latent(FnoDev d, const __bf16* __restrict__ v,
+                                                           float* __restrict__ out) {
+    const size_t n = (size_t)d.B * d.width * d.Hp * d.Wp;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const int w = (int)(i % d.Wp);
+        size_t r = i / d.Wp;
+        const int h = (int)(r % d.Hp);
+        r /= d.Hp;
+        const int c = (int)(r % d.width);
+        const size_t b = r / d.width;
+        out[i] = (float)v[((b * d.Hp + h) * d.Wpad + w) * d.CP + c];
+    }
+}
+
+extern "C" int fno_train_latent(const fno_model* m, const void* d_ws, size_t ws_bytes, int32_t B,
+                                int32_t layer, float* d_out, void* stream) {
+    int rc = check_train_args(m, B, const_cast<void*>(d_ws), ws_bytes);
+    if (rc) return rc;
+    if (!d_out) return fail(LBM_EINVAL, "NULL buffer");
+    if (layer < 0 || layer > m->d.L) return fail(LBM_EINVAL, "layer = %d (0..%d)", layer, m->d.L);
+    FnoDev d = m->d;
+    d.B = B;
+    const TrainPtrs P = train_ptrs(d, train_layout(d, B), const_cast<void*>(d_ws));
+    const size_t n = (size_t)B * d.width * d.Hp * d.Wp;
+    const unsigned grid = (unsigned)std::min<size_t>((n + 255) / 256, 65536);
+    k_fno_export_latent<<<grid, 256, 0, (hipStream_t)stream>>>(d, P.v[layer], d_out);
+    LBM_HIP(hipGetLastError());
+    return LBM_OK;
+}
+
 static void outer_reduce(hipStream_t st, float* partials, const float* A, int lda, const void* X,
                          bool xbf, int ldx, size_t P, int N, int M, float* gw, float* gb) {
     const unsigned chunks = (unsigned)std::min<size_t>((P + OUT_TP - 1) / OUT_TP, OUT_MAX_BLOCKS);

@@ -160,6 +160,18 @@ class Trainer:
                  "fno_forward_train")
         return out
 
+    def latent(self, B: int, layer: int):
+        """Latent v_layer [B][width][H'][W'] float32 that the last forward() saved
+        (0: the lift's output, l: the output of Fourier layer l - 1)."""
+        import torch
+        s = self.fno.spec
+        out = torch.empty((B, s.width, self.fno.H + s.padding, self.fno.W + s.padding),
+                          dtype=torch.float32, device="cuda")
+        ws = self.workspace(B)
+        _L.check(self.lib.fno_train_latent(self.fno.model, ws.data_ptr(), ws.numel(), int(B), int(layer),
+                                           out.data_ptr(), _L.stream_handle(self.stream)), "fno_train_latent")
+        return out
+
     def backward(self, x, dout):
         """Gradient (into self.g) for the activations the last forward() saved."""
         self._check_x(x)

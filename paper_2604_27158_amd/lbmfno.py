@@ -123,6 +123,7 @@ SIGNATURES = [
     ("fno_train_workspace_size", ctypes.c_int, [_p, _i32, ctypes.POINTER(ctypes.c_size_t)]),
     ("fno_forward_train", ctypes.c_int, [_p, _p, _p, _i32, _p, ctypes.c_size_t, _p]),
     ("fno_backward", ctypes.c_int, [_p, _p, _p, _i32, _p, ctypes.c_size_t, _p, _p]),
+    ("fno_train_latent", ctypes.c_int, [_p, _p, ctypes.c_size_t, _i32, _i32, _p, _p]),
     ("fno_mse", ctypes.c_int, [_p, _p, ctypes.c_size_t, _p, _p, ctypes.c_size_t,
                                ctypes.POINTER(ctypes.c_double), _p]),
     ("fno_set_params", ctypes.c_int, [_p, _p, _p]),

@@ -41,6 +41,8 @@ def rel(a, b):
 CASES = [
     # (name, spec, H, W, B)
     ("flagship-w32-L4-m12", W.FnoSpec(), 64, 64, 2),
+    # the flagship at its own 256 x 128 grid
+    ("flagship-128x256", W.FnoSpec(), 128, 256, 1),
     ("porous-rho-paper", W.FnoSpec(cin=1, width=16, layers=3, m1=6, m2=6, dec_layers=3, dec_size=32,
                                    cout=1, padding=9), 64, 128, 1),
     ("ragged-50x70-w64", W.FnoSpec(cin=3, width=64, layers=2, m1=5, m2=7, dec_layers=2, dec_size=48,
