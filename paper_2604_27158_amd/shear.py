@@ -178,9 +178,17 @@ def is_fno_interval(t: int, k: int) -> bool:
     return t % (k + 1) == 0
 
 
-def rollouts(sur: Surrogate, seed: int, neq: bool = False, mass: bool = False):
-    """Outputs 1..30 of the plain lattice, the pure FNO and the 1:k hybrids from one
-    initial condition, as raw (rho, ux, uy) numpy fields, plus the hybrids' counts."""
+def host_fields(G):
+    """(rho, ux, uy) of a lattice as float64 host fields, rho = 1 + (rho - 1) from the
+    library's full-resolution density deviation."""
+    m = G.macros(rho_minus_one=True).cpu().numpy().astype(np.float64)
+    m[0] += 1.0
+    return m
+
+
+def rollouts(sur: Surrogate, seed: int, neq: bool = False, mass: bool = False, ks=HYBRIDS):
+    """Outputs 1..30 of the plain lattice, the pure FNO and the 1:k hybrids (k in ks)
+    from one initial condition, as raw (rho, ux, uy) numpy fields."""
     import torch
     from paper_2604_27158_amd import lbmfno
     lat, r0, u0, v0 = W.double_shear_layer(seed, N)
@@ -190,14 +198,14 @@ def rollouts(sur: Surrogate, seed: int, neq: bool = False, mass: bool = False):
     ref = []
     for _ in range(OUTPUTS):
         G.step(DT)
-        ref.append(G.macros().cpu().numpy().astype(np.float64))
+        ref.append(host_fields(G))
     x = ic.clone()
     pure = []
     for _ in range(OUTPUTS):
         x = sur.step(x)
         pure.append(x.cpu().numpy().astype(np.float64))
     hyb = {}
-    for k in HYBRIDS:
+    for k in ks:
         H = lbmfno.Lattice.from_workload(lat)
         out = []
         with torch.cuda.stream(H.stream):
@@ -210,12 +218,13 @@ def rollouts(sur: Surrogate, seed: int, neq: bool = False, mass: bool = False):
                     out.append(y.cpu().numpy().astype(np.float64))
                 else:
                     H.step(DT)
-                    out.append(H.macros().cpu().numpy().astype(np.float64))
+                    out.append(host_fields(H))
         hyb[k] = out
     return ref, pure, hyb
 
 
-def timed_runs(sur: Surrogate, seed: int, reps: int = 3, neq: bool = False, mass: bool = False):
+def timed_runs(sur: Surrogate, seed: int, reps: int = 3, neq: bool = False, mass: bool = False,
+               ks=HYBRIDS):
     """Wall time of the 30 Delta T horizon on this GPU: plain lattice and each 1:k
     hybrid (FNO calls, re-initialisations and lattice steps; no measurements)."""
     import torch
@@ -262,9 +271,51 @@ def timed_runs(sur: Surrogate, seed: int, reps: int = 3, neq: bool = False, mass
         return best
 
     res = {"plain": clock(plain)}
-    for k in HYBRIDS:
+    for k in ks:
         res[k] = clock(lambda k=k: hybrid(k))
     return res
+
+
+SWEEP = (1, 2, 3, 4, 6, 9, 14, 29)   # 1:k cadences of the sweep (1:29: one FNO interval)
+
+
+def cadence_sweep(group: str, seeds, ks=SWEEP, thresholds=(0.02, 0.05, 0.1), log=None,
+                  path: str | None = None):
+    """Wall time against error for 1:k hybrids over the 30-output horizon: for every
+    cadence the global vorticity error and MSE (means over the outputs and the
+    seeds) and eps_T (mean over the seeds of each seed's best-of-three wall times);
+    then, for each stated vorticity error, the fastest cadence whose error stays
+    within it and its eps_T against the plain lattice (time to error)."""
+    sur = Surrogate(group, path)
+    errs = {k: [] for k in ks}
+    eps_t = {k: [] for k in ks}
+    plain_s = []
+    for n, s in enumerate(seeds):
+        ref, _, hyb = rollouts(sur, s, ks=ks)
+        times = timed_runs(sur, s, ks=ks)
+        plain_s.append(times["plain"])
+        for k in ks:
+            e = np.array([errors(p, r) for p, r in zip(hyb[k], ref)])
+            errs[k].append(e.mean(axis=0))
+            eps_t[k].append((times["plain"] - times[k]) / times["plain"])
+        if log:
+            log(f"cadence sweep: seed {s} ({n + 1}/{len(seeds)})")
+    rows = []
+    for k in ks:
+        m = np.mean(errs[k], axis=0)
+        rows.append({"cadence": f"1:{k}", "k": k,
+                     "eps_N_pct": 100.0 * sum(is_fno_interval(t, k) for t in range(OUTPUTS)) / OUTPUTS,
+                     "eps_T_pct": 100.0 * float(np.mean(eps_t[k])),
+                     "eps_T_pct_std": 100.0 * float(np.std(eps_t[k])),
+                     "global_vorticity": float(m[1]), "global_mse": float(m[0])})
+    tte = {}
+    for eps in thresholds:
+        ok = [r for r in rows if r["global_vorticity"] <= eps]
+        best = max(ok, key=lambda r: r["eps_T_pct"]) if ok else None
+        tte[f"vorticity<={eps:g}"] = ({"cadence": best["cadence"], "eps_T_pct": best["eps_T_pct"],
+                                        "global_vorticity": best["global_vorticity"]} if best else None)
+    return {"group": group, "seeds": len(seeds), "seconds_plain_mean": float(np.mean(plain_s)),
+            "sweep": rows, "time_to_error": tte}
 
 
 def study(group: str, seeds, log=None, path: str | None = None, neq: bool = False, mass: bool = False):
@@ -326,9 +377,18 @@ def main():
     e.add_argument("--json", default=None)
     e.add_argument("--neq", action="store_true", help="re-initialise with the non-equilibrium part")
     e.add_argument("--mass", action="store_true", help="mass-conserving re-initialisation")
+    c = sub.add_parser("sweep")
+    c.add_argument("--group", default="small", choices=sorted(GROUPS))
+    c.add_argument("--weights", default=None)
+    c.add_argument("--seeds", type=int, default=6)
     args = ap.parse_args()
     from paper_2604_27158_amd import lbmfno
     lbmfno.load()
+    if args.cmd == "sweep":
+        import json
+        log_print(json.dumps(cadence_sweep(args.group, list(TEST_SEEDS)[:args.seeds], log=log_print,
+                                           path=args.weights)))
+        return
     if args.cmd == "eval":
         import json
         res = study(args.group, list(TEST_SEEDS)[:args.seeds], log_print, args.weights, neq=args.neq,
