@@ -274,6 +274,93 @@ def hybrid_study(fno: "TrainedFno", seeds, log=None):
             "per_seed": per_seed}
 
 
+# (K FNO calls of DT_FNO steps, n lattice steps) per cycle; every cycle length divides
+# the 14 000-step horizon.  (5, 200) is the configured cadence.
+CADENCES = ((1, 100), (1, 300), (1, 400), (1, 600), (2, 500), (5, 200), (1, 900), (5, 500), (1, 1900),
+            (1, 3400))
+HORIZON = CYCLES * (K_FNO * DT_FNO + N_LBM)
+
+
+def velocity_error(a, b, fl):
+    """rel-L2 over fluid nodes of the velocity as a vector field, fields [3][ny][nx]."""
+    d = (a[1:] - b[1:])[:, fl].double().pow(2).sum().sqrt()
+    return float(d / b[1:][:, fl].double().pow(2).sum().sqrt())
+
+
+def cadence_study(fno: "TrainedFno", seeds, cadences=CADENCES, thresholds=(0.05, 0.1, 0.2),
+                  reps: int = 3, log=None):
+    """Wall time against error for hybrid cadences over the same 14 000-step horizon
+    after the spin-up: for each cadence the velocity error at the horizon against the
+    plain lattice (mean over seeds) and eps_T (mean over seeds of best-of-`reps` wall
+    times, speculative guard); then, per stated velocity error, the fastest cadence
+    within it (time to error).  Seeds whose plain run loses stability are skipped."""
+    import torch
+    from paper_2604_27158_amd import lbmfno
+    from paper_2604_27158_amd.hybrid import HybridRunner, Guard, step_reduction
+    err = {c: [] for c in cadences}
+    eps_t = {c: [] for c in cadences}
+    used = []
+    for s in seeds:
+        lat = geometry(s)
+        G = lbmfno.Lattice.from_workload(lat)
+        G.reinit(*(torch.from_numpy(a) for a in W.plug_flow(lat)))
+        G.step(SPINUP)
+        start = G.save_state()
+        G.step(HORIZON)
+        ref = G.macros().clone()
+        if not bool(torch.isfinite(ref).all()) or float(ref[1:].abs().max()) > 0.35:
+            if log:
+                log(f"seed {s}: plain run unstable, skipped")
+            continue
+        used.append(s)
+        fl = G.mask == 0
+        H = lbmfno.Lattice.from_workload(lat)
+
+        def run_plain():
+            G.load_state(start)
+            G.synchronize()
+            t0 = time.perf_counter()
+            with torch.cuda.stream(G.stream):
+                G.step(HORIZON)
+            G.synchronize()
+            return time.perf_counter() - t0
+
+        def run_hybrid(K, n):
+            H.load_state(start)
+            r = HybridRunner(H, fno.model, dt_fno=DT_FNO, k_fno=K, n_lbm=n,
+                             guard=Guard(max_speed=0.35, mass_rel_tol=0.05), speculative=True)
+            H.synchronize()
+            t0 = time.perf_counter()
+            r.run(HORIZON // (K * DT_FNO + n))
+            H.synchronize()
+            return time.perf_counter() - t0
+
+        run_plain()
+        t_plain = min(run_plain() for _ in range(reps))
+        for (K, n) in cadences:
+            run_hybrid(K, n)
+            err[(K, n)].append(velocity_error(H.macros(), ref, fl))
+            t = min(run_hybrid(K, n) for _ in range(reps))
+            eps_t[(K, n)].append((t_plain - t) / t_plain)
+        if log:
+            log(f"seed {s}: " + " ".join(f"{K}x{DT_FNO}+{n}: err {err[(K, n)][-1]:.3f} eps_T "
+                                          f"{100 * eps_t[(K, n)][-1]:.1f}%" for (K, n) in cadences))
+    rows = []
+    for (K, n) in cadences:
+        rows.append({"cadence": f"{K} x {DT_FNO} FNO + {n} LBM", "k_fno": K, "n_lbm": n,
+                     "eps_N_pct": 100.0 * step_reduction(K, DT_FNO, n),
+                     "eps_T_pct": 100.0 * float(np.mean(eps_t[(K, n)])),
+                     "eps_T_pct_std": 100.0 * float(np.std(eps_t[(K, n)])),
+                     "velocity_rel_l2_at_horizon": float(np.mean(err[(K, n)]))})
+    tte = {}
+    for eps in thresholds:
+        ok = [r for r in rows if r["velocity_rel_l2_at_horizon"] <= eps]
+        best = max(ok, key=lambda r: r["eps_T_pct"]) if ok else None
+        tte[f"velocity<={eps:g}"] = ({k: best[k] for k in ("cadence", "eps_T_pct", "velocity_rel_l2_at_horizon")}
+                                      if best else None)
+    return {"seeds": len(used), "horizon_steps": HORIZON, "sweep": rows, "time_to_error": tte}
+
+
 def log_print(msg):
     print(msg, flush=True)
 
@@ -290,10 +377,18 @@ def main():
     e.add_argument("--weights", default=DEFAULT_WEIGHTS)
     e.add_argument("--seeds", type=int, default=len(TEST_SEEDS))
     e.add_argument("--json", default=None)
+    c = sub.add_parser("sweep")
+    c.add_argument("--weights", default=DEFAULT_WEIGHTS)
+    c.add_argument("--seeds", type=int, default=8)
     args = ap.parse_args()
     import torch
     from paper_2604_27158_amd import lbmfno
     lbmfno.load()
+    if args.cmd == "sweep":
+        import json
+        log_print(json.dumps(cadence_study(TrainedFno(args.weights), list(TEST_SEEDS)[:args.seeds],
+                                           log=log_print)))
+        return
     if args.cmd == "eval":
         import json
         res = hybrid_study(TrainedFno(args.weights), list(TEST_SEEDS)[:args.seeds], log=log_print)
