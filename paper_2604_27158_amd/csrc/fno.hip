@@ -5,13 +5,15 @@
 // Data layout (device workspace, per sample b):
 //   v  [Hp][Wpad][CP]   bf16  activations, channels last (CP = width rounded up to
 //                             32, Wpad = W' rounded up to 32; w >= W' is zero)
-//   T  [m2][CP][2][Hpad] bf16 row-DFT coefficients (re, im) with h fastest
+//   T  [Hpad][m2][CP][2] bf16 row-DFT coefficients (re, im): each row h one
+//                             contiguous block, written by the row's own workgroup
 //   Z  [2 m2][Hp][CP]   bf16  column-inverse coefficients, row kk = 2 k2 + (re/im),
 //                             channels fastest (each mode group stores whole rows)
 // Every contraction is arranged so that both MFMA operands are contiguous along
 // the summed index, i.e. each lane fetches its eight bf16 as one 16-byte load:
 //   row forward   T[kk][c]   = sum_w  EwT[kk][w]   * vt[c][w]     (vt staged in LDS)
-//   column        X[r][c]    = sum_hk EcolA[r][hk] * T[c][hk]     (per sample, k2)
+//   column        X[r][c]    = sum_hk EcolA[r][hk] * T[c][hk]     (per sample, k2; T of
+//                                the column staged transposed into LDS)
 //   mixing        Y[k][o]    = sum_i  X[k][i] R[i][o]              (complex, per mode)
 //   column inv    Zc[q][o]   = sum_r  EcolB[q][r]  * Y[o][r]
 //   row inverse   s[w][o]    = sum_kk BinvT[w][kk] * Z[o][kk] + sum_i v[w][i] * Wc[o][i]
@@ -82,6 +84,43 @@ __device__ __forceinline__ int acc_row(int r) {
 }
 __device__ __forceinline__ int acc_col() { return threadIdx.x & 31; }
 
+// C += A[32 x 16 KS] * Bt[32 x 16 KS]^T with KS (the number of 16-wide k-steps)
+// known at compile time: every operand is requested before the first product (one
+// exposed memory latency), with no loop and no unused operand slots.  Same operand
+// layout and k order as mma_tile, so the two give identical results.
+template <int KS>
+__device__ __forceinline__ f32x16 mma_k(const __bf16* A, int lda, const __bf16* Bt, int ldb, f32x16 acc) {
+    const int lane = threadIdx.x & 63;
+    const __bf16* a = A + (lane & 31) * lda + 8 * (lane >> 5);
+    const __bf16* b = Bt + (lane & 31) * ldb + 8 * (lane >> 5);
+    bf16x8 av[KS], bv[KS];
+#pragma unroll
+    for (int j = 0; j < KS; ++j) {
+        av[j] = *reinterpret_cast<const bf16x8*>(a + 16 * j);
+        bv[j] = *reinterpret_cast<const bf16x8*>(b + 16 * j);
+    }
+#pragma unroll
+    for (int j = 0; j < KS; ++j) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[j], bv[j], acc, 0, 0, 0);
+    return acc;
+}
+
+// K = 16 KS with KS a template constant when it is 2 or 4 (KS = 0: run-time K).
+template <int KS>
+__device__ __forceinline__ f32x16 mma_any(const __bf16* A, int lda, const __bf16* Bt, int ldb, int K,
+                                          f32x16 acc) {
+    if constexpr (KS > 0) return mma_k<KS>(A, lda, Bt, ldb, acc);
+    else return mma_tile(A, lda, Bt, ldb, K, acc);
+}
+
+// Packed round-to-nearest-even bf16 pair (lo, hi) in one 32-bit word.
+__device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    bf16x2 p;
+    p[0] = (__bf16)lo;
+    p[1] = (__bf16)hi;
+    return *reinterpret_cast<uint32_t*>(&p);
+}
+
 // GELU x Phi(x) = x (1 + erf(x / sqrt 2)) / 2 for the forward kernels, with erf from
 // Abramowitz & Stegun, Handbook of Mathematical Functions, 7.1.26: for z >= 0,
 // erf z = 1 - t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-z^2), t = 1 / (1 + p z),
@@ -137,6 +176,7 @@ struct FnoDev {
     const __bf16* B1;       // [Wpad][KKp] unit-coefficient inverse row basis (backward)
     const __bf16* decwT;    // hidden decoder layers transposed, [din_p][DSP] each (backward)
     int DKP;                // decoder LDS row stride (bf16 elements)
+    int colS;               // column kernel: parts its column DFT's K range is split into
     // workspace
     __bf16 *v0, *v1, *T, *Z;
     // training forward: saved activations (NULL in plain inference)
@@ -240,9 +280,19 @@ __global__ __launch_bounds__(256) void k_fno_lift(FnoDev d, const float* __restr
 // the column transform's padded K range is exactly zero).
 // Row DFT of row (b, h < Hp) from its transposed copy vt[c][w] in LDS:
 // T[k2][c][ri][h] = sum_w EwT[2 k2 + ri][w] vt[c][w].
+// Row h of sample b in T: m2 * CP (re, im) pairs, pair (k2, c) at 2 (k2 CP + c).
+__device__ __forceinline__ __bf16* t_row(const FnoDev& d, int b, int h) {
+    return d.T + ((size_t)b * d.Hpad + h) * d.m2 * d.CP * 2;
+}
+
+// Rows h >= Hp of T are zero (the column transform's K range runs over Hpad rows).
+__device__ __forceinline__ void t_zero_row(const FnoDev& d, int b, int h) {
+    uint32_t* row = reinterpret_cast<uint32_t*>(t_row(d, b, h));
+    for (int i = threadIdx.x; i < d.m2 * d.CP; i += blockDim.x) row[i] = 0u;
+}
+
 __device__ __forceinline__ void row_dft_from_lds(const FnoDev& d, const __bf16* vt, int b, int h) {
-    const size_t tstride = (size_t)2 * d.Hpad;
-    __bf16* Tb = d.T + (size_t)b * d.m2 * d.CP * tstride;
+    uint32_t* Tr = reinterpret_cast<uint32_t*>(t_row(d, b, h));
     const int wave = threadIdx.x >> 6;
     const int Mt = d.KKp / 32, Nt = d.CP / 32;
     for (int t = wave; t < Mt * Nt; t += blockDim.x >> 6) {
@@ -251,14 +301,27 @@ __device__ __forceinline__ void row_dft_from_lds(const FnoDev& d, const __bf16* 
         acc = mma_tile(d.EwT + (size_t)mi * 32 * d.Wpad, d.Wpad, vt + ni * 32 * vt_stride(d), vt_stride(d),
                        d.Wpad, acc);
         const int c = ni * 32 + acc_col();
+        // rows kk = 2 k2 + ri come in (re, im) pairs: one packed word per pair, and the
+        // 32 lanes of a half-wave store 32 consecutive words
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
+        for (int r = 0; r < 16; r += 2) {
             const int kk = mi * 32 + acc_row(r);
-            if (kk < 2 * d.m2) {
-                const int k2 = kk >> 1, ri = kk & 1;
-                Tb[((size_t)k2 * d.CP + c) * tstride + ri * d.Hpad + h] = to_bf16(acc[r]);
-            }
+            if (kk < 2 * d.m2) Tr[(kk >> 1) * d.CP + c] = pack_bf16(acc[r], acc[r + 1]);
         }
+    }
+}
+
+// The row held transposed in LDS, vt[c][w], stored channels last to orow[w][c]:
+// each thread assembles 8 channels of one point, and consecutive threads take
+// consecutive 16-byte pieces of the row, so a wave writes 1 KB of it contiguously.
+__device__ __forceinline__ void store_row_from_vt(const FnoDev& d, const __bf16* vt, __bf16* orow) {
+    const int VS = vt_stride(d), ncg = d.CP / 8;
+    for (int i = threadIdx.x; i < d.Wpad * ncg; i += blockDim.x) {
+        const int w = i / ncg, c0 = 8 * (i - w * ncg);
+        bf16x8 t;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) t[e] = vt[(c0 + e) * VS + w];
+        *reinterpret_cast<bf16x8*>(orow + w * d.CP + c0) = t;
     }
 }
 
@@ -267,13 +330,8 @@ __global__ __launch_bounds__(256) void k_fno_rowfwd(FnoDev d, const __bf16* __re
     __bf16* vt = reinterpret_cast<__bf16*>(smem);  // [CP][vt_stride]
     const int b = blockIdx.x / d.Hpad, h = blockIdx.x % d.Hpad;
     const int tid = threadIdx.x;
-    const size_t tstride = (size_t)2 * d.Hpad;
-    __bf16* Tb = d.T + (size_t)b * d.m2 * d.CP * tstride;
     if (h >= d.Hp) {
-        for (int i = tid; i < d.m2 * d.CP * 2; i += blockDim.x) {
-            const int ri = i & 1, kc = i >> 1;  // kc = k2 * CP + c
-            Tb[(size_t)kc * tstride + ri * d.Hpad + h] = to_bf16(0.0f);
-        }
+        t_zero_row(d, b, h);
         return;
     }
     const __bf16* row = v + ((size_t)b * d.Hp + h) * d.Wpad * d.CP;
@@ -304,12 +362,7 @@ __global__ __launch_bounds__(1024) void k_fno_lift_row(FnoDev d, const float* __
     const int b = blockIdx.x / d.Hpad, h = blockIdx.x % d.Hpad;
     const int tid = threadIdx.x;
     if (h >= d.Hp) {
-        const size_t tstride = (size_t)2 * d.Hpad;
-        __bf16* Tb = d.T + (size_t)b * d.m2 * d.CP * tstride;
-        for (int i = tid; i < d.m2 * d.CP * 2; i += blockDim.x) {
-            const int ri = i & 1, kc = i >> 1;  // kc = k2 * CP + c
-            Tb[(size_t)kc * tstride + ri * d.Hpad + h] = to_bf16(0.0f);
-        }
+        t_zero_row(d, b, h);
         return;
     }
     for (int t = tid; t < 32 * 8; t += blockDim.x) {
@@ -325,7 +378,6 @@ __global__ __launch_bounds__(1024) void k_fno_lift_row(FnoDev d, const float* __
     __syncthreads();
     const int w = tid;
     if (w < d.Wpad) {
-        __bf16* out = d.v0 + (((size_t)b * d.Hp + h) * d.Wpad + w) * d.CP;
         float o[NO];
 #pragma unroll
         for (int c = 0; c < NO; ++c) o[c] = 0.0f;
@@ -361,16 +413,30 @@ __global__ __launch_bounds__(1024) void k_fno_lift_row(FnoDev d, const float* __
         }
 #pragma unroll
         for (int c0 = 0; c0 < NO; c0 += 8) {
-            bf16x8 t;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) t[e] = to_bf16(o[c0 + e]);
-            *reinterpret_cast<bf16x8*>(out + c0) = t;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) vt[(size_t)(c0 + e) * vt_stride(d) + w] = t[e];
+            for (int e = 0; e < 8; ++e) vt[(size_t)(c0 + e) * vt_stride(d) + w] = to_bf16(o[c0 + e]);
         }
     }
     __syncthreads();
     row_dft_from_lds(d, vt, b, h);
+    store_row_from_vt(d, vt, d.v0 + ((size_t)b * d.Hp + h) * d.Wpad * d.CP);
+}
+
+// Row stride (bf16) of a column's T staged in LDS, [CP][TS], K = (ri, h) contiguous.
+__host__ __device__ __forceinline__ int ts_stride(const FnoDev& d) { return 2 * d.Hpad + 8; }
+
+// T of column k2 of sample b, staged transposed: tsl[c][ri * Hpad + h] (the MFMA
+// operand layout, K contiguous).  Each row h holds the column's CP (re, im) pairs
+// as one 128-byte (CP = 32) piece, read with 16-byte loads.  Ends with a barrier.
+__device__ __forceinline__ void stage_t(const FnoDev& d, int b, int k2, __bf16* tsl) {
+    const int TS = ts_stride(d), nq = d.CP / 4;
+    for (int i = threadIdx.x; i < d.Hpad * nq; i += blockDim.x) {
+        const int h = i / nq, q = i - h * nq;
+        const bf16x8 t = *reinterpret_cast<const bf16x8*>(t_row(d, b, h) + (size_t)k2 * d.CP * 2 + 8 * q);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) tsl[(4 * q + (e >> 1)) * TS + (e & 1) * d.Hpad + h] = t[e];
+    }
+    __syncthreads();
 }
 
 // Column forward DFT, per-mode complex mixing and column inverse DFT for one
@@ -381,21 +447,23 @@ constexpr int COL_THREADS = 512;
 
 __global__ __launch_bounds__(COL_THREADS) void k_fno_col(FnoDev d, int layer) {
     extern __shared__ __align__(16) unsigned char smem[];
-    float* xs = reinterpret_cast<float*>(smem);                                  // [R2][CP]
-    __bf16* ys = reinterpret_cast<__bf16*>(smem + sizeof(float) * d.R2 * d.CP);  // [CP][R2]
+    __bf16* Ts = reinterpret_cast<__bf16*>(smem);                                // [CP][TS]
+    unsigned char* sm2 = smem + (size_t)d.CP * ts_stride(d) * 2;
+    float* xs = reinterpret_cast<float*>(sm2);                                   // [R2][CP]
+    __bf16* ys = reinterpret_cast<__bf16*>(sm2 + sizeof(float) * d.R2 * d.CP);   // [CP][R2]
     const int b = blockIdx.x / d.m2, k2 = blockIdx.x % d.m2;
     const int tid = threadIdx.x, wave = tid >> 6, nw = blockDim.x >> 6;
-    const int H2 = 2 * d.Hpad;
+    const int H2 = 2 * d.Hpad, TS = ts_stride(d);
     const int Nt = d.CP / 32;
-    const __bf16* Ts = d.T + ((size_t)b * d.m2 + k2) * d.CP * H2;  // [CP][2 Hpad]
+    stage_t(d, b, k2, Ts);
     float* svX = d.sv_X ? d.sv_X + ((size_t)b * d.m2 + k2) * d.R2 * d.CP : nullptr;
     // X[r][c] = sum_{ri,h} EcolA[r][ri,h] T[c][ri,h]
     const int Mt1 = d.R2 / 32, T1 = Mt1 * Nt;
-    if (T1 >= nw) {
+    if (d.colS == 1) {
         for (int t = wave; t < T1; t += nw) {
             const int mi = t / Nt, ni = t % Nt;
             f32x16 acc = {};
-            acc = mma_tile(d.EcolA + (size_t)mi * 32 * H2, H2, Ts + (size_t)ni * 32 * H2, H2, H2, acc);
+            acc = mma_tile(d.EcolA + (size_t)mi * 32 * H2, H2, Ts + ni * 32 * TS, TS, H2, acc);
             const int c = ni * 32 + acc_col();
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
@@ -409,15 +477,15 @@ __global__ __launch_bounds__(COL_THREADS) void k_fno_col(FnoDev d, int layer) {
         // into S parts, wave w taking tile w mod T1 and part w / T1.  Part 0 writes
         // xs, part s > 0 its own [R2][CP] partial after ys; the parts are then added
         // in part order (deterministic) and rounded.
-        const int S = nw / T1, KS = H2 / 16;
+        const int S = d.colS, KS = H2 / 16;
         const int tile = wave % T1, part = wave / T1;
         const int mi = tile / Nt, ni = tile % Nt;
         const int k0 = 16 * (part * KS / S), k1 = 16 * ((part + 1) * KS / S);
-        float* parts = reinterpret_cast<float*>(smem + (size_t)d.R2 * d.CP * 6);  // [S-1][R2][CP]
+        float* parts = reinterpret_cast<float*>(sm2 + (size_t)d.R2 * d.CP * 6);  // [S-1][R2][CP]
         if (part < S) {
             f32x16 acc = {};
             if (k1 > k0)
-                acc = mma_tile(d.EcolA + (size_t)mi * 32 * H2 + k0, H2, Ts + (size_t)ni * 32 * H2 + k0, H2,
+                acc = mma_tile(d.EcolA + (size_t)mi * 32 * H2 + k0, H2, Ts + ni * 32 * TS + k0, TS,
                                k1 - k0, acc);
             float* dst = part == 0 ? xs : parts + (size_t)(part - 1) * d.R2 * d.CP;
             const int c = ni * 32 + acc_col();
@@ -503,45 +571,78 @@ __device__ __forceinline__ void stage_z(const FnoDev& d, int b, int h, __bf16* z
 // ACT: d.act, or the identity for the last layer.  DFT: also take the next layer's
 // row DFT of the output row (kept in LDS, transposed), so the next layer needs no
 // row-forward launch; rows h >= Hp of T stay the zeros the first row DFT wrote.
-template <int ACT, bool DFT>
+// KZ, KC: 16-wide k-steps of the coefficient and channel contractions (KKp / 16,
+// CP / 16) as template constants, 0 for a run-time count.
+//
+// Each 32 x 32 output tile is formed transposed, C^T[o][w] = Z[o][:] . Binv[w][:] +
+// Wc[o][:] . v[w][:]: a lane then holds the four channels o, o+1, o+2, o+3 of one
+// point w in four register groups, so it stores 8-byte packed bf16 quads of the
+// channels-last output row (four stores per tile), and the transposed LDS copy
+// for the next row DFT is written along w (consecutive lanes, consecutive bf16).
+template <int ACT, bool DFT, int KZ, int KC>
 __global__ __launch_bounds__(256) void k_fno_rowinv(FnoDev d, const __bf16* __restrict__ v,
                                                     __bf16* __restrict__ vout, int layer) {
     const int b = blockIdx.x / d.Hp, h = blockIdx.x % d.Hp;
     const int tid = threadIdx.x, wave = tid >> 6, nw = blockDim.x >> 6;
+    const int lane = tid & 63, wl = lane & 31, g = lane >> 5;
     const size_t rowoff = ((size_t)b * d.Hp + h) * d.Wpad * d.CP;
     const __bf16* vrow = v + rowoff;
+    __bf16* orow = vout + rowoff;
     extern __shared__ __align__(16) unsigned char smem[];
     __bf16* zs = reinterpret_cast<__bf16*>(smem);  // [CP][KKp + 8]
     __bf16* vt = zs + (size_t)d.CP * (d.KKp + 8);  // [CP][vt_stride] (DFT)
     stage_z(d, b, h, zs);
-    const int KKs = d.KKp + 8;
-    const __bf16* Wc = d.Wc + (size_t)layer * d.CP * d.CP;
-    const float* bias = d.bc + (size_t)layer * d.CP;
-    const int Mt = d.Wpad / 32, Nt = d.CP / 32;
+    const int KKs = d.KKp + 8, VS = vt_stride(d), CP = d.CP;
+    const __bf16* Wc = d.Wc + (size_t)layer * CP * CP;
+    const float* bias = d.bc + (size_t)layer * CP;
+    const int Mt = d.Wpad / 32, Nt = CP / 32;
     for (int t = wave; t < Mt * Nt; t += nw) {
         const int mi = t / Nt, ni = t % Nt;
         f32x16 acc = {};
-        acc = mma_tile(d.BinvT + (size_t)mi * 32 * d.KKp, d.KKp, zs + (size_t)ni * 32 * KKs, KKs,
-                       d.KKp, acc);
-        acc = mma_tile(vrow + (size_t)mi * 32 * d.CP, d.CP, Wc + (size_t)ni * 32 * d.CP, d.CP,
-                       d.CP, acc);
-        const int o = ni * 32 + acc_col();
-        const float bo = bias[o];
+        acc = mma_any<KZ>(zs + ni * 32 * KKs, KKs, d.BinvT + mi * 32 * d.KKp, d.KKp, d.KKp, acc);
+        acc = mma_any<KC>(Wc + ni * 32 * CP, CP, vrow + mi * 32 * CP, CP, CP, acc);
+        const int w = mi * 32 + wl;
+        const bool live = w < d.Wp;
+        const int ob = ni * 32 + 4 * g;  // channels of register group j: ob + 8 j + 0..3
+        float val[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int w = mi * 32 + acc_row(r);
-            float val = acc[r] + bo;
-            if (d.sv_pre) d.sv_pre[rowoff + (size_t)w * d.CP + o] = w < d.Wp ? val : 0.0f;
-            val = act_t<ACT>(val);
-            if (w >= d.Wp) val = 0.0f;
-            const __bf16 vb = to_bf16(val);
-            vout[rowoff + (size_t)w * d.CP + o] = vb;
-            if constexpr (DFT) vt[o * vt_stride(d) + w] = vb;
+        for (int j = 0; j < 4; ++j) {
+            const float4 bq = *reinterpret_cast<const float4*>(bias + ob + 8 * j);
+            val[4 * j + 0] = acc[4 * j + 0] + bq.x;
+            val[4 * j + 1] = acc[4 * j + 1] + bq.y;
+            val[4 * j + 2] = acc[4 * j + 2] + bq.z;
+            val[4 * j + 3] = acc[4 * j + 3] + bq.w;
+        }
+        if (d.sv_pre) {   // training: the pre-activation, zero beyond W'
+            float* sp = d.sv_pre + rowoff + (size_t)w * CP + ob;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                *reinterpret_cast<float4*>(sp + 8 * j) =
+                    live ? make_float4(val[4 * j], val[4 * j + 1], val[4 * j + 2], val[4 * j + 3])
+                         : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
+        __bf16* op = orow + w * CP + ob;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            uint2 q;
+            q.x = live ? pack_bf16(act_t<ACT>(val[4 * j + 0]), act_t<ACT>(val[4 * j + 1])) : 0u;
+            q.y = live ? pack_bf16(act_t<ACT>(val[4 * j + 2]), act_t<ACT>(val[4 * j + 3])) : 0u;
+            if constexpr (DFT) {   // the row goes out from LDS below
+                __bf16* vc = vt + (ob + 8 * j) * VS + w;
+                const __bf16* e = reinterpret_cast<const __bf16*>(&q);
+                vc[0] = e[0];
+                vc[VS] = e[1];
+                vc[2 * VS] = e[2];
+                vc[3 * VS] = e[3];
+            } else {
+                *reinterpret_cast<uint2*>(op + 8 * j) = q;
+            }
         }
     }
     if constexpr (DFT) {
         __syncthreads();
         row_dft_from_lds(d, vt, b, h);
+        store_row_from_vt(d, vt, orow);
     }
 }
 
@@ -582,6 +683,38 @@ __device__ __forceinline__ void dec_stage_input(const FnoDev& d, const __bf16* _
     }
 }
 
+// One hidden decoder layer for the wave's 32 points: out[pt][su] = act(W[su][:] .
+// in[pt][:] + b[su]) for su < dec_size (zero for the padded units), formed
+// transposed so that a lane holds four consecutive units of one point and writes
+// them as one 8-byte bf16 quad.  With sv != NULL (training) the pre-activations
+// go to sv[pt][su] (float, DSP per point) for points below `valid`.
+template <int ACT>
+__device__ __forceinline__ void dec_hidden_layer(const FnoDev& d, const __bf16* in, __bf16* outb, int KP,
+                                                 const __bf16* wp, const float* bp, int din, float* sv,
+                                                 int valid) {
+    const int lane = threadIdx.x & 63, pt = lane & 31, g = lane >> 5;
+    for (int nt = 0; nt < d.DSP / 32; ++nt) {
+        f32x16 acc = {};
+        const __bf16* A = wp + (size_t)nt * 32 * din;
+        if (din == 32) acc = mma_k<2>(A, din, in, KP, acc);
+        else if (din == 64) acc = mma_k<4>(A, din, in, KP, acc);
+        else acc = mma_tile(A, din, in, KP, din, acc);
+        const int sb = nt * 32 + 4 * g;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int su = sb + 8 * j;
+            const float4 bq = *reinterpret_cast<const float4*>(bp + su);
+            const float x0 = acc[4 * j] + bq.x, x1 = acc[4 * j + 1] + bq.y;
+            const float x2 = acc[4 * j + 2] + bq.z, x3 = acc[4 * j + 3] + bq.w;
+            if (sv && pt < valid) *reinterpret_cast<float4*>(sv + (size_t)pt * d.DSP + su) = make_float4(x0, x1, x2, x3);
+            uint2 q;
+            q.x = pack_bf16(su < d.dec_size ? act_t<ACT>(x0) : 0.0f, su + 1 < d.dec_size ? act_t<ACT>(x1) : 0.0f);
+            q.y = pack_bf16(su + 2 < d.dec_size ? act_t<ACT>(x2) : 0.0f, su + 3 < d.dec_size ? act_t<ACT>(x3) : 0.0f);
+            *reinterpret_cast<uint2*>(outb + pt * KP + su) = q;
+        }
+    }
+}
+
 // ACT = d.dec_act.
 template <int ACT>
 __global__ __launch_bounds__(256) void k_fno_dec(FnoDev d, const __bf16* __restrict__ v,
@@ -614,21 +747,9 @@ __global__ __launch_bounds__(256) void k_fno_dec(FnoDev d, const __bf16* __restr
     const __bf16* wp = d.decw;
     const float* bp = d.decb;
     for (int l = 0; l < d.dec_layers; ++l) {
-        for (int nt = 0; nt < d.DSP / 32; ++nt) {
-            f32x16 acc = {};
-            acc = mma_tile(bufA, KP, wp + (size_t)nt * 32 * din, din, din, acc);
-            const int su = nt * 32 + acc_col();
-            const float bs = bp[su];
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int pp = acc_row(r);
-                const size_t pt = pt0 + pp;
-                const float val = acc[r] + bs;
-                if (d.sv_dec && pt < total) d.sv_dec[((size_t)l * total + pt) * d.DSP + su] = val;
-                const float a = su < d.dec_size ? act_t<ACT>(val) : 0.0f;
-                bufB[pp * KP + su] = to_bf16(a);
-            }
-        }
+        dec_hidden_layer<ACT>(d, bufA, bufB, KP, wp, bp, din,
+                              d.sv_dec ? d.sv_dec + ((size_t)l * total + pt0) * d.DSP : nullptr,
+                              (int)(pt0 < total ? total - pt0 : 0));
         __syncthreads();
         __bf16* t = bufA; bufA = bufB; bufB = t;
         wp += (size_t)d.DSP * din;
@@ -658,7 +779,7 @@ __global__ __launch_bounds__(256) void k_fno_dec(FnoDev d, const __bf16* __restr
 // memory and the padded rows h >= H are not formed.  The waves take the row's
 // 32-point groups in turn; every wave runs the same number of rounds and layers, so
 // a wave without a group still meets every barrier.
-template <int DACT>
+template <int DACT, int KZ, int KC>
 __global__ __launch_bounds__(256) void k_fno_rowinv_dec(FnoDev d, const __bf16* __restrict__ v,
                                                         float* __restrict__ out, int layer) {
     const int b = blockIdx.x / d.H, h = blockIdx.x % d.H;
@@ -689,20 +810,23 @@ __global__ __launch_bounds__(256) void k_fno_rowinv_dec(FnoDev d, const __bf16* 
     const __bf16* Wc = d.Wc + (size_t)layer * d.CP * d.CP;
     const float* bias = d.bc + (size_t)layer * d.CP;
     const int Mt = d.Wpad / 32, Nt = d.CP / 32;
+    const int wl = lane & 31, gq = lane >> 5;
     for (int t = wave; t < Mt * Nt; t += nw) {
         const int mi = t / Nt, ni = t % Nt;
         f32x16 acc = {};
-        acc = mma_tile(d.BinvT + (size_t)mi * 32 * d.KKp, d.KKp, zs + (size_t)ni * 32 * KKs, KKs,
-                       d.KKp, acc);
-        acc = mma_tile(vrow + (size_t)mi * 32 * d.CP, d.CP, Wc + (size_t)ni * 32 * d.CP, d.CP,
-                       d.CP, acc);
-        const int o = ni * 32 + acc_col();
-        const float bc = bias[o];
+        // transposed tile C^T[o][w], as k_fno_rowinv forms it (same values)
+        acc = mma_any<KZ>(zs + ni * 32 * KKs, KKs, d.BinvT + mi * 32 * d.KKp, d.KKp, d.KKp, acc);
+        acc = mma_any<KC>(Wc + ni * 32 * d.CP, d.CP, vrow + mi * 32 * d.CP, d.CP, d.CP, acc);
+        const int w = mi * 32 + wl;
+        const bool live = w < d.Wp;
+        const int ob = ni * 32 + 4 * gq;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int w = mi * 32 + acc_row(r);
-            const float val = w < d.Wp ? acc[r] + bc : 0.0f;
-            vr[(size_t)w * KP + o] = to_bf16(val);
+        for (int j = 0; j < 4; ++j) {
+            const float4 bq = *reinterpret_cast<const float4*>(bias + ob + 8 * j);
+            uint2 q;
+            q.x = live ? pack_bf16(acc[4 * j] + bq.x, acc[4 * j + 1] + bq.y) : 0u;
+            q.y = live ? pack_bf16(acc[4 * j + 2] + bq.z, acc[4 * j + 3] + bq.w) : 0u;
+            *reinterpret_cast<uint2*>(vr + (size_t)w * KP + ob + 8 * j) = q;
         }
     }
     __syncthreads();
@@ -716,19 +840,7 @@ __global__ __launch_bounds__(256) void k_fno_rowinv_dec(FnoDev d, const __bf16* 
         const __bf16* wp = d.decw;
         const float* bp = d.decb;
         for (int l = 0; l < d.dec_layers; ++l) {
-            if (live) {
-                for (int nt = 0; nt < d.DSP / 32; ++nt) {
-                    f32x16 acc = {};
-                    acc = mma_tile(bufA, KP, wp + (size_t)nt * 32 * din, din, din, acc);
-                    const int su = nt * 32 + acc_col();
-                    const float bs = bp[su];
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) {
-                        const float a = su < d.dec_size ? act_t<DACT>(acc[r] + bs) : 0.0f;
-                        bufB[acc_row(r) * KP + su] = to_bf16(a);
-                    }
-                }
-            }
+            if (live) dec_hidden_layer<DACT>(d, bufA, bufB, KP, wp, bp, din, nullptr, 0);
             __syncthreads();
             __bf16* t = bufA; bufA = bufB; bufB = t;
             wp += (size_t)d.DSP * din;
@@ -812,16 +924,26 @@ static bool fuse_row_dft(const FnoDev& d) {
     return zs_lds(d) + (size_t)d.CP * vt_stride(d) * 2 <= 64 * 1024;
 }
 
+// Host dispatch of the row-inverse contraction sizes to template constants KZ
+// (KKp / 16: 2 or 4, else 0 for a run-time loop) and KC (CP / 16: 2 or 4).
+#define FNO_WITH_K(dev, ...)                                                           \
+    if ((dev).KKp == 32 && (dev).CP == 32) { constexpr int KZ = 2, KC = 2; __VA_ARGS__; }      \
+    else if ((dev).KKp == 64 && (dev).CP == 32) { constexpr int KZ = 4, KC = 2; __VA_ARGS__; } \
+    else if ((dev).KKp == 32 && (dev).CP == 64) { constexpr int KZ = 2, KC = 4; __VA_ARGS__; } \
+    else if ((dev).KKp == 64 && (dev).CP == 64) { constexpr int KZ = 4, KC = 4; __VA_ARGS__; } \
+    else if ((dev).CP == 32) { constexpr int KZ = 0, KC = 2; __VA_ARGS__; }                     \
+    else { constexpr int KZ = 0, KC = 4; __VA_ARGS__; }
+
 // row inverse of layer l over all (b, h) rows; the last layer has no activation,
 // the others also take the next layer's row DFT when it fits (fuse_row_dft)
 static void launch_rowinv(const FnoDev& d, const __bf16* v, __bf16* vout, int l, hipStream_t st) {
     const unsigned grid = (unsigned)(d.B * d.Hp);
     if (l < d.L - 1 && fuse_row_dft(d)) {
         const size_t lds = zs_lds(d) + (size_t)d.CP * vt_stride(d) * 2;
-        FNO_WITH_ACT(d.act, (k_fno_rowinv<A, true><<<grid, 256, lds, st>>>(d, v, vout, l)))
+        FNO_WITH_K(d, FNO_WITH_ACT(d.act, (k_fno_rowinv<A, true, KZ, KC><<<grid, 256, lds, st>>>(d, v, vout, l))))
     } else {
-        FNO_WITH_ACT(l == d.L - 1 ? FNO_ACT_IDENTITY : d.act,
-                     (k_fno_rowinv<A, false><<<grid, 256, zs_lds(d), st>>>(d, v, vout, l)))
+        FNO_WITH_K(d, FNO_WITH_ACT(l == d.L - 1 ? FNO_ACT_IDENTITY : d.act,
+                                   (k_fno_rowinv<A, false, KZ, KC><<<grid, 256, zs_lds(d), st>>>(d, v, vout, l))))
     }
 }
 
@@ -843,16 +965,26 @@ static bool fuse_dec(const FnoDev& d) {
 }
 static void launch_rowinv_dec(const FnoDev& d, const __bf16* v, float* out, int l, hipStream_t st) {
     const unsigned grid = (unsigned)(d.B * d.H);
-    FNO_WITH_ACT(d.dec_act, (k_fno_rowinv_dec<A><<<grid, 256, rowinv_dec_lds(d), st>>>(d, v, out, l)))
+    FNO_WITH_K(d, FNO_WITH_ACT(d.dec_act, (k_fno_rowinv_dec<A, KZ, KC><<<grid, 256, rowinv_dec_lds(d), st>>>(d, v, out, l))))
 }
 
 // dynamic LDS of the column kernel: xs [R2][CP] float, ys [CP][R2] bf16 and, when
 // its K range is split over spare waves, S - 1 float partials of xs
-static size_t col_lds(const FnoDev& d) {
-    const int T1 = (d.R2 / 32) * (d.CP / 32), nw = COL_THREADS / 64;
-    const int S = T1 >= nw ? 1 : nw / T1;
-    return (size_t)d.R2 * d.CP * (4 + 2) + (size_t)(S - 1) * d.R2 * d.CP * 4;
+static size_t col_lds_parts(const FnoDev& d, int S) {
+    return (size_t)d.CP * ts_stride(d) * 2 + (size_t)d.R2 * d.CP * (4 + 2) +
+           (size_t)(S - 1) * d.R2 * d.CP * 4;
 }
+
+// K-split of the column DFT: spare waves (fewer 32 x 32 tiles than waves) take
+// parts of the K range, as many as the 64 KB of LDS leave room for.
+static int col_split(const FnoDev& d) {
+    const int T1 = (d.R2 / 32) * (d.CP / 32), nw = COL_THREADS / 64;
+    int S = T1 >= nw ? 1 : nw / T1;
+    while (S > 1 && col_lds_parts(d, S) > 64 * 1024) --S;
+    return S;
+}
+
+static size_t col_lds(const FnoDev& d) { return col_lds_parts(d, d.colS); }
 
 // dynamic LDS of the row-inverse kernels: the row's Z transposed, [CP][KKp + 8] bf16
 static size_t zs_lds(const FnoDev& d) { return (size_t)d.CP * (d.KKp + 8) * 2; }
@@ -1076,6 +1208,7 @@ extern "C" int fno_model_create(fno_model** out, const fno_spec* spec, const flo
     d.cout = s.cout;
     d.act = s.act; d.dec_act = s.dec_act;
     if ((size_t)d.CP * vt_stride(d) * 2 > 64 * 1024) return fail(LBM_EUNSUPPORTED, "row of %d x %d too large for LDS", d.Wpad, d.CP);
+    d.colS = col_split(d);
     if (col_lds(d) > 64 * 1024) return fail(LBM_EUNSUPPORTED, "mode block too large for LDS");
     if (zs_lds(d) > 64 * 1024) return fail(LBM_EUNSUPPORTED, "row coefficients too large for LDS");
     fno_model* m = new (std::nothrow) fno_model();
@@ -1661,17 +1794,20 @@ __global__ __launch_bounds__(256) void k_fno_act_bwd(FnoDev d, FnoBwd g, const f
 // mixing with conj(R), inverse column DFT of dX into Z.
 __global__ __launch_bounds__(256) void k_fno_col_bwd(FnoDev d, FnoBwd g, int layer) {
     extern __shared__ __align__(16) unsigned char smem[];
-    float* xs = reinterpret_cast<float*>(smem);
-    __bf16* ys = reinterpret_cast<__bf16*>(smem + sizeof(float) * d.R2 * d.CP);
+    __bf16* Ts = reinterpret_cast<__bf16*>(smem);                                // [CP][TS]
+    unsigned char* sm2 = smem + (size_t)d.CP * ts_stride(d) * 2;
+    float* xs = reinterpret_cast<float*>(sm2);
+    __bf16* ys = reinterpret_cast<__bf16*>(sm2 + sizeof(float) * d.R2 * d.CP);
     const int b = blockIdx.x / d.m2, k2 = blockIdx.x % d.m2;
     const int tid = threadIdx.x, wave = tid >> 6, nw = blockDim.x >> 6;
     const int H2 = 2 * d.Hpad, Nt = d.CP / 32;
     const float scale = (k2 == 0 ? 1.0f : 2.0f) / ((float)d.Hp * (float)d.Wp);
-    const __bf16* Ts = d.T + ((size_t)b * d.m2 + k2) * d.CP * H2;
+    const int TS = ts_stride(d);
+    stage_t(d, b, k2, Ts);
     for (int t = wave; t < (d.R2 / 32) * Nt; t += nw) {
         const int mi = t / Nt, ni = t % Nt;
         f32x16 acc = {};
-        acc = mma_tile(d.EcolA + (size_t)mi * 32 * H2, H2, Ts + (size_t)ni * 32 * H2, H2, H2, acc);
+        acc = mma_tile(d.EcolA + (size_t)mi * 32 * H2, H2, Ts + ni * 32 * TS, TS, H2, acc);
         const int c = ni * 32 + acc_col();
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
@@ -2054,7 +2190,7 @@ extern "C" int fno_backward(const fno_model* m, const float* d_in, const float* 
     }
     // Fourier layers, last first
     const size_t lds_row = (size_t)d.CP * vt_stride(d) * 2;
-    const size_t lds_col = (size_t)d.R2 * d.CP * 4 + (size_t)d.CP * d.R2 * 2;
+    const size_t lds_col = (size_t)d.CP * ts_stride(d) * 2 + (size_t)d.R2 * d.CP * 4 + (size_t)d.CP * d.R2 * 2;
     for (int l = d.L - 1; l >= 0; --l) {
         const size_t lo = o_layers + (size_t)l * per_layer;
         k_fno_act_bwd<<<(unsigned)((lat + 255) / 256), 256, 0, st>>>(d, g, P.pre[l], l == d.L - 1);
