@@ -57,6 +57,11 @@ int oracle_q(void) { return Q; }
 #ifdef _OPENMP
 #include <omp.h>
 int oracle_threads(void) { return omp_get_max_threads(); }
+/* Rows run in parallel only on lattices large enough to pay for a parallel region:
+ * on a tiny lattice run for tens of thousands of steps, the per-step fork and join
+ * (worse, spinning threads when several such processes share the cores) costs
+ * far more than the step.  Each row is independent, so the result is the same. */
+#define PAR(nx, ny) ((size_t)(nx) * (size_t)(ny) >= 4096)
 #else
 int oracle_threads(void) { return 1; }
 #endif
@@ -302,7 +307,7 @@ void oracle_init_neq(int nx, int ny, double tau, double gx, double gy, int bc_x,
 static void collide_all(const cfg_t* cp, const uint8_t* mask, const double* f, double* fstar) {
     const cfg_t c = *cp;
     const int nx = c.nx, ny = c.ny;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (PAR(nx, ny))
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
             double g[Q], h[Q];
@@ -334,7 +339,7 @@ void oracle_collide_trt(int nx, int ny, double tau, double lambda, double gx, do
 void oracle_stream(int nx, int ny, int bc_x, int bc_y, double u_in, double rho_out,
                    const uint8_t* mask, const double* fstar, double* fnew) {
     cfg_t c = make_cfg(nx, ny, 1.0, 0.0, 0.0, bc_x, bc_y, u_in, rho_out);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (PAR(nx, ny))
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
             if (mask[(size_t)j * nx + i]) {
@@ -498,7 +503,7 @@ static int adjoint_step(int nx, int ny, double tau, double lambda, double gx, do
     oracle_bc_vjp(nx, ny, bc_x, u_in, rho_out, mask, lam_np1);
     const double om = 1.0 / tau;
     const double pref = 1.0 - 0.5 * om;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (PAR(nx, ny))
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
             if (mask[(size_t)j * nx + i]) {
