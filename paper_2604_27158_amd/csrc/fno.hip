@@ -112,6 +112,47 @@ __device__ __forceinline__ f32x16 mma_any(const __bf16* A, int lda, const __bf16
     else return mma_tile(A, lda, Bt, ldb, K, acc);
 }
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// One 16x16 tile C += A[16 x K] * Bt[16 x K]^T on v_mfma_f32_16x16x32_bf16 (K a
+// multiple of 32, operands K-contiguous as for mma_tile): lane l supplies
+// A[l % 16][8 (l / 16) + e] and B[8 (l / 16) + e][l % 16], e = 0..7, and holds
+// C[4 (l / 16) + r][l % 16] in acc[r], r = 0..3.  Groups of four k-steps, the next
+// group requested before the current group's products.
+__device__ __forceinline__ f32x4 mma16_tile(const __bf16* A, int lda, const __bf16* Bt, int ldb, int K,
+                                            f32x4 acc) {
+    const int lane = threadIdx.x & 63;
+    const __bf16* a = A + (lane & 15) * lda + 8 * (lane >> 4);
+    const __bf16* b = Bt + (lane & 15) * ldb + 8 * (lane >> 4);
+    constexpr int U = 4;
+    bf16x8 av[U] = {}, bv[U] = {};   // slots past K stay defined (zero) and unused
+#pragma unroll
+    for (int j = 0; j < U; ++j)
+        if (32 * j < K) {
+            av[j] = *reinterpret_cast<const bf16x8*>(a + 32 * j);
+            bv[j] = *reinterpret_cast<const bf16x8*>(b + 32 * j);
+        }
+    for (int k0 = 0; k0 < K; k0 += 32 * U) {
+        bf16x8 an[U] = {}, bn[U] = {};
+        const int k1 = k0 + 32 * U;
+#pragma unroll
+        for (int j = 0; j < U; ++j)
+            if (k1 + 32 * j < K) {
+                an[j] = *reinterpret_cast<const bf16x8*>(a + k1 + 32 * j);
+                bn[j] = *reinterpret_cast<const bf16x8*>(b + k1 + 32 * j);
+            }
+#pragma unroll
+        for (int j = 0; j < U; ++j)
+            if (k0 + 32 * j < K) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[j], bv[j], acc, 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            av[j] = an[j];
+            bv[j] = bn[j];
+        }
+    }
+    return acc;
+}
+
 // Packed round-to-nearest-even bf16 pair (lo, hi) in one 32-bit word.
 __device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
     typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
@@ -125,14 +166,17 @@ __device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
 // Abramowitz & Stegun, Handbook of Mathematical Functions, 7.1.26: for z >= 0,
 // erf z = 1 - t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-z^2), t = 1 / (1 + p z),
 // absolute error below 1.5e-7.  With z = |x| / sqrt 2 and
-// g = x t (a1 + ...) exp(-x^2 / 2) / 2, GELU is x - g for x >= 0 and g for x < 0.
+// q = |x| t (a1 + ...) exp(-x^2 / 2) / 2, GELU is x - q for x >= 0 and -q for x < 0,
+// that is max(x, 0) - q (the halved coefficients are the a_k / 2, exactly).
 // The error (a few 1e-7 of |x|) is far below the bf16 rounding that follows.
 __device__ __forceinline__ float gelu_fast(float x) {
-    const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * 0.70710678118654752f * fabsf(x));
-    const float p = t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f +
-                    t * (-1.453152027f + t * 1.061405429f))));
-    const float g = 0.5f * x * p * __expf(-0.5f * x * x);
-    return x >= 0.0f ? x - g : g;
+    const float ax = fabsf(x);
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f * 0.70710678118654752f, ax, 1.0f));
+    const float p = t * (0.127414796f + t * (-0.142248368f + t * (0.7107068705f +
+                    t * (-0.7265760135f + t * 0.5307027145f))));
+    // exp(-x^2 / 2) = 2^(-x^2 log2(e) / 2)
+    const float e = __builtin_amdgcn_exp2f((-0.72134752044448170368f * x) * x);
+    return fmaf(-(ax * p), e, fmaxf(x, 0.0f));
 }
 
 template <int KIND>
@@ -291,23 +335,24 @@ __device__ __forceinline__ void t_zero_row(const FnoDev& d, int b, int h) {
     for (int i = threadIdx.x; i < d.m2 * d.CP; i += blockDim.x) row[i] = 0u;
 }
 
+// The KKp x CP result is taken in 16 x 16 tiles, so that every wave of the
+// workgroup has one (the 2 m2 <= KKp rows in use fill fewer 32-row tiles than there
+// are waves).
 __device__ __forceinline__ void row_dft_from_lds(const FnoDev& d, const __bf16* vt, int b, int h) {
     uint32_t* Tr = reinterpret_cast<uint32_t*>(t_row(d, b, h));
-    const int wave = threadIdx.x >> 6;
-    const int Mt = d.KKp / 32, Nt = d.CP / 32;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int Mt = (2 * d.m2 + 15) / 16, Nt = d.CP / 16;
     for (int t = wave; t < Mt * Nt; t += blockDim.x >> 6) {
         const int mi = t / Nt, ni = t % Nt;
-        f32x16 acc = {};
-        acc = mma_tile(d.EwT + (size_t)mi * 32 * d.Wpad, d.Wpad, vt + ni * 32 * vt_stride(d), vt_stride(d),
-                       d.Wpad, acc);
-        const int c = ni * 32 + acc_col();
-        // rows kk = 2 k2 + ri come in (re, im) pairs: one packed word per pair, and the
-        // 32 lanes of a half-wave store 32 consecutive words
-#pragma unroll
-        for (int r = 0; r < 16; r += 2) {
-            const int kk = mi * 32 + acc_row(r);
-            if (kk < 2 * d.m2) Tr[(kk >> 1) * d.CP + c] = pack_bf16(acc[r], acc[r + 1]);
-        }
+        f32x4 acc = {};
+        acc = mma16_tile(d.EwT + (size_t)mi * 16 * d.Wpad, d.Wpad, vt + ni * 16 * vt_stride(d), vt_stride(d),
+                         d.Wpad, acc);
+        // rows kk = 2 k2 + ri come in (re, im) pairs, two per lane: one packed word
+        // per pair, and the 16 lanes of a quarter-wave store 16 consecutive words
+        const int c = ni * 16 + (lane & 15);
+        const int kk = mi * 16 + 4 * (lane >> 4);
+        if (kk < 2 * d.m2) Tr[(kk >> 1) * d.CP + c] = pack_bf16(acc[0], acc[1]);
+        if (kk + 2 < 2 * d.m2) Tr[((kk >> 1) + 1) * d.CP + c] = pack_bf16(acc[2], acc[3]);
     }
 }
 
@@ -422,6 +467,47 @@ __global__ __launch_bounds__(1024) void k_fno_lift_row(FnoDev d, const float* __
     store_row_from_vt(d, vt, d.v0 + ((size_t)b * d.Hp + h) * d.Wpad * d.CP);
 }
 
+// Column inverse of column k2 of sample b from Y[o][r] in LDS: Zc[q][o] =
+// sum_r EcolB[q][r] Y[o][r], q = ri * Hpad + h, stored to Z rows kk = 2 k2 + ri
+// (rows h < Hp; the 32 lanes of a half-wave write 32 consecutive channels).
+__device__ __forceinline__ void z_store_column(const FnoDev& d, int b, int k2, const __bf16* ys) {
+    const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int Mt = 2 * d.Hpad / 32, Nt = d.CP / 32;
+    for (int t = wave; t < Mt * Nt; t += nw) {
+        const int mi = t / Nt, ni = t % Nt;
+        f32x16 acc = {};
+        acc = mma_tile(d.EcolB + (size_t)mi * 32 * d.R2, d.R2, ys + ni * 32 * d.R2, d.R2, d.R2, acc);
+        const int o = ni * 32 + acc_col();
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int q = mi * 32 + acc_row(r);
+            const int ri = q >= d.Hpad ? 1 : 0, h = q - ri * d.Hpad;
+            if (h < d.Hp)
+                d.Z[(((size_t)b * 2 * d.m2 + 2 * k2 + ri) * d.Hp + h) * d.CP + o] = to_bf16(acc[r]);
+        }
+    }
+}
+
+// Z coefficients of row (b, h) transposed into LDS, zs[o][kk] with row stride
+// KKp + 8, and the padded coefficient columns kk >= 2 m2 set to zero.  Reads are
+// 16-byte channel vectors of whole Z rows.
+__device__ __forceinline__ void stage_z(const FnoDev& d, int b, int h, __bf16* zs) {
+    const int KKs = d.KKp + 8, nvec = d.CP / 8;
+    for (int i = threadIdx.x; i < d.KKp * nvec; i += blockDim.x) {
+        const int kk = i / nvec, o0 = 8 * (i % nvec);
+        bf16x8 t;
+        if (kk < 2 * d.m2) {
+            t = *reinterpret_cast<const bf16x8*>(d.Z + (((size_t)b * 2 * d.m2 + kk) * d.Hp + h) * d.CP + o0);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) t[e] = to_bf16(0.0f);
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) zs[(o0 + e) * KKs + kk] = t[e];
+    }
+    __syncthreads();
+}
+
 // Row stride (bf16) of a column's T staged in LDS, [CP][TS], K = (ri, h) contiguous.
 __host__ __device__ __forceinline__ int ts_stride(const FnoDev& d) { return 2 * d.Hpad + 8; }
 
@@ -530,41 +616,7 @@ __global__ __launch_bounds__(COL_THREADS) void k_fno_col(FnoDev d, int layer) {
         ys[o * d.R2 + d.K1 + k] = to_bf16(si);
     }
     __syncthreads();
-    // Zc[q][o] = sum_r EcolB[q][r] Y[o][r], q = ri * Hpad + h
-    const int Mt2 = H2 / 32;
-    for (int t = wave; t < Mt2 * Nt; t += nw) {
-        const int mi = t / Nt, ni = t % Nt;
-        f32x16 acc = {};
-        acc = mma_tile(d.EcolB + (size_t)mi * 32 * d.R2, d.R2, ys + ni * 32 * d.R2, d.R2, d.R2, acc);
-        const int o = ni * 32 + acc_col();
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int q = mi * 32 + acc_row(r);
-            const int ri = q >= d.Hpad ? 1 : 0, h = q - ri * d.Hpad;
-            if (h < d.Hp)
-                d.Z[(((size_t)b * 2 * d.m2 + 2 * k2 + ri) * d.Hp + h) * d.CP + o] = to_bf16(acc[r]);
-        }
-    }
-}
-
-// Z coefficients of row (b, h) transposed into LDS, zs[o][kk] with row stride
-// KKp + 8, and the padded coefficient columns kk >= 2 m2 set to zero.  Reads are
-// 16-byte channel vectors of whole Z rows.
-__device__ __forceinline__ void stage_z(const FnoDev& d, int b, int h, __bf16* zs) {
-    const int KKs = d.KKp + 8, nvec = d.CP / 8;
-    for (int i = threadIdx.x; i < d.KKp * nvec; i += blockDim.x) {
-        const int kk = i / nvec, o0 = 8 * (i % nvec);
-        bf16x8 t;
-        if (kk < 2 * d.m2) {
-            t = *reinterpret_cast<const bf16x8*>(d.Z + (((size_t)b * 2 * d.m2 + kk) * d.Hp + h) * d.CP + o0);
-        } else {
-#pragma unroll
-            for (int e = 0; e < 8; ++e) t[e] = to_bf16(0.0f);
-        }
-#pragma unroll
-        for (int e = 0; e < 8; ++e) zs[(o0 + e) * KKs + kk] = t[e];
-    }
-    __syncthreads();
+    z_store_column(d, b, k2, ys);
 }
 
 // Row inverse DFT + 1x1 convolution + bias (+ activation) for one (b, h).
@@ -715,6 +767,34 @@ __device__ __forceinline__ void dec_hidden_layer(const FnoDev& d, const __bf16* 
     }
 }
 
+// Output weights of the decoder (cout <= 8 rows of din <= 64, bf16) staged in LDS
+// as the A operand of one 32-row MFMA tile, rows cout..31 zero, and the output bias.
+__device__ __forceinline__ int dec_stage_output(const FnoDev& d, __bf16* wo, float* bo) {
+    const __bf16* wg = d.decw;
+    const float* bg = d.decb;
+    int dn = d.CP;
+    for (int l = 0; l < d.dec_layers; ++l) {
+        wg += (size_t)d.DSP * dn;
+        bg += d.DSP;
+        dn = d.DSP;
+    }
+    for (int t = threadIdx.x; t < 32 * dn; t += blockDim.x) wo[t] = t < d.cout * dn ? wg[t] : to_bf16(0.0f);
+    for (int t = threadIdx.x; t < d.cout; t += blockDim.x) bo[t] = bg[t];
+    return dn;
+}
+
+// Output layer for the wave's 32 points on MFMA, C^T[o][pt] = Wo[o][:] . in[pt][:]
+// (bf16 operands, float32 sums, as the per-point dot products would form them up to
+// the order of the sums): lane l holds outputs o = 4 (l / 32) + i of point l % 32 in
+// acc[i], i = 0..3.
+__device__ __forceinline__ f32x16 dec_output_layer(const __bf16* wo, const __bf16* in, int KP, int din) {
+    f32x16 acc = {};
+    if (din == 32) acc = mma_k<2>(wo, din, in, KP, acc);
+    else if (din == 64) acc = mma_k<4>(wo, din, in, KP, acc);
+    else acc = mma_tile(wo, din, in, KP, din, acc);
+    return acc;
+}
+
 // ACT = d.dec_act.
 template <int ACT>
 __global__ __launch_bounds__(256) void k_fno_dec(FnoDev d, const __bf16* __restrict__ v,
@@ -726,21 +806,9 @@ __global__ __launch_bounds__(256) void k_fno_dec(FnoDev d, const __bf16* __restr
     __bf16* bufB = bufA + DEC_PTS * KP;
     const size_t total = (size_t)d.B * d.H * d.W;
     const size_t pt0 = ((size_t)blockIdx.x * 4 + wave) * DEC_PTS;
-    // output layer's weights (cout <= 8 rows of din <= 64) and bias staged in LDS
-    __shared__ __align__(16) __bf16 wo[8 * 64];
+    __shared__ __align__(16) __bf16 wo[32 * 64];
     __shared__ float bo[8];
-    {
-        const __bf16* wg = d.decw;
-        const float* bg = d.decb;
-        int dn = d.CP;
-        for (int l = 0; l < d.dec_layers; ++l) {
-            wg += (size_t)d.DSP * dn;
-            bg += d.DSP;
-            dn = d.DSP;
-        }
-        for (int t = threadIdx.x; t < d.cout * dn; t += blockDim.x) wo[t] = wg[t];
-        for (int t = threadIdx.x; t < d.cout; t += blockDim.x) bo[t] = bg[t];
-    }
+    dec_stage_output(d, wo, bo);
     dec_stage_input(d, v, pt0, total, bufA, lane);
     __syncthreads();
     int din = d.CP;
@@ -756,18 +824,13 @@ __global__ __launch_bounds__(256) void k_fno_dec(FnoDev d, const __bf16* __restr
         bp += d.DSP;
         din = d.DSP;
     }
-    const int pp = lane & 31;
-    const size_t pt = pt0 + pp;
+    const f32x16 acc = dec_output_layer(wo, bufA, KP, din);
+    const size_t pt = pt0 + (lane & 31);
     if (pt < total) {
-        for (int o = lane >> 5; o < d.cout; o += 2) {
-            float acc = bo[o];
-            for (int i = 0; i < din; i += 8) {   // din is a multiple of 32
-                const bf16x8 a = *reinterpret_cast<const bf16x8*>(bufA + pp * KP + i);
-                const bf16x8 w = *reinterpret_cast<const bf16x8*>(wo + o * din + i);
 #pragma unroll
-                for (int e = 0; e < 8; ++e) acc = fmaf(from_bf16(w[e]), from_bf16(a[e]), acc);
-            }
-            out[dec_out_offset(d, pt, o)] = acc;
+        for (int i = 0; i < 4; ++i) {
+            const int o = 4 * (lane >> 5) + i;
+            if (o < d.cout) out[dec_out_offset(d, pt, o)] = acc[i] + bo[o];
         }
     }
 }
@@ -791,20 +854,9 @@ __global__ __launch_bounds__(256) void k_fno_rowinv_dec(FnoDev d, const __bf16* 
     __bf16* zs = reinterpret_cast<__bf16*>(smem);                     // [CP][KKp + 8]
     __bf16* vr = zs + (size_t)d.CP * (d.KKp + 8);                     // [Wpad][DKP]
     __bf16* own = vr + (size_t)d.Wpad * KP + (size_t)wave * DEC_PTS * KP;  // [32][DKP] per wave
-    __shared__ __align__(16) __bf16 wo[8 * 64];
+    __shared__ __align__(16) __bf16 wo[32 * 64];
     __shared__ float bo[8];
-    {
-        const __bf16* wg = d.decw;
-        const float* bg = d.decb;
-        int dn = d.CP;
-        for (int l = 0; l < d.dec_layers; ++l) {
-            wg += (size_t)d.DSP * dn;
-            bg += d.DSP;
-            dn = d.DSP;
-        }
-        for (int t = tid; t < d.cout * dn; t += blockDim.x) wo[t] = wg[t];
-        for (int t = tid; t < d.cout; t += blockDim.x) bo[t] = bg[t];
-    }
+    dec_stage_output(d, wo, bo);
     stage_z(d, b, h, zs);  // ends with a barrier, which also covers wo and bo
     const int KKs = d.KKp + 8;
     const __bf16* Wc = d.Wc + (size_t)layer * d.CP * d.CP;
@@ -848,17 +900,13 @@ __global__ __launch_bounds__(256) void k_fno_rowinv_dec(FnoDev d, const __bf16* 
             din = d.DSP;
         }
         if (live) {
-            const int pp = lane & 31, w = g * DEC_PTS + pp;
+            const f32x16 acc = dec_output_layer(wo, bufA, KP, din);
+            const int w = g * DEC_PTS + (lane & 31);
             if (w < d.W) {
-                for (int o = lane >> 5; o < d.cout; o += 2) {
-                    float acc = bo[o];
-                    for (int i = 0; i < din; i += 8) {   // din is a multiple of 32
-                        const bf16x8 a = *reinterpret_cast<const bf16x8*>(bufA + pp * KP + i);
-                        const bf16x8 wv = *reinterpret_cast<const bf16x8*>(wo + o * din + i);
 #pragma unroll
-                        for (int e = 0; e < 8; ++e) acc = fmaf(from_bf16(wv[e]), from_bf16(a[e]), acc);
-                    }
-                    out[(((size_t)b * d.cout + o) * d.H + h) * d.W + w] = acc;
+                for (int i = 0; i < 4; ++i) {
+                    const int o = 4 * (lane >> 5) + i;
+                    if (o < d.cout) out[(((size_t)b * d.cout + o) * d.H + h) * d.W + w] = acc[i] + bo[o];
                 }
             }
         }
@@ -917,7 +965,8 @@ static void launch_lift(const FnoDev& d, size_t npts, const float* d_in, hipStre
     }
 }
 
-static size_t zs_lds(const FnoDev& d);
+// dynamic LDS of the row-inverse kernels: the row's Z transposed, [CP][KKp + 8] bf16
+static size_t zs_lds(const FnoDev& d) { return (size_t)d.CP * (d.KKp + 8) * 2; }
 
 // whether the row inverse can also hold the output row for the next row DFT in LDS
 static bool fuse_row_dft(const FnoDev& d) {
@@ -961,7 +1010,7 @@ static size_t rowinv_dec_lds(const FnoDev& d) {
     return zs_lds(d) + (size_t)d.Wpad * d.DKP * 2 + (size_t)4 * DEC_PTS * d.DKP * 2;
 }
 static bool fuse_dec(const FnoDev& d) {
-    return !d.sv_pre && !d.sv_dec && rowinv_dec_lds(d) + 2048 <= 64 * 1024;
+    return !d.sv_pre && !d.sv_dec && rowinv_dec_lds(d) + 32 * 64 * 2 + 64 <= 64 * 1024;
 }
 static void launch_rowinv_dec(const FnoDev& d, const __bf16* v, float* out, int l, hipStream_t st) {
     const unsigned grid = (unsigned)(d.B * d.H);
@@ -985,9 +1034,6 @@ static int col_split(const FnoDev& d) {
 }
 
 static size_t col_lds(const FnoDev& d) { return col_lds_parts(d, d.colS); }
-
-// dynamic LDS of the row-inverse kernels: the row's Z transposed, [CP][KKp + 8] bf16
-static size_t zs_lds(const FnoDev& d) { return (size_t)d.CP * (d.KKp + 8) * 2; }
 
 static uint16_t host_bf16(double v) {
     float f = (float)v;
@@ -1838,19 +1884,7 @@ __global__ __launch_bounds__(256) void k_fno_col_bwd(FnoDev d, FnoBwd g, int lay
         ys[i * d.R2 + d.K1 + k] = to_bf16(si);
     }
     __syncthreads();
-    for (int t = wave; t < (H2 / 32) * Nt; t += nw) {
-        const int mi = t / Nt, ni = t % Nt;
-        f32x16 acc = {};
-        acc = mma_tile(d.EcolB + (size_t)mi * 32 * d.R2, d.R2, ys + ni * 32 * d.R2, d.R2, d.R2, acc);
-        const int o = ni * 32 + acc_col();
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int q = mi * 32 + acc_row(r);
-            const int ri = q >= d.Hpad ? 1 : 0, h = q - ri * d.Hpad;
-            if (h < d.Hp)
-                d.Z[(((size_t)b * 2 * d.m2 + 2 * k2 + ri) * d.Hp + h) * d.CP + o] = to_bf16(acc[r]);
-        }
-    }
+    z_store_column(d, b, k2, ys);
 }
 
 // dv[w][i] = sum_kk B1[w][kk] Z[i][kk] + sum_o dpre[w][o] Wc[o][i], per (b, h) row.
