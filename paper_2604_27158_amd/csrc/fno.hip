@@ -104,6 +104,23 @@ __device__ __forceinline__ f32x16 mma_k(const __bf16* A, int lda, const __bf16* 
     return acc;
 }
 
+// One operand of a 32 x 32 tile with KS k-steps held in registers, in mma_k's
+// layout (rows lane % 32, k = 8 (lane / 32) + 16 j + e), and the products of two
+// such operands: mma_rows(load_rows(A), load_rows(Bt)) is exactly mma_k(A, Bt).
+template <int KS>
+__device__ __forceinline__ void load_rows(bf16x8 (&o)[KS], const __bf16* A, int lda) {
+    const int lane = threadIdx.x & 63;
+    const __bf16* a = A + (lane & 31) * lda + 8 * (lane >> 5);
+#pragma unroll
+    for (int j = 0; j < KS; ++j) o[j] = *reinterpret_cast<const bf16x8*>(a + 16 * j);
+}
+template <int KS>
+__device__ __forceinline__ f32x16 mma_rows(const bf16x8 (&a)[KS], const bf16x8 (&b)[KS], f32x16 acc) {
+#pragma unroll
+    for (int j = 0; j < KS; ++j) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[j], b[j], acc, 0, 0, 0);
+    return acc;
+}
+
 // K = 16 KS with KS a template constant when it is 2 or 4 (KS = 0: run-time K).
 template <int KS>
 __device__ __forceinline__ f32x16 mma_any(const __bf16* A, int lda, const __bf16* Bt, int ldb, int K,
@@ -221,6 +238,7 @@ struct FnoDev {
     const __bf16* decwT;    // hidden decoder layers transposed, [din_p][DSP] each (backward)
     int DKP;                // decoder LDS row stride (bf16 elements)
     int colS;               // column kernel: parts its column DFT's K range is split into
+    int ncu;                // compute units of the device (persistent row kernels)
     // workspace
     __bf16 *v0, *v1, *T, *Z;
     // training forward: saved activations (NULL in plain inference)
@@ -239,84 +257,143 @@ __host__ __device__ __forceinline__ int vt_stride(const FnoDev& d) { return d.Wp
 
 // ---------------------------------------------------------------- kernels
 
-// Lift: x (cin channels, float32) + coordinates -> width/2 (act) -> width, rounded
-// to bf16, written channels-last; the zero-padded region and w >= W' hold zeros.
-// NO = CP (32 or 64): the register tile of output channels; ACT = d.act.
-template <int NO, int ACT>
-__global__ __launch_bounds__(256) void k_fno_lift(FnoDev d, const float* __restrict__ x) {
-    // weights staged in LDS once per workgroup, zero-padded to the register tile
-    // (8 inputs, NO outputs) so that the point loop has no channel-count branches
-    // and reads each weight row with 16-byte broadcasts
-    __shared__ __align__(16) float w1s[32][8];
-    __shared__ __align__(16) float w2t[32][NO];  // w2t[k][c] = W2[c][k]
-    __shared__ __align__(16) float b2s[NO];
-    __shared__ float b1s[32];
+// Lift weights staged in LDS, zero-padded to 32 hidden units, 8 inputs and NO
+// outputs, so that the point loop has no channel-count branches.
+template <int NO>
+struct LiftW {
+    float w1[32][8];   // W1[k][c]
+    float b1[32];
+    float w2t[32][NO];  // w2t[k][c] = W2[c][k]
+    float b2[NO];
+};
+
+template <int NO>
+__device__ __forceinline__ void lift_stage_weights(const FnoDev& d, LiftW<NO>& s) {
     for (int t = threadIdx.x; t < 32 * 8; t += blockDim.x) {
         const int k = t / 8, c = t % 8;
-        w1s[k][c] = (k < d.half && c < d.cl) ? d.lift1w[k * d.cl + c] : 0.0f;
+        s.w1[k][c] = (k < d.half && c < d.cl) ? d.lift1w[k * d.cl + c] : 0.0f;
     }
     for (int t = threadIdx.x; t < 32 * NO; t += blockDim.x) {
         const int k = t / NO, c = t % NO;
-        w2t[k][c] = (k < d.half && c < d.width) ? d.lift2w[c * d.half + k] : 0.0f;
+        s.w2t[k][c] = (k < d.half && c < d.width) ? d.lift2w[c * d.half + k] : 0.0f;
     }
-    for (int t = threadIdx.x; t < NO; t += blockDim.x) b2s[t] = t < d.width ? d.lift2b[t] : 0.0f;
-    for (int t = threadIdx.x; t < 32; t += blockDim.x) b1s[t] = t < d.half ? d.lift1b[t] : 0.0f;
+    for (int t = threadIdx.x; t < NO; t += blockDim.x) s.b2[t] = t < d.width ? d.lift2b[t] : 0.0f;
+    for (int t = threadIdx.x; t < 32; t += blockDim.x) s.b1[t] = t < d.half ? d.lift1b[t] : 0.0f;
+}
+
+// Hidden layer of the lift for point (b, h, w) of this lane: hid[k] = act(b1[k] +
+// sum_c W1[k][c] z[c]) for k < KH (KH = 16 when half <= 16, else 32; the padded
+// units come out as exact zeros), z = the fields and the two coordinates; zeros for
+// a point outside H x W.  sv (training): the pre-activations, k < half.
+template <int NO, int ACT, int KH>
+__device__ __forceinline__ void lift_hidden(const FnoDev& d, const LiftW<NO>& s, const float* __restrict__ x,
+                                            int b, int h, int w, bool valid, float (&hid)[KH], float* sv) {
+#pragma unroll
+    for (int k = 0; k < KH; ++k) hid[k] = 0.0f;
+    if (!valid) return;
+    float z[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) z[c] = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 6; ++c)
+        if (c < d.cin) z[c] = x[(((size_t)b * d.cin + c) * d.H + h) * d.W + w];
+    if (d.coords) {
+        const float xc = d.W > 1 ? (float)w / (float)(d.W - 1) : 0.0f;
+        const float yc = d.H > 1 ? (float)h / (float)(d.H - 1) : 0.0f;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            if (c == d.cin) z[c] = xc;
+            if (c == d.cin + 1) z[c] = yc;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < KH; ++k) {
+        // padded inputs carry zero weights and zero values: exact no-ops
+        float a = s.b1[k];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) a = fmaf(s.w1[k][c], z[c], a);
+        if (sv && k < d.half) sv[k] = a;
+        hid[k] = act_t<ACT>(a);
+    }
+}
+
+// Output layer of the lift for the wave's 64 points (lane l holds the hidden units
+// of point p0 + l) on the float32 matrix cores (v_mfma_f32_32x32x2_f32: lane l
+// supplies A[l % 32][l / 32] and B[l / 32][l % 32], one float each, and holds the
+// 32 x 32 result in the layout of the bf16 tiles).  Tile u covers points
+// p0 + 32 u + (l % 32); step s sums hidden units 2 s and 2 s + 1, the half-wave
+// that does not own the point receiving its unit from the other half.  acc[u][nt][r]
+// = b2[o] + sum_k W2[o][k] hid[k] for channel o = 32 nt + acc_row(r).
+template <int NO, int KH>
+__device__ __forceinline__ void lift_output(const LiftW<NO>& s, const float (&hid)[KH], f32x16 (&acc)[2][NO / 32]) {
+    const int lane = threadIdx.x & 63, p = lane & 31, g = lane >> 5;
+#pragma unroll
+    for (int nt = 0; nt < NO / 32; ++nt)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[0][nt][r] = acc[1][nt][r] = s.b2[32 * nt + acc_row(r)];
+#pragma unroll
+    for (int st = 0; st < KH / 2; ++st) {
+        const float a = hid[2 * st], c = hid[2 * st + 1];
+        const float sa = __shfl_xor(a, 32), sc = __shfl_xor(c, 32);
+        const float b0 = g == 0 ? a : sc;   // tile 0: unit 2 st from the lower half, 2 st + 1 from the upper
+        const float b1 = g == 0 ? sa : c;   // tile 1: the points of the upper half
+#pragma unroll
+        for (int nt = 0; nt < NO / 32; ++nt) {
+            const float wa = s.w2t[2 * st + g][32 * nt + p];
+            acc[0][nt] = __builtin_amdgcn_mfma_f32_32x32x2f32(wa, b0, acc[0][nt], 0, 0, 0);
+            acc[1][nt] = __builtin_amdgcn_mfma_f32_32x32x2f32(wa, b1, acc[1][nt], 0, 0, 0);
+        }
+    }
+}
+
+// Lift: x (cin channels, float32) + coordinates -> width/2 (act) -> width, rounded
+// to bf16, written channels-last; the zero-padded region and w >= W' hold zeros.
+// A lane per point, a wave per 64 consecutive points.  NO = CP (32 or 64); ACT =
+// d.act; KH as for lift_hidden.
+template <int NO, int ACT, int KH>
+__global__ __launch_bounds__(256) void k_fno_lift(FnoDev d, const float* __restrict__ x) {
+    __shared__ LiftW<NO> lw;
+    lift_stage_weights<NO>(d, lw);
     __syncthreads();
     // point indices fit 32 bits (B Hp Wpad CP < 2^31 is checked on the host), so
     // the index arithmetic avoids 64-bit division
-    const unsigned idx = blockIdx.x * blockDim.x + threadIdx.x;
     const unsigned total = (unsigned)d.B * d.Hp * d.Wpad;
-    if (idx >= total) return;
-    const unsigned rw = idx / (unsigned)d.Wpad;
-    const int w = (int)(idx - rw * d.Wpad);
-    const int b = (int)(rw / (unsigned)d.Hp);
-    const int h = (int)(rw - (unsigned)b * d.Hp);
-    __bf16* out = d.v0 + (size_t)idx * d.CP;
-    float o[NO];
+    const unsigned p0 = (blockIdx.x * blockDim.x + threadIdx.x) & ~63u;   // the wave's first point
+    if (p0 >= total) return;   // uniform over the wave
+    const int lane = threadIdx.x & 63;
+    auto locate = [&](unsigned idx, int& b, int& h, int& w) {
+        const unsigned rw = idx / (unsigned)d.Wpad;
+        w = (int)(idx - rw * d.Wpad);
+        b = (int)(rw / (unsigned)d.Hp);
+        h = (int)(rw - (unsigned)b * d.Hp);
+    };
+    int b, h, w;
+    const unsigned idx = p0 + lane;
+    locate(idx, b, h, w);
+    const bool valid = idx < total && h < d.H && w < d.W;
+    float hid[KH];
+    lift_hidden<NO, ACT, KH>(d, lw, x, b, h, w, valid, hid,
+                             d.sv_a1 && valid ? d.sv_a1 + (((size_t)b * d.H + h) * d.W + w) * 32 : nullptr);
+    f32x16 acc[2][NO / 32];
+    lift_output<NO, KH>(lw, hid, acc);
+    const int g = lane >> 5;
 #pragma unroll
-    for (int c = 0; c < NO; ++c) o[c] = 0.0f;
-    if (h < d.H && w < d.W) {
-        float z[8];
+    for (int u = 0; u < 2; ++u) {
+        const unsigned pt = p0 + 32 * u + (lane & 31);
+        if (pt >= total) continue;
+        int pb, ph, pw;
+        locate(pt, pb, ph, pw);
+        const bool live = ph < d.H && pw < d.W;
+        __bf16* op = d.v0 + (size_t)pt * d.CP;
 #pragma unroll
-        for (int c = 0; c < 8; ++c) z[c] = 0.0f;
+        for (int nt = 0; nt < NO / 32; ++nt)
 #pragma unroll
-        for (int c = 0; c < 6; ++c)
-            if (c < d.cin) z[c] = x[(((size_t)b * d.cin + c) * d.H + h) * d.W + w];
-        if (d.coords) {
-            const float xc = d.W > 1 ? (float)w / (float)(d.W - 1) : 0.0f;
-            const float yc = d.H > 1 ? (float)h / (float)(d.H - 1) : 0.0f;
-#pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                if (c == d.cin) z[c] = xc;
-                if (c == d.cin + 1) z[c] = yc;
+            for (int j = 0; j < 4; ++j) {
+                uint2 q;
+                q.x = live ? pack_bf16(acc[u][nt][4 * j], acc[u][nt][4 * j + 1]) : 0u;
+                q.y = live ? pack_bf16(acc[u][nt][4 * j + 2], acc[u][nt][4 * j + 3]) : 0u;
+                *reinterpret_cast<uint2*>(op + 32 * nt + 8 * j + 4 * g) = q;
             }
-        }
-        const size_t pt = ((size_t)b * d.H + h) * d.W + w;
-#pragma unroll
-        for (int c = 0; c < NO; ++c) o[c] = b2s[c];
-        for (int k = 0; k < d.half; ++k) {
-            // padded inputs carry zero weights and zero values: exact no-ops
-            float s = b1s[k];
-#pragma unroll
-            for (int c = 0; c < 8; ++c) s = fmaf(w1s[k][c], z[c], s);
-            if (d.sv_a1) d.sv_a1[pt * 32 + k] = s;
-            const float hk = act_t<ACT>(s);
-            // o[c] += W2[c][k] * hid[k], accumulated over k in order
-#pragma unroll
-            for (int c = 0; c < NO; ++c) o[c] = fmaf(w2t[k][c], hk, o[c]);
-        }
-#pragma unroll
-        for (int c = 0; c < NO; ++c)
-            if (c >= d.width) o[c] = 0.0f;  // padded channels stay zero
-    }
-#pragma unroll
-    for (int c0 = 0; c0 < NO; c0 += 8) {
-        {
-            bf16x8 t;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) t[e] = to_bf16(o[c0 + e]);
-            *reinterpret_cast<bf16x8*>(out + c0) = t;
-        }
     }
 }
 
@@ -354,6 +431,41 @@ __device__ __forceinline__ void row_dft_from_lds(const FnoDev& d, const __bf16* 
         if (kk < 2 * d.m2) Tr[(kk >> 1) * d.CP + c] = pack_bf16(acc[0], acc[1]);
         if (kk + 2 < 2 * d.m2) Tr[((kk >> 1) + 1) * d.CP + c] = pack_bf16(acc[2], acc[3]);
     }
+}
+
+// The same row DFT with the EwT operand held in registers: when the 16 x 16 tiles
+// number at most one per wave and Wpad = 32 KW, each wave requests its tile's EwT
+// rows at the start of the row kernel (row_dft_load), long before the transposed
+// row in LDS is complete, so that after the barrier the products wait on LDS only
+// (row_dft_regs).  Same products in the same order as row_dft_from_lds.
+__host__ __device__ __forceinline__ int row_dft_tiles(const FnoDev& d) { return (2 * d.m2 + 15) / 16 * (d.CP / 16); }
+
+template <int KW>
+__device__ __forceinline__ void row_dft_load(const FnoDev& d, bf16x8 (&ew)[KW]) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int mi = wave / (d.CP / 16);
+    const __bf16* a = d.EwT + (size_t)(mi * 16 + (lane & 15)) * d.Wpad + 8 * (lane >> 4);
+#pragma unroll
+    for (int j = 0; j < KW; ++j) ew[j] = *reinterpret_cast<const bf16x8*>(a + 32 * j);
+}
+
+template <int KW>
+__device__ __forceinline__ void row_dft_regs(const FnoDev& d, const bf16x8 (&ew)[KW], const __bf16* vt, int b,
+                                             int h) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int Nt = d.CP / 16, mi = wave / Nt, ni = wave % Nt;
+    const __bf16* bp = vt + (ni * 16 + (lane & 15)) * vt_stride(d) + 8 * (lane >> 4);
+    bf16x8 bv[KW];
+#pragma unroll
+    for (int j = 0; j < KW; ++j) bv[j] = *reinterpret_cast<const bf16x8*>(bp + 32 * j);
+    f32x4 acc = {};
+#pragma unroll
+    for (int j = 0; j < KW; ++j) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ew[j], bv[j], acc, 0, 0, 0);
+    uint32_t* Tr = reinterpret_cast<uint32_t*>(t_row(d, b, h));
+    const int c = ni * 16 + (lane & 15);
+    const int kk = mi * 16 + 4 * (lane >> 4);
+    if (kk < 2 * d.m2) Tr[(kk >> 1) * d.CP + c] = pack_bf16(acc[0], acc[1]);
+    if (kk + 2 < 2 * d.m2) Tr[((kk >> 1) + 1) * d.CP + c] = pack_bf16(acc[2], acc[3]);
 }
 
 // The row held transposed in LDS, vt[c][w], stored channels last to orow[w][c]:
@@ -396,75 +508,57 @@ __global__ __launch_bounds__(256) void k_fno_rowfwd(FnoDev d, const __bf16* __re
 // lifts its point as k_fno_lift does (same operations, same order), stores it to v
 // and into the row's transposed copy in LDS, from which the row DFT is taken as in
 // k_fno_rowfwd; rows h >= Hp only write T's zero rows.
-template <int NO, int ACT>
+template <int NO, int ACT, int KH, int KW>
 __global__ __launch_bounds__(1024) void k_fno_lift_row(FnoDev d, const float* __restrict__ x) {
-    __shared__ __align__(16) float w1s[32][8];
-    __shared__ __align__(16) float w2t[32][NO];  // w2t[k][c] = W2[c][k]
-    __shared__ __align__(16) float b2s[NO];
-    __shared__ float b1s[32];
+    __shared__ LiftW<NO> lw;
     extern __shared__ __align__(16) unsigned char smem[];
     __bf16* vt = reinterpret_cast<__bf16*>(smem);  // [CP][vt_stride]
-    const int b = blockIdx.x / d.Hpad, h = blockIdx.x % d.Hpad;
-    const int tid = threadIdx.x;
-    if (h >= d.Hp) {
-        t_zero_row(d, b, h);
-        return;
-    }
-    for (int t = tid; t < 32 * 8; t += blockDim.x) {
-        const int k = t / 8, c = t % 8;
-        w1s[k][c] = (k < d.half && c < d.cl) ? d.lift1w[k * d.cl + c] : 0.0f;
-    }
-    for (int t = tid; t < 32 * NO; t += blockDim.x) {
-        const int k = t / NO, c = t % NO;
-        w2t[k][c] = (k < d.half && c < d.width) ? d.lift2w[c * d.half + k] : 0.0f;
-    }
-    for (int t = tid; t < NO; t += blockDim.x) b2s[t] = t < d.width ? d.lift2b[t] : 0.0f;
-    for (int t = tid; t < 32; t += blockDim.x) b1s[t] = t < d.half ? d.lift1b[t] : 0.0f;
-    __syncthreads();
-    const int w = tid;
-    if (w < d.Wpad) {
-        float o[NO];
+    const int tid = threadIdx.x, lane = tid & 63, g = lane >> 5;
+    const int VS = vt_stride(d);
+    bf16x8 ew[KW > 0 ? KW : 1];
+    const bool dft_wave = KW > 0 && (int)(tid >> 6) < row_dft_tiles(d);
+    if constexpr (KW > 0)
+        if (dft_wave) row_dft_load<KW>(d, ew);
+    lift_stage_weights<NO>(d, lw);
+    // the workgroups step through the rows (one row each when launched with a
+    // workgroup per row); the weights and, with KW > 0, the row-DFT operand are
+    // loaded once per workgroup
+    const int rows = d.B * d.Hpad;
+    for (int row = blockIdx.x; row < rows; row += gridDim.x) {
+        const int b = row / d.Hpad, h = row - b * d.Hpad;
+        if (h >= d.Hp) {
+            t_zero_row(d, b, h);
+            continue;
+        }
+        // the staged weights (first row); the previous row's reads of vt
+        __syncthreads();
+        const int w = tid, w0 = tid & ~63;   // the wave's points w0 .. w0 + 63
+        float hid[KH];
+        lift_hidden<NO, ACT, KH>(d, lw, x, b, h, w, h < d.H && w < d.W, hid, nullptr);
+        f32x16 acc[2][NO / 32];
+        lift_output<NO, KH>(lw, hid, acc);
 #pragma unroll
-        for (int c = 0; c < NO; ++c) o[c] = 0.0f;
-        if (h < d.H && w < d.W) {
-            float z[8];
+        for (int u = 0; u < 2; ++u) {
+            const int wu = w0 + 32 * u + (lane & 31);
+            if (wu >= d.Wpad) continue;
+            const bool live = h < d.H && wu < d.W;
 #pragma unroll
-            for (int c = 0; c < 8; ++c) z[c] = 0.0f;
+            for (int nt = 0; nt < NO / 32; ++nt)
 #pragma unroll
-            for (int c = 0; c < 6; ++c)
-                if (c < d.cin) z[c] = x[(((size_t)b * d.cin + c) * d.H + h) * d.W + w];
-            if (d.coords) {
-                const float xc = d.W > 1 ? (float)w / (float)(d.W - 1) : 0.0f;
-                const float yc = d.H > 1 ? (float)h / (float)(d.H - 1) : 0.0f;
+                for (int j = 0; j < 4; ++j) {
+                    __bf16* vc = vt + (32 * nt + 8 * j + 4 * g) * VS + wu;
 #pragma unroll
-                for (int c = 0; c < 8; ++c) {
-                    if (c == d.cin) z[c] = xc;
-                    if (c == d.cin + 1) z[c] = yc;
+                    for (int i = 0; i < 4; ++i) vc[i * VS] = to_bf16(live ? acc[u][nt][4 * j + i] : 0.0f);
                 }
-            }
-#pragma unroll
-            for (int c = 0; c < NO; ++c) o[c] = b2s[c];
-            for (int k = 0; k < d.half; ++k) {
-                float s = b1s[k];
-#pragma unroll
-                for (int c = 0; c < 8; ++c) s = fmaf(w1s[k][c], z[c], s);
-                const float hk = act_t<ACT>(s);
-#pragma unroll
-                for (int c = 0; c < NO; ++c) o[c] = fmaf(w2t[k][c], hk, o[c]);
-            }
-#pragma unroll
-            for (int c = 0; c < NO; ++c)
-                if (c >= d.width) o[c] = 0.0f;
         }
-#pragma unroll
-        for (int c0 = 0; c0 < NO; c0 += 8) {
-#pragma unroll
-            for (int e = 0; e < 8; ++e) vt[(size_t)(c0 + e) * vt_stride(d) + w] = to_bf16(o[c0 + e]);
+        __syncthreads();
+        if constexpr (KW > 0) {
+            if (dft_wave) row_dft_regs<KW>(d, ew, vt, b, h);
+        } else {
+            row_dft_from_lds(d, vt, b, h);
         }
+        store_row_from_vt(d, vt, d.v0 + ((size_t)b * d.Hp + h) * d.Wpad * d.CP);
     }
-    __syncthreads();
-    row_dft_from_lds(d, vt, b, h);
-    store_row_from_vt(d, vt, d.v0 + ((size_t)b * d.Hp + h) * d.Wpad * d.CP);
 }
 
 // Column inverse of column k2 of sample b from Y[o][r] in LDS: Zc[q][o] =
@@ -698,6 +792,106 @@ __global__ __launch_bounds__(256) void k_fno_rowinv(FnoDev d, const __bf16* __re
     }
 }
 
+// The row inverse as a persistent kernel for row shapes whose 32 x 32 tiles number
+// at most two per wave (Wpad / 32 x CP / 32 <= 8) and, with DFT, whose row-DFT tiles
+// number at most one per wave, with Wpad = 32 KW: the workgroups step through the
+// rows, and each wave keeps its constant operands in registers across them (the Wc
+// rows of its channel tile, the BinvT rows of its two point tiles and, with DFT,
+// the EwT rows of its row-DFT tile).  Per row only the activations and the row's Z
+// are read, where the one-row kernel also re-reads some 50 KB of constant operands
+// through the vector memory path.  Same products in the same order as k_fno_rowinv,
+// so the results are identical.
+template <int ACT, bool DFT, int KZ, int KC, int KW>
+__global__ __launch_bounds__(256) void k_fno_rowinv_p(FnoDev d, const __bf16* __restrict__ v,
+                                                      __bf16* __restrict__ vout, int layer) {
+    const int tid = threadIdx.x, wave = tid >> 6, nw = blockDim.x >> 6;
+    const int lane = tid & 63, wl = lane & 31, g = lane >> 5;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __bf16* zs = reinterpret_cast<__bf16*>(smem);  // [CP][KKp + 8]
+    __bf16* vt = zs + (size_t)d.CP * (d.KKp + 8);  // [CP][vt_stride] (DFT)
+    const int KKs = d.KKp + 8, VS = vt_stride(d), CP = d.CP;
+    const int Mt = d.Wpad / 32, Nt = CP / 32, T = Mt * Nt;
+    const int ni = wave % Nt;  // both tiles of the wave (t = wave, wave + nw; nw is a multiple of Nt)
+    const int ob = ni * 32 + 4 * g;  // channels of register group j: ob + 8 j + 0..3
+    bf16x8 wc[KC], bi[2][KZ];
+    load_rows<KC>(wc, d.Wc + ((size_t)layer * CP + ni * 32) * CP, CP);
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+        if (wave + u * nw < T) load_rows<KZ>(bi[u], d.BinvT + ((wave + u * nw) / Nt) * 32 * d.KKp, d.KKp);
+    bf16x8 ew[DFT ? KW : 1];
+    const bool dft_wave = DFT && wave < row_dft_tiles(d);
+    if constexpr (DFT)
+        if (dft_wave) row_dft_load<KW>(d, ew);
+    float4 bq[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) bq[j] = *reinterpret_cast<const float4*>(d.bc + (size_t)layer * CP + ob + 8 * j);
+    const int rows = d.B * d.Hp;
+    for (int row = blockIdx.x; row < rows; row += gridDim.x) {
+        const int b = row / d.Hp, h = row - b * d.Hp;
+        const size_t rowoff = (size_t)row * d.Wpad * CP;
+        const __bf16* vrow = v + rowoff;
+        __bf16* orow = vout + rowoff;
+        // (with DFT, the barrier of the previous row's DFT already keeps these writes
+        // of zs behind every wave's reads of it, and the barrier in stage_z keeps this
+        // row's writes of vt behind every wave's reads of the previous row)
+        stage_z(d, b, h, zs);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int t = wave + u * nw;
+            if (t >= T) break;
+            const int mi = t / Nt;
+            bf16x8 za[KZ], vb[KC];
+            load_rows<KZ>(za, zs + ni * 32 * KKs, KKs);
+            load_rows<KC>(vb, vrow + mi * 32 * CP, CP);
+            f32x16 acc = {};
+            acc = mma_rows<KZ>(za, bi[u], acc);
+            acc = mma_rows<KC>(wc, vb, acc);
+            const int w = mi * 32 + wl;
+            const bool live = w < d.Wp;
+            float val[16];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                val[4 * j + 0] = acc[4 * j + 0] + bq[j].x;
+                val[4 * j + 1] = acc[4 * j + 1] + bq[j].y;
+                val[4 * j + 2] = acc[4 * j + 2] + bq[j].z;
+                val[4 * j + 3] = acc[4 * j + 3] + bq[j].w;
+            }
+            if (d.sv_pre) {   // training: the pre-activation, zero beyond W'
+                float* sp = d.sv_pre + rowoff + (size_t)w * CP + ob;
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    *reinterpret_cast<float4*>(sp + 8 * j) =
+                        live ? make_float4(val[4 * j], val[4 * j + 1], val[4 * j + 2], val[4 * j + 3])
+                             : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            }
+            __bf16* op = orow + w * CP + ob;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                uint2 q;
+                q.x = live ? pack_bf16(act_t<ACT>(val[4 * j + 0]), act_t<ACT>(val[4 * j + 1])) : 0u;
+                q.y = live ? pack_bf16(act_t<ACT>(val[4 * j + 2]), act_t<ACT>(val[4 * j + 3])) : 0u;
+                if constexpr (DFT) {
+                    __bf16* vc = vt + (ob + 8 * j) * VS + w;
+                    const __bf16* e = reinterpret_cast<const __bf16*>(&q);
+                    vc[0] = e[0];
+                    vc[VS] = e[1];
+                    vc[2 * VS] = e[2];
+                    vc[3 * VS] = e[3];
+                } else {
+                    *reinterpret_cast<uint2*>(op + 8 * j) = q;
+                }
+            }
+        }
+        if constexpr (DFT) {
+            __syncthreads();
+            if (dft_wave) row_dft_regs<KW>(d, ew, vt, b, h);
+            store_row_from_vt(d, vt, orow);
+        } else {
+            __syncthreads();  // every wave's reads of zs before the next row's stage_z
+        }
+    }
+}
+
 // Decoder on MFMA.  Each wave takes 32 consecutive output points; a layer's input
 // (bf16, channels contiguous) sits in LDS and is multiplied by the layer's
 // [DSP][din_p] weights, both operands contiguous along the input channels; bias,
@@ -914,6 +1108,107 @@ __global__ __launch_bounds__(256) void k_fno_rowinv_dec(FnoDev d, const __bf16* 
     }
 }
 
+// Decoder hidden-layer weights ([DSP][din] per layer, bf16) and biases (float)
+// in elements, as the persistent fused decoder stages them in LDS.
+__host__ __device__ __forceinline__ int dec_hidden_weights(const FnoDev& d) {
+    return d.dec_layers > 0 ? d.DSP * d.CP + (d.dec_layers - 1) * d.DSP * d.DSP : 0;
+}
+
+// The fused last row inverse + decoder as a persistent kernel (same conditions on
+// the row shape as k_fno_rowinv_p): the workgroups step through the rows, the
+// decoder's weights and biases are staged in LDS once per workgroup, and each wave
+// keeps its row-inverse operands (Wc rows, BinvT rows of its two point tiles, the
+// bias) in registers.  Same products in the same order as k_fno_rowinv_dec.
+template <int DACT, int KZ, int KC>
+__global__ __launch_bounds__(256) void k_fno_rowinv_dec_p(FnoDev d, const __bf16* __restrict__ v,
+                                                          float* __restrict__ out, int layer) {
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, nw = blockDim.x >> 6;
+    const int KP = d.DKP, CP = d.CP;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __bf16* zs = reinterpret_cast<__bf16*>(smem);                     // [CP][KKp + 8]
+    __bf16* vr = zs + (size_t)CP * (d.KKp + 8);                       // [Wpad][DKP]
+    __bf16* own = vr + (size_t)d.Wpad * KP + (size_t)wave * DEC_PTS * KP;  // [32][DKP] per wave
+    __bf16* dw = vr + (size_t)d.Wpad * KP + (size_t)nw * DEC_PTS * KP;    // hidden weights
+    float* db = reinterpret_cast<float*>(dw + dec_hidden_weights(d));      // hidden biases
+    __shared__ __align__(16) __bf16 wo[32 * 64];
+    __shared__ float bo[8];
+    dec_stage_output(d, wo, bo);
+    for (int i = tid; i < dec_hidden_weights(d); i += blockDim.x) dw[i] = d.decw[i];
+    for (int i = tid; i < d.dec_layers * d.DSP; i += blockDim.x) db[i] = d.decb[i];
+    const int KKs = d.KKp + 8;
+    const int Mt = d.Wpad / 32, Nt = CP / 32, T = Mt * Nt;
+    const int wl = lane & 31, gq = lane >> 5;
+    const int ni = wave % Nt;  // both tiles of the wave (nw is a multiple of Nt)
+    const int ob = ni * 32 + 4 * gq;
+    bf16x8 wc[KC], bi[2][KZ];
+    load_rows<KC>(wc, d.Wc + ((size_t)layer * CP + ni * 32) * CP, CP);
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+        if (wave + u * nw < T) load_rows<KZ>(bi[u], d.BinvT + ((wave + u * nw) / Nt) * 32 * d.KKp, d.KKp);
+    const float* bias = d.bc + (size_t)layer * CP + ob;
+    const int ng = (d.W + DEC_PTS - 1) / DEC_PTS, rounds = (ng + nw - 1) / nw;
+    const int rows = d.B * d.H;
+    for (int row = blockIdx.x; row < rows; row += gridDim.x) {
+        const int b = row / d.H, h = row - b * d.H;
+        const __bf16* vrow = v + ((size_t)b * d.Hp + h) * d.Wpad * CP;
+        // the barrier in stage_z also covers the staged weights (first row) and keeps
+        // this row's writes of vr behind every wave's reads of the previous row
+        stage_z(d, b, h, zs);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int t = wave + u * nw;
+            if (t >= T) break;
+            const int mi = t / Nt;
+            bf16x8 za[KZ], vb[KC];
+            load_rows<KZ>(za, zs + ni * 32 * KKs, KKs);
+            load_rows<KC>(vb, vrow + mi * 32 * CP, CP);
+            f32x16 acc = {};
+            acc = mma_rows<KZ>(za, bi[u], acc);
+            acc = mma_rows<KC>(wc, vb, acc);
+            const int w = mi * 32 + wl;
+            const bool live = w < d.Wp;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float4 bqj = *reinterpret_cast<const float4*>(bias + 8 * j);
+                uint2 q;
+                q.x = live ? pack_bf16(acc[4 * j] + bqj.x, acc[4 * j + 1] + bqj.y) : 0u;
+                q.y = live ? pack_bf16(acc[4 * j + 2] + bqj.z, acc[4 * j + 3] + bqj.w) : 0u;
+                *reinterpret_cast<uint2*>(vr + (size_t)w * KP + ob + 8 * j) = q;
+            }
+        }
+        __syncthreads();
+        for (int rd = 0; rd < rounds; ++rd) {
+            const int g = rd * nw + wave;
+            const bool live = g < ng;  // uniform over the wave
+            __bf16* bufA = vr + (size_t)(live ? g : 0) * DEC_PTS * KP;
+            __bf16* bufB = own;
+            int din = CP;
+            const __bf16* wp = dw;
+            const float* bp = db;
+            for (int l = 0; l < d.dec_layers; ++l) {
+                if (live) dec_hidden_layer<DACT>(d, bufA, bufB, KP, wp, bp, din, nullptr, 0);
+                __syncthreads();
+                __bf16* t = bufA; bufA = bufB; bufB = t;
+                wp += (size_t)d.DSP * din;
+                bp += d.DSP;
+                din = d.DSP;
+            }
+            if (live) {
+                const f32x16 acc = dec_output_layer(wo, bufA, KP, din);
+                const int w = g * DEC_PTS + wl;
+                if (w < d.W) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int o = 4 * gq + i;
+                        if (o < d.cout) out[(((size_t)b * d.cout + o) * d.H + h) * d.W + w] = acc[i] + bo[o];
+                    }
+                }
+            }
+            __syncthreads();  // this round's reads of own / vr before the next writes
+        }
+    }
+}
+
 }  // namespace lbmfno
 
 // ------------------------------------------------------------ host side
@@ -955,14 +1250,17 @@ static size_t dec_bwd_lds(const FnoDev& d) { return (size_t)4 * DEC_PTS * d.DKP 
         default: { constexpr int A = FNO_ACT_IDENTITY; __VA_ARGS__; break; }        \
     }
 
-// lift over npts padded points, with the register tile matching CP (32 or 64)
+// The lift kernels' template arguments: NO = CP (32 or 64), KH = 16 when
+// half <= 16, else 32.
+#define FNO_WITH_LIFT(dev, ...)                                                                   \
+    if ((dev).CP <= 32) { constexpr int NO = 32, KH = 16; __VA_ARGS__; }                         \
+    else if ((dev).half <= 16) { constexpr int NO = 64, KH = 16; __VA_ARGS__; }                  \
+    else { constexpr int NO = 64, KH = 32; __VA_ARGS__; }
+
+// lift over npts padded points (a wave per 64 points)
 static void launch_lift(const FnoDev& d, size_t npts, const float* d_in, hipStream_t st) {
     const unsigned grid = (unsigned)((npts + 255) / 256);
-    if (d.CP <= 32) {
-        FNO_WITH_ACT(d.act, (k_fno_lift<32, A><<<grid, 256, 0, st>>>(d, d_in)))
-    } else {
-        FNO_WITH_ACT(d.act, (k_fno_lift<64, A><<<grid, 256, 0, st>>>(d, d_in)))
-    }
+    FNO_WITH_LIFT(d, FNO_WITH_ACT(d.act, (k_fno_lift<NO, A, KH><<<grid, 256, 0, st>>>(d, d_in))));
 }
 
 // dynamic LDS of the row-inverse kernels: the row's Z transposed, [CP][KKp + 8] bf16
@@ -983,13 +1281,52 @@ static bool fuse_row_dft(const FnoDev& d) {
     else if ((dev).CP == 32) { constexpr int KZ = 0, KC = 2; __VA_ARGS__; }                     \
     else { constexpr int KZ = 0, KC = 4; __VA_ARGS__; }
 
+// KZ, KC both compile-time (the persistent row inverse)
+#define FNO_WITH_KZC(dev, ...)                                                                  \
+    if ((dev).KKp == 32 && (dev).CP == 32) { constexpr int KZ = 2, KC = 2; __VA_ARGS__; }      \
+    else if ((dev).KKp == 64 && (dev).CP == 32) { constexpr int KZ = 4, KC = 2; __VA_ARGS__; } \
+    else if ((dev).KKp == 32 && (dev).CP == 64) { constexpr int KZ = 2, KC = 4; __VA_ARGS__; } \
+    else { constexpr int KZ = 4, KC = 4; __VA_ARGS__; }
+
+// A persistent row kernel over `rows` rows: as many 256-thread workgroups as fit on
+// the device at once (the occupancy the runtime reports for this kernel and LDS
+// size, times the compute units), at most one per row.
+template <typename... P, typename... Args>
+static void launch_persistent(void (*kernel)(P...), const FnoDev& d, size_t lds, unsigned rows, hipStream_t st,
+                              unsigned threads, Args... args) {
+    int per = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, (int)threads, lds) != hipSuccess || per < 1)
+        per = 1;
+    const unsigned grid = std::min(rows, (unsigned)(per * d.ncu));
+    kernel<<<grid, threads, lds, st>>>(d, args...);
+}
+
+// whether the persistent row inverse applies: compile-time k-steps, at most two
+// 32 x 32 tiles per wave and, with the fused row DFT, at most one row-DFT tile per
+// wave and a row of 160 or 256 points
+static bool rowinv_persistent(const FnoDev& d, bool dft) {
+    const bool kzc = (d.KKp == 32 || d.KKp == 64) && (d.CP == 32 || d.CP == 64);
+    const bool tiles = (d.Wpad / 32) * (d.CP / 32) <= 8;
+    return kzc && tiles && (!dft || (row_dft_tiles(d) <= 4 && (d.Wpad == 256 || d.Wpad == 160)));
+}
+
 // row inverse of layer l over all (b, h) rows; the last layer has no activation,
 // the others also take the next layer's row DFT when it fits (fuse_row_dft)
 static void launch_rowinv(const FnoDev& d, const __bf16* v, __bf16* vout, int l, hipStream_t st) {
     const unsigned grid = (unsigned)(d.B * d.Hp);
     if (l < d.L - 1 && fuse_row_dft(d)) {
         const size_t lds = zs_lds(d) + (size_t)d.CP * vt_stride(d) * 2;
-        FNO_WITH_K(d, FNO_WITH_ACT(d.act, (k_fno_rowinv<A, true, KZ, KC><<<grid, 256, lds, st>>>(d, v, vout, l))))
+        if (rowinv_persistent(d, true) && d.Wpad == 256) {
+            FNO_WITH_KZC(d, FNO_WITH_ACT(d.act, (launch_persistent(k_fno_rowinv_p<A, true, KZ, KC, 8>, d, lds, grid, st, 256u, v, vout, l))))
+        } else if (rowinv_persistent(d, true) && d.Wpad == 160) {
+            FNO_WITH_KZC(d, FNO_WITH_ACT(d.act, (launch_persistent(k_fno_rowinv_p<A, true, KZ, KC, 5>, d, lds, grid, st, 256u, v, vout, l))))
+        } else {
+            FNO_WITH_K(d, FNO_WITH_ACT(d.act, (k_fno_rowinv<A, true, KZ, KC><<<grid, 256, lds, st>>>(d, v, vout, l))))
+        }
+    } else if (rowinv_persistent(d, false)) {
+        FNO_WITH_KZC(d, FNO_WITH_ACT(l == d.L - 1 ? FNO_ACT_IDENTITY : d.act,
+                                     (launch_persistent(k_fno_rowinv_p<A, false, KZ, KC, 1>, d, zs_lds(d), grid, st,
+                                                        256u, v, vout, l))))
     } else {
         FNO_WITH_K(d, FNO_WITH_ACT(l == d.L - 1 ? FNO_ACT_IDENTITY : d.act,
                                    (k_fno_rowinv<A, false, KZ, KC><<<grid, 256, zs_lds(d), st>>>(d, v, vout, l))))
@@ -1014,7 +1351,13 @@ static bool fuse_dec(const FnoDev& d) {
 }
 static void launch_rowinv_dec(const FnoDev& d, const __bf16* v, float* out, int l, hipStream_t st) {
     const unsigned grid = (unsigned)(d.B * d.H);
-    FNO_WITH_K(d, FNO_WITH_ACT(d.dec_act, (k_fno_rowinv_dec<A, KZ, KC><<<grid, 256, rowinv_dec_lds(d), st>>>(d, v, out, l))))
+    const size_t lds_p = rowinv_dec_lds(d) + (size_t)dec_hidden_weights(d) * 2 + (size_t)d.dec_layers * d.DSP * 4;
+    if (rowinv_persistent(d, false) && lds_p + 32 * 64 * 2 + 64 <= 64 * 1024) {
+        FNO_WITH_KZC(d, FNO_WITH_ACT(d.dec_act, (launch_persistent(k_fno_rowinv_dec_p<A, KZ, KC>, d, lds_p, grid, st,
+                                                                   256u, v, out, l))));
+    } else {
+        FNO_WITH_K(d, FNO_WITH_ACT(d.dec_act, (k_fno_rowinv_dec<A, KZ, KC><<<grid, 256, rowinv_dec_lds(d), st>>>(d, v, out, l))))
+    }
 }
 
 // dynamic LDS of the column kernel: xs [R2][CP] float, ys [CP][R2] bf16 and, when
@@ -1255,6 +1598,13 @@ extern "C" int fno_model_create(fno_model** out, const fno_spec* spec, const flo
     d.act = s.act; d.dec_act = s.dec_act;
     if ((size_t)d.CP * vt_stride(d) * 2 > 64 * 1024) return fail(LBM_EUNSUPPORTED, "row of %d x %d too large for LDS", d.Wpad, d.CP);
     d.colS = col_split(d);
+    {
+        int dev = 0, ncu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
+            ncu = 256;
+        d.ncu = ncu;
+    }
     if (col_lds(d) > 64 * 1024) return fail(LBM_EUNSUPPORTED, "mode block too large for LDS");
     if (zs_lds(d) > 64 * 1024) return fail(LBM_EUNSUPPORTED, "row coefficients too large for LDS");
     fno_model* m = new (std::nothrow) fno_model();
@@ -1459,10 +1809,17 @@ static void launch_forward(const fno_model* m, const float* d_in, float* d_out, 
     const bool flift = !d.sv_a1 && d.Wpad <= 1024 && lds_row + 12 * 1024 <= 64 * 1024;
     if (flift) {
         const unsigned threads = (unsigned)rup(d.Wpad, 64), grid = (unsigned)(B * d.Hpad);
-        if (d.CP <= 32) {
-            FNO_WITH_ACT(d.act, (k_fno_lift_row<32, A><<<grid, threads, lds_row, st>>>(d, d_in)))
+        // with the row-DFT operand held in registers (at most one row-DFT tile per
+        // wave, rows of 160 or 256 points) the workgroups are persistent
+        const int kw = row_dft_tiles(d) > (int)threads / 64 ? 0 : d.Wpad == 256 ? 8 : d.Wpad == 160 ? 5 : 0;
+        if (kw == 8) {
+            FNO_WITH_LIFT(d, FNO_WITH_ACT(d.act, (launch_persistent(k_fno_lift_row<NO, A, KH, 8>, d, lds_row, grid,
+                                                                    st, threads, d_in))));
+        } else if (kw == 5) {
+            FNO_WITH_LIFT(d, FNO_WITH_ACT(d.act, (launch_persistent(k_fno_lift_row<NO, A, KH, 5>, d, lds_row, grid,
+                                                                    st, threads, d_in))));
         } else {
-            FNO_WITH_ACT(d.act, (k_fno_lift_row<64, A><<<grid, threads, lds_row, st>>>(d, d_in)))
+            FNO_WITH_LIFT(d, FNO_WITH_ACT(d.act, (k_fno_lift_row<NO, A, KH, 0><<<grid, threads, lds_row, st>>>(d, d_in))));
         }
     } else {
         launch_lift(d, npts, d_in, st);
