@@ -563,21 +563,26 @@ __global__ __launch_bounds__(1024) void k_fno_lift_row(FnoDev d, const float* __
 
 // Column inverse of column k2 of sample b from Y[o][r] in LDS: Zc[q][o] =
 // sum_r EcolB[q][r] Y[o][r], q = ri * Hpad + h, stored to Z rows kk = 2 k2 + ri
-// (rows h < Hp; the 32 lanes of a half-wave write 32 consecutive channels).
+// (rows h < Hp).  Each tile is formed transposed, C^T[o][q], so that a lane holds
+// four consecutive channels of one (ri, h) and stores them as one 8-byte quad.
 __device__ __forceinline__ void z_store_column(const FnoDev& d, int b, int k2, const __bf16* ys) {
-    const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6, lane = threadIdx.x & 63;
     const int Mt = 2 * d.Hpad / 32, Nt = d.CP / 32;
     for (int t = wave; t < Mt * Nt; t += nw) {
         const int mi = t / Nt, ni = t % Nt;
         f32x16 acc = {};
-        acc = mma_tile(d.EcolB + (size_t)mi * 32 * d.R2, d.R2, ys + ni * 32 * d.R2, d.R2, d.R2, acc);
-        const int o = ni * 32 + acc_col();
+        acc = mma_tile(ys + ni * 32 * d.R2, d.R2, d.EcolB + (size_t)mi * 32 * d.R2, d.R2, d.R2, acc);
+        const int q = mi * 32 + (lane & 31);
+        const int ri = q >= d.Hpad ? 1 : 0, h = q - ri * d.Hpad;
+        if (h < d.Hp) {
+            __bf16* zp = d.Z + (((size_t)b * 2 * d.m2 + 2 * k2 + ri) * d.Hp + h) * d.CP + ni * 32 + 4 * (lane >> 5);
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int q = mi * 32 + acc_row(r);
-            const int ri = q >= d.Hpad ? 1 : 0, h = q - ri * d.Hpad;
-            if (h < d.Hp)
-                d.Z[(((size_t)b * 2 * d.m2 + 2 * k2 + ri) * d.Hp + h) * d.CP + o] = to_bf16(acc[r]);
+            for (int j = 0; j < 4; ++j) {
+                uint2 w;
+                w.x = pack_bf16(acc[4 * j], acc[4 * j + 1]);
+                w.y = pack_bf16(acc[4 * j + 2], acc[4 * j + 3]);
+                *reinterpret_cast<uint2*>(zp + 8 * j) = w;
+            }
         }
     }
 }
