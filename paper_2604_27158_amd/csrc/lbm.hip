@@ -614,9 +614,15 @@ __device__ __forceinline__ bool ring_node(const LatticeGeom& g, int& i, int& j) 
     return true;
 }
 
+// Link codes of the level-0 region of a fused tile, kept in LDS for every level:
+// the node's link bits, or LK_SKIP for a solid node or a position outside a
+// non-periodic axis.
+constexpr unsigned short LK_SKIP = 0x100;
+
 // Levels 1 .. S-2: the ring S-1-LVL nodes wide, from level LVL-1 in LDS.
 template <int S, int RY, int LVL, bool ZH, bool FORCE, typename R>
-__device__ __forceinline__ void ring_levels(const StepArgs& a, int x0, int y0, int tid, float* __restrict__ P) {
+__device__ __forceinline__ void ring_levels(const StepArgs& a, int x0, int y0, int tid, float* __restrict__ P,
+                                            const unsigned short* __restrict__ LKS) {
     if constexpr (LVL < S - 1) {
         using G = Ring<S, RY>;
         constexpr int W = G::W(LVL), LN = G::LN(LVL), WP = G::W(LVL - 1), LNP = G::LN(LVL - 1);
@@ -630,11 +636,10 @@ __device__ __forceinline__ void ring_levels(const StepArgs& a, int x0, int y0, i
             const int e = tid + t * TX * RY;
             if (e >= LN) continue;
             const int ly = e / W, lx = e - ly * W;
+            const unsigned lk = LKS[(ly + LVL) * G::W(0) + lx + LVL];
+            if (lk == LK_SKIP) continue;
             int i = x0 - RING + lx, j = y0 - RING + ly;
-            if (!ring_node(a.g, i, j)) continue;
-            const int n = j * a.g.nx + i;
-            const unsigned lk = a.link[n];
-            if (is_solid(lk, a.mask, n)) continue;
+            (void)ring_node(a.g, i, j);  // wraps i on a periodic axis (the node is inside)
             float f[9];
             pull_lds(P, WP, LNP, (ly + 1) * WP + lx + 1, lk, f);
             (void)collide_node<ZH, FORCE, R>(f, i, a.g.nx, a);
@@ -650,56 +655,78 @@ __device__ __forceinline__ void ring_levels(const StepArgs& a, int x0, int y0, i
             for (int q = 0; q < 9; ++q) P[q * LN + tid + t * TX * RY] = v[t][q];
         }
         __syncthreads();
-        ring_levels<S, RY, LVL + 1, ZH, FORCE, R>(a, x0, y0, tid, P);
+        ring_levels<S, RY, LVL + 1, ZH, FORCE, R>(a, x0, y0, tid, P, LKS);
     }
 }
 
 template <int S, int RY, bool ZH, bool FORCE, bool NT, typename R>
-__device__ __forceinline__ void step_multi(const StepArgs& a, int bx, int by, float* __restrict__ P) {
+__device__ __forceinline__ void step_multi(const StepArgs& a, int bx, int by, float* __restrict__ P,
+                                           unsigned short* __restrict__ LKS) {
     using G = Ring<S, RY>;
     constexpr int W0 = G::W(0), LN0 = G::LN(0);
+    constexpr int NTH = TX * RY, IT0 = (LN0 + NTH - 1) / NTH;
     const int x0 = bx * TX, y0 = by * RY;
     const int nx = a.g.nx, ny = a.g.ny;
     const int tid = threadIdx.y * TX + threadIdx.x;
-    for (int e = tid; e < LN0; e += TX * RY) {
+    // level 0: a lane's IT0 nodes in three passes (link codes, then every
+    // population load, then the collisions), so that their memory latencies overlap;
+    // the link codes go to LDS for the later levels
+    unsigned code[IT0];
+    int ii[IT0], jj[IT0];
+#pragma unroll
+    for (int t = 0; t < IT0; ++t) {
+        code[t] = LK_SKIP;
+        const int e = tid + t * NTH;
+        if (e >= LN0) continue;
         const int ly = e / W0, lx = e - ly * W0;
         int i = x0 - (S - 1) + lx, j = y0 - (S - 1) + ly;
-        if (!ring_node(a.g, i, j)) continue;
-        const int n = j * nx + i;
-        const unsigned lk = a.link[n];
-        if (is_solid(lk, a.mask, n)) continue;
-        float f[9];
-        gather_stream<float>(a.src, a.g, i, j, n, f);
-        gather_bounce<float>(a.src, a.g, lk, n, f);
-        (void)collide_node<ZH, FORCE, R>(f, i, nx, a);
+        if (ring_node(a.g, i, j)) {
+            const int n = j * nx + i;
+            const unsigned lk = a.link[n];
+            if (!is_solid(lk, a.mask, n)) code[t] = lk;
+        }
+        ii[t] = i;
+        jj[t] = j;
+        LKS[e] = (unsigned short)code[t];
+    }
+    float f[IT0][9];
 #pragma unroll
-        for (int q = 0; q < 9; ++q) P[q * LN0 + e] = f[q];
+    for (int t = 0; t < IT0; ++t)
+        if (code[t] != LK_SKIP) gather_stream<float>(a.src, a.g, ii[t], jj[t], jj[t] * nx + ii[t], f[t]);
+#pragma unroll
+    for (int t = 0; t < IT0; ++t) {
+        if (code[t] == LK_SKIP) continue;
+        gather_bounce<float>(a.src, a.g, code[t], jj[t] * nx + ii[t], f[t]);
+        (void)collide_node<ZH, FORCE, R>(f[t], ii[t], nx, a);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) P[q * LN0 + tid + t * NTH] = f[t][q];
     }
     __syncthreads();
-    ring_levels<S, RY, 1, ZH, FORCE, R>(a, x0, y0, tid, P);
+    ring_levels<S, RY, 1, ZH, FORCE, R>(a, x0, y0, tid, P, LKS);
     constexpr int WL = G::W(S - 2), LNL = G::LN(S - 2);
     const int i = x0 + threadIdx.x, j = y0 + threadIdx.y;
     if (i >= nx || j >= ny) return;
     const int n = j * nx + i;
-    const unsigned lk = a.link[n];
-    if (is_solid(lk, a.mask, n)) return;
-    float f[9];
-    pull_lds(P, WL, LNL, (threadIdx.y + 1) * WL + threadIdx.x + 1, lk, f);
-    (void)collide_node<ZH, FORCE, R>(f, i, nx, a);
+    const unsigned lk = LKS[(threadIdx.y + S - 1) * W0 + threadIdx.x + S - 1];
+    if (lk == LK_SKIP) return;
+    float fl[9];
+    pull_lds(P, WL, LNL, (threadIdx.y + 1) * WL + threadIdx.x + 1, lk, fl);
+    (void)collide_node<ZH, FORCE, R>(fl, i, nx, a);
     const size_t N = (size_t)a.g.N;
     float* __restrict__ d = a.dst + n;
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
-        if (NT) __builtin_nontemporal_store(f[q], d + q * N); else d[q * N] = f[q];
+        if (NT) __builtin_nontemporal_store(fl[q], d + q * N); else d[q * N] = fl[q];
     }
 }
 
 template <int S, int RY, bool ZH, bool FORCE, bool NT, typename R>
 __global__ __launch_bounds__(TX * RY) void k_bgk_multi(StepArgs a) {
     __shared__ float P[9 * Ring<S, RY>::LN(0)];
+    __shared__ unsigned short LKS[Ring<S, RY>::LN(0)];
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int by = b / a.g.gridx;
-    step_multi<S, RY, ZH, FORCE, NT, R>(a, b - by * a.g.gridx, by, P);
+    step_multi<S, RY, ZH, FORCE, NT, R>(a, b - by * a.g.gridx, by, P, LKS);
 }
 
 // Four-wide step (nx % 4 == 0): each lane owns four consecutive x nodes of one
@@ -865,17 +892,18 @@ template <int S, int RY, bool NT, typename R>
 __global__ __launch_bounds__(TX * RY) void k_bgk_batchm(const StepArgs* __restrict__ args,
                                                         const BatchTile* __restrict__ tiles) {
     __shared__ float P[9 * Ring<S, RY>::LN(0)];
+    __shared__ unsigned short LKS[Ring<S, RY>::LN(0)];
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const BatchTile t = tiles[b];
     const StepArgs a = args[t.traj];
     const bool zh = a.g.bc_x == LBM_BC_ZOUHE;
     const bool force = a.gx != 0.0 || a.gy != 0.0;
     if (zh) {
-        if (force) step_multi<S, RY, true, true, NT, R>(a, t.bx, t.by, P);
-        else step_multi<S, RY, true, false, NT, R>(a, t.bx, t.by, P);
+        if (force) step_multi<S, RY, true, true, NT, R>(a, t.bx, t.by, P, LKS);
+        else step_multi<S, RY, true, false, NT, R>(a, t.bx, t.by, P, LKS);
     } else {
-        if (force) step_multi<S, RY, false, true, NT, R>(a, t.bx, t.by, P);
-        else step_multi<S, RY, false, false, NT, R>(a, t.bx, t.by, P);
+        if (force) step_multi<S, RY, false, true, NT, R>(a, t.bx, t.by, P, LKS);
+        else step_multi<S, RY, false, false, NT, R>(a, t.bx, t.by, P, LKS);
     }
 }
 
