@@ -26,6 +26,8 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <tuple>
+#include <utility>
 #include <vector>
 
 #include "common.hpp"
@@ -1296,12 +1298,29 @@ static bool fuse_row_dft(const FnoDev& d) {
 // A persistent row kernel over `rows` rows: as many 256-thread workgroups as fit on
 // the device at once (the occupancy the runtime reports for this kernel and LDS
 // size, times the compute units), at most one per row.
-template <typename... P, typename... Args>
-static void launch_persistent(void (*kernel)(P...), const FnoDev& d, size_t lds, unsigned rows, hipStream_t st,
-                              unsigned threads, Args... args) {
+// The runtime's occupancy query, remembered per (kernel, block size, LDS size): the
+// forward asks it for every persistent launch.
+static int blocks_per_cu(const void* kernel, unsigned threads, size_t lds) {
+    static std::mutex mu;
+    static std::vector<std::pair<std::tuple<const void*, unsigned, size_t>, int>> seen;
+    const auto key = std::make_tuple(kernel, threads, lds);
+    {
+        std::lock_guard<std::mutex> g(mu);
+        for (const auto& e : seen)
+            if (e.first == key) return e.second;
+    }
     int per = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, (int)threads, lds) != hipSuccess || per < 1)
         per = 1;
+    std::lock_guard<std::mutex> g(mu);
+    seen.emplace_back(key, per);
+    return per;
+}
+
+template <typename... P, typename... Args>
+static void launch_persistent(void (*kernel)(P...), const FnoDev& d, size_t lds, unsigned rows, hipStream_t st,
+                              unsigned threads, Args... args) {
+    const int per = blocks_per_cu(reinterpret_cast<const void*>(kernel), threads, lds);
     const unsigned grid = std::min(rows, (unsigned)(per * d.ncu));
     kernel<<<grid, threads, lds, st>>>(d, args...);
 }
