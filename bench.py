@@ -266,6 +266,11 @@ def bench_fno(out):
         ms = time_call(lambda: model.forward(x, out=y, stream=s), s, reps)
         res[f"B{B}"] = {"ms": ms, "samples_per_s": B / (ms * 1e-3),
                         "tflops": flops * B / (ms * 1e-3) / 1e12}
+        if B == 1:
+            # the hybrids' form: the launches replayed from a captured HIP graph
+            for _ in range(3):
+                model.forward(x, out=y, stream=s, graph=True)
+            res["B1"]["ms_graph"] = time_call(lambda: model.forward(x, out=y, stream=s, graph=True), s, reps)
         s.synchronize()
         samples[B] = (x[k:k + 1].cpu().numpy().astype(np.float64), y[k:k + 1].cpu().numpy().astype(np.float64))
     # roofline at batch 100: achieved FLOP/s against min(dense bf16 MFMA peak,

@@ -229,7 +229,8 @@ struct FnoDev {
     int dec_layers, dec_size, DSP, cout, act, dec_act, coords;
     // parameters (device)
     const float *lift1w, *lift1b, *lift2w, *lift2b;  // float32
-    const __bf16* Rmix;     // [L][m2][K1][CP][CP][2]
+    const __bf16* Rmix;     // [L][m2][K1][CP o][CP i][2] (backward: i contiguous)
+    const __bf16* RmixT;    // [L][m2][K1][CP i][CP o][2] (forward: o contiguous)
     const __bf16* Wc;       // [L][CP][CP]
     const float* bc;        // [L][CP]
     const __bf16* decw;     // per decoder layer [DSP][in_p], then out [CoutP][DSP]
@@ -614,14 +615,27 @@ __host__ __device__ __forceinline__ int ts_stride(const FnoDev& d) { return 2 * 
 
 // T of column k2 of sample b, staged transposed: tsl[c][ri * Hpad + h] (the MFMA
 // operand layout, K contiguous).  Each row h holds the column's CP (re, im) pairs
-// as one 128-byte (CP = 32) piece, read with 16-byte loads.  Ends with a barrier.
+// as one 128-byte (CP = 32) piece, read with 16-byte loads (eight lanes per piece);
+// a thread takes one 16-byte slot q of four consecutive rows and writes each of its
+// eight values' four rows as one 8-byte LDS store (Hpad is a multiple of 16).
+// Ends with a barrier.
 __device__ __forceinline__ void stage_t(const FnoDev& d, int b, int k2, __bf16* tsl) {
-    const int TS = ts_stride(d), nq = d.CP / 4;
-    for (int i = threadIdx.x; i < d.Hpad * nq; i += blockDim.x) {
-        const int h = i / nq, q = i - h * nq;
-        const bf16x8 t = *reinterpret_cast<const bf16x8*>(t_row(d, b, h) + (size_t)k2 * d.CP * 2 + 8 * q);
+    const int TS = ts_stride(d), nq = d.CP / 4, ng = d.Hpad / 4;
+    for (int i = threadIdx.x; i < ng * nq; i += blockDim.x) {
+        const int g = i / nq, q = i - g * nq;
+        bf16x8 t[4];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) tsl[(4 * q + (e >> 1)) * TS + (e & 1) * d.Hpad + h] = t[e];
+        for (int u = 0; u < 4; ++u)
+            t[u] = *reinterpret_cast<const bf16x8*>(t_row(d, b, 4 * g + u) + (size_t)k2 * d.CP * 2 + 8 * q);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            bf16x4 v;
+            v[0] = t[0][e];
+            v[1] = t[1][e];
+            v[2] = t[2][e];
+            v[3] = t[3][e];
+            *reinterpret_cast<bf16x4*>(tsl + (4 * q + (e >> 1)) * TS + (e & 1) * d.Hpad + 4 * g) = v;
+        }
     }
     __syncthreads();
 }
@@ -631,6 +645,8 @@ __device__ __forceinline__ void stage_t(const FnoDev& d, int b, int k2, __bf16* 
 // Launched with COL_THREADS threads: at batch 1 there is one workgroup per mode
 // column and the kernel is a chain of memory latencies, so more waves shorten it.
 constexpr int COL_THREADS = 512;
+
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
 
 __global__ __launch_bounds__(COL_THREADS) void k_fno_col(FnoDev d, int layer) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -642,10 +658,13 @@ __global__ __launch_bounds__(COL_THREADS) void k_fno_col(FnoDev d, int layer) {
     const int tid = threadIdx.x, wave = tid >> 6, nw = blockDim.x >> 6;
     const int H2 = 2 * d.Hpad, TS = ts_stride(d);
     const int Nt = d.CP / 32;
+    const int nmix = d.K1 * d.width;
+    const uint32_t* R =
+        reinterpret_cast<const uint32_t*>(d.RmixT + ((size_t)layer * d.m2 + k2) * d.K1 * d.CP * d.CP * 2);
+    const int Mt1 = d.R2 / 32, T1 = Mt1 * Nt;
     stage_t(d, b, k2, Ts);
     float* svX = d.sv_X ? d.sv_X + ((size_t)b * d.m2 + k2) * d.R2 * d.CP : nullptr;
     // X[r][c] = sum_{ri,h} EcolA[r][ri,h] T[c][ri,h]
-    const int Mt1 = d.R2 / 32, T1 = Mt1 * Nt;
     if (d.colS == 1) {
         for (int t = wave; t < T1; t += nw) {
             const int mi = t / Nt, ni = t % Nt;
@@ -688,29 +707,52 @@ __global__ __launch_bounds__(COL_THREADS) void k_fno_col(FnoDev d, int layer) {
             if (svX) svX[i] = xv;
         }
     }
+    __syncthreads();
+    // X as the mixing's bf16 operand pairs, in place: the slot of xr = X[k][c] takes
+    // (xr, -xi) and that of xi = X[K1 + k][c] takes (xi, xr), so that with a weight
+    // pair w = (rr, ri), dot((xr, -xi), w) = Re(x r) and dot((xi, xr), w) = Im(x r).
+    // (X is already bf16, so the packing is exact.)
+    uint32_t* xu = reinterpret_cast<uint32_t*>(xs);
+    for (int i = tid; i < d.K1 * d.CP; i += blockDim.x) {
+        const float xr = xs[i], xi = xs[d.K1 * d.CP + i];
+        xu[i] = pack_bf16(xr, -xi);
+        xu[d.K1 * d.CP + i] = pack_bf16(xi, xr);
+    }
     for (int i = tid; i < d.CP * d.R2; i += blockDim.x) ys[i] = to_bf16(0.0f);
     __syncthreads();
     // Y[k][o] = sum_i X[k][i] R[i][o][k][k2] (complex), k over the 2 m1 kept rows
-    // Only the width real channels take part: the padded channels of X are zero and
-    // so are R's padded rows and columns, and ys was cleared above.  Weights are read
-    // two complex values (8 bytes) at a time; width is even.
-    const __bf16* R = d.Rmix + ((size_t)layer * d.m2 + k2) * d.K1 * d.CP * d.CP * 2;
-    for (int idx = tid; idx < d.K1 * d.width; idx += blockDim.x) {
+    // Only the width real channels take part, and ys was cleared above.  A thread
+    // forms one (k, o) with two bf16 dot products per i (each product exact in
+    // FP32); the weights are laid out with o contiguous, so for each i the lanes of
+    // a wave read consecutive (re, im) pairs of one or two weight rows, and the
+    // operand pairs of X are the same for 32 lanes.
+    for (int idx = tid; idx < nmix; idx += blockDim.x) {
         const int k = idx / d.width, o = idx % d.width;
-        const float* xr = xs + k * d.CP;
-        const float* xi = xs + (d.K1 + k) * d.CP;
-        const bf16x4* Rk = reinterpret_cast<const bf16x4*>(R + ((size_t)k * d.CP + o) * d.CP * 2);
+        const uint32_t* p1 = xu + (size_t)k * d.CP;
+        const uint32_t* p2 = xu + (size_t)(d.K1 + k) * d.CP;
+        const uint32_t* Rk = R + (size_t)k * d.CP * d.CP + o;
         float sr = 0.0f, si = 0.0f;
-        for (int i = 0; i < d.width; i += 2) {
-            const bf16x4 r4 = Rk[i >> 1];
+        if (d.width <= 32) {
+            // 32 channels (CP >= 32) in two groups of 16 weights requested together;
+            // the padded channels' X and R are zero and add nothing
 #pragma unroll
-            for (int e = 0; e < 2; ++e) {
-                const float rr = from_bf16(r4[2 * e]), rim = from_bf16(r4[2 * e + 1]);
-                const float a = xr[i + e], c = xi[i + e];
-                sr = fmaf(a, rr, sr);
-                sr = fmaf(-c, rim, sr);
-                si = fmaf(a, rim, si);
-                si = fmaf(c, rr, si);
+            for (int i0 = 0; i0 < 32; i0 += 16) {
+                uint32_t wv[16];
+#pragma unroll
+                for (int j = 0; j < 16; ++j) wv[j] = Rk[(size_t)(i0 + j) * d.CP];
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    const bf16x2v w = __builtin_bit_cast(bf16x2v, wv[j]);
+                    sr = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2v, p1[i0 + j]), w, sr, false);
+                    si = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2v, p2[i0 + j]), w, si, false);
+                }
+            }
+        } else {
+#pragma unroll 8
+            for (int i = 0; i < d.width; ++i) {
+                const bf16x2v w = __builtin_bit_cast(bf16x2v, Rk[(size_t)i * d.CP]);
+                sr = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2v, p1[i]), w, sr, false);
+                si = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2v, p2[i]), w, si, false);
             }
         }
         ys[o * d.R2 + k] = to_bf16(sr);
@@ -1469,6 +1511,20 @@ static int upload(fno_model* m, const std::vector<T>& h, const T** out) {
     return LBM_OK;
 }
 
+// The forward mixing layout of the spectral weights: (o, i) of every [CP][CP][2]
+// block of the backward layout swapped.
+template <typename T>
+static std::vector<T> mix_transpose(const std::vector<T>& a, int CP) {
+    std::vector<T> t(a.size());
+    const size_t blk = (size_t)CP * CP * 2;
+    for (size_t b0 = 0; b0 < a.size(); b0 += blk)
+        for (int o = 0; o < CP; ++o)
+            for (int i = 0; i < CP; ++i)
+                for (int ri = 0; ri < 2; ++ri)
+                    t[b0 + ((size_t)i * CP + o) * 2 + ri] = a[b0 + ((size_t)o * CP + i) * 2 + ri];
+    return t;
+}
+
 static int build_param_maps(fno_model* m, const FnoDev& d) {
     const fno_spec& s = m->spec;
     const int wd = s.width, CP = d.CP, half = d.half, cl = d.cl;
@@ -1540,9 +1596,10 @@ static int build_param_maps(fno_model* m, const FnoDev& d) {
         off += s.cout;
     }
     m->nparams = off;
+    std::vector<int32_t> RmT = mix_transpose(Rm, CP);
     struct Item { const void* dst; std::vector<int32_t>* v; bool bf; };
     Item items[] = {{d.lift1w, &l1w, false}, {d.lift1b, &l1b, false}, {d.lift2w, &l2w, false},
-                    {d.lift2b, &l2b, false}, {d.Rmix, &Rm, true}, {d.Wc, &Wc, true},
+                    {d.lift2b, &l2b, false}, {d.Rmix, &Rm, true}, {d.RmixT, &RmT, true}, {d.Wc, &Wc, true},
                     {d.WcT, &WcT, true}, {d.bc, &bc, false}, {d.decw, &decw, true},
                     {d.decb, &decb, false}, {d.decwT, &decwT, true}};
     for (const Item& it : items) {
@@ -1754,16 +1811,17 @@ extern "C" int fno_model_create(fno_model** out, const fno_spec* spec, const flo
     }
     // ---- upload
     const float *f1, *f2, *f3, *f4, *f5, *f6;
-    const uint16_t *u1, *u2, *u3, *u4, *u5, *u6, *u7, *u8, *u9, *u10;
+    const uint16_t *u1, *u2, *u3, *u4, *u5, *u6, *u7, *u8, *u9, *u10, *u11;
     if ((rc = upload(m, l1w, &f1)) || (rc = upload(m, l1b, &f2)) || (rc = upload(m, l2w, &f3)) ||
         (rc = upload(m, l2b, &f4)) || (rc = upload(m, bc, &f5)) || (rc = upload(m, decb, &f6)) ||
         (rc = upload(m, Rmix, &u1)) || (rc = upload(m, Wc, &u2)) || (rc = upload(m, decw, &u3)) ||
         (rc = upload(m, EwT, &u4)) || (rc = upload(m, BinvT, &u5)) || (rc = upload(m, EcolA, &u6)) ||
         (rc = upload(m, EcolB, &u7)) || (rc = upload(m, WcT, &u8)) || (rc = upload(m, B1, &u9)) ||
-        (rc = upload(m, decwT, &u10)))
+        (rc = upload(m, decwT, &u10)) || (rc = upload(m, mix_transpose(Rmix, CP), &u11)))
         return bail(rc);
     d.lift1w = f1; d.lift1b = f2; d.lift2w = f3; d.lift2b = f4; d.bc = f5; d.decb = f6;
     d.Rmix = reinterpret_cast<const __bf16*>(u1);
+    d.RmixT = reinterpret_cast<const __bf16*>(u11);
     d.Wc = reinterpret_cast<const __bf16*>(u2);
     d.decw = reinterpret_cast<const __bf16*>(u3);
     d.EwT = reinterpret_cast<const __bf16*>(u4);
