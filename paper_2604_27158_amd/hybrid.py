@@ -81,7 +81,7 @@ class HybridRunner:
     the host no longer waits for the GPU twice per cycle."""
 
     def __init__(self, lattice, fno, dt_fno: int = 100, k_fno: int = 5, n_lbm: int = 200,
-                 guard: Optional[Guard] = None, speculative: bool = False):
+                 guard: Optional[Guard] = None, speculative: bool = False, graph: bool = False):
         import torch
         if fno.spec.cin != 4 or fno.spec.cout != 3:
             raise ValueError("the hybrid FNO maps (rho, ux, uy, mask) -> (rho, ux, uy)")
@@ -90,6 +90,9 @@ class HybridRunner:
         self.lat, self.fno = lattice, fno
         self.dt_fno, self.k_fno, self.n_lbm = int(dt_fno), int(k_fno), int(n_lbm)
         self.guard = guard or Guard()
+        # graph=True replays the FNO's launches from a captured HIP graph; on MI355X
+        # that is no faster than launching them (a few microseconds slower)
+        self.graph = bool(graph)
         with torch.cuda.stream(lattice.stream):
             self.x = torch.empty((1, 4, lattice.ny, lattice.nx), dtype=torch.float32, device="cuda")
             self.y = torch.empty((1, 3, lattice.ny, lattice.nx), dtype=torch.float32, device="cuda")
@@ -114,7 +117,7 @@ class HybridRunner:
             if macros.data_ptr() != self.x.data_ptr():
                 self.x[0, :3].copy_(macros)
             for k in range(self.k_fno):
-                self.fno.forward(self.x, out=self.y, stream=self.lat.stream, graph=True)
+                self.fno.forward(self.x, out=self.y, stream=self.lat.stream, graph=self.graph)
                 if k + 1 < self.k_fno:
                     self.x[0, :3].copy_(self.y[0])
         return self.y[0]

@@ -131,7 +131,7 @@ class Surrogate:
     """Both trained models of a group on the 128 x 128 grid.  step(fields) maps raw
     (rho, ux, uy) [3][N][N] (device) one Delta T ahead."""
 
-    def __init__(self, group: str, path: str | None = None, graph: bool = True):
+    def __init__(self, group: str, path: str | None = None, graph: bool = False):
         import torch
         from paper_2604_27158_amd import fno as gfno
         spec_r, spec_u = GROUPS[group]
@@ -140,7 +140,8 @@ class Surrogate:
             self.u = gfno.Fno(spec_u, z["u_params"], N, N)
         self.group = group
         self.graph = graph
-        # fixed input and output buffers: the two forwards replay captured graphs
+        # fixed input and output buffers (graph=True: the two forwards replay captured
+        # graphs, which on MI355X is no faster than launching them)
         self.x = torch.empty((3, N, N), dtype=torch.float32, device="cuda")
         self.y = torch.empty((3, N, N), dtype=torch.float32, device="cuda")
 
