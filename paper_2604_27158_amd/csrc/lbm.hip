@@ -1956,34 +1956,44 @@ static int autotune(lbm_batch* b, bool quad_ok, const char* cache) {
         b->choice = std::string("cached ") + shape_name(q) + (t ? "+nt" : "");
         return LBM_OK;
     }
-    float best = 1e30f;
-    int bq = 0;
-    bool bt = false;
+    // three rounds over all candidates (the order reversed every round), each
+    // candidate keeping its fastest round: one noisy timing does not decide
+    float tmin[kBatchShapes][2];
+    for (auto& r : tmin) r[0] = r[1] = 1e30f;
     hipEvent_t e0, e1;
     LBM_HIP(hipEventCreate(&e0));
     LBM_HIP(hipEventCreate(&e1));
-    for (int qi = kBatchShapes - 1; qi >= 0; --qi) {
-        if (qi == 1 && !quad_ok) continue;
-        int rc = set_shape(b, qi);
-        if (rc) return rc;
-        for (int ti = 0; ti < 2; ++ti) {
-            b->nt = ti != 0;
-            // 16 timed launches (16 x spl steps), after an even warm-up
-            for (int k = 0; k < 4; ++k) {
-                if (b->spl > 1) launch_batch2(b, k & 1); else launch_batch(b, k & 1);
+    for (int round = 0; round < 3; ++round) {
+        for (int c = 0; c < kBatchShapes; ++c) {
+            const int qi = round % 2 ? c : kBatchShapes - 1 - c;
+            if (qi == 1 && !quad_ok) continue;
+            int rc = set_shape(b, qi);
+            if (rc) return rc;
+            for (int ti = 0; ti < 2; ++ti) {
+                b->nt = ti != 0;
+                // 16 timed launches (16 x spl steps), after an even warm-up
+                for (int k = 0; k < 4; ++k) {
+                    if (b->spl > 1) launch_batch2(b, k & 1); else launch_batch(b, k & 1);
+                }
+                LBM_HIP(hipEventRecord(e0, b->stream));
+                for (int k = 0; k < 16; ++k) {
+                    if (b->spl > 1) launch_batch2(b, k & 1); else launch_batch(b, k & 1);
+                }
+                LBM_HIP(hipEventRecord(e1, b->stream));
+                LBM_HIP(hipEventSynchronize(e1));
+                float ms = 0.0f;
+                LBM_HIP(hipEventElapsedTime(&ms, e0, e1));
+                ms /= 16.0f * b->spl;   // per lattice step
+                tmin[qi][ti] = std::min(tmin[qi][ti], ms);
             }
-            LBM_HIP(hipEventRecord(e0, b->stream));
-            for (int k = 0; k < 16; ++k) {
-                if (b->spl > 1) launch_batch2(b, k & 1); else launch_batch(b, k & 1);
-            }
-            LBM_HIP(hipEventRecord(e1, b->stream));
-            LBM_HIP(hipEventSynchronize(e1));
-            float ms = 0.0f;
-            LBM_HIP(hipEventElapsedTime(&ms, e0, e1));
-            ms /= 16.0f * b->spl;   // per lattice step
-            if (ms < best) { best = ms; bq = qi; bt = b->nt; }
         }
     }
+    float best = 1e30f;
+    int bq = 0;
+    bool bt = false;
+    for (int qi = kBatchShapes - 1; qi >= 0; --qi)
+        for (int ti = 0; ti < 2; ++ti)
+            if (tmin[qi][ti] < best) { best = tmin[qi][ti]; bq = qi; bt = ti != 0; }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     b->nt = bt;
