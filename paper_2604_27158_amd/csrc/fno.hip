@@ -404,22 +404,22 @@ __global__ __launch_bounds__(256) void k_fno_lift(FnoDev d, const float* __restr
 // the column transform's padded K range is exactly zero).
 // Row DFT of row (b, h < Hp) from its transposed copy vt[c][w] in LDS:
 // T[k2][c][ri][h] = sum_w EwT[2 k2 + ri][w] vt[c][w].
-// Row h of sample b in T: m2 * CP (re, im) pairs, pair (k2, c) at 2 (k2 CP + c).
-__device__ __forceinline__ __bf16* t_row(const FnoDev& d, int b, int h) {
-    return d.T + ((size_t)b * d.Hpad + h) * d.m2 * d.CP * 2;
+// T is laid out [B][m2][Hpad][CP] (re, im) pairs, so that the column kernel of
+// (b, k2) reads one contiguous block: the CP pairs of row h, mode k2.
+__device__ __forceinline__ __bf16* t_piece(const FnoDev& d, int b, int h, int k2) {
+    return d.T + (((size_t)b * d.m2 + k2) * d.Hpad + h) * d.CP * 2;
 }
 
 // Rows h >= Hp of T are zero (the column transform's K range runs over Hpad rows).
 __device__ __forceinline__ void t_zero_row(const FnoDev& d, int b, int h) {
-    uint32_t* row = reinterpret_cast<uint32_t*>(t_row(d, b, h));
-    for (int i = threadIdx.x; i < d.m2 * d.CP; i += blockDim.x) row[i] = 0u;
+    for (int i = threadIdx.x; i < d.m2 * d.CP; i += blockDim.x)
+        reinterpret_cast<uint32_t*>(t_piece(d, b, h, i / d.CP))[i % d.CP] = 0u;
 }
 
 // The KKp x CP result is taken in 16 x 16 tiles, so that every wave of the
 // workgroup has one (the 2 m2 <= KKp rows in use fill fewer 32-row tiles than there
 // are waves).
 __device__ __forceinline__ void row_dft_from_lds(const FnoDev& d, const __bf16* vt, int b, int h) {
-    uint32_t* Tr = reinterpret_cast<uint32_t*>(t_row(d, b, h));
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int Mt = (2 * d.m2 + 15) / 16, Nt = d.CP / 16;
     for (int t = wave; t < Mt * Nt; t += blockDim.x >> 6) {
@@ -431,8 +431,9 @@ __device__ __forceinline__ void row_dft_from_lds(const FnoDev& d, const __bf16* 
         // per pair, and the 16 lanes of a quarter-wave store 16 consecutive words
         const int c = ni * 16 + (lane & 15);
         const int kk = mi * 16 + 4 * (lane >> 4);
-        if (kk < 2 * d.m2) Tr[(kk >> 1) * d.CP + c] = pack_bf16(acc[0], acc[1]);
-        if (kk + 2 < 2 * d.m2) Tr[((kk >> 1) + 1) * d.CP + c] = pack_bf16(acc[2], acc[3]);
+        if (kk < 2 * d.m2) reinterpret_cast<uint32_t*>(t_piece(d, b, h, kk >> 1))[c] = pack_bf16(acc[0], acc[1]);
+        if (kk + 2 < 2 * d.m2)
+            reinterpret_cast<uint32_t*>(t_piece(d, b, h, (kk >> 1) + 1))[c] = pack_bf16(acc[2], acc[3]);
     }
 }
 
@@ -464,11 +465,11 @@ __device__ __forceinline__ void row_dft_regs(const FnoDev& d, const bf16x8 (&ew)
     f32x4 acc = {};
 #pragma unroll
     for (int j = 0; j < KW; ++j) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ew[j], bv[j], acc, 0, 0, 0);
-    uint32_t* Tr = reinterpret_cast<uint32_t*>(t_row(d, b, h));
     const int c = ni * 16 + (lane & 15);
     const int kk = mi * 16 + 4 * (lane >> 4);
-    if (kk < 2 * d.m2) Tr[(kk >> 1) * d.CP + c] = pack_bf16(acc[0], acc[1]);
-    if (kk + 2 < 2 * d.m2) Tr[((kk >> 1) + 1) * d.CP + c] = pack_bf16(acc[2], acc[3]);
+    if (kk < 2 * d.m2) reinterpret_cast<uint32_t*>(t_piece(d, b, h, kk >> 1))[c] = pack_bf16(acc[0], acc[1]);
+    if (kk + 2 < 2 * d.m2)
+        reinterpret_cast<uint32_t*>(t_piece(d, b, h, (kk >> 1) + 1))[c] = pack_bf16(acc[2], acc[3]);
 }
 
 // The row held transposed in LDS, vt[c][w], stored channels last to orow[w][c]:
@@ -626,7 +627,7 @@ __device__ __forceinline__ void stage_t(const FnoDev& d, int b, int k2, __bf16* 
         bf16x8 t[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-            t[u] = *reinterpret_cast<const bf16x8*>(t_row(d, b, 4 * g + u) + (size_t)k2 * d.CP * 2 + 8 * q);
+            t[u] = *reinterpret_cast<const bf16x8*>(t_piece(d, b, 4 * g + u, k2) + 8 * q);
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             bf16x4 v;
