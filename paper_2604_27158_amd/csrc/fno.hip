@@ -5,8 +5,9 @@
 // Data layout (device workspace, per sample b):
 //   v  [Hp][Wpad][CP]   bf16  activations, channels last (CP = width rounded up to
 //                             32, Wpad = W' rounded up to 32; w >= W' is zero)
-//   T  [Hpad][m2][CP][2] bf16 row-DFT coefficients (re, im): each row h one
-//                             contiguous block, written by the row's own workgroup
+//   T  [m2][Hpad][CP][2] bf16 row-DFT coefficients (re, im): mode k2 of all rows
+//                             one contiguous block (one column workgroup's input);
+//                             row h writes one 128-byte (CP = 32) piece per mode
 //   Z  [2 m2][Hp][CP]   bf16  column-inverse coefficients, row kk = 2 k2 + (re/im),
 //                             channels fastest (each mode group stores whole rows)
 // Every contraction is arranged so that both MFMA operands are contiguous along
@@ -14,7 +15,8 @@
 //   row forward   T[kk][c]   = sum_w  EwT[kk][w]   * vt[c][w]     (vt staged in LDS)
 //   column        X[r][c]    = sum_hk EcolA[r][hk] * T[c][hk]     (per sample, k2; T of
 //                                the column staged transposed into LDS)
-//   mixing        Y[k][o]    = sum_i  X[k][i] R[i][o]              (complex, per mode)
+//   mixing        Y[k][o]    = sum_i  X[k][i] R[i][o]              (complex, per mode; bf16
+//                                dot products, weights with o contiguous)
 //   column inv    Zc[q][o]   = sum_r  EcolB[q][r]  * Y[o][r]
 //   row inverse   s[w][o]    = sum_kk BinvT[w][kk] * Z[o][kk] + sum_i v[w][i] * Wc[o][i]
 //                                (Z of the row transposed into LDS, kk >= 2 m2 zero)
