@@ -6,8 +6,12 @@ FP32 (GPU) vs FP64 (oracle) accumulation and the one-ulp bf16 flips it causes.
 A value whose two accumulations differ by delta flips with probability
 ~delta/ulp, so one rounding stage contributes ~sqrt(eps_acc * u_bf16) relative L2
 (eps_acc up to ~1e-4 for high modes with cancellation, u_bf16 = 2^-8): about
-2e-4 to 6e-4 per stage over 12-20 stages.  Bars: 5e-3 relative L2, and at most
-half of the oracle's own bf16-vs-FP64 distance.  The "fp64" oracle gives the
+2e-4 to 6e-4 per stage over 12-20 stages.  Bars: 1e-3 relative L2 for the
+models of width 32 or more and the porous models on their own 512x256 grid
+(measured 1e-4 to 5e-4); 5e-3 for the narrow (14-16 channel) models on small
+grids, where each output sums few bf16-rounded terms and one flipped rounding is a
+larger share of it (measured 7e-4 to 2.7e-3); and always at most half of the
+oracle's own bf16-vs-FP64 distance.  The "fp64" oracle gives the
 error against FP64, reported and bounded by 3e-2."""
 import zlib
 
@@ -20,6 +24,9 @@ from paper_2604_27158_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 TOL_BF16 = 5e-3
+TOL_BF16_TIGHT = 1e-3
+TIGHT = {"flagship-4to3-w32-L4-m12", "ragged-50x70-w64", "no-hidden-decoder-40x72", "all-modes-18x22",
+         "porous-rho-512x256", "porous-u-512x256"}
 TOL_FP64 = 3e-2
 
 
@@ -100,7 +107,8 @@ def test_fno_forward_parity(gpu, name, spec, H, Wd, B):
     print(f"{name}: rel-L2 vs bf16-emulating oracle {e_bf:.2e}, vs FP64 {e_64:.2e} "
           f"(oracle bf16 vs fp64 {rel(y_bf, y_64):.2e})")
     assert np.isfinite(y).all()
-    assert e_bf < TOL_BF16 and e_bf < 0.5 * rel(y_bf, y_64) and e_64 < TOL_FP64
+    bar = TOL_BF16_TIGHT if name in TIGHT else TOL_BF16
+    assert e_bf < bar and e_bf < 0.5 * rel(y_bf, y_64) and e_64 < TOL_FP64
 
 
 def test_fno_batch_is_per_sample(gpu):
