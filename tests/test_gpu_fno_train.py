@@ -8,9 +8,10 @@ Gradient references, both float64 autograd of the oracle's forward:
           gradient, its row transform, the conjugate-mixed coefficients and the
           column-inverse coefficients, four roundings of relative RMS
           2^-9 / sqrt(3) ~ 1.1e-3 each) plus the forward's accumulation-order flips.
-          Over up to 6 layers in quadrature that is ~6e-3 relative L2 for the
-          whole gradient; bar 2e-2, and 5e-2 for any single parameter tensor
-          (the smaller groups average fewer independent roundings);
+          Over up to 6 layers in quadrature that is at most ~6e-3 relative L2 for
+          the whole gradient (measured 1e-4 to 1e-3 on these shapes); bar 5e-3,
+          and 5e-2 for any single parameter tensor (the smaller groups average
+          fewer independent roundings; measured up to 1.3e-2);
   "fp64"  the exact gradient; reported, bound 8e-2."""
 import zlib
 
@@ -23,7 +24,7 @@ from paper_2604_27158_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-TOL_ALL = 2e-2
+TOL_ALL = 5e-3
 TOL_GROUP = 5e-2
 TOL_FP64 = 8e-2
 
