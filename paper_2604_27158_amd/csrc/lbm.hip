@@ -619,6 +619,24 @@ __device__ __forceinline__ bool ring_node(const LatticeGeom& g, int& i, int& j) 
 // non-periodic axis.
 constexpr unsigned short LK_SKIP = 0x100;
 
+// A level of LN nodes takes IT passes of nth lanes, the last one partial: the
+// waves that have a node in it do one collision more than the rest, and the
+// barrier at the end of the level waits for them.  On the 1024-lane tiles their
+// instructions are issued first (a wave priority above the others' until the
+// level's barrier), so that the others fill the issue slots they leave: 1024x512
+// porous flow 19.35 -> 18.6 us per four-step launch.  The 512-lane 64x8 tiles run
+// in many rounds of workgroups and got slower with it (8192x4096 lattice 141 ->
+// 132 GLUPS, batched flows 141 -> 134), so they keep one priority.
+template <int NTH>
+__device__ __forceinline__ void long_waves_first(int tid, int IT, int LN) {
+    if constexpr (NTH == 1024)
+        if ((tid & ~63) + (IT - 1) * NTH < LN) __builtin_amdgcn_s_setprio(2);
+}
+template <int NTH>
+__device__ __forceinline__ void same_priority() {
+    if constexpr (NTH == 1024) __builtin_amdgcn_s_setprio(0);
+}
+
 // Levels 1 .. S-2: the ring S-1-LVL nodes wide, from level LVL-1 in LDS.
 template <int S, int RY, int LVL, bool ZH, bool FORCE, typename R>
 __device__ __forceinline__ void ring_levels(const StepArgs& a, int x0, int y0, int tid, float* __restrict__ P,
@@ -630,6 +648,7 @@ __device__ __forceinline__ void ring_levels(const StepArgs& a, int x0, int y0, i
         constexpr int RING = S - 1 - LVL;
         float v[IT][9];
         bool ok[IT];
+        long_waves_first<TX * RY>(tid, IT, LN);
 #pragma unroll
         for (int t = 0; t < IT; ++t) {
             ok[t] = false;
@@ -647,6 +666,7 @@ __device__ __forceinline__ void ring_levels(const StepArgs& a, int x0, int y0, i
             for (int q = 0; q < 9; ++q) v[t][q] = f[q];
             ok[t] = true;
         }
+        same_priority<TX * RY>();
         __syncthreads();
 #pragma unroll
         for (int t = 0; t < IT; ++t) {
@@ -690,6 +710,7 @@ __device__ __forceinline__ void step_multi(const StepArgs& a, int bx, int by, fl
         LKS[e] = (unsigned short)code[t];
     }
     float f[IT0][9];
+    long_waves_first<NTH>(tid, IT0, LN0);
 #pragma unroll
     for (int t = 0; t < IT0; ++t)
         if (code[t] != LK_SKIP) gather_stream<float>(a.src, a.g, ii[t], jj[t], jj[t] * nx + ii[t], f[t]);
@@ -701,6 +722,7 @@ __device__ __forceinline__ void step_multi(const StepArgs& a, int bx, int by, fl
 #pragma unroll
         for (int q = 0; q < 9; ++q) P[q * LN0 + tid + t * NTH] = f[t][q];
     }
+    same_priority<NTH>();
     __syncthreads();
     ring_levels<S, RY, 1, ZH, FORCE, R>(a, x0, y0, tid, P, LKS);
     constexpr int WL = G::W(S - 2), LNL = G::LN(S - 2);
