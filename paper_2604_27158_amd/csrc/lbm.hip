@@ -459,11 +459,15 @@ __device__ __forceinline__ void collide_pair_trt(float v[9], double dr64, double
 // Boundary closure, moments and collision of one fluid node in arithmetic R
 // (float, double, Lean or LeanTRT) on its gathered float populations v (replaced
 // by the post-collision deviations); returns drho.  Every step kernel calls this,
-// so all of them evaluate one operation sequence.
-template <bool ZH, bool FORCE, typename R>
+// so all of them evaluate one operation sequence.  ZB: evaluate the Zou-He
+// closures only on the two boundary columns (a branch) instead of on every node
+// with a select; the same values either way.  The branch pays on the 512-lane
+// fused tiles (8192x4096 lattice 141 -> 147 GLUPS, batched flows 141 -> 144) and
+// costs on the 1024-lane ones (1024x512: 18.5 -> 18.8 us per launch).
+template <bool ZH, bool FORCE, typename R, bool ZB = false>
 __device__ __forceinline__ float collide_node(float v[9], int x, int nx, const StepArgs& a) {
     if constexpr (std::is_same<R, Lean>::value || std::is_same<R, LeanTRT>::value) {
-        if (ZH) zouhe<float>(v, x, nx, (float)a.u_in, (float)a.rho_out);
+        if (ZH && (!ZB || x == 0 || x == nx - 1)) zouhe<float>(v, x, nx, (float)a.u_in, (float)a.rho_out);
         const float dr = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7])) + v[8];
         const float jx = (v[1] - v[3]) + (v[5] - v[6]) + (v[8] - v[7]);
         const float jy = (v[2] - v[4]) + (v[5] - v[8]) + (v[6] - v[7]);
@@ -661,7 +665,7 @@ __device__ __forceinline__ void ring_levels(const StepArgs& a, int x0, int y0, i
             (void)ring_node(a.g, i, j);  // wraps i on a periodic axis (the node is inside)
             float f[9];
             pull_lds(P, WP, LNP, (ly + 1) * WP + lx + 1, lk, f);
-            (void)collide_node<ZH, FORCE, R>(f, i, a.g.nx, a);
+            (void)collide_node<ZH, FORCE, R, TX * RY != 1024>(f, i, a.g.nx, a);
 #pragma unroll
             for (int q = 0; q < 9; ++q) v[t][q] = f[q];
             ok[t] = true;
@@ -718,7 +722,7 @@ __device__ __forceinline__ void step_multi(const StepArgs& a, int bx, int by, fl
     for (int t = 0; t < IT0; ++t) {
         if (code[t] == LK_SKIP) continue;
         gather_bounce<float>(a.src, a.g, code[t], jj[t] * nx + ii[t], f[t]);
-        (void)collide_node<ZH, FORCE, R>(f[t], ii[t], nx, a);
+        (void)collide_node<ZH, FORCE, R, NTH != 1024>(f[t], ii[t], nx, a);
 #pragma unroll
         for (int q = 0; q < 9; ++q) P[q * LN0 + tid + t * NTH] = f[t][q];
     }
@@ -733,7 +737,7 @@ __device__ __forceinline__ void step_multi(const StepArgs& a, int bx, int by, fl
     if (lk == LK_SKIP) return;
     float fl[9];
     pull_lds(P, WL, LNL, (threadIdx.y + 1) * WL + threadIdx.x + 1, lk, fl);
-    (void)collide_node<ZH, FORCE, R>(fl, i, nx, a);
+    (void)collide_node<ZH, FORCE, R, NTH != 1024>(fl, i, nx, a);
     const size_t N = (size_t)a.g.N;
     float* __restrict__ d = a.dst + n;
 #pragma unroll
