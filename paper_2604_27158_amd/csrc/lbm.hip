@@ -627,8 +627,9 @@ constexpr unsigned short LK_SKIP = 0x100;
 // waves that have a node in it do one collision more than the rest, and the
 // barrier at the end of the level waits for them.  On the 1024-lane tiles their
 // instructions are issued first (a wave priority above the others' until the
-// level's barrier), so that the others fill the issue slots they leave: 1024x512
-// porous flow 19.35 -> 18.6 us per four-step launch.  The 512-lane 64x8 tiles run
+// level's barrier; on level 0 from the link-code reads on), so that the others
+// fill the issue slots they leave: 1024x512 porous flow 19.35 -> 18.25 us per
+// four-step launch.  The 512-lane 64x8 tiles run
 // in many rounds of workgroups and got slower with it (8192x4096 lattice 141 ->
 // 132 GLUPS, batched flows 141 -> 134), so they keep one priority.
 template <int NTH>
@@ -697,6 +698,7 @@ __device__ __forceinline__ void step_multi(const StepArgs& a, int bx, int by, fl
     // the link codes go to LDS for the later levels
     unsigned code[IT0];
     int ii[IT0], jj[IT0];
+    long_waves_first<NTH>(tid, IT0, LN0);
 #pragma unroll
     for (int t = 0; t < IT0; ++t) {
         code[t] = LK_SKIP;
@@ -714,7 +716,6 @@ __device__ __forceinline__ void step_multi(const StepArgs& a, int bx, int by, fl
         LKS[e] = (unsigned short)code[t];
     }
     float f[IT0][9];
-    long_waves_first<NTH>(tid, IT0, LN0);
 #pragma unroll
     for (int t = 0; t < IT0; ++t)
         if (code[t] != LK_SKIP) gather_stream<float>(a.src, a.g, ii[t], jj[t], jj[t] * nx + ii[t], f[t]);
