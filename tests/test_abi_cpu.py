@@ -126,7 +126,7 @@ def test_fno_model_create_validates_on_host(lib):
 
 @pytest.mark.parametrize("name,spl", [("node/lean", 1), ("quad/fp32", 1), ("pair-64x8/lean", 2),
                                       ("pair-64x4/mixed", 2), ("deep3-64x8/lean", 3),
-                                      ("deep4-64x16/lean", 4), ("deep4-64x8/fp32", 4),
+                                      ("deep5-64x16/lean", 5), ("deep4-64x8/fp32", 4),
                                       ("tuned deep3+nt 0.0616 ms/step".split()[1].split("+")[0], 3)])
 def test_bench_steps_per_launch_parses_every_kernel_name(name, spl):
     """bench.py divides the algorithmic bytes of one launch by its duration; the
@@ -146,6 +146,6 @@ def test_every_fused_shape_name_is_reported_by_the_library(lib):
     import bench
     src = open(os.path.join(ROOT, "paper_2604_27158_amd", "csrc", "lbm.hip")).read()
     names = set(re.findall(r'"((?:pair|deep\d)-64x\d+)/(?:lean|fp32|mixed)"', src))
-    assert names == {"pair-64x8", "pair-64x4", "deep3-64x8", "deep4-64x16", "deep4-64x8"}
+    assert names == {"pair-64x8", "pair-64x4", "deep3-64x8", "deep5-64x16", "deep4-64x8"}
     for n in names:
         assert bench.steps_per_launch(n + "/lean") == (2 if n.startswith("pair") else int(n[4]))

@@ -323,7 +323,7 @@ def test_step_kernels_agree_bitwise(gpu):
 
 @pytest.mark.parametrize("lat,shapes", [
     (W.porous_circles(5, nx=2048, ny=1024, keepout=60, rmin=12, rmax=30), ("pair-64x4", "deep4-64x8")),
-    (W.porous_circles(6, nx=1024, ny=512, keepout=30, rmin=8, rmax=20), ("pair-64x8", "deep4-64x16")),
+    (W.porous_circles(6, nx=1024, ny=512, keepout=30, rmin=8, rmax=20), ("pair-64x8", "deep5-64x16")),
     (W.porous_circles(7, nx=520, ny=200, keepout=20, rmin=6, rmax=14), ("pair-64x8", "deep3-64x8")),
     (W.periodic_box(70, 5, 0.7, gx=2e-6, shapes=[W.circle(30, 2, 1.5)]), ("pair-64x8", "deep3-64x8"))],
     ids=["2048x1024", "1024x512", "520x200", "70x5-periodic"])
