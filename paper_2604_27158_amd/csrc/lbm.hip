@@ -573,7 +573,8 @@ __global__ __launch_bounds__(256) void k_bgk_step(StepArgs a) {
 //   S = 5, 64 x 16  cache-resident lattices whose grid gives every CU two
 //                   workgroups (1024x512: 119.7 against 116.0 GLUPS for S = 4 and
 //                   117.5 for S = 6 with the levels updated in place; 66 KB of LDS)
-//   S = 3, 64 x 8   smaller cache-resident lattices (512x256: 47 against 44)
+//   S = 4, 64 x 8   smaller cache-resident lattices (512x256: 52.0 against 49.4 for
+//                   S = 3 and 49.8 for S = 5 with the levels updated in place)
 //   S = 4, 64 x 8   lattices streamed from HBM (8192x4096: 127 against 97; S = 3
 //                   reaches 119, 64 x 16 tiles 113)
 // Deeper blocking trades redundant ring collisions (29 % at S = 2, 64 x 8; 45 %
@@ -1227,7 +1228,7 @@ __global__ __launch_bounds__(64) void k_compare_final(const double* __restrict__
 using namespace lbmfno;
 
 // Fused multi-step kernel shapes: steps per launch, tile height, store kind.
-enum FusedShape { SHAPE_NONE, SHAPE_PAIR8, SHAPE_PAIR4_NT, SHAPE_DEEP3_8, SHAPE_DEEP5_16, SHAPE_DEEP4_8_NT };
+enum FusedShape { SHAPE_NONE, SHAPE_PAIR8, SHAPE_PAIR4_NT, SHAPE_DEEP4_8, SHAPE_DEEP5_16, SHAPE_DEEP4_8_NT };
 
 struct lbm_ctx {
     lbm_config cfg;
@@ -1489,7 +1490,7 @@ static int launch_multi(lbm_ctx* c) {
     switch (c->shape) {
         case SHAPE_PAIR8: launch_multi_shape<2, 8, false>(c, a); break;
         case SHAPE_PAIR4_NT: launch_multi_shape<2, 4, true>(c, a); break;
-        case SHAPE_DEEP3_8: launch_multi_shape<3, 8, false>(c, a); break;
+        case SHAPE_DEEP4_8: launch_multi_shape<4, 8, false>(c, a); break;
         case SHAPE_DEEP5_16: launch_multi_shape<5, 16, false>(c, a); break;
         case SHAPE_DEEP4_8_NT: launch_multi_shape<4, 8, true>(c, a); break;
         default: return fail(LBM_EINVAL, "no fused shape selected");
@@ -1579,8 +1580,8 @@ extern "C" int lbm_init(lbm_ctx** out, const lbm_config* cfg, const uint8_t* d_m
         c->shape = c->nontemporal ? SHAPE_PAIR4_NT : SHAPE_PAIR8;
         c->spl = 2;
     } else if (cfg->kernel == LBM_KERNEL_DEEP || cfg->kernel == LBM_KERNEL_AUTO) {
-        c->shape = c->nontemporal ? SHAPE_DEEP4_8_NT : tiles16 >= 512 ? SHAPE_DEEP5_16 : SHAPE_DEEP3_8;
-        c->spl = c->shape == SHAPE_DEEP3_8 ? 3 : c->shape == SHAPE_DEEP5_16 ? 5 : 4;
+        c->shape = c->nontemporal ? SHAPE_DEEP4_8_NT : tiles16 >= 512 ? SHAPE_DEEP5_16 : SHAPE_DEEP4_8;
+        c->spl = c->shape == SHAPE_DEEP5_16 ? 5 : 4;
     }
     c->vec4 = cfg->kernel == LBM_KERNEL_QUAD;
     c->gridx4 = (cfg->nx + 4 * TX - 1) / (4 * TX);
@@ -1838,7 +1839,7 @@ extern "C" const char* lbm_step_kernel(const lbm_ctx* c) {
         {"", "", ""},
         {"pair-64x8/lean", "pair-64x8/fp32", "pair-64x8/mixed"},
         {"pair-64x4/lean", "pair-64x4/fp32", "pair-64x4/mixed"},
-        {"deep3-64x8/lean", "deep3-64x8/fp32", "deep3-64x8/mixed"},
+        {"deep4-64x8/lean", "deep4-64x8/fp32", "deep4-64x8/mixed"},
         {"deep5-64x16/lean", "deep5-64x16/fp32", "deep5-64x16/mixed"},
         {"deep4-64x8/lean", "deep4-64x8/fp32", "deep4-64x8/mixed"}};
     if (c->spl > 1) return fused[c->shape][lean ? 0 : f32 ? 1 : 2];

@@ -146,6 +146,6 @@ def test_every_fused_shape_name_is_reported_by_the_library(lib):
     import bench
     src = open(os.path.join(ROOT, "paper_2604_27158_amd", "csrc", "lbm.hip")).read()
     names = set(re.findall(r'"((?:pair|deep\d)-64x\d+)/(?:lean|fp32|mixed)"', src))
-    assert names == {"pair-64x8", "pair-64x4", "deep3-64x8", "deep5-64x16", "deep4-64x8"}
+    assert names == {"pair-64x8", "pair-64x4", "deep5-64x16", "deep4-64x8"}
     for n in names:
         assert bench.steps_per_launch(n + "/lean") == (2 if n.startswith("pair") else int(n[4]))

@@ -324,17 +324,17 @@ def test_step_kernels_agree_bitwise(gpu):
 @pytest.mark.parametrize("lat,shapes", [
     (W.porous_circles(5, nx=2048, ny=1024, keepout=60, rmin=12, rmax=30), ("pair-64x4", "deep4-64x8")),
     (W.porous_circles(6, nx=1024, ny=512, keepout=30, rmin=8, rmax=20), ("pair-64x8", "deep5-64x16")),
-    (W.porous_circles(7, nx=520, ny=200, keepout=20, rmin=6, rmax=14), ("pair-64x8", "deep3-64x8")),
-    (W.periodic_box(70, 5, 0.7, gx=2e-6, shapes=[W.circle(30, 2, 1.5)]), ("pair-64x8", "deep3-64x8"))],
+    (W.porous_circles(7, nx=520, ny=200, keepout=20, rmin=6, rmax=14), ("pair-64x8", "deep4-64x8")),
+    (W.periodic_box(70, 5, 0.7, gx=2e-6, shapes=[W.circle(30, 2, 1.5)]), ("pair-64x8", "deep4-64x8"))],
     ids=["2048x1024", "1024x512", "520x200", "70x5-periodic"])
 def test_fused_shapes_agree_bitwise(gpu, lat, shapes):
     """Every fused multi-step shape gives the one-step kernel's bits after 101
     steps and after a report step: two-step 64 x 4 tiles with streaming stores and
     four-step 64 x 8 tiles on a 2048 x 1024 Zou-He lattice (151 MB of populations,
-    above the 128 MiB cache-residency threshold); two-step 64 x 8 and four-step
-    64 x 16 tiles on 1024 x 512; three-step 64 x 8 tiles on a 520 x 200 lattice
+    above the 128 MiB cache-residency threshold); two-step 64 x 8 and five-step
+    64 x 16 tiles on 1024 x 512; four-step 64 x 8 tiles on a 520 x 200 lattice
     (ragged tiles in x and y) and on a forced periodic 70 x 5 box, whose
-    two-node ring wraps around the 5 rows more than once."""
+    three-node ring wraps around the 5 rows more than once."""
     one = gpu_lattice(gpu, lat, 1)
     fused = [gpu_lattice(gpu, lat, k) for k in (3, 4)]
     assert tuple(G.step_kernel().split("/")[0] for G in fused) == shapes
