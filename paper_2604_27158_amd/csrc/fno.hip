@@ -477,10 +477,12 @@ __device__ __forceinline__ void row_dft_regs(const FnoDev& d, const bf16x8 (&ew)
 // The row held transposed in LDS, vt[c][w], stored channels last to orow[w][c]:
 // each thread assembles 8 channels of one point, and consecutive threads take
 // consecutive 16-byte pieces of the row, so a wave writes 1 KB of it contiguously.
+// CP is 32 or 64, so the CP / 8 pieces of a point divide the workgroup size (a
+// multiple of 64): a thread keeps its channel group c0 and steps through w.
 __device__ __forceinline__ void store_row_from_vt(const FnoDev& d, const __bf16* vt, __bf16* orow) {
     const int VS = vt_stride(d), ncg = d.CP / 8;
-    for (int i = threadIdx.x; i < d.Wpad * ncg; i += blockDim.x) {
-        const int w = i / ncg, c0 = 8 * (i - w * ncg);
+    const int c0 = 8 * (threadIdx.x % ncg), wstep = blockDim.x / ncg;
+    for (int w = threadIdx.x / ncg; w < d.Wpad; w += wstep) {
         bf16x8 t;
 #pragma unroll
         for (int e = 0; e < 8; ++e) t[e] = vt[(c0 + e) * VS + w];
@@ -597,9 +599,10 @@ __device__ __forceinline__ void z_store_column(const FnoDev& d, int b, int k2, c
 // KKp + 8, and the padded coefficient columns kk >= 2 m2 set to zero.  Reads are
 // 16-byte channel vectors of whole Z rows.
 __device__ __forceinline__ void stage_z(const FnoDev& d, int b, int h, __bf16* zs) {
+    // (nvec = CP / 8 is 4 or 8 and divides the workgroup size, as in store_row_from_vt)
     const int KKs = d.KKp + 8, nvec = d.CP / 8;
-    for (int i = threadIdx.x; i < d.KKp * nvec; i += blockDim.x) {
-        const int kk = i / nvec, o0 = 8 * (i % nvec);
+    const int o0 = 8 * (threadIdx.x % nvec), kstep = blockDim.x / nvec;
+    for (int kk = threadIdx.x / nvec; kk < d.KKp; kk += kstep) {
         bf16x8 t;
         if (kk < 2 * d.m2) {
             t = *reinterpret_cast<const bf16x8*>(d.Z + (((size_t)b * 2 * d.m2 + kk) * d.Hp + h) * d.CP + o0);
