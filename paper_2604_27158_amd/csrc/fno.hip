@@ -804,6 +804,7 @@ __global__ __launch_bounds__(256) void k_fno_rowinv(FnoDev d, const __bf16* __re
         acc = mma_any<KC>(Wc + ni * 32 * CP, CP, vrow + mi * 32 * CP, CP, CP, acc);
         const int w = mi * 32 + wl;
         const bool live = w < d.Wp;
+        const uint32_t lmask = live ? 0xffffffffu : 0u;
         const int ob = ni * 32 + 4 * g;  // channels of register group j: ob + 8 j + 0..3
         float val[16];
 #pragma unroll
@@ -826,8 +827,9 @@ __global__ __launch_bounds__(256) void k_fno_rowinv(FnoDev d, const __bf16* __re
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             uint2 q;
-            q.x = live ? pack_bf16(act_t<ACT>(val[4 * j + 0]), act_t<ACT>(val[4 * j + 1])) : 0u;
-            q.y = live ? pack_bf16(act_t<ACT>(val[4 * j + 2]), act_t<ACT>(val[4 * j + 3])) : 0u;
+            // (the activations unconditionally, then the mask: see k_fno_rowinv_p)
+            q.x = pack_bf16(act_t<ACT>(val[4 * j + 0]), act_t<ACT>(val[4 * j + 1])) & lmask;
+            q.y = pack_bf16(act_t<ACT>(val[4 * j + 2]), act_t<ACT>(val[4 * j + 3])) & lmask;
             if constexpr (DFT) {   // the row goes out from LDS below
                 __bf16* vc = vt + (ob + 8 * j) * VS + w;
                 const __bf16* e = reinterpret_cast<const __bf16*>(&q);
@@ -903,6 +905,7 @@ __global__ __launch_bounds__(256) void k_fno_rowinv_p(FnoDev d, const __bf16* __
             acc = mma_rows<KC>(wc, vb, acc);
             const int w = mi * 32 + wl;
             const bool live = w < d.Wp;
+            const uint32_t lmask = live ? 0xffffffffu : 0u;
             float val[16];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -923,8 +926,11 @@ __global__ __launch_bounds__(256) void k_fno_rowinv_p(FnoDev d, const __bf16* __
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 uint2 q;
-                q.x = live ? pack_bf16(act_t<ACT>(val[4 * j + 0]), act_t<ACT>(val[4 * j + 1])) : 0u;
-                q.y = live ? pack_bf16(act_t<ACT>(val[4 * j + 2]), act_t<ACT>(val[4 * j + 3])) : 0u;
+                // every lane evaluates the activations and a mask clears the points beyond W'
+                // (a select on the packed words would put each pair behind its own branch,
+                // and the sixteen evaluations could not be interleaved)
+                q.x = pack_bf16(act_t<ACT>(val[4 * j + 0]), act_t<ACT>(val[4 * j + 1])) & lmask;
+                q.y = pack_bf16(act_t<ACT>(val[4 * j + 2]), act_t<ACT>(val[4 * j + 3])) & lmask;
                 if constexpr (DFT) {
                     __bf16* vc = vt + (ob + 8 * j) * VS + w;
                     const __bf16* e = reinterpret_cast<const __bf16*>(&q);
@@ -989,6 +995,11 @@ __device__ __forceinline__ void dec_stage_input(const FnoDev& d, const __bf16* _
 // transposed so that a lane holds four consecutive units of one point and writes
 // them as one 8-byte bf16 quad.  With sv != NULL (training) the pre-activations
 // go to sv[pt][su] (float, DSP per point) for points below `valid`.
+// Mask of a packed bf16 pair (units u, u + 1) that keeps the units below n.
+__device__ __forceinline__ uint32_t unit_mask(int u, int n) {
+    return (u < n ? 0x0000ffffu : 0u) | (u + 1 < n ? 0xffff0000u : 0u);
+}
+
 template <int ACT>
 __device__ __forceinline__ void dec_hidden_layer(const FnoDev& d, const __bf16* in, __bf16* outb, int KP,
                                                  const __bf16* wp, const float* bp, int din, float* sv,
@@ -1008,9 +1019,11 @@ __device__ __forceinline__ void dec_hidden_layer(const FnoDev& d, const __bf16* 
             const float x0 = acc[4 * j] + bq.x, x1 = acc[4 * j + 1] + bq.y;
             const float x2 = acc[4 * j + 2] + bq.z, x3 = acc[4 * j + 3] + bq.w;
             if (sv && pt < valid) *reinterpret_cast<float4*>(sv + (size_t)pt * d.DSP + su) = make_float4(x0, x1, x2, x3);
+            // the activations unconditionally, the padded units (su >= dec_size) cleared
+            // by a bit mask afterwards, so that no activation sits behind a branch
             uint2 q;
-            q.x = pack_bf16(su < d.dec_size ? act_t<ACT>(x0) : 0.0f, su + 1 < d.dec_size ? act_t<ACT>(x1) : 0.0f);
-            q.y = pack_bf16(su + 2 < d.dec_size ? act_t<ACT>(x2) : 0.0f, su + 3 < d.dec_size ? act_t<ACT>(x3) : 0.0f);
+            q.x = pack_bf16(act_t<ACT>(x0), act_t<ACT>(x1)) & unit_mask(su, d.dec_size);
+            q.y = pack_bf16(act_t<ACT>(x2), act_t<ACT>(x3)) & unit_mask(su + 2, d.dec_size);
             *reinterpret_cast<uint2*>(outb + pt * KP + su) = q;
         }
     }
