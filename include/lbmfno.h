@@ -80,10 +80,10 @@ extern "C" {
                               traffic per step).  64 x 8 tiles when both population
                               copies fit 128 MiB, else 64 x 4 tiles with streaming
                               stores.  Any nx. */
-#define LBM_KERNEL_DEEP 4  /* deeper temporal blocking: four steps per launch (a
-                              three-node ring) on 64 x 16 tiles when both population
+#define LBM_KERNEL_DEEP 4  /* deeper temporal blocking: five steps per launch (a
+                              four-node ring) on 64 x 16 tiles when both population
                               copies fit 128 MiB and the lattice has at least 512
-                              such tiles, three steps (a two-node ring) on 64 x 8
+                              such tiles, four steps (a three-node ring) on 64 x 8
                               tiles on smaller ones, four steps on 64 x 8 tiles with
                               streaming stores above 128 MiB.  Any nx. */
 

@@ -578,8 +578,9 @@ __global__ __launch_bounds__(256) void k_bgk_step(StepArgs a) {
 //   S = 4, 64 x 8   lattices streamed from HBM (8192x4096: 127 against 97; S = 3
 //                   reaches 119, 64 x 16 tiles 113)
 // Deeper blocking trades redundant ring collisions (29 % at S = 2, 64 x 8; 45 %
-// at S = 4, 64 x 8; 25 % at S = 4, 64 x 16) for fewer global-memory round trips;
-// the kernel is bound by memory latency, not by the vector ALUs (42 % busy).
+// at S = 4, 64 x 8; 34 % at S = 5, 64 x 16) for fewer global-memory round trips;
+// on 1024x512 the vector ALUs are 60 % busy, the rest is memory latency and the
+// barriers between levels.
 template <int S, int RY>
 struct Ring {
     static constexpr int W(int lvl) { return TX + 2 * (S - 1 - lvl); }
@@ -1569,9 +1570,9 @@ extern "C" int lbm_init(lbm_ctx** out, const lbm_config* cfg, const uint8_t* d_m
     // Fused multi-step launches beat every one-step kernel at every size measured
     // (128x128 to 8192x4096): on large lattices by cutting the population traffic
     // per step, on small, latency-bound ones by cutting the launches.  The deep
-    // kernel (the default) runs four steps per launch on 64 x 16 tiles on
+    // kernel (the default) runs five steps per launch on 64 x 16 tiles on
     // cache-resident lattices whose grid still gives every CU two such workgroups,
-    // three steps on 64 x 8 tiles on smaller ones, and four steps on 64 x 8 tiles
+    // four steps on 64 x 8 tiles on smaller ones, and four steps on 64 x 8 tiles
     // with streaming stores on lattices streamed from HBM.
     const int64_t tiles16 = (int64_t)c->g.gridx * ((cfg->ny + 15) / 16);
     c->shape = SHAPE_NONE;
