@@ -197,7 +197,9 @@ __device__ __forceinline__ float gelu_fast(float x) {
                     t * (-0.7265760135f + t * 0.5307027145f))));
     // exp(-x^2 / 2) = 2^(-x^2 log2(e) / 2)
     const float e = __builtin_amdgcn_exp2f((-0.72134752044448170368f * x) * x);
-    return fmaf(-(ax * p), e, fmaxf(x, 0.0f));
+    // max(x, 0) as a median of three (one instruction; fmaxf adds a canonicalising
+    // max of x with itself); equal for every finite x
+    return fmaf(-(ax * p), e, __builtin_amdgcn_fmed3f(x, 0.0f, 3.402823466e38f));
 }
 
 template <int KIND>
